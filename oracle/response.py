@@ -1,0 +1,286 @@
+"""EOM states, Lagrangian multipliers, densities and the derivative coupling.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Every derivative object of the method is taken here from its definition by
+automatic differentiation (torch.func, fp64) of the residual and energy in
+``oracle.ccsd``:
+
+* Jacobian A_mu,nu = <mu~|[Hbar, tau_nu]|HF> = dOmega_mu/dt_nu (Sec. II B);
+* eta_nu = <HF|[Hbar, tau_nu]|HF> = dE/dt_nu, which fixes the reference
+  weight R0 = eta.R / omega of a right EOM state;
+* F-matrix transform (F(gamma) R)_sigma = d/dt_sigma [gamma . A(t) R] (Sec. II B);
+* the orbital-rotation derivatives under H -> exp(kappa) H exp(-kappa)
+  (Sec. II A), i.e. integrals rotated by U = exp(K);
+* the effective densities as derivatives of the (linear) Hamiltonian
+  functional with respect to h and g.
+
+Packed vectors: singles (i*v + a) then unique doubles (P <= Q, P = i*v + a);
+the biorthonormal inner product of two packed vectors is their plain dot
+product (``ccsd.dot_bio``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+import torch
+from torch.func import grad, jvp, vjp, vmap
+
+from . import ccsd
+from .ccsd import DT, as_t
+
+
+# ------------------------------------------------------------- packed maps
+def omega_vec(x, h, g, o, v):
+    t1, t2 = ccsd.unpack(x, o, v)
+    return ccsd.pack(*ccsd.residual(t1, t2, h, g))
+
+
+def energy_vec(x, h, g, o, v):
+    t1, t2 = ccsd.unpack(x, o, v)
+    return ccsd.energy(t1, t2, h, g)
+
+
+def right_transform(x, R, h, g, o, v):
+    """A(t) R."""
+    return jvp(lambda y: omega_vec(y, h, g, o, v), (x,), (R,))[1]
+
+
+def left_transform(x, L, h, g, o, v):
+    """L^T A(t)."""
+    _, f = vjp(lambda y: omega_vec(y, h, g, o, v), x)
+    return f(L)[0]
+
+
+def eta(x, h, g, o, v):
+    return grad(lambda y: energy_vec(y, h, g, o, v))(x)
+
+
+def dense_jacobian(x, h, g, o, v, chunk: int = 128):
+    n = x.numel()
+    f = lambda R: right_transform(x, R, h, g, o, v)  # noqa: E731
+    cols = []
+    I = torch.eye(n, dtype=DT)
+    for s in range(0, n, chunk):
+        cols.append(vmap(f)(I[s:s + chunk]))
+    return torch.cat(cols, 0).T.contiguous()
+
+
+# ----------------------------------------------------------------- EOM
+def gauge_right(R: np.ndarray) -> np.ndarray:
+    """dot_bio(R, R) = 1 and the largest-magnitude component positive
+    (ties resolved towards the lowest packed index)."""
+    R = R / np.linalg.norm(R)
+    k = int(np.argmax(np.abs(R)))
+    return R if R[k] > 0 else -R
+
+
+def eom_dense(A: np.ndarray, nroots: int, imag_tol: float = 1e-8):
+    """Lowest nroots (by Re omega) right and left eigenpairs of A.
+
+    Returns (omega[nroots], R[nroots, dim], L[nroots, dim]) with R gauged by
+    ``gauge_right`` and L biorthonormal to R (L R^T = 1).
+    """
+    w, vl, vr = scipy.linalg.eig(A, left=True, right=True)
+    order = np.argsort(w.real)[:nroots]
+    if np.abs(w[order].imag).max() > imag_tol:
+        raise ValueError("complex EOM root among the requested states")
+    om = w[order].real
+    R = np.array([gauge_right(vr[:, k].real) for k in order])
+    L = np.array([vl[:, k].real for k in order])
+    L = np.linalg.solve(L @ R.T, L)
+    return om, R, L
+
+
+# ------------------------------------------------------- state overlaps
+def outer(x1, y1):
+    """(x (x) y)_aibj = x_ai y_bj as a [i, j, a, b] tensor."""
+    return torch.einsum("ia,jb->ijab", x1, y1)
+
+
+def overlap(dT, L, R0, R, o, v):
+    """<HF| L_i exp(-T0) (R0 + R_j) exp(T0 + dT) |HF> for L0 = 0 (Sec. II A).
+
+    Exact in the CC parameterisation: L holds only single and double
+    de-excitations, so only the singles and doubles of
+    (R0 + R)(1 + dT + dT^2/2)|HF> contribute.
+    """
+    d1, d2 = ccsd.unpack(dT, o, v)
+    r1, r2 = ccsd.unpack(R, o, v)
+    s1 = R0 * d1 + r1
+    s2 = R0 * (d2 + outer(d1, d1)) + r2 + outer(d1, r1) + outer(r1, d1)
+    return torch.dot(L, ccsd.pack(s1, s2))
+
+
+def transition_density(x, L, R0, R, o, v, n):
+    """D_pq = <HF| L exp(-T) E_pq (R0 + R) exp(T) |HF> (L0 = 0).
+
+    With a one-electron operator h1 and Hbar1 = exp(-T) h1 exp(T):
+    <L| Hbar1 (R0 + R) |HF> = R0 L.Omega(h1) + L.(A(h1) R) + E(h1) L.R
+    + L2 . (R1 (x) Omega1(h1) + Omega1(h1) (x) R1), all linear in h1;
+    D is its gradient with respect to h1.
+    """
+    g0 = torch.zeros((n, n, n, n), dtype=DT)
+    r1, _ = ccsd.unpack(R, o, v)
+    nov = o * v
+
+    def functional(h1):
+        om = omega_vec(x, h1, g0, o, v)
+        ar = right_transform(x, R, h1, g0, o, v)
+        e1 = energy_vec(x, h1, g0, o, v)
+        om1 = om[:nov].reshape(o, v)
+        z = torch.zeros((o, v), dtype=DT)
+        x2 = ccsd.pack(z, outer(r1, om1) + outer(om1, r1))
+        return (R0 * torch.dot(L, om) + torch.dot(L, ar) + e1 * torch.dot(L, R)
+                + torch.dot(L, x2))
+
+    return grad(functional)(torch.zeros((n, n), dtype=DT))
+
+
+# ------------------------------------------------------ orbital rotation
+def kappa_matrix(kappa, o, v):
+    """K with K_ai = kappa_ai, K_ia = -kappa_ai (kappa[i, a])."""
+    lower = torch.nn.functional.pad(kappa.T, (0, v, o, 0))
+    return lower - lower.T
+
+
+def rotate(h, g, kappa, o, v):
+    """Integrals of exp(kappa) H exp(-kappa): U h U^T and U^(x4) g, U = exp(K)."""
+    U = torch.linalg.matrix_exp(kappa_matrix(kappa, o, v))
+    hr = U @ h @ U.T
+    gr = torch.einsum("pP,PQRS->pQRS", U, g)
+    gr = torch.einsum("qQ,pQRS->pqRS", U, gr)
+    gr = torch.einsum("rR,pqRS->pqrS", U, gr)
+    gr = torch.einsum("sS,pqrS->pqrs", U, gr)
+    return hr, gr
+
+
+def fock_ai(h, g, o):
+    """Brillouin vector F_ai in [i, a] layout."""
+    return ccsd.fock(h, g, o)[o:, :o].T
+
+
+def hf_hessian(h, g, o, v):
+    """A^HF[(ai), (bj)] = dF_ai / dkappa_bj at kappa = 0."""
+    f = lambda k: fock_ai(*rotate(h, g, k.reshape(o, v), o, v), o).reshape(-1)  # noqa: E731
+    k0 = torch.zeros(o * v, dtype=DT)
+    I = torch.eye(o * v, dtype=DT)
+    cols = vmap(lambda e: jvp(f, (k0,), (e,))[1])(I)
+    return cols.T.contiguous()
+
+
+# ------------------------------------------------------------ multipliers
+def lagrangian_hamiltonian_part(x, gamma, zeta, Rj, h, g, o, v):
+    """gamma . A(t; h, g) R_j + zeta . Omega(t; h, g)."""
+    return (torch.dot(gamma, right_transform(x, Rj, h, g, o, v))
+            + torch.dot(zeta, omega_vec(x, h, g, o, v)))
+
+
+def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
+    """Multipliers of the ordered excited-state pair (i, j), i != j.
+
+    gamma = L_i/(omega_j - omega_i) and xi = -omega_j gamma.R_j (Sec. II B);
+    t-stationarity A^T zeta = -eta_t with
+    eta_t = d/dt <L_i| exp(-T0) (R0 + R_j) exp(T) |HF> + F(gamma) R_j;
+    kappa-stationarity (A^HF)^T kappa_bar = -eta_kappa with
+    eta_kappa = d/dkappa [O + zeta.Omega + gamma.(A R_j)] under
+    H -> exp(kappa) H exp(-kappa) and |psi_j^R> -> exp(-kappa) |psi_j^R>.
+    """
+    o, v, h, g, x = st["o"], st["v"], st["h"], st["g"], st["x"]
+    n = o + v
+    om, R, L, R0 = st["omega"], st["R"], st["L"], st["R0"]
+    Li, Rj, R0j = L[i], R[j], R0[j]
+    gamma = Li / (om[j] - om[i])
+    xi = -om[j] * torch.dot(gamma, Rj)
+    # eta_t
+    zero = torch.zeros_like(x)
+    eta_o = grad(lambda d: overlap(d, Li, R0j, Rj, o, v))(zero)
+    eta_f = grad(lambda y: torch.dot(gamma, right_transform(y, Rj, h, g, o, v)))(x)
+    eta_t = eta_o + eta_f
+    A = st.get("A")
+    if A is None:
+        A = dense_jacobian(x, h, g, o, v)
+        st["A"] = A
+    zeta = torch.linalg.solve(A.T, -eta_t)
+    out = dict(gamma=gamma, xi=xi, eta_t=eta_t, eta_t_overlap=eta_o, zeta=zeta)
+    D = transition_density(x, Li, R0j, Rj, o, v, n)
+    out["D"] = D
+    if relaxed:
+        k1 = -(D[o:, :o].T - D[:o, o:])
+        k0 = torch.zeros((o, v), dtype=DT)
+        k23 = grad(lambda k: lagrangian_hamiltonian_part(
+            x, gamma, zeta, Rj, *rotate(h, g, k, o, v), o, v))(k0)
+        eta_k = k1 + k23
+        AHF = hf_hessian(h, g, o, v)
+        kbar = torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
+        out.update(eta_kappa=eta_k, eta_kappa_overlap=k1, AHF=AHF, kappa_bar=kbar)
+    else:
+        out["kappa_bar"] = torch.zeros((o, v), dtype=DT)
+    return out
+
+
+# ----------------------------------------------------------- coupling
+def coupling_direct(st: dict, mult: dict, j: int, dh, dg) -> float:
+    """F^q = gamma.(A(t; H^q) R_j) + zeta.Omega(t; H^q) + kappa_bar.F^q_ai (Sec. II C)."""
+    o, v, x = st["o"], st["v"], st["x"]
+    dh, dg = as_t(dh), as_t(dg)
+    val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"], st["R"][j],
+                                      dh, dg, o, v)
+    val = val + torch.sum(mult["kappa_bar"] * fock_ai(dh, dg, o))
+    return float(val)
+
+
+def effective_densities(st: dict, mult: dict, j: int):
+    """(D_eff[n,n], d_eff[n,n,n,n]) with F^q = sum D_eff dh + 1/2 sum d_eff dg.
+
+    Gradient of the Hamiltonian-linear part of the Lagrangian,
+    gamma.A(t;h,g)R_j + zeta.Omega(t;h,g) + kappa_bar.F_ai(h,g), with respect
+    to h and g; d_eff is symmetrised over the 8-fold permutation group of
+    real two-electron integrals.
+    """
+    o, v, x = st["o"], st["v"], st["x"]
+    n = o + v
+
+    def functional(h, g):
+        val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"],
+                                          st["R"][j], h, g, o, v)
+        return val + torch.sum(mult["kappa_bar"] * fock_ai(h, g, o))
+
+    h0 = torch.zeros((n, n), dtype=DT)
+    g0 = torch.zeros((n, n, n, n), dtype=DT)
+    Dh, Dg = grad(functional, argnums=(0, 1))(h0, g0)
+    Dh = 0.5 * (Dh + Dh.T)
+    d = 2.0 * Dg
+    d = 0.5 * (d + d.permute(2, 3, 0, 1))
+    d = 0.5 * (d + d.permute(1, 0, 2, 3))
+    d = 0.5 * (d + d.permute(0, 1, 3, 2))
+    return Dh, d
+
+
+def coupling_from_densities(D, d, dh, dg) -> float:
+    return float(torch.sum(D * as_t(dh)) + 0.5 * torch.sum(d * as_t(dg)))
+
+
+# -------------------------------------------------------------- pipeline
+def ground_and_eom(h, g, o: int, nroots: int, tol: float = 1e-11, t_init=None):
+    """Solve CCSD and the lowest nroots right/left EOM states (dense)."""
+    h, g = as_t(h), as_t(g)
+    n = h.shape[0]
+    v = n - o
+    t1, t2, E0, it = ccsd.solve_ground(h, g, o, tol=tol, t_init=t_init)
+    x = ccsd.pack(t1, t2)
+    A = dense_jacobian(x, h, g, o, v)
+    om, R, L = eom_dense(A.numpy(), nroots)
+    R, L = torch.as_tensor(R), torch.as_tensor(L)
+    et = eta(x, h, g, o, v)
+    R0 = torch.stack([torch.dot(et, R[k]) / om[k] for k in range(nroots)])
+    return dict(o=o, v=v, h=h, g=g, x=x, t1=t1, t2=t2, E0=E0, iters=it, A=A,
+                omega=torch.as_tensor(om), R=R, L=L, R0=R0, eta=et)
+
+
+def system_hamiltonian(eps, B, o):
+    """(h, g) of a synthetic system: g from the DF factor, h such that the
+    Fock matrix is diag(eps) (canonical Hartree-Fock reference)."""
+    g = ccsd.eri_from_factor(B)
+    h = ccsd.hamiltonian_from_eps(eps, g, o)
+    return h, g
