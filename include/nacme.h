@@ -1,0 +1,170 @@
+/*
+ * nacme.h - C ABI of the MI355X (gfx950) CCSD non-adiabatic derivative
+ * coupling library (libnacme.so).
+ *
+ * The library evaluates, for the closed-shell CCSD model, the biorthonormal
+ * derivative coupling F_ij = <psi_i^L | d psi_j^R>  between excited states i
+ * and j (Kjonstad & Koch, Sec. II A, eq. nac) through the Lagrangian route of
+ * Sec. II: ground-state amplitudes (Sec. II A), right and left EOM states
+ * (Sec. II A), the multipliers gamma, zeta and kappa-bar (Sec. II B, eqs.
+ * amplituderelax and orbitalrelax), effective densities (Sec. II C, eq.
+ * NAC_NC_densities) and their contraction with Hamiltonian derivatives
+ * (Sec. II C, eq. NAC_NC).
+ *
+ * Hamiltonian: H = sum_pq h_pq E_pq + 1/2 sum_pqrs g_pqrs e_pqrs over n = o + v
+ * orthonormal spatial orbitals (o occupied first), with density-fitted
+ * two-electron integrals g_pqrs = (pq|rs) = sum_P B[P][p][q] B[P][r][s] and
+ * a canonical Hartree-Fock reference: the Fock matrix
+ * f_pq = h_pq + sum_k (2 g_pqkk - g_pkkq) equals diag(eps).  The one-electron
+ * integrals are implied by that condition and are never passed.
+ *
+ * Conventions
+ *  - Every call returns a status: 0 OK, 1 CC_NOT_CONVERGED (outputs hold the
+ *    last iterate), negative = error: -1 ARG, -2 STATE (call order), -3 HIP
+ *    (device failure; sticky), -4 OOM, -5 NUMERIC (NaN/Inf), -6 COMPLEX_ROOT.
+ *    cc_last_error() returns a readable message for the last failure.
+ *  - Large arrays are DEVICE pointers owned by the caller, fp64, row-major;
+ *    they are read during the call and copied where the library keeps them.
+ *    Small results (energies, omega[], F[], iteration counts) are HOST
+ *    pointers.  All device work is enqueued on the stream given to
+ *    cc_create (NULL = default stream); the call synchronises that stream
+ *    before it writes host outputs.  A context is not thread-safe.
+ *  - Amplitude-shaped vectors (t, R_k, L_k, zeta, ...) are stored as
+ *    [o*v singles x1[i][a]] followed by [o*o*v*v doubles x2[i][j][a][b]],
+ *    with x2[i][j][a][b] == x2[j][i][b][a].  The doubles parameters are the
+ *    unique pairs (ai) <= (bj), T2 = 1/2 sum t_aibj E_ai E_bj; the
+ *    biorthonormal inner product is sum_mu x_mu y_mu over the unique
+ *    parameters.  Left vectors are coefficients of the biorthonormal dual
+ *    basis <mu~|.
+ *  - Excited states are numbered 1..nroots in ascending excitation energy;
+ *    0 is the ground state.  Right states are normalised to unit
+ *    biorthonormal norm with their largest-magnitude parameter positive; left
+ *    states satisfy L_k . R_l = delta_kl.
+ *  - Call order: cc_create -> cc_ground -> eom_solve(RIGHT) and
+ *    eom_solve(LEFT) (or BOTH) -> multipliers(i,j) -> densities(i,j) ->
+ *    nacme(i,j).  Anything else returns -2.
+ */
+#ifndef NACME_H
+#define NACME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CC_OK 0
+#define CC_NOT_CONVERGED 1
+#define CC_ERR_ARG (-1)
+#define CC_ERR_STATE (-2)
+#define CC_ERR_HIP (-3)
+#define CC_ERR_OOM (-4)
+#define CC_ERR_NUMERIC (-5)
+#define CC_ERR_COMPLEX_ROOT (-6)
+
+#define CC_RIGHT 1
+#define CC_LEFT 2
+#define CC_BOTH 3
+
+#define CC_FP64 0
+
+/* Export / guess selectors. */
+#define CC_T 1        /* ground amplitudes (amplitude-shaped)                 */
+#define CC_R 2        /* right EOM state idx (amplitude-shaped)               */
+#define CC_L 3        /* left EOM state idx (amplitude-shaped)                */
+#define CC_R0 4       /* reference weight R0 of right state idx (1 double)    */
+#define CC_ZETA 5     /* zeta-bar of the pair (i, j) (amplitude-shaped)       */
+#define CC_KAPPA 6    /* kappa-bar of the pair (i, j) ([o][v])                */
+#define CC_D1 7       /* effective one-electron density of (i, j) ([n][n])   */
+#define CC_ETA_T 8    /* right-hand side eta_t of the zeta equation of (i, j) */
+#define CC_ETA_K 9    /* right-hand side eta_kappa of the kappa equation      */
+#define CC_DTRANS 10  /* transition density <L_i|E_pq|R_j> ([n][n])           */
+
+typedef struct cc_ctx cc_ctx;
+
+typedef struct {
+  int precision;       /* CC_FP64                                              */
+  int relaxed;         /* 1: orbital-relaxed (kappa-bar solved), 0: fixed      */
+                       /*    reference (kappa-bar = 0)                         */
+  double tol_ground;   /* max |Omega_mu| of the ground state                   */
+  double tol_eom;      /* biorthonormal norm of each EOM residual              */
+  double tol_mult;     /* biorthonormal norm of the multiplier residuals      */
+  int maxit;           /* iteration cap of every solver                        */
+  int diis_dim;        /* DIIS history of the ground-state solver              */
+  int davidson_block;  /* extra trial vectors beyond nroots                    */
+  int davidson_max;    /* subspace size before a restart                       */
+} cc_opts;
+
+/* Defaults: FP64, relaxed, tolerances 1e-10 / 1e-9 / 1e-9, maxit 200,
+ * diis_dim 8, davidson_block 2, davidson_max 48.                               */
+void cc_default_opts(cc_opts* opts);
+
+/* Creates a context.  eps[n]: canonical orbital energies (device); B[naux][n][n]
+ * (device), symmetric in p, q.  Copies both; builds the two-electron
+ * integrals.  opts may be NULL (defaults).  stream: hipStream_t or NULL.
+ * Errors: -1 bad sizes/pointers, -4 out of device memory, -3 HIP failure.   */
+int cc_create(cc_ctx** ctx, int o, int v, int naux, const double* eps, const double* B,
+              const cc_opts* opts, void* stream);
+
+/* Solves the CCSD amplitude equations Omega(t) = 0 (Sec. II A) from t = 0 (or
+ * from a guess set with cc_set_guess(CC_T)).  e_corr: correlation energy
+ * <HF|exp(-T) H exp(T)|HF> - E_HF (host).  iters (host, may be NULL).       */
+int cc_ground(cc_ctx* ctx, double* e_corr, int* iters);
+
+/* Lowest nroots excitation energies of the CC Jacobian A = dOmega/dt
+ * (Sec. II B) and the right (A R = omega R) and/or left (L A = omega L)
+ * states; after both sides are known they are gauged and biorthonormalised
+ * and R0_k = eta.R_k / omega_k is formed.  omega: host [nroots].
+ * -6 if a requested root is complex.                                        */
+int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
+
+/* Multipliers of the ordered pair (i, j), 1 <= i != j <= nroots:
+ * gamma = L_i/(omega_j - omega_i), xi = 0 (Sec. II B); zeta-bar from
+ * A^T zeta = -eta_t (eq. amplituderelax) and, when relaxed, kappa-bar from
+ * (A^HF)^T kappa = -eta_kappa (eq. orbitalrelax).  iters: host [2] or NULL
+ * (zeta and kappa iterations).                                               */
+int multipliers(cc_ctx* ctx, int i, int j, int* iters);
+
+/* Effective densities of the pair (i, j): D_eff (n x n) and the two-electron
+ * density d_eff, such that F^q = sum D_eff dh^q + 1/2 sum d_eff dg^q
+ * (Sec. II C, eq. NAC_NC_densities).  Kept on the device for nacme();
+ * D1 (device [n][n], may be NULL) receives D_eff.                            */
+int densities(cc_ctx* ctx, int i, int j, double* D1);
+
+/* Derivative coupling F_ij^q for nq perturbation directions (Sec. II C):
+ * dh[nq][n][n] one-electron derivatives, dB[nq][naux][n][n] derivative
+ * factors with dg^q_pqrs = sum_P dB[q][P][p][q'] dB[q][P][r][s] (device).
+ * F: host [nq].                                                              */
+int nacme(cc_ctx* ctx, int i, int j, int nq, const double* dh, const double* dB, double* F);
+
+/* ---- test / benchmark surface ------------------------------------------- */
+/* Y = A X (side CC_RIGHT) or Y = X^T A (side CC_LEFT) at the current ground
+ * amplitudes; X, Y amplitude-shaped device vectors.                          */
+int cc_apply_jacobian(cc_ctx* ctx, int side, const double* X, double* Y);
+/* omega = Omega(t) for amplitudes t (device, amplitude-shaped).              */
+int cc_residual(cc_ctx* ctx, const double* t, double* omega);
+/* Copies a stored quantity (selectors above) to dst (device; CC_R0 host).
+ * idx: state (CC_R, CC_L, CC_R0) or i (pair quantities); jdx: j.            */
+int cc_export(cc_ctx* ctx, int what, int idx, int jdx, double* dst);
+/* Sets a starting guess: CC_T (amplitudes for cc_ground).                    */
+int cc_set_guess(cc_ctx* ctx, int what, int idx, const double* src);
+const char* cc_last_error(const cc_ctx* ctx);
+void cc_destroy(cc_ctx* ctx);
+
+/* Engine surface.  C = alpha * einsum(spec)(A, B) + beta * C on device
+ * arrays; spec "ab,bc->ac" (lowercase letters, <= 6 per operand, repeated
+ * letters inside one operand select a diagonal).  dims* give the shapes.    */
+int nm_contract(const char* spec, double alpha, const double* A, const int64_t* dimsA,
+                const double* B, const int64_t* dimsB, double beta, double* C,
+                const int64_t* dimsC, void* stream);
+/* Host-only: eigen-decomposition of a real m x m row-major matrix used for
+ * Davidson subspaces; wr, wi [m]; V [m][m] real parts of unit eigenvectors
+ * (row k = vector k, phase chosen so its largest component is real).       */
+int nm_eig_host(int m, const double* G, double* wr, double* wi, double* V);
+/* Library version string. */
+const char* nm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1302 @@
+// Closed-shell CCSD derivative couplings on the device: residual graph,
+// ground state, EOM (Davidson), multipliers, densities and the coupling
+// contraction, behind the C ABI of include/nacme.h.
+//
+// Only the residual Omega(t; f, g) is written out by hand (the spin-adapted
+// T1-transformed CCSD equations).  Every other operator of the Lagrangian is
+// obtained by differentiating that graph on the device:
+//   A R            = forward derivative (jvp) of Omega along R      (Sec. II B)
+//   L^T A          = reverse derivative (vjp) of L.Omega             (Sec. II B)
+//   F(gamma) R     = reverse derivative of gamma.(A R)               (Sec. II B)
+//   densities      = reverse derivative of the Hamiltonian-linear
+//                    part of the Lagrangian w.r.t. the integrals      (Sec. II C)
+//   eta_kappa, A^HF = derivatives through H -> exp(kappa) H exp(-kappa),
+//                    linearised at kappa = 0                          (Sec. II A/B)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nacme.h"
+#include "engine.h"
+#include "linalg.h"
+
+#include <cstdio>
+#include <cstdlib>
+
+namespace nm {
+
+static bool verbose() {
+  static int v = -1;
+  if (v < 0) v = std::getenv("NACME_VERBOSE") ? 1 : 0;
+  return v == 1;
+}
+
+// ------------------------------------------------------------------ context
+struct PairData {
+  double* zeta = nullptr;    // amplitude-shaped
+  double* gamma = nullptr;   // amplitude-shaped
+  double* eta_t = nullptr;
+  double* kbar = nullptr;    // [o][v]
+  double* eta_k = nullptr;   // [o][v]
+  double* dtrans = nullptr;  // [n][n] transition density
+  double* Fbar = nullptr;    // [n][n]  d Phi / d f
+  double* Gbar = nullptr;    // [n]^4   d Phi / d g
+  double* Deff = nullptr;    // [n][n]
+  double* Gam = nullptr;     // [n]^4   two-electron density (1/2 d_eff)
+  bool have_mult = false, have_dens = false;
+};
+
+}  // namespace nm
+
+struct cc_ctx {
+  int o = 0, v = 0, n = 0, naux = 0;
+  int64_t N = 0;  // amplitude-shaped length
+  cc_opts opts{};
+  hipStream_t s = nullptr;
+  std::unique_ptr<nm::Engine> eng;
+  std::vector<void*> owned;
+  nm::Tensor eps, f, g, I;
+  std::vector<double> eps_h;
+  double* t = nullptr;
+  bool have_guess = false;
+  int stage = 0;  // 1 ground done
+  bool have_right = false, have_left = false, gauged = false;
+  double ecorr = 0.0;
+  int nroots = 0;
+  std::vector<double> omega_r, omega_l, R0;
+  std::vector<double*> R, L;
+  std::map<std::pair<int, int>, nm::PairData> pairs;
+  std::string err;
+  bool sticky = false;
+};
+
+namespace nm {
+
+using Ctx = cc_ctx;
+
+static double* palloc(Ctx& c, int64_t n) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(-4, "device allocation failed (" + std::to_string(n * 8) + " bytes)");
+  }
+  c.owned.push_back(p);
+  return (double*)p;
+}
+
+static void kc(int rc, const char* what) {
+  if (rc != 0) throw Error(-3, std::string("kernel launch failed: ") + what);
+}
+
+static void sync(Ctx& c) { hip_check(hipStreamSynchronize(c.s), "stream synchronize"); }
+
+static double d2h(Ctx& c, const double* dptr) {
+  double x;
+  hip_check(hipMemcpyAsync(&x, dptr, sizeof(double), hipMemcpyDeviceToHost, c.s), "memcpy D2H");
+  sync(c);
+  return x;
+}
+
+static void copy_d(Ctx& c, double* dst, const double* src, int64_t n) {
+  if (n > 0)
+    hip_check(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c.s), "memcpy D2D");
+}
+
+struct ArenaScope {
+  Arena& a;
+  Arena::Mark m;
+  explicit ArenaScope(Arena& ar) : a(ar), m(ar.mark()) {}
+  ~ArenaScope() { a.rewind(m); }
+};
+
+static Tensor tview(double* p, std::vector<int64_t> shape) {
+  Tensor t;
+  t.p = p;
+  t.nd = (int)shape.size();
+  for (int k = 0; k < t.nd; ++k) t.d[k] = shape[k];
+  return t;
+}
+
+// Vector-space helpers on amplitude-shaped vectors (biorthonormal metric).
+static double dot_bio(Ctx& c, const double* x, const double* y) {
+  kc(dot(c.s, x, y, c.N, c.o, c.v, 1, c.eng->scratch_reduce(), c.eng->scalar_slot(0)), "dot");
+  return d2h(c, c.eng->scalar_slot(0));
+}
+static double dot_plain(Ctx& c, const double* x, const double* y, int64_t n) {
+  kc(dot(c.s, x, y, n, 1, 1, 0, c.eng->scratch_reduce(), c.eng->scalar_slot(0)), "dot");
+  return d2h(c, c.eng->scalar_slot(0));
+}
+static double amax(Ctx& c, const double* x, int64_t n) {
+  kc(absmax(c.s, x, n, c.eng->scratch_reduce(), c.eng->scalar_slot(1)), "absmax");
+  return d2h(c, c.eng->scalar_slot(1));
+}
+static void axpby_(Ctx& c, double* y, const double* x, double a, double b, int64_t n) {
+  kc(axpby(c.s, y, x, a, b, n), "axpby");
+}
+
+// ------------------------------------------------------------ residual graph
+struct ResNodes {
+  int t1, t2, f, g;
+  int om1, om2;
+  int first;  // first non-leaf node of the residual
+};
+
+// Omega(t; f, g) of closed-shell CCSD in the T1-transformed form:
+// ghat = (X (x) Y (x) X (x) Y) g with X = 1 - t~, Y = 1 + t~^T (t~[a,i] = t_ai),
+// Fhat = X (f + sum_kc t_kc (2 g_pqkc - g_pckq)) Y^T; singles and doubles
+// projections as in the oracle's residual.
+static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2,
+                               const Tensor& F, const Tensor& Gi) {
+  const int64_t o = c.o, v = c.v, n = c.n;
+  const Range O{0, o}, V{o, v}, A{0, n};
+  ResNodes r;
+  r.t1 = G.leaf(T1);
+  r.t2 = G.leaf(T2);
+  r.f = G.leaf(F);
+  r.g = G.leaf(Gi);
+  r.first = G.size();
+  const int t1 = r.t1, t2 = r.t2, f = r.f, g = r.g;
+  // one-index T1 transformations of g (creators: X, annihilators: Y)
+  const int g1 = G.node({n, n, n, n}, {lin(1, op(g, "pqrs"), "pqrs"),
+                                       mul(-1, op(t1, "ka"), op(g, "kqrs", {O, A, A, A}), "aqrs", {V, A, A, A})});
+  const int g2 = G.node({n, n, n, n}, {lin(1, op(g1, "pqrs"), "pqrs"),
+                                       mul(1, op(t1, "qc"), op(g1, "pcrs", {A, V, A, A}), "pqrs", {A, O, A, A})});
+  const int g3 = G.node({n, n, n, n}, {lin(1, op(g2, "pqrs"), "pqrs"),
+                                       mul(-1, op(t1, "ka"), op(g2, "pqks", {A, A, O, A}), "pqas", {A, A, V, A})});
+  const int gg = G.node({n, n, n, n}, {lin(1, op(g3, "pqrs"), "pqrs"),
+                                       mul(1, op(g3, "pqrc", {A, A, A, V}), op(t1, "sc"), "pqrs", {A, A, A, O})});
+  // transformed Fock matrix
+  const int fp = G.node({n, n}, {lin(1, op(f, "pq"), "pq"),
+                                 mul(2, op(g, "pqkc", {A, A, O, V}), op(t1, "kc"), "pq"),
+                                 mul(-1, op(g, "pckq", {A, V, O, A}), op(t1, "kc"), "pq")});
+  const int f1 = G.node({n, n}, {lin(1, op(fp, "pq"), "pq"),
+                                 mul(-1, op(t1, "ka"), op(fp, "kq", {O, A}), "aq", {V, A})});
+  const int Fh = G.node({n, n}, {lin(1, op(f1, "pq"), "pq"),
+                                 mul(1, op(f1, "pc", {A, V}), op(t1, "qc"), "pq", {A, O})});
+  const int u = G.node({o, o, v, v}, {lin(2, op(t2, "ijab"), "ijab"), lin(-1, op(t2, "ijba"), "ijab")});
+  // singles
+  r.om1 = G.node({o, v}, {mul(1, op(u, "kicd"), op(gg, "adkc", {V, V, O, V}), "ia"),
+                          mul(-1, op(u, "klac"), op(gg, "kilc", {O, O, O, V}), "ia"),
+                          mul(1, op(u, "ikac"), op(Fh, "kc", {O, V}), "ia"),
+                          lin(1, op(Fh, "ai", {V, O}), "ia")});
+  // doubles
+  const int W = G.node({o, o, o, o}, {lin(1, op(gg, "kilj", {O, O, O, O}), "kilj"),
+                                      mul(1, op(t2, "ijcd"), op(gg, "kcld", {O, V, O, V}), "kilj")});
+  const int Xc = G.node({o, o, v, v}, {lin(1, op(gg, "kiac", {O, O, V, V}), "kiac"),
+                                       mul(-0.5, op(t2, "liad"), op(gg, "kdlc", {O, V, O, V}), "kiac")});
+  const int Lvoov = G.node({v, o, o, v}, {lin(2, op(gg, "aikc", {V, O, O, V}), "aikc"),
+                                          lin(-1, op(gg, "acki", {V, V, O, O}), "aikc")});
+  const int Lovov = G.node({o, v, o, v}, {lin(2, op(gg, "ldkc", {O, V, O, V}), "ldkc"),
+                                          lin(-1, op(gg, "lckd", {O, V, O, V}), "ldkc")});
+  const int Xd = G.node({v, o, o, v}, {lin(1, op(Lvoov, "aikc"), "aikc"),
+                                       mul(0.5, op(u, "ilad"), op(Lovov, "ldkc"), "aikc")});
+  const int Ev = G.node({v, v}, {lin(1, op(Fh, "bc", {V, V}), "bc"),
+                                 mul(-1, op(u, "klbd"), op(gg, "ldkc", {O, V, O, V}), "bc")});
+  const int Eo = G.node({o, o}, {lin(1, op(Fh, "kj", {O, O}), "kj"),
+                                 mul(1, op(u, "ljcd"), op(gg, "kdlc", {O, V, O, V}), "kj")});
+  const int P = G.node({o, o, v, v}, {mul(-0.5, op(t2, "kjbc"), op(Xc, "kiac"), "ijab"),
+                                      mul(-1, op(t2, "kibc"), op(Xc, "kjac"), "ijab"),
+                                      mul(0.5, op(u, "jkbc"), op(Xd, "aikc"), "ijab"),
+                                      mul(1, op(t2, "ijac"), op(Ev, "bc"), "ijab"),
+                                      mul(-1, op(t2, "ikab"), op(Eo, "kj"), "ijab")});
+  r.om2 = G.node({o, o, v, v}, {lin(1, op(gg, "aibj", {V, O, V, O}), "ijab"),
+                                mul(1, op(t2, "ijcd"), op(gg, "acbd", {V, V, V, V}), "ijab"),
+                                mul(1, op(t2, "klab"), op(W, "kilj"), "ijab"),
+                                lin(1, op(P, "ijab"), "ijab"),
+                                lin(1, op(P, "jiba"), "ijab")});
+  return r;
+}
+
+// E_corr = 2 sum f_ia t_ai + sum (t_aibj + t_ai t_bj)(2 g_iajb - g_ibja).
+struct EnergyNodes { int t1, t2, e; };
+static EnergyNodes energy_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2) {
+  const int64_t o = c.o, v = c.v;
+  const Range O{0, o}, V{o, v};
+  EnergyNodes r;
+  r.t1 = G.leaf(T1);
+  r.t2 = G.leaf(T2);
+  const int f = G.leaf(c.f), g = G.leaf(c.g);
+  const int tau = G.node({o, o, v, v}, {lin(1, op(r.t2, "ijab"), "ijab"),
+                                        mul(1, op(r.t1, "ia"), op(r.t1, "jb"), "ijab")});
+  const int Lb = G.node({o, v, o, v}, {lin(2, op(g, "iajb", {O, V, O, V}), "iajb"),
+                                       lin(-1, op(g, "ibja", {O, V, O, V}), "iajb")});
+  r.e = G.node({}, {mul(2, op(f, "ia", {O, V}), op(r.t1, "ia"), ""),
+                    mul(1, op(tau, "ijab"), op(Lb, "iajb"), "")});
+  return r;
+}
+
+static Tensor T1of(Ctx& c, double* x) { return tview(x, {c.o, c.v}); }
+static Tensor T2of(Ctx& c, double* x) {
+  return tview(x + (int64_t)c.o * c.v, {c.o, c.o, c.v, c.v});
+}
+
+// Residual at amplitudes x -> out (amplitude-shaped).
+static void residual(Ctx& c, double* x, double* out) {
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.g);
+  const int64_t nov = (int64_t)c.o * c.v;
+  copy_d(c, out, G.val(r.om1).p, nov);
+  copy_d(c, out + nov, G.val(r.om2).p, c.N - nov);
+}
+
+static double energy(Ctx& c, double* x) {
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  EnergyNodes e = energy_graph(G, c, T1of(c, x), T2of(c, x));
+  return d2h(c, G.val(e.e).p);
+}
+
+// dE/dt . R (full-tensor directional derivative).
+static double energy_jvp(Ctx& c, double* x, double* Rv) {
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  EnergyNodes e = energy_graph(G, c, T1of(c, x), T2of(c, x));
+  const int r1 = G.leaf(T1of(c, Rv)), r2 = G.leaf(T2of(c, Rv));
+  auto tan = G.jvp({{e.t1, r1}, {e.t2, r2}});
+  if (!tan.count(e.e)) return 0.0;
+  return d2h(c, G.val(tan[e.e]).p);
+}
+
+// --------------------------------------------------- linearisation (tape)
+// The residual graph recorded at the current amplitudes; right and left
+// Jacobian transforms reuse it for every trial vector.
+struct Tape {
+  Ctx& c;
+  Arena::Mark base;
+  Graph G;
+  ResNodes r;
+  explicit Tape(Ctx& cc) : c(cc), base(cc.eng->arena().mark()), G(*cc.eng) {
+    r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g);
+  }
+  ~Tape() { c.eng->arena().rewind(base); }
+
+  // y = A x
+  void right(const double* x, double* y) {
+    const int n0 = G.size();
+    Arena::Mark mk = c.eng->arena().mark();
+    const int r1 = G.leaf(T1of(c, const_cast<double*>(x))), r2 = G.leaf(T2of(c, const_cast<double*>(x)));
+    auto tan = G.jvp({{r.t1, r1}, {r.t2, r2}}, r.first);
+    const int64_t nov = (int64_t)c.o * c.v;
+    copy_d(c, y, G.val(tan.at(r.om1)).p, nov);
+    copy_d(c, y + nov, G.val(tan.at(r.om2)).p, c.N - nov);
+    G.truncate(n0);
+    c.eng->arena().rewind(mk);
+  }
+
+  // y = x^T A (packed-gradient convention, amplitude-shaped)
+  void left(const double* x, double* y) {
+    Arena::Mark mk = c.eng->arena().mark();
+    double* seed = c.eng->arena().alloc(c.N);
+    kc(apply_metric(c.s, seed, x, c.o, c.v, 0), "metric");
+    const int64_t nov = (int64_t)c.o * c.v;
+    auto adj = G.vjp({{r.om1, seed}, {r.om2, seed + nov}}, {r.t1, r.t2});
+    double* tmp = c.eng->arena().alloc(c.N);
+    copy_d(c, tmp, adj[r.t1].p, nov);
+    copy_d(c, tmp + nov, adj[r.t2].p, c.N - nov);
+    kc(apply_metric(c.s, y, tmp, c.o, c.v, 1), "metric");
+    c.eng->arena().rewind(mk);
+  }
+};
+
+// ------------------------------------------------------------ ground state
+static int ground(Ctx& c, double* e_out, int* it_out) {
+  const int64_t N = c.N;
+  if (!c.have_guess) kc(fill(c.s, c.t, 0.0, N), "fill");
+  ArenaScope sc(c.eng->arena());
+  const int m = std::max(1, c.opts.diis_dim);
+  double* r = c.eng->arena().alloc(N);
+  double* dt = c.eng->arena().alloc(N);
+  double* hv = c.eng->arena().alloc((int64_t)m * N);
+  double* he = c.eng->arena().alloc((int64_t)m * N);
+  std::vector<std::vector<double>> B;   // error overlaps (host)
+  int nh = 0, head = 0;
+  std::vector<int> slot;                // history order -> slot
+  int it = 0;
+  double err = 0.0;
+  int status = CC_NOT_CONVERGED;
+  for (it = 1; it <= c.opts.maxit; ++it) {
+    residual(c, c.t, r);
+    err = amax(c, r, N);
+    if (!std::isfinite(err)) throw Error(-5, "non-finite CCSD residual");
+    if (verbose()) std::fprintf(stderr, "[ground] it %d max|Omega| %.3e\n", it, err);
+    if (err < c.opts.tol_ground) {
+      status = CC_OK;
+      break;
+    }
+    kc(apply_denominator(c.s, dt, r, c.eps.p, c.o, c.v, 0.0, 0), "denominator");  // -r/D
+    axpby_(c, c.t, dt, 1.0, 1.0, N);
+    // DIIS on (t, dt)
+    int sidx;
+    if (nh < m) {
+      sidx = nh++;
+      slot.push_back(sidx);
+    } else {
+      sidx = slot[head];
+      slot.erase(slot.begin() + head);
+      slot.push_back(sidx);
+    }
+    copy_d(c, hv + (int64_t)sidx * N, c.t, N);
+    copy_d(c, he + (int64_t)sidx * N, dt, N);
+    B.resize(m, std::vector<double>(m, 0.0));
+    for (int k = 0; k < nh; ++k) {
+      const int sk = slot[k];
+      const double b = dot_plain(c, he + (int64_t)sidx * N, he + (int64_t)sk * N, N);
+      B[sidx][sk] = B[sk][sidx] = b;
+    }
+    if (nh >= 2) {
+      const int q = nh + 1;
+      std::vector<double> Am(q * q, 0.0), rhs(q, 0.0);
+      double scale = 0.0;
+      for (int a = 0; a < nh; ++a) scale = std::max(scale, B[slot[a]][slot[a]]);
+      for (int a = 0; a < nh; ++a) {
+        for (int b = 0; b < nh; ++b) Am[a * q + b] = B[slot[a]][slot[b]] / scale;
+        Am[a * q + nh] = Am[nh * q + a] = -1.0;
+      }
+      rhs[nh] = -1.0;
+      if (lu_solve(Am, rhs, q, 1)) {
+        kc(fill(c.s, c.t, 0.0, N), "fill");
+        for (int a = 0; a < nh; ++a) axpby_(c, c.t, hv + (int64_t)slot[a] * N, rhs[a], 1.0, N);
+      }
+    }
+  }
+  if (it > c.opts.maxit) it = c.opts.maxit;
+  c.ecorr = energy(c, c.t);
+  if (e_out) *e_out = c.ecorr;
+  if (it_out) *it_out = it;
+  return status;
+}
+
+// ------------------------------------------------------------------ Davidson
+struct Ritz {
+  std::vector<double> w;
+  std::vector<double*> X;  // arena buffers (caller copies)
+  int iters = 0;
+  bool converged = false;
+  bool complex_root = false;
+};
+
+// Lowest-nroots eigenpairs of a non-symmetric operator on amplitude-shaped
+// vectors (biorthonormal metric), preconditioned by orbital-energy differences.
+static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*)>& T,
+                     std::vector<double*>& out) {
+  const int64_t N = c.N, nov = (int64_t)c.o * c.v;
+  const int nb = nroots + std::max(0, c.opts.davidson_block);
+  const int maxm = std::max(c.opts.davidson_max, 2 * nb + 2);
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  double* V = ar.alloc((int64_t)maxm * N);
+  double* W = ar.alloc((int64_t)maxm * N);
+  double* X = ar.alloc((int64_t)nb * N);
+  double* AX = ar.alloc((int64_t)nb * N);
+  double* Rs = ar.alloc(N);
+  double* ydev = ar.alloc((int64_t)nb * maxm);
+  std::vector<double> G((size_t)maxm * maxm, 0.0);
+  int m = 0;
+
+  // add x (and optionally its image ax) to the subspace after biorthonormal
+  // Gram-Schmidt; returns false if x is (numerically) in the span.
+  auto add = [&](double* x, double* ax) -> bool {
+    if (!ax) kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
+    double n0 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+    if (!(n0 > 0)) return false;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < m; ++k) {
+        const double h = dot_bio(c, V + (int64_t)k * N, x);
+        axpby_(c, x, V + (int64_t)k * N, -h, 1.0, N);
+        if (ax) axpby_(c, ax, W + (int64_t)k * N, -h, 1.0, N);
+      }
+    const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+    if (n1 < 1e-4 * n0 || n1 < 1e-14) return false;
+    axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
+    if (ax)
+      axpby_(c, W + (int64_t)m * N, ax, 1.0 / n1, 0.0, N);
+    else
+      T(V + (int64_t)m * N, W + (int64_t)m * N);
+    ++m;
+    for (int k = 0; k < m; ++k) {
+      G[(size_t)k * maxm + (m - 1)] = dot_bio(c, V + (int64_t)k * N, W + (int64_t)(m - 1) * N);
+      G[(size_t)(m - 1) * maxm + k] = dot_bio(c, V + (int64_t)(m - 1) * N, W + (int64_t)k * N);
+    }
+    return true;
+  };
+
+  // initial guess: singles unit vectors at the smallest e_a - e_i
+  {
+    std::vector<std::pair<double, int64_t>> d;
+    for (int i = 0; i < c.o; ++i)
+      for (int a = 0; a < c.v; ++a) d.push_back({c.eps_h[c.o + a] - c.eps_h[i], (int64_t)i * c.v + a});
+    std::sort(d.begin(), d.end());
+    const double one = 1.0;
+    for (int k = 0; k < nb && k < (int)d.size(); ++k) {
+      kc(fill(c.s, Rs, 0.0, N), "fill");
+      hip_check(hipMemcpyAsync(Rs + d[k].second, &one, sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+      sync(c);
+      add(Rs, nullptr);
+    }
+  }
+  Ritz res;
+  for (int it = 1; it <= c.opts.maxit; ++it) {
+    res.iters = it;
+    std::vector<double> Gm((size_t)m * m);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) Gm[(size_t)a * m + b] = G[(size_t)a * maxm + b];
+    std::vector<std::complex<double>> w, Vc;
+    if (!eig_nonsym(Gm, m, w, Vc)) throw Error(-5, "subspace eigensolver failed");
+    std::vector<int> ord(m);
+    for (int k = 0; k < m; ++k) ord[k] = k;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
+    const int nk = std::min(nb, m);
+    std::vector<double> Y((size_t)nk * m);
+    res.w.assign(nk, 0.0);
+    res.complex_root = false;
+    for (int k = 0; k < nk; ++k) {
+      const int kk = ord[k];
+      res.w[k] = w[kk].real();
+      if (k < nroots && std::fabs(w[kk].imag()) > 1e-8 * std::max(1.0, std::fabs(w[kk].real())))
+        res.complex_root = true;
+      int imax = 0;
+      for (int i = 1; i < m; ++i)
+        if (std::abs(Vc[(size_t)kk * m + i]) > std::abs(Vc[(size_t)kk * m + imax])) imax = i;
+      const std::complex<double> ph = std::conj(Vc[(size_t)kk * m + imax]) / std::abs(Vc[(size_t)kk * m + imax]);
+      for (int i = 0; i < m; ++i) Y[(size_t)k * m + i] = (Vc[(size_t)kk * m + i] * ph).real();
+    }
+    // Ritz vectors and images: X = Y V, AX = Y W
+    hip_check(hipMemcpyAsync(ydev, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+    kc(gemm_f64(c.s, false, false, nk, (int)N, m, 1, 1.0, ydev, m, 0, V, N, 0, 0.0, X, N, 0), "ritz");
+    kc(gemm_f64(c.s, false, false, nk, (int)N, m, 1, 1.0, ydev, m, 0, W, N, 0, 0.0, AX, N, 0), "ritz");
+    std::vector<double> rn(nk);
+    std::vector<double*> newv;
+    double worst = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      double* xk = X + (int64_t)k * N;
+      double* axk = AX + (int64_t)k * N;
+      copy_d(c, Rs, axk, N);
+      axpby_(c, Rs, xk, -res.w[k], 1.0, N);
+      const double xn = std::sqrt(dot_bio(c, xk, xk));
+      rn[k] = std::sqrt(std::max(0.0, dot_bio(c, Rs, Rs))) / xn;
+      if (k < nroots) worst = std::max(worst, rn[k]);
+    }
+    if (!std::isfinite(worst)) throw Error(-5, "non-finite Davidson residual");
+    if (verbose()) {
+      std::fprintf(stderr, "[davidson] it %d m %d", it, m);
+      for (int k = 0; k < nk; ++k) std::fprintf(stderr, " w%d=%.12f r=%.2e", k, res.w[k], rn[k]);
+      std::fprintf(stderr, "\n");
+    }
+    if (worst < c.opts.tol_eom) {
+      res.converged = true;
+      break;
+    }
+    // restart when the subspace is full
+    if (m + nk > maxm) {
+      m = 0;
+      std::fill(G.begin(), G.end(), 0.0);
+      double* tmpx = ar.alloc(N);
+      double* tmpa = ar.alloc(N);
+      for (int k = 0; k < nk; ++k) {
+        copy_d(c, tmpx, X + (int64_t)k * N, N);
+        copy_d(c, tmpa, AX + (int64_t)k * N, N);
+        add(tmpx, tmpa);
+      }
+      continue;
+    }
+    for (int k = 0; k < nk; ++k) {
+      if (rn[k] < c.opts.tol_eom) continue;
+      copy_d(c, Rs, AX + (int64_t)k * N, N);
+      axpby_(c, Rs, X + (int64_t)k * N, -res.w[k], 1.0, N);
+      kc(apply_denominator(c.s, Rs, Rs, c.eps.p, c.o, c.v, res.w[k], 1), "precondition");
+      if (m < maxm) add(Rs, nullptr);
+    }
+  }
+  // normalise and hand out the nroots lowest Ritz vectors
+  for (int k = 0; k < nroots; ++k) {
+    const double xn = std::sqrt(dot_bio(c, X + (int64_t)k * N, X + (int64_t)k * N));
+    axpby_(c, out[k], X + (int64_t)k * N, 1.0 / xn, 0.0, N);
+  }
+  res.w.resize(nroots);
+  (void)nov;
+  return res;
+}
+
+// Signed value of the largest-magnitude unique parameter (lowest packed index
+// on ties) of an amplitude-shaped vector.
+__global__ void signed_max_partial(const double* x, int o, int v, int64_t n, double* pv,
+                                   int64_t* pi) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int64_t nov = (int64_t)o * v;
+  double best = -1.0, bval = 0.0;
+  int64_t bidx = INT64_MAX;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t pidx;
+    if (e < nov) {
+      pidx = e;
+    } else {
+      int64_t r = e - nov;
+      const int b = (int)(r % v); r /= v;
+      const int a = (int)(r % v); r /= v;
+      const int j = (int)(r % o);
+      const int i = (int)(r / o);
+      const int64_t P = (int64_t)i * v + a, Q = (int64_t)j * v + b;
+      if (P > Q) continue;
+      pidx = nov + P * nov - P * (P - 1) / 2 + (Q - P);
+    }
+    const double a = fabs(x[e]);
+    if (a > best || (a == best && pidx < bidx)) { best = a; bval = x[e]; bidx = pidx; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bidx;
+  __shared__ double sval[256];
+  sval[threadIdx.x] = bval;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const int o2 = threadIdx.x + s;
+      if (sv[o2] > sv[threadIdx.x] || (sv[o2] == sv[threadIdx.x] && si[o2] < si[threadIdx.x])) {
+        sv[threadIdx.x] = sv[o2];
+        si[threadIdx.x] = si[o2];
+        sval[threadIdx.x] = sval[o2];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pv[2 * blockIdx.x] = sv[0];
+    pv[2 * blockIdx.x + 1] = sval[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+static double signed_max(Ctx& c, const double* x) {
+  const int nbk = 256;
+  ArenaScope sc(c.eng->arena());
+  double* pv = c.eng->arena().alloc(2 * nbk);
+  int64_t* pi = (int64_t*)c.eng->arena().alloc(nbk);
+  hipLaunchKernelGGL(signed_max_partial, dim3(nbk), dim3(256), 0, c.s, x, c.o, c.v, c.N, pv, pi);
+  hip_check(hipGetLastError(), "signed_max");
+  std::vector<double> hv(2 * nbk);
+  std::vector<int64_t> hi(nbk);
+  hip_check(hipMemcpyAsync(hv.data(), pv, 2 * nbk * sizeof(double), hipMemcpyDeviceToHost, c.s), "D2H");
+  hip_check(hipMemcpyAsync(hi.data(), pi, nbk * sizeof(int64_t), hipMemcpyDeviceToHost, c.s), "D2H");
+  sync(c);
+  double best = -1.0, val = 0.0;
+  int64_t bi = INT64_MAX;
+  for (int k = 0; k < nbk; ++k)
+    if (hv[2 * k] > best || (hv[2 * k] == best && hi[k] < bi)) {
+      best = hv[2 * k];
+      val = hv[2 * k + 1];
+      bi = hi[k];
+    }
+  return val;
+}
+
+static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
+  if (nroots != c.nroots) {
+    c.R.clear();
+    c.L.clear();
+    c.have_right = c.have_left = c.gauged = false;
+    c.pairs.clear();
+    for (int k = 0; k < nroots; ++k) {
+      c.R.push_back(palloc(c, c.N));
+      c.L.push_back(palloc(c, c.N));
+    }
+    c.nroots = nroots;
+  }
+  int status = CC_OK, itsum = 0;
+  Tape tp(c);
+  if (side & CC_RIGHT) {
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.right(x, y); }, c.R);
+    if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
+    c.omega_r = r.w;
+    c.have_right = true;
+    c.gauged = false;
+    itsum += r.iters;
+    if (!r.converged) status = CC_NOT_CONVERGED;
+  }
+  if (side & CC_LEFT) {
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.left(x, y); }, c.L);
+    if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
+    c.omega_l = r.w;
+    c.have_left = true;
+    c.gauged = false;
+    itsum += r.iters;
+    if (!r.converged) status = CC_NOT_CONVERGED;
+  }
+  if (iters) *iters = itsum;
+  if (c.have_right && c.have_left && !c.gauged) {
+    // gauge of R: unit norm (already), largest parameter positive
+    for (int k = 0; k < nroots; ++k) {
+      const double sv = signed_max(c, c.R[k]);
+      if (sv < 0) axpby_(c, c.R[k], c.R[k], -1.0, 0.0, c.N);
+    }
+    // biorthonormalise L: L <- S^{-1} L with S_kl = L_k . R_l
+    std::vector<double> S((size_t)nroots * nroots), Id((size_t)nroots * nroots, 0.0);
+    for (int k = 0; k < nroots; ++k)
+      for (int l = 0; l < nroots; ++l) S[(size_t)k * nroots + l] = dot_bio(c, c.L[k], c.R[l]);
+    for (int k = 0; k < nroots; ++k) Id[(size_t)k * nroots + k] = 1.0;
+    if (!lu_solve(S, Id, nroots, nroots)) throw Error(-5, "left and right states not biorthogonalisable");
+    {
+      ArenaScope sc(c.eng->arena());
+      double* tmp = c.eng->arena().alloc((int64_t)nroots * c.N);
+      for (int k = 0; k < nroots; ++k) {
+        kc(fill(c.s, tmp + (int64_t)k * c.N, 0.0, c.N), "fill");
+        for (int l = 0; l < nroots; ++l)
+          axpby_(c, tmp + (int64_t)k * c.N, c.L[l], Id[(size_t)k * nroots + l], 1.0, c.N);
+      }
+      for (int k = 0; k < nroots; ++k) copy_d(c, c.L[k], tmp + (int64_t)k * c.N, c.N);
+    }
+    c.R0.assign(nroots, 0.0);
+    for (int k = 0; k < nroots; ++k) c.R0[k] = energy_jvp(c, c.t, c.R[k]) / c.omega_r[k];
+    c.gauged = true;
+  }
+  if (omega) {
+    const std::vector<double>& w = (side & CC_RIGHT) ? c.omega_r : c.omega_l;
+    for (int k = 0; k < nroots; ++k) omega[k] = w[k];
+  }
+  return status;
+}
+
+// --------------------------------------------------------- linear solver
+// Solves T(x) = b (T: amplitude-shaped or small vectors of length n, metric
+// `packed`) by Galerkin projection on a growing preconditioned subspace.
+static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(const double*, double*)>& T,
+                    const std::function<void(double*, const double*)>& precond, const double* b,
+                    double* x, double tol, int maxit, int* iters) {
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  const int maxm = std::min(maxit, 120);
+  double* V = ar.alloc((int64_t)maxm * n);
+  double* W = ar.alloc((int64_t)maxm * n);
+  double* r = ar.alloc(n);
+  double* y = ar.alloc(maxm);
+  auto dotf = [&](const double* p, const double* q) {
+    return packed ? dot_bio(c, p, q) : dot_plain(c, p, q, n);
+  };
+  std::vector<double> G((size_t)maxm * maxm), bv(maxm);
+  int m = 0;
+  precond(r, b);
+  int status = CC_NOT_CONVERGED;
+  int it = 0;
+  const double bn = std::sqrt(std::max(dotf(b, b), 1e-300));
+  for (it = 1; it <= maxit && m < maxm; ++it) {
+    if (packed) kc(apply_metric(c.s, r, r, c.o, c.v, 2), "symmetrise");
+    const double n0 = std::sqrt(std::max(0.0, dotf(r, r)));
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < m; ++k) {
+        const double h = dotf(V + (int64_t)k * n, r);
+        axpby_(c, r, V + (int64_t)k * n, -h, 1.0, n);
+      }
+    const double n1 = std::sqrt(std::max(0.0, dotf(r, r)));
+    if (!(n1 > 1e-14 * std::max(n0, 1e-300))) break;
+    axpby_(c, V + (int64_t)m * n, r, 1.0 / n1, 0.0, n);
+    T(V + (int64_t)m * n, W + (int64_t)m * n);
+    ++m;
+    for (int k = 0; k < m; ++k) {
+      G[(size_t)k * maxm + m - 1] = dotf(V + (int64_t)k * n, W + (int64_t)(m - 1) * n);
+      G[(size_t)(m - 1) * maxm + k] = dotf(V + (int64_t)(m - 1) * n, W + (int64_t)k * n);
+    }
+    bv[m - 1] = dotf(V + (int64_t)(m - 1) * n, b);
+    std::vector<double> Gm((size_t)m * m), cvec(bv.begin(), bv.begin() + m);
+    for (int a = 0; a < m; ++a)
+      for (int bb = 0; bb < m; ++bb) Gm[(size_t)a * m + bb] = G[(size_t)a * maxm + bb];
+    if (!lu_solve(Gm, cvec, m, 1)) throw Error(-5, "singular projected linear system");
+    hip_check(hipMemcpyAsync(y, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+    kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, V, n, 0, 0.0, x, n, 0), "combine");
+    kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, W, n, 0, 0.0, r, n, 0), "combine");
+    axpby_(c, r, b, -1.0, 1.0, n);    // r = T x - b
+    const double rn = std::sqrt(std::max(0.0, dotf(r, r)));
+    if (!std::isfinite(rn)) throw Error(-5, "non-finite linear-solver residual");
+    if (verbose()) std::fprintf(stderr, "[linsolve] it %d m %d |r| %.3e\n", it, m, rn);
+    if (rn < tol * std::max(1.0, bn) ) {
+      status = CC_OK;
+      break;
+    }
+    precond(r, r);
+  }
+  if (iters) *iters = it;
+  return status;
+}
+
+// ------------------------------------------------------ orbital rotation
+// Integrals of exp(kappa) H exp(-kappa) to first order in kappa (exact for
+// derivatives at kappa = 0): h + K h + h K^T, g + sum of one-index K
+// insertions, and their Fock matrix; K_ai = kappa_ai, K_ia = -kappa_ai.
+struct RotNodes { int kap, fr, gr; };
+static RotNodes rotation_graph(Graph& G, Ctx& c, const Tensor& kappa) {
+  const int64_t o = c.o, v = c.v, n = c.n;
+  const Range O{0, o}, V{o, v}, A{0, n};
+  RotNodes r;
+  r.kap = G.leaf(kappa);
+  const int fl = G.leaf(c.f), gl = G.leaf(c.g);
+  const int h = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"), lin(-2, op(gl, "pqkk", {A, A, O, O}), "pq"),
+                                lin(1, op(gl, "pkkq", {A, O, O, A}), "pq")});
+  const int K = G.node({n, n}, {lin(1, op(r.kap, "ia"), "ai", {V, O}), lin(-1, op(r.kap, "ia"), "ia", {O, V})});
+  const int hr = G.node({n, n}, {lin(1, op(h, "pq"), "pq"), mul(1, op(K, "pt"), op(h, "tq"), "pq"),
+                                 mul(1, op(h, "pt"), op(K, "qt"), "pq")});
+  r.gr = G.node({n, n, n, n}, {lin(1, op(gl, "pqrs"), "pqrs"), mul(1, op(K, "pt"), op(gl, "tqrs"), "pqrs"),
+                               mul(1, op(K, "qt"), op(gl, "ptrs"), "pqrs"),
+                               mul(1, op(K, "rt"), op(gl, "pqts"), "pqrs"),
+                               mul(1, op(gl, "pqrt"), op(K, "st"), "pqrs")});
+  r.fr = G.node({n, n}, {lin(1, op(hr, "pq"), "pq"), lin(2, op(r.gr, "pqkk", {A, A, O, O}), "pq"),
+                         lin(-1, op(r.gr, "pkkq", {A, O, O, A}), "pq")});
+  return r;
+}
+
+// ------------------------------------------------------------- multipliers
+static PairData& pair_of(Ctx& c, int i, int j) {
+  PairData& p = c.pairs[{i, j}];
+  if (!p.zeta) {
+    p.zeta = palloc(c, c.N);
+    p.gamma = palloc(c, c.N);
+    p.eta_t = palloc(c, c.N);
+    p.kbar = palloc(c, (int64_t)c.o * c.v);
+    p.eta_k = palloc(c, (int64_t)c.o * c.v);
+    p.dtrans = palloc(c, (int64_t)c.n * c.n);
+    p.Fbar = palloc(c, (int64_t)c.n * c.n);
+    p.Deff = palloc(c, (int64_t)c.n * c.n);
+  }
+  return p;
+}
+
+static int64_t n4(Ctx& c) { return (int64_t)c.n * c.n * c.n * c.n; }
+
+static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
+  const int i = i1 - 1, j = j1 - 1;
+  const int64_t N = c.N, nov = (int64_t)c.o * c.v, nn = (int64_t)c.n * c.n;
+  PairData& P = pair_of(c, i1, j1);
+  const double wi = c.omega_r[i], wj = c.omega_r[j];
+  axpby_(c, P.gamma, c.L[i], 1.0 / (wj - wi), 0.0, N);
+  Arena& ar = c.eng->arena();
+  int status = CC_OK;
+  int it_z = 0, it_k = 0;
+  {
+    Tape tp(c);
+    // JVP along R_j, kept on the tape
+    const int r1 = tp.G.leaf(T1of(c, c.R[j])), r2 = tp.G.leaf(T2of(c, c.R[j]));
+    auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
+    const int ar1 = tan.at(tp.r.om1), ar2 = tan.at(tp.r.om2);
+    ArenaScope sc(ar);
+    double* wg = ar.alloc(N);     // metric-weighted gamma
+    kc(apply_metric(c.s, wg, P.gamma, c.o, c.v, 0), "metric");
+    double* tmp = ar.alloc(N);
+    // F-matrix term: d/dt [gamma . A(t) R_j]
+    {
+      ArenaScope s2(ar);
+      auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}}, {tp.r.t1, tp.r.t2});
+      copy_d(c, tmp, adj[tp.r.t1].p, nov);
+      copy_d(c, tmp + nov, adj[tp.r.t2].p, N - nov);
+      kc(apply_metric(c.s, P.eta_t, tmp, c.o, c.v, 1), "metric");
+    }
+    // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
+    {
+      ArenaScope s2(ar);
+      Graph Gs(*c.eng);
+      const int l2 = Gs.leaf(T2of(c, c.L[i])), rr1 = Gs.leaf(T1of(c, c.R[j]));
+      const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
+                                          mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
+      axpby_(c, P.eta_t, c.L[i], c.R0[j], 1.0, N);
+      axpby_(c, P.eta_t, Gs.val(sn).p, 1.0, 1.0, nov);
+      // transition density D_pq = <L_i| E_pq |R_j>: seeds L_i on A R_j,
+      // R0_j L_i + s on Omega (singles), wrt f
+      double* wl = ar.alloc(N);
+      kc(apply_metric(c.s, wl, c.L[i], c.o, c.v, 0), "metric");
+      double* sp = ar.alloc(N);
+      axpby_(c, sp, wl, c.R0[j], 0.0, N);
+      axpby_(c, sp, Gs.val(sn).p, 1.0, 1.0, nov);
+      auto adj = tp.G.vjp({{ar1, wl}, {ar2, wl + nov}, {tp.r.om1, sp}, {tp.r.om2, sp + nov}}, {tp.r.f});
+      copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
+    }
+    // zeta: A^T zeta = -eta_t
+    {
+      double* b = ar.alloc(N);
+      axpby_(c, b, P.eta_t, -1.0, 0.0, N);
+      auto T = [&](const double* x, double* y) { tp.left(x, y); };
+      auto pre = [&](double* y, const double* x) {
+        kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
+      };
+      const int st = linsolve(c, N, true, T, pre, b, P.zeta, c.opts.tol_mult, c.opts.maxit, &it_z);
+      if (st != CC_OK) status = st;
+    }
+    // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j)
+    {
+      double* wz = ar.alloc(N);
+      kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
+      ArenaScope s2(ar);
+      auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}, {tp.r.om1, wz}, {tp.r.om2, wz + nov}},
+                          {tp.r.f, tp.r.g});
+      copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
+      if (!P.Gbar) P.Gbar = palloc(c, n4(c));
+      copy_d(c, P.Gbar, adj[tp.r.g].p, n4(c));
+    }
+  }
+  if (c.opts.relaxed) {
+    ArenaScope sc(ar);
+    Graph G(*c.eng);
+    double* k0 = ar.alloc(nov);
+    kc(fill(c.s, k0, 0.0, nov), "fill");
+    RotNodes rn = rotation_graph(G, c, tview(k0, {c.o, c.v}));
+    // eta_kappa = -(D_ai - D_ia) + d/dkappa Phi
+    {
+      ArenaScope s2(ar);
+      auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.gr, P.Gbar}}, {rn.kap});
+      copy_d(c, P.eta_k, adj[rn.kap].p, nov);
+      Graph Gd(*c.eng);
+      const int d = Gd.leaf(tview(P.dtrans, {c.n, c.n}));
+      const Range O{0, c.o}, V{c.o, c.v};
+      const int e1 = Gd.node({c.o, c.v}, {lin(-1, op(d, "ai", {V, O}), "ia"), lin(1, op(d, "ia", {O, V}), "ia")});
+      axpby_(c, P.eta_k, Gd.val(e1).p, 1.0, 1.0, nov);
+    }
+    // (A^HF)^T kappa_bar = -eta_kappa, A^HF_(ai),(bj) = dF_ai/dkappa_bj
+    double* b = ar.alloc(nov);
+    axpby_(c, b, P.eta_k, -1.0, 0.0, nov);
+    double* seed = ar.alloc(nn);
+    auto T = [&](const double* x, double* y) {
+      ArenaScope s2(ar);
+      kc(fill(c.s, seed, 0.0, nn), "fill");
+      ViewSpec vs;  // seed[o+a][i] = x[i][a]
+      vs.nd = 2;
+      vs.dims[0] = c.o; vs.dims[1] = c.v;
+      vs.ostr[0] = 1; vs.ostr[1] = c.n;
+      vs.obase = (int64_t)c.o * c.n;
+      vs.istr[0] = c.v; vs.istr[1] = 1;
+      kc(view_gather(c.s, seed, x, vs, 1.0, 0.0), "embed");
+      auto adj = G.vjp({{rn.fr, seed}}, {rn.kap});
+      copy_d(c, y, adj[rn.kap].p, nov);
+    };
+    // preconditioner: orbital-energy differences on the singles block
+    auto pre1 = [&](double* y, const double* x) {
+      ArenaScope s3(ar);
+      double* big = ar.alloc(N);
+      kc(fill(c.s, big, 0.0, N), "fill");
+      copy_d(c, big, x, nov);
+      kc(apply_denominator(c.s, big, big, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
+      copy_d(c, y, big, nov);
+    };
+    const int st = linsolve(c, nov, false, T, pre1, b, P.kbar, c.opts.tol_mult, c.opts.maxit, &it_k);
+    if (st != CC_OK) status = st;
+  } else {
+    kc(fill(c.s, P.kbar, 0.0, nov), "fill");
+    kc(fill(c.s, P.eta_k, 0.0, nov), "fill");
+  }
+  P.have_mult = true;
+  P.have_dens = false;
+  if (iters) {
+    iters[0] = it_z;
+    iters[1] = it_k;
+  }
+  sync(c);
+  return status;
+}
+
+// D_eff = dPhi/df + kappa-bar embedded in the vo block; the two-electron
+// density Gamma = dPhi/dg + 2 D_eff(pq) delta_rs(occ) - D_eff(ps) delta_qr(occ)
+// so that F^q = sum D_eff dh^q + sum Gamma dg^q.
+static void densities_impl(Ctx& c, int i1, int j1) {
+  PairData& P = c.pairs.at({i1, j1});
+  const int64_t nn = (int64_t)c.n * c.n;
+  copy_d(c, P.Deff, P.Fbar, nn);
+  {
+    ViewSpec vs;  // Deff[o+a][i] += kbar[i][a]
+    vs.nd = 2;
+    vs.dims[0] = c.o; vs.dims[1] = c.v;
+    vs.ostr[0] = 1; vs.ostr[1] = c.n;
+    vs.obase = (int64_t)c.o * c.n;
+    vs.istr[0] = c.v; vs.istr[1] = 1;
+    kc(view_gather(c.s, P.Deff, P.kbar, vs, 1.0, 1.0), "kappa embed");
+  }
+  if (!P.Gam) P.Gam = palloc(c, n4(c));
+  copy_d(c, P.Gam, P.Gbar, n4(c));
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  const Range O{0, c.o}, A{0, c.n};
+  const int d = G.leaf(tview(P.Deff, {c.n, c.n}));
+  const int gm = G.leaf(tview(P.Gam, {c.n, c.n, c.n, c.n}));
+  (void)gm;
+  // broadcast adds into diagonal views of Gamma
+  DView src = full_view(G.val(d), "pq");
+  {
+    Op o1 = op(gm, "pqkk", {A, A, O, O});
+    DView dst;
+    {
+      // build the merged view by hand (p, q, k with k stride n + 1)
+      const int64_t n = c.n;
+      dst.p = P.Gam;
+      dst.nd = 3;
+      dst.lab[0] = 'p'; dst.lab[1] = 'q'; dst.lab[2] = 'k';
+      dst.dims[0] = n; dst.dims[1] = n; dst.dims[2] = c.o;
+      dst.str[0] = n * n * n; dst.str[1] = n * n; dst.str[2] = n + 1;
+    }
+    c.eng->linear(2.0, src, dst);
+    (void)o1;
+  }
+  {
+    const int64_t n = c.n;
+    DView dst;
+    dst.p = P.Gam;
+    dst.nd = 3;
+    dst.lab[0] = 'p'; dst.lab[1] = 'q'; dst.lab[2] = 'k';
+    dst.dims[0] = n; dst.dims[1] = n; dst.dims[2] = c.o;
+    dst.str[0] = n * n * n; dst.str[1] = 1; dst.str[2] = n * n + n;   // Gam[p][k][k][q]
+    c.eng->linear(-1.0, src, dst);
+  }
+  P.have_dens = true;
+}
+
+static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const double* dB,
+                       double* F) {
+  PairData& P = c.pairs.at({i1, j1});
+  const int64_t n = c.n, nn = n * n, naux = c.naux;
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  double* Z = ar.alloc(naux * nn);
+  for (int q = 0; q < nq; ++q) {
+    const double* dhq = dh + (int64_t)q * nn;
+    const double* dBq = dB + (int64_t)q * naux * nn;
+    const double f1 = dot_plain(c, P.Deff, dhq, nn);
+    // Z[P][pq] = sum_rs dB[P][rs] Gamma[pq][rs];  F2 = sum_P,pq Z[P][pq] dB[P][pq]
+    kc(gemm_f64(c.s, false, true, (int)naux, (int)nn, (int)nn, 1, 1.0, dBq, nn, 0, P.Gam, nn, 0, 0.0, Z,
+                nn, 0),
+       "nacme gemm");
+    const double f2 = dot_plain(c, Z, dBq, naux * nn);
+    F[q] = f1 + f2;
+  }
+}
+
+}  // namespace nm
+
+// ======================================================================= ABI
+using nm::Ctx;
+using nm::Error;
+
+static int fail(Ctx* c, const Error& e) {
+  if (c) {
+    c->err = e.what();
+    if (e.code == CC_ERR_HIP) c->sticky = true;
+  }
+  return e.code;
+}
+
+#define ABI_GUARD(c)                                                   \
+  if (!(c)) return CC_ERR_ARG;                                         \
+  if ((c)->sticky) {                                                   \
+    (c)->err = "context unusable after an earlier device failure";     \
+    return CC_ERR_HIP;                                                 \
+  }
+
+extern "C" {
+
+void cc_default_opts(cc_opts* o) {
+  if (!o) return;
+  o->precision = CC_FP64;
+  o->relaxed = 1;
+  o->tol_ground = 1e-10;
+  o->tol_eom = 1e-9;
+  o->tol_mult = 1e-9;
+  o->maxit = 200;
+  o->diis_dim = 8;
+  o->davidson_block = 2;
+  o->davidson_max = 48;
+}
+
+const char* nm_version(void) { return "nacme-mi355x 0.1 (gfx950, fp64)"; }
+
+int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const double* B,
+              const cc_opts* opts, void* stream) {
+  if (!out || o < 1 || v < 1 || naux < 1 || !eps || !B) return CC_ERR_ARG;
+  *out = nullptr;
+  Ctx* c = new Ctx();
+  try {
+    c->o = o;
+    c->v = v;
+    c->n = o + v;
+    c->naux = naux;
+    const int64_t nov = (int64_t)o * v;
+    c->N = nov + nov * nov;
+    if (opts) c->opts = *opts; else cc_default_opts(&c->opts);
+    if (c->opts.precision != CC_FP64) throw Error(CC_ERR_ARG, "only CC_FP64 is available");
+    c->s = (hipStream_t)stream;
+    c->eng.reset(new nm::Engine(c->s));
+    const int64_t n = c->n, nn = n * n;
+    c->eps = nm::tview(nm::palloc(*c, n), {n});
+    nm::copy_d(*c, c->eps.p, eps, n);
+    c->eps_h.resize(n);
+    nm::hip_check(hipMemcpyAsync(c->eps_h.data(), eps, n * sizeof(double), hipMemcpyDeviceToHost, c->s), "D2H");
+    nm::sync(*c);
+    for (int k = 0; k < n; ++k)
+      if (!std::isfinite(c->eps_h[k])) throw Error(CC_ERR_ARG, "non-finite orbital energy");
+    for (int i = 0; i < o; ++i)
+      for (int a = 0; a < v; ++a)
+        if (!(c->eps_h[o + a] > c->eps_h[i])) throw Error(CC_ERR_ARG, "virtual orbital energy below an occupied one");
+    // f = diag(eps)
+    c->f = nm::tview(nm::palloc(*c, nn), {n, n});
+    nm::kc(nm::fill(c->s, c->f.p, 0.0, nn), "fill");
+    {
+      nm::ViewSpec vs;
+      vs.nd = 1;
+      vs.dims[0] = n;
+      vs.ostr[0] = n + 1;
+      vs.istr[0] = 1;
+      nm::kc(nm::view_gather(c->s, c->f.p, c->eps.p, vs, 1.0, 0.0), "diag");
+    }
+    // g_pqrs = sum_P B[P][pq] B[P][rs]
+    c->g = nm::tview(nm::palloc(*c, nn * nn), {n, n, n, n});
+    nm::kc(nm::gemm_f64(c->s, true, false, (int)nn, (int)nn, naux, 1, 1.0, B, nn, 0, B, nn, 0, 0.0, c->g.p,
+                        nn, 0),
+           "eri build");
+    c->t = nm::palloc(*c, c->N);
+    nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
+    nm::sync(*c);
+    *out = c;
+    return CC_OK;
+  } catch (const Error& e) {
+    int code = e.code;
+    delete c;
+    return code;
+  } catch (const std::exception& e) {
+    delete c;
+    return CC_ERR_HIP;
+  }
+}
+
+void cc_destroy(cc_ctx* c) {
+  if (!c) return;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  c->eng.reset();
+  for (void* p : c->owned) (void)hipFree(p);
+  delete c;
+}
+
+const char* cc_last_error(const cc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int cc_ground(cc_ctx* c, double* e_corr, int* iters) {
+  ABI_GUARD(c);
+  try {
+    int st = nm::ground(*c, e_corr, iters);
+    c->stage = 1;
+    c->have_guess = false;
+    c->have_right = c->have_left = c->gauged = false;
+    c->pairs.clear();
+    if (st == CC_NOT_CONVERGED) c->err = "CCSD amplitudes not converged";
+    return st;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int eom_solve(cc_ctx* c, int side, int nroots, double* omega, int* iters) {
+  ABI_GUARD(c);
+  if (c->stage < 1) { c->err = "eom_solve before cc_ground"; return CC_ERR_STATE; }
+  if (side < 1 || side > 3 || nroots < 1 || nroots > (int)std::min<int64_t>(c->N, 64)) {
+    c->err = "bad side or nroots";
+    return CC_ERR_ARG;
+  }
+  try {
+    int st = nm::eom(*c, side, nroots, omega, iters);
+    if (st == CC_ERR_COMPLEX_ROOT) c->err = "complex EOM root among the requested states";
+    if (st == CC_NOT_CONVERGED) c->err = "EOM states not converged";
+    return st;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int multipliers(cc_ctx* c, int i, int j, int* iters) {
+  ABI_GUARD(c);
+  if (!c->gauged) { c->err = "multipliers before right and left EOM states"; return CC_ERR_STATE; }
+  if (i < 1 || j < 1 || i > c->nroots || j > c->nroots || i == j) {
+    c->err = "pair indices must satisfy 1 <= i != j <= nroots";
+    return CC_ERR_ARG;
+  }
+  try {
+    return nm::multipliers_impl(*c, i, j, iters);
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int densities(cc_ctx* c, int i, int j, double* D1) {
+  ABI_GUARD(c);
+  auto it = c->pairs.find({i, j});
+  if (it == c->pairs.end() || !it->second.have_mult) {
+    c->err = "densities before multipliers of this pair";
+    return CC_ERR_STATE;
+  }
+  try {
+    nm::densities_impl(*c, i, j);
+    if (D1) nm::copy_d(*c, D1, it->second.Deff, (int64_t)c->n * c->n);
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int nacme(cc_ctx* c, int i, int j, int nq, const double* dh, const double* dB, double* F) {
+  ABI_GUARD(c);
+  auto it = c->pairs.find({i, j});
+  if (it == c->pairs.end() || !it->second.have_dens) {
+    c->err = "nacme before densities of this pair";
+    return CC_ERR_STATE;
+  }
+  if (nq < 0 || (nq > 0 && (!dh || !dB || !F))) {
+    c->err = "bad directions";
+    return CC_ERR_ARG;
+  }
+  try {
+    nm::nacme_impl(*c, i, j, nq, dh, dB, F);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_apply_jacobian(cc_ctx* c, int side, const double* X, double* Y) {
+  ABI_GUARD(c);
+  if (c->stage < 1) { c->err = "cc_apply_jacobian before cc_ground"; return CC_ERR_STATE; }
+  if (!X || !Y || (side != CC_RIGHT && side != CC_LEFT)) return CC_ERR_ARG;
+  try {
+    nm::Tape tp(*c);
+    if (side == CC_RIGHT) tp.right(X, Y); else tp.left(X, Y);
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_residual(cc_ctx* c, const double* t, double* omega) {
+  ABI_GUARD(c);
+  if (!t || !omega) return CC_ERR_ARG;
+  try {
+    nm::ArenaScope sc(c->eng->arena());
+    double* tt = c->eng->arena().alloc(c->N);
+    nm::copy_d(*c, tt, t, c->N);
+    nm::residual(*c, tt, omega);
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_export(cc_ctx* c, int what, int idx, int jdx, double* dst) {
+  ABI_GUARD(c);
+  if (!dst) return CC_ERR_ARG;
+  try {
+    const int64_t nn = (int64_t)c->n * c->n, nov = (int64_t)c->o * c->v;
+    switch (what) {
+      case CC_T: nm::copy_d(*c, dst, c->t, c->N); break;
+      case CC_R:
+      case CC_L:
+      case CC_R0: {
+        if (idx < 1 || idx > c->nroots) return CC_ERR_ARG;
+        if (what == CC_R0) {
+          if (!c->gauged) return CC_ERR_STATE;
+          *dst = c->R0[idx - 1];
+          return CC_OK;
+        }
+        nm::copy_d(*c, dst, (what == CC_R ? c->R : c->L)[idx - 1], c->N);
+        break;
+      }
+      default: {
+        auto it = c->pairs.find({idx, jdx});
+        if (it == c->pairs.end() || !it->second.have_mult) return CC_ERR_STATE;
+        nm::PairData& P = it->second;
+        if (what == CC_ZETA) nm::copy_d(*c, dst, P.zeta, c->N);
+        else if (what == CC_KAPPA) nm::copy_d(*c, dst, P.kbar, nov);
+        else if (what == CC_ETA_T) nm::copy_d(*c, dst, P.eta_t, c->N);
+        else if (what == CC_ETA_K) nm::copy_d(*c, dst, P.eta_k, nov);
+        else if (what == CC_DTRANS) nm::copy_d(*c, dst, P.dtrans, nn);
+        else if (what == CC_D1) {
+          if (!P.have_dens) return CC_ERR_STATE;
+          nm::copy_d(*c, dst, P.Deff, nn);
+        } else return CC_ERR_ARG;
+      }
+    }
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_set_guess(cc_ctx* c, int what, int idx, const double* src) {
+  ABI_GUARD(c);
+  (void)idx;
+  if (!src || what != CC_T) return CC_ERR_ARG;
+  try {
+    nm::copy_d(*c, c->t, src, c->N);
+    c->have_guess = true;
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int nm_contract(const char* spec, double alpha, const double* A, const int64_t* dA, const double* B,
+                const int64_t* dB, double beta, double* C, const int64_t* dC, void* stream) {
+  if (!spec || !A || !B || !C || !dA || !dB || !dC) return CC_ERR_ARG;
+  try {
+    std::string s(spec);
+    const size_t c1 = s.find(','), ar = s.find("->");
+    if (c1 == std::string::npos || ar == std::string::npos || ar < c1) return CC_ERR_ARG;
+    const std::string la = s.substr(0, c1), lb = s.substr(c1 + 1, ar - c1 - 1), lc = s.substr(ar + 2);
+    if (la.size() > 6 || lb.size() > 6 || lc.size() > 6) return CC_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    static thread_local std::unique_ptr<nm::Engine> eng;
+    if (!eng || eng->stream() != st) eng.reset(new nm::Engine(st));
+    std::vector<int64_t> sa(dA, dA + la.size()), sb(dB, dB + lb.size()), sc(dC, dC + lc.size());
+    nm::ArenaScope scope(eng->arena());
+    nm::Graph G(*eng);
+    const int ia = G.leaf(nm::tview(const_cast<double*>(A), sa));
+    const int ib = G.leaf(nm::tview(const_cast<double*>(B), sb));
+    const int ic = G.leaf(nm::tview(C, sc));
+    nm::DView vc = nm::full_view(G.val(ic), lc);
+    if (beta != 1.0) {
+      int64_t n = 1;
+      for (auto x : sc) n *= x;
+      nm::kc(nm::axpby(st, C, C, 0.0, beta, n), "scale");
+    }
+    // views with repeated labels handled by the graph's view builder
+    nm::Term t = nm::mul(alpha, nm::op(ia, la), nm::op(ib, lb), lc);
+    const int out = G.node(sc, {t});
+    int64_t n = 1;
+    for (auto x : sc) n *= x;
+    nm::kc(nm::axpby(st, C, G.val(out).p, 1.0, 1.0, n), "accumulate");
+    (void)vc;
+    nm::hip_check(hipStreamSynchronize(st), "sync");
+    return CC_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+int nm_eig_host(int m, const double* G, double* wr, double* wi, double* V) {
+  if (m < 1 || !G || !wr || !wi || !V) return CC_ERR_ARG;
+  std::vector<double> g(G, G + (size_t)m * m);
+  std::vector<std::complex<double>> w, Vc;
+  if (!nm::eig_nonsym(g, m, w, Vc)) return CC_ERR_NUMERIC;
+  for (int k = 0; k < m; ++k) {
+    wr[k] = w[k].real();
+    wi[k] = w[k].imag();
+    int imax = 0;
+    for (int i = 1; i < m; ++i)
+      if (std::abs(Vc[(size_t)k * m + i]) > std::abs(Vc[(size_t)k * m + imax])) imax = i;
+    const std::complex<double> ph = std::conj(Vc[(size_t)k * m + imax]) / std::abs(Vc[(size_t)k * m + imax]);
+    for (int i = 0; i < m; ++i) V[(size_t)k * m + i] = (Vc[(size_t)k * m + i] * ph).real();
+  }
+  return CC_OK;
+}
+
+}  // extern "C"

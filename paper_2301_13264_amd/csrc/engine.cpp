@@ -1,0 +1,622 @@
+// Device tensor engine with a recording tape (see engine.h).
+#include "engine.h"
+
+#include <algorithm>
+#include <cstring>
+#include <set>
+
+namespace nm {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw Error(-3, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static void kcheck(int rc, const char* what) {
+  if (rc != 0) throw Error(-3, std::string("kernel launch failed: ") + what);
+}
+
+// ------------------------------------------------------------------- Arena
+Arena::~Arena() {
+  for (auto& c : chunks_) hipFree(c.base);
+}
+
+double* Arena::alloc(int64_t ndouble) {
+  size_t bytes = ((size_t)std::max<int64_t>(ndouble, 1) * sizeof(double) + 255) & ~size_t(255);
+  while (true) {
+    if (cur_ < chunks_.size()) {
+      Chunk& c = chunks_[cur_];
+      if (c.top + bytes <= c.cap) {
+        double* p = (double*)(c.base + c.top);
+        c.top += bytes;
+        live_ += bytes;
+        peak_ = std::max(peak_, live_);
+        return p;
+      }
+      if (cur_ + 1 < chunks_.size()) {
+        ++cur_;
+        chunks_[cur_].top = 0;
+        continue;
+      }
+    }
+    size_t cap = std::max(bytes, (size_t)1 << 30);
+    char* base = nullptr;
+    hipError_t e = hipMalloc(&base, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(-4, "device allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    chunks_.push_back({base, cap, 0});
+    cur_ = chunks_.size() - 1;
+  }
+}
+
+void Arena::rewind(Mark m) {
+  if (chunks_.empty()) return;
+  // recompute live bytes: chunks before m.chunk full up to their top
+  for (size_t k = m.chunk + 1; k < chunks_.size(); ++k) chunks_[k].top = 0;
+  cur_ = m.chunk;
+  chunks_[cur_].top = m.top;
+  size_t live = 0;
+  for (size_t k = 0; k <= cur_; ++k) live += chunks_[k].top;
+  live_ = live;
+}
+
+size_t Arena::reserved_bytes() const {
+  size_t s = 0;
+  for (auto& c : chunks_) s += c.cap;
+  return s;
+}
+
+// ------------------------------------------------------------------ helpers
+Tensor make_tensor(Arena& a, const std::vector<int64_t>& shape, bool zero, hipStream_t s) {
+  Tensor t;
+  t.nd = (int)shape.size();
+  if (t.nd > kMaxViewDims) throw Error(-1, "tensor rank too large");
+  for (int k = 0; k < t.nd; ++k) t.d[k] = shape[k];
+  t.p = a.alloc(t.size());
+  if (zero) kcheck(fill(s, t.p, 0.0, t.size()), "fill");
+  return t;
+}
+
+static void strides_of(const Tensor& t, int64_t* st) {
+  int64_t s = 1;
+  for (int k = t.nd - 1; k >= 0; --k) {
+    st[k] = s;
+    s *= t.d[k];
+  }
+}
+
+DView full_view(const Tensor& t, const std::string& lab) {
+  if ((int)lab.size() != t.nd) throw Error(-1, "label count mismatch");
+  DView v;
+  v.p = t.p;
+  v.nd = t.nd;
+  strides_of(t, v.str);
+  for (int k = 0; k < t.nd; ++k) {
+    v.dims[k] = t.d[k];
+    v.lab[k] = lab[k];
+  }
+  return v;
+}
+
+static int find_lab(const DView& v, char c) {
+  for (int k = 0; k < v.nd; ++k)
+    if (v.lab[k] == c) return k;
+  return -1;
+}
+
+static int64_t vsize(const DView& v) {
+  int64_t s = 1;
+  for (int k = 0; k < v.nd; ++k) s *= v.dims[k];
+  return s;
+}
+
+// Is `v` a contiguous row-major tensor when its dims are taken in label
+// order `order`?
+static bool contiguous_in(const DView& v, const std::string& order) {
+  int64_t s = 1;
+  for (int k = (int)order.size() - 1; k >= 0; --k) {
+    const int d = find_lab(v, order[k]);
+    if (d < 0) return false;
+    if (v.dims[d] != 1 && v.str[d] != s) return false;
+    s *= v.dims[d];
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ Engine
+Engine::Engine(hipStream_t s) : s_(s) {
+  red_ = arena_.alloc(reduce_scratch_doubles());
+  scal_ = arena_.alloc(64);
+}
+
+double* Engine::scratch_reduce() { return red_; }
+double* Engine::scalar_slot(int k) { return scal_ + k; }
+
+// dst (+)= alpha * sum over labels of src not in dst of src, dst labels in src.
+static bool same_compact(const DView& a, const DView& b) {
+  if (a.nd != b.nd) return false;
+  int64_t s = 1;
+  for (int k = a.nd - 1; k >= 0; --k) {
+    if (a.lab[k] != b.lab[k] || a.dims[k] != b.dims[k]) return false;
+    if (a.dims[k] != 1 && (a.str[k] != s || b.str[k] != s)) return false;
+    s *= a.dims[k];
+  }
+  return true;
+}
+
+static void gather_into(hipStream_t s, double alpha, const DView& src, const DView& dst,
+                        double beta) {
+  if (src.nd > 0 && same_compact(src, dst)) {
+    int64_t n = 1;
+    for (int k = 0; k < src.nd; ++k) n *= src.dims[k];
+    kcheck(axpby(s, dst.p, src.p, alpha, beta, n), "axpby");
+    return;
+  }
+  ViewSpec vs;
+  vs.nd = dst.nd;
+  vs.obase = 0;
+  vs.ibase = 0;
+  for (int k = 0; k < dst.nd; ++k) {
+    const int j = find_lab(src, dst.lab[k]);
+    if (j < 0) throw Error(-1, std::string("label '") + dst.lab[k] + "' missing in source");
+    if (src.dims[j] != dst.dims[k]) throw Error(-1, "dimension mismatch in view copy");
+    vs.dims[k] = dst.dims[k];
+    vs.ostr[k] = dst.str[k];
+    vs.istr[k] = src.str[j];
+  }
+  for (int j = 0; j < src.nd; ++j) {
+    if (find_lab(dst, src.lab[j]) >= 0) continue;
+    if (vs.nr == 2) throw Error(-1, "more than two summed labels in a view term");
+    vs.rdims[vs.nr] = src.dims[j];
+    vs.rstr[vs.nr] = src.str[j];
+    vs.nr++;
+  }
+  if (vs.nd == 0) {  // scalar output: treat as one element
+    vs.nd = 1;
+    vs.dims[0] = 1;
+    vs.ostr[0] = 0;
+    vs.istr[0] = 0;
+  }
+  // kernel indexes relative to pointers; pass them via base pointer args
+  kcheck(view_gather(s, dst.p, src.p, vs, alpha, beta), "view_gather");
+}
+
+// dst (labels ld) += alpha * broadcast(src (labels ls)), ls subset of ld.
+static void scatter_into(hipStream_t s, double alpha, const DView& src, const DView& dst) {
+  ViewSpec vs;
+  vs.nd = src.nd;
+  for (int k = 0; k < src.nd; ++k) {
+    const int j = find_lab(dst, src.lab[k]);
+    if (j < 0) throw Error(-1, "broadcast target lacks a source label");
+    vs.dims[k] = src.dims[k];
+    vs.ostr[k] = src.str[k];
+    vs.istr[k] = dst.str[j];
+  }
+  for (int j = 0; j < dst.nd; ++j) {
+    if (find_lab(src, dst.lab[j]) >= 0) continue;
+    if (vs.nr == 2) throw Error(-1, "more than two broadcast labels");
+    vs.rdims[vs.nr] = dst.dims[j];
+    vs.rstr[vs.nr] = dst.str[j];
+    vs.nr++;
+  }
+  if (vs.nd == 0) {
+    vs.nd = 1;
+    vs.dims[0] = 1;
+  }
+  kcheck(view_scatter(s, dst.p, src.p, vs, alpha), "view_scatter");
+}
+
+void Engine::linear(double alpha, const DView& A, const DView& C) {
+  // forward reduction if every C label is in A, else broadcast
+  bool all_in = true;
+  for (int k = 0; k < C.nd; ++k)
+    if (find_lab(A, C.lab[k]) < 0) all_in = false;
+  if (all_in)
+    gather_into(s_, alpha, A, C, 1.0);
+  else
+    scatter_into(s_, alpha, A, C);
+}
+
+static DView packed_view(Arena& ar, const DView& src, const std::string& order, hipStream_t s) {
+  DView d;
+  d.nd = (int)order.size();
+  int64_t st = 1;
+  for (int k = d.nd - 1; k >= 0; --k) {
+    const int j = find_lab(src, order[k]);
+    d.lab[k] = order[k];
+    d.dims[k] = src.dims[j];
+    d.str[k] = st;
+    st *= d.dims[k];
+  }
+  d.p = ar.alloc(st);
+  gather_into(s, 1.0, src, d, 0.0);
+  return d;
+}
+
+__global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, int M, int N,
+                                   int nsplit, double alpha, double beta) {
+  const int64_t tot = (int64_t)M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < nsplit; ++z) acc += part[(int64_t)z * tot + e];
+    const int64_t m = e / N, n = e - m * N;
+    double* c = C + m * ldc + n;
+    *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * (*c));
+  }
+}
+
+// Can `v` be read as a (batched) row-major matrix rows x cols with a leading
+// dimension?  cols must be compact with unit innermost stride; rows must be
+// nested uniformly with the last row stride = ld; batch labels nested above.
+static bool as_matrix(const DView& v, const std::string& batch, const std::string& rows,
+                      const std::string& cols, int64_t& ld, int64_t& bstride) {
+  int64_t s = 1;
+  for (int k = (int)cols.size() - 1; k >= 0; --k) {
+    const int d = find_lab(v, cols[k]);
+    if (d < 0) return false;
+    if (v.dims[d] != 1 && v.str[d] != s) return false;
+    s *= v.dims[d];
+  }
+  const int64_t ncols = s;
+  if (rows.empty()) {
+    ld = std::max<int64_t>(ncols, 1);
+    s = ld;
+  } else {
+    const int dl = find_lab(v, rows.back());
+    if (dl < 0) return false;
+    ld = v.dims[dl] == 1 ? std::max<int64_t>(ncols, 1) : v.str[dl];
+    if (ld < ncols) return false;
+    s = ld;
+    for (int k = (int)rows.size() - 1; k >= 0; --k) {
+      const int d = find_lab(v, rows[k]);
+      if (d < 0) return false;
+      if (v.dims[d] != 1 && v.str[d] != s) return false;
+      s *= v.dims[d];
+    }
+  }
+  // batch labels: nested uniformly (any outer stride)
+  if (batch.empty()) {
+    bstride = s;
+    return true;
+  }
+  const int db = find_lab(v, batch.back());
+  if (db < 0) return false;
+  bstride = v.str[db];
+  if (v.dims[db] != 1 && bstride < s) return false;
+  int64_t t = bstride;
+  for (int k = (int)batch.size() - 1; k >= 0; --k) {
+    const int d = find_lab(v, batch[k]);
+    if (d < 0) return false;
+    if (v.dims[d] != 1 && v.str[d] != t) return false;
+    t *= v.dims[d];
+  }
+  return true;
+}
+
+static int64_t prod_of(const DView& v, const std::string& s) {
+  int64_t p = 1;
+  for (char c : s) p *= v.dims[find_lab(v, c)];
+  return p;
+}
+
+static std::string labels_of(const DView& v) { return std::string(v.lab, v.lab + v.nd); }
+
+__global__ void scalar_axpy_kernel(double* y, const double* x, double a) { *y += a * (*x); }
+
+void Engine::contract(double alpha, const DView& A, const DView& B, const DView& C) {
+  std::string sb, sm, sn, sk;
+  for (int k = 0; k < A.nd; ++k) {
+    const char c = A.lab[k];
+    const bool inB = find_lab(B, c) >= 0, inC = find_lab(C, c) >= 0;
+    if (inB && inC) sb += c;
+    else if (inC) sm += c;
+    else if (inB) sk += c;
+    else throw Error(-1, std::string("label '") + c + "' only in first operand");
+  }
+  for (int k = 0; k < B.nd; ++k) {
+    const char c = B.lab[k];
+    const bool inA = find_lab(A, c) >= 0, inC = find_lab(C, c) >= 0;
+    if (!inA && inC) sn += c;
+    else if (!inA) throw Error(-1, std::string("label '") + c + "' only in second operand");
+  }
+  for (int k = 0; k < C.nd; ++k)
+    if (find_lab(A, C.lab[k]) < 0 && find_lab(B, C.lab[k]) < 0)
+      throw Error(-1, "output label in neither operand");
+  for (char c : sk)
+    if (A.dims[find_lab(A, c)] != B.dims[find_lab(B, c)]) throw Error(-1, "contracted dim mismatch");
+  for (char c : sb)
+    if (A.dims[find_lab(A, c)] != B.dims[find_lab(B, c)]) throw Error(-1, "batch dim mismatch");
+  const int64_t nb0 = prod_of(A, sb), M0 = prod_of(A, sm), N0 = prod_of(B, sn), K = prod_of(A, sk);
+  if (nb0 == 0 || M0 == 0 || N0 == 0) return;
+  flops_ += (uint64_t)(2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K);
+  if (K == 0) return;
+  Arena::Mark mk = arena_.mark();
+
+  // Full contraction to a scalar: deterministic dot product.
+  if (C.nd == 0 && sb.empty()) {
+    const std::string ord = sk;
+    const double* pa = contiguous_in(A, ord) ? A.p : packed_view(arena_, A, ord, s_).p;
+    const double* pb = contiguous_in(B, ord) ? B.p : packed_view(arena_, B, ord, s_).p;
+    double* tmp = scalar_slot(63);
+    kcheck(dot(s_, pa, pb, K, 1, 1, 0, red_, tmp), "dot");
+    hipLaunchKernelGGL(scalar_axpy_kernel, dim3(1), dim3(1), 0, s_, C.p, tmp, alpha);
+    kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "scalar axpy");
+    arena_.rewind(mk);
+    return;
+  }
+
+  // Promote outer labels shared by C and B (N labels) or by C and A (M labels)
+  // to a batch dimension with a broadcast (stride 0) other operand.
+  std::string pb_lab, pa_lab;   // promoted labels
+  if (sb.empty()) {
+    const std::string cl = labels_of(C), bl = labels_of(B), al = labels_of(A);
+    std::string cand;
+    for (size_t k = 0; k < cl.size() && k < bl.size(); ++k) {
+      if (cl[k] != bl[k] || sn.find(cl[k]) == std::string::npos) break;
+      cand += cl[k];
+    }
+    std::string candA;
+    for (size_t k = 0; k < cl.size() && k < al.size(); ++k) {
+      if (cl[k] != al[k] || sm.find(cl[k]) == std::string::npos) break;
+      candA += cl[k];
+    }
+    auto strip = [](std::string s, const std::string& rm) {
+      std::string r;
+      for (char c : s)
+        if (rm.find(c) == std::string::npos) r += c;
+      return r;
+    };
+    int64_t ld, bs;
+    // only promote when the unpromoted layout would need a copy
+    auto direct_ok = [&](const std::string& b, const std::string& m, const std::string& n) {
+      return (as_matrix(A, b, m, sk, ld, bs) || as_matrix(A, b, sk, m, ld, bs)) &&
+             (as_matrix(B, b, sk, n, ld, bs) || as_matrix(B, b, n, sk, ld, bs)) &&
+             as_matrix(C, b, m, n, ld, bs);
+    };
+    if (!direct_ok("", sm, sn)) {
+      for (size_t len = cand.size(); len > 0 && pb_lab.empty(); --len) {
+        const std::string pre = cand.substr(0, len);
+        if (direct_ok(pre, sm, strip(sn, pre))) pb_lab = pre;
+      }
+      if (pb_lab.empty())
+        for (size_t len = candA.size(); len > 0 && pa_lab.empty(); --len) {
+          const std::string pre = candA.substr(0, len);
+          if (direct_ok(pre, strip(sm, pre), sn)) pa_lab = pre;
+        }
+    }
+    if (!pb_lab.empty()) {
+      sb = pb_lab;
+      sn = strip(sn, pb_lab);
+    } else if (!pa_lab.empty()) {
+      sb = pa_lab;
+      sm = strip(sm, pa_lab);
+    }
+  }
+  const bool bcastA = !pb_lab.empty(), bcastB = !pa_lab.empty();
+  const int64_t nb = bcastA ? prod_of(B, sb) : prod_of(A, sb);
+  const int64_t M = prod_of(A, sm), N = prod_of(B, sn);
+
+  bool ta = false, tb = false;
+  const double* pa;
+  const double* pb;
+  int64_t lda, ldb, sA, sB;
+  const std::string sbA = bcastA ? "" : sb, sbB = bcastB ? "" : sb;
+  if (as_matrix(A, sbA, sm, sk, lda, sA)) { pa = A.p; }
+  else if (as_matrix(A, sbA, sk, sm, lda, sA)) { pa = A.p; ta = true; }
+  else { DView p = packed_view(arena_, A, sbA + sm + sk, s_); pa = p.p; lda = K; sA = M * K; }
+  if (as_matrix(B, sbB, sk, sn, ldb, sB)) { pb = B.p; }
+  else if (as_matrix(B, sbB, sn, sk, ldb, sB)) { pb = B.p; tb = true; }
+  else { DView p = packed_view(arena_, B, sbB + sk + sn, s_); pb = p.p; ldb = N; sB = K * N; }
+  if (bcastA) sA = 0;
+  if (bcastB) sB = 0;
+
+  int64_t ldc, sC;
+  const bool direct = as_matrix(C, sb, sm, sn, ldc, sC);
+  double* pc;
+  DView cbuf;
+  if (direct) {
+    pc = C.p;
+  } else {
+    const std::string ord = sb + sm + sn;
+    cbuf.nd = (int)ord.size();
+    int64_t st = 1;
+    for (int k = cbuf.nd - 1; k >= 0; --k) {
+      const char c = ord[k];
+      const int ja = find_lab(A, c);
+      cbuf.lab[k] = c;
+      cbuf.dims[k] = ja >= 0 ? A.dims[ja] : B.dims[find_lab(B, c)];
+      cbuf.str[k] = st;
+      st *= cbuf.dims[k];
+    }
+    cbuf.p = arena_.alloc(st);
+    pc = cbuf.p;
+    ldc = N;
+    sC = M * N;
+  }
+  const double a_ = direct ? alpha : 1.0, b_ = direct ? 1.0 : 0.0;
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) throw Error(-1, "GEMM dimension overflow");
+
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * nb;
+  if (nb == 1 && tiles < 512 && K >= 4096) {
+    // split K so that the grid fills the device; partials folded in order
+    int64_t ns = std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), K / 1024);
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
+    const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
+    ns = (K + kc - 1) / kc;
+    double* part = arena_.alloc(ns * M * N);
+    for (int64_t z = 0; z < ns; ++z) {
+      const int64_t k0 = z * kc, kl = std::min(kc, K - k0);
+      const double* az = ta ? pa + k0 * lda : pa + k0;
+      const double* bz = tb ? pb + k0 : pb + k0 * ldb;
+      kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kl, 1, 1.0, az, lda, 0, bz, ldb, 0, 0.0,
+                      part + z * M * N, N, 0),
+             "gemm(splitk)");
+    }
+    const int64_t tot = M * N;
+    const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc, ldc, part, (int)M,
+                       (int)N, (int)ns, a_, b_);
+    kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+  } else {
+    kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)K, (int)nb, a_, pa, lda, sA, pb, ldb, sB, b_,
+                    pc, ldc, sC),
+           "gemm");
+  }
+  if (!direct) gather_into(s_, alpha, cbuf, C, 1.0);
+  arena_.rewind(mk);
+}
+
+// ------------------------------------------------------------------- Graph
+Graph::~Graph() {}
+
+int Graph::leaf(const Tensor& t) {
+  Node n;
+  n.val = t;
+  n.leaf = true;
+  nodes_.push_back(n);
+  return (int)nodes_.size() - 1;
+}
+
+DView Graph::view_of(const Op& o, const Tensor& t) const {
+  if ((int)o.lab.size() != t.nd) throw Error(-1, "operand label count != tensor rank");
+  if (!o.box.empty() && (int)o.box.size() != t.nd) throw Error(-1, "operand box rank mismatch");
+  int64_t st[kMaxViewDims];
+  strides_of(t, st);
+  DView v;
+  int64_t base = 0;
+  for (int k = 0; k < t.nd; ++k) {
+    const int64_t lo = o.box.empty() ? 0 : o.box[k].lo;
+    const int64_t len = o.box.empty() ? t.d[k] : o.box[k].len;
+    if (lo < 0 || lo + len > t.d[k]) throw Error(-1, "operand box out of range");
+    base += lo * st[k];
+    const int j = find_lab(v, o.lab[k]);
+    if (j >= 0) {
+      if (v.dims[j] != len) throw Error(-1, "repeated label with different extents");
+      v.str[j] += st[k];
+    } else {
+      v.lab[v.nd] = o.lab[k];
+      v.dims[v.nd] = len;
+      v.str[v.nd] = st[k];
+      v.nd++;
+    }
+  }
+  v.p = t.p + base;
+  return v;
+}
+
+DView Graph::out_view(const Term& tm, const Tensor& t) const {
+  Op o;
+  o.lab = tm.olab;
+  o.box = tm.obox;
+  DView v = view_of(o, t);
+  if (v.nd != t.nd) throw Error(-1, "output labels must be distinct");
+  return v;
+}
+
+int Graph::node(const std::vector<int64_t>& shape, const std::vector<Term>& terms) {
+  Node n;
+  n.val = make_tensor(e_.arena(), shape, true, e_.stream());
+  n.terms = terms;
+  for (const Term& tm : terms) {
+    DView C = out_view(tm, n.val);
+    DView A = view_of(tm.a, nodes_.at(tm.a.node).val);
+    if (tm.bilinear) {
+      DView B = view_of(tm.b, nodes_.at(tm.b.node).val);
+      e_.contract(tm.alpha, A, B, C);
+    } else {
+      e_.linear(tm.alpha, A, C);
+    }
+  }
+  nodes_.push_back(n);
+  return (int)nodes_.size() - 1;
+}
+
+std::map<int, int> Graph::jvp(const std::map<int, int>& seeds, int first) {
+  std::map<int, int> tan = seeds;
+  const int end = (int)nodes_.size();
+  for (int k = first; k < end; ++k) {
+    if (tan.count(k)) continue;
+    const Node nk = nodes_[k];   // copy: nodes_ grows below
+    if (nk.leaf) continue;
+    std::vector<Term> tt;
+    for (const Term& tm : nk.terms) {
+      auto ia = tan.find(tm.a.node);
+      if (tm.bilinear) {
+        auto ib = tan.find(tm.b.node);
+        if (ia != tan.end()) {
+          Term x = tm;
+          x.a.node = ia->second;
+          tt.push_back(x);
+        }
+        if (ib != tan.end()) {
+          Term x = tm;
+          x.b.node = ib->second;
+          tt.push_back(x);
+        }
+      } else if (ia != tan.end()) {
+        Term x = tm;
+        x.a.node = ia->second;
+        tt.push_back(x);
+      }
+    }
+    if (!tt.empty()) tan[k] = node(nk.val.shape(), tt);
+  }
+  return tan;
+}
+
+std::map<int, Tensor> Graph::vjp(const std::map<int, const double*>& seeds,
+                                 const std::vector<int>& wrt) {
+  const int n = (int)nodes_.size();
+  std::vector<char> needs(n, 0);
+  for (int w : wrt) needs.at(w) = 1;
+  for (int k = 0; k < n; ++k) {
+    if (needs[k]) continue;
+    for (const Term& tm : nodes_[k].terms) {
+      if (needs[tm.a.node] || (tm.bilinear && needs[tm.b.node])) {
+        needs[k] = 1;
+        break;
+      }
+    }
+  }
+  std::vector<Tensor> adj(n);
+  auto get_adj = [&](int k) -> Tensor& {
+    if (!adj[k].p) adj[k] = make_tensor(e_.arena(), nodes_[k].val.shape(), true, e_.stream());
+    return adj[k];
+  };
+  for (auto& kv : seeds) {
+    if (!needs.at(kv.first)) continue;
+    Tensor& a = get_adj(kv.first);
+    kcheck(axpby(e_.stream(), a.p, kv.second, 1.0, 1.0, a.size()), "seed");
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    if (!adj[k].p || nodes_[k].leaf) continue;
+    const Node& nk = nodes_[k];
+    for (const Term& tm : nk.terms) {
+      DView Cb = out_view(tm, adj[k]);
+      if (tm.bilinear) {
+        const bool na = needs[tm.a.node], nb = needs[tm.b.node];
+        if (na) {
+          DView Ab = view_of(tm.a, get_adj(tm.a.node));
+          DView B = view_of(tm.b, nodes_[tm.b.node].val);
+          e_.contract(tm.alpha, Cb, B, Ab);
+        }
+        if (nb) {
+          DView Bb = view_of(tm.b, get_adj(tm.b.node));
+          DView A = view_of(tm.a, nodes_[tm.a.node].val);
+          e_.contract(tm.alpha, A, Cb, Bb);
+        }
+      } else if (needs[tm.a.node]) {
+        DView Ab = view_of(tm.a, get_adj(tm.a.node));
+        e_.linear(tm.alpha, Cb, Ab);
+      }
+    }
+  }
+  std::map<int, Tensor> out;
+  for (int w : wrt) out[w] = get_adj(w);
+  return out;
+}
+
+}  // namespace nm

@@ -1,0 +1,182 @@
+// Device tensor engine with a recording tape.
+//
+// A Graph is a list of nodes; each node holds one contiguous fp64 device
+// tensor equal to a sum of terms, where a term is either
+//   * a contraction  alpha * einsum(la, lb -> lout)(A_view, B_view), or
+//   * a linear view  alpha * einsum(la -> lout)(A_view)   (permutation,
+//     block extraction, diagonal, partial sums),
+// written into a sub-box of the node.  Operands are strided views (sub-box +
+// index labels, repeated labels = diagonals) of earlier nodes.  Values are
+// computed eagerly when a node is created.
+//
+// Because every node is multilinear in its inputs, derivatives are taken on
+// the graph itself:
+//   * jvp(): appends one tangent node per node that depends on a seeded leaf
+//     (product rule on each contraction term), so tangents can themselves be
+//     differentiated;
+//   * vjp(): reverse sweep accumulating adjoints into the requested nodes.
+// Contractions run as [batch][M][K] x [batch][K][N] GEMMs on the FP64 matrix
+// cores after packing the operand views with the strided-view kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace nm {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Device memory: a stack of chunks with mark/rewind (LIFO lifetimes).
+class Arena {
+ public:
+  ~Arena();
+  double* alloc(int64_t ndouble);
+  struct Mark { size_t chunk; size_t top; };
+  Mark mark() const { return {cur_, chunks_.empty() ? 0 : chunks_[cur_].top}; }
+  void rewind(Mark m);
+  size_t peak_bytes() const { return peak_; }
+  size_t reserved_bytes() const;
+
+ private:
+  struct Chunk { char* base; size_t cap; size_t top; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+  size_t peak_ = 0, live_ = 0;
+};
+
+struct Range { int64_t lo, len; };
+
+struct Tensor {
+  double* p = nullptr;
+  int nd = 0;
+  int64_t d[kMaxViewDims] = {0};
+  int64_t size() const {
+    int64_t s = 1;
+    for (int k = 0; k < nd; ++k) s *= d[k];
+    return s;
+  }
+  std::vector<int64_t> shape() const { return std::vector<int64_t>(d, d + nd); }
+};
+
+struct Op {             // operand: node + box + labels (one label per dim)
+  int node = -1;
+  std::string lab;
+  std::vector<Range> box;   // empty = whole tensor
+};
+
+struct Term {
+  double alpha = 1.0;
+  bool bilinear = false;
+  Op a, b;                 // b unused for linear terms
+  std::string olab;        // labels of the output box dims
+  std::vector<Range> obox; // empty = whole node
+};
+
+struct Node {
+  Tensor val;
+  std::vector<Term> terms;  // empty for leaves
+  bool leaf = false;
+};
+
+// Device view with distinct labels (repeats merged into one strided dim).
+struct DView {
+  double* p = nullptr;
+  int nd = 0;
+  int64_t dims[kMaxViewDims] = {0};
+  int64_t str[kMaxViewDims] = {0};
+  char lab[kMaxViewDims] = {0};
+};
+
+class Engine {
+ public:
+  Engine(hipStream_t s);
+  hipStream_t stream() const { return s_; }
+  Arena& arena() { return arena_; }
+
+  // primitives on views
+  void contract(double alpha, const DView& A, const DView& B, const DView& C);  // C += alpha A.B
+  void linear(double alpha, const DView& A, const DView& C);                    // C += alpha sum A
+  double* scratch_reduce();
+  double* scalar_slot(int k);   // small device scalars
+  uint64_t gemm_flops() const { return flops_; }
+  void reset_flops() { flops_ = 0; }
+
+ private:
+  hipStream_t s_;
+  Arena arena_;
+  double* red_ = nullptr;
+  double* scal_ = nullptr;
+  uint64_t flops_ = 0;
+};
+
+class Graph {
+ public:
+  explicit Graph(Engine& e) : e_(e) {}
+  ~Graph();
+  int leaf(const Tensor& t);
+  int node(const std::vector<int64_t>& shape, const std::vector<Term>& terms);
+  const Tensor& val(int id) const { return nodes_[id].val; }
+  int size() const { return (int)nodes_.size(); }
+
+  // Tangents of every node from `first` on, given tangents of some nodes
+  // (node -> tangent node).  Returns the completed map (absent = zero).
+  std::map<int, int> jvp(const std::map<int, int>& seeds, int first = 0);
+
+  // Reverse sweep.  seeds: node -> device tensor (same shape) holding the
+  // adjoint of a scalar functional; returns adjoints of `wrt` nodes (device
+  // tensors allocated in the arena; zero-filled when unreachable).
+  std::map<int, Tensor> vjp(const std::map<int, const double*>& seeds,
+                            const std::vector<int>& wrt);
+
+  // Truncate the tape to `n` nodes (values of removed nodes are released
+  // when the arena is rewound by the caller).
+  void truncate(int n) { nodes_.resize(n); }
+  Engine& engine() { return e_; }
+
+ private:
+  DView view_of(const Op& op, const Tensor& t) const;
+  DView out_view(const Term& tm, const Tensor& t) const;
+  Engine& e_;
+  std::vector<Node> nodes_;
+};
+
+// Term builders.
+inline Op op(int node, const std::string& lab, std::vector<Range> box = {}) {
+  return Op{node, lab, std::move(box)};
+}
+inline Term mul(double alpha, Op a, Op b, const std::string& olab, std::vector<Range> obox = {}) {
+  Term t;
+  t.alpha = alpha;
+  t.bilinear = true;
+  t.a = std::move(a);
+  t.b = std::move(b);
+  t.olab = olab;
+  t.obox = std::move(obox);
+  return t;
+}
+inline Term lin(double alpha, Op a, const std::string& olab, std::vector<Range> obox = {}) {
+  Term t;
+  t.alpha = alpha;
+  t.bilinear = false;
+  t.a = std::move(a);
+  t.olab = olab;
+  t.obox = std::move(obox);
+  return t;
+}
+
+// Contiguous tensor helpers.
+Tensor make_tensor(Arena& a, const std::vector<int64_t>& shape, bool zero, hipStream_t s);
+DView full_view(const Tensor& t, const std::string& lab);
+
+}  // namespace nm

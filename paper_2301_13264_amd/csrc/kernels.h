@@ -1,0 +1,40 @@
+// Host-side launchers of the device kernels (see kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace nm {
+
+constexpr int kMaxViewDims = 6;
+
+// A strided map between an output box and an input tensor:
+// out[obase + sum_d i_d ostr_d]  <->  in[ibase + sum_d i_d istr_d + sum_r j_r rstr_r]
+// for 0 <= i_d < dims[d] and 0 <= j_r < rdims[r] (j_r are summed over).
+struct ViewSpec {
+  int nd = 0;
+  int nr = 0;
+  int64_t obase = 0, ibase = 0;
+  int64_t dims[kMaxViewDims] = {0};
+  int64_t ostr[kMaxViewDims] = {0};
+  int64_t istr[kMaxViewDims] = {0};
+  int64_t rdims[2] = {0, 0};
+  int64_t rstr[2] = {0, 0};
+};
+
+int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
+             const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,
+             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC);
+int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v, double alpha,
+                double beta);
+int view_scatter(hipStream_t s, double* in, const double* out, const ViewSpec& v, double alpha);
+int fill(hipStream_t s, double* x, double val, int64_t n);
+int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n);
+int apply_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o, int v,
+                      double shift, int mode);
+int apply_metric(hipStream_t s, double* y, const double* x, int o, int v, int mode);
+int dot(hipStream_t s, const double* x, const double* y, int64_t n, int o, int v, int packed,
+        double* scratch, double* out_dev);
+int absmax(hipStream_t s, const double* x, int64_t n, double* scratch, double* out_dev);
+int reduce_scratch_doubles();
+
+}  // namespace nm

@@ -1,0 +1,406 @@
+// Device kernels of the CCSD derivative-coupling library (gfx950 / CDNA4).
+//
+// * gemm_f64      : batched C = alpha op(A) op(B) + beta C on the FP64 matrix
+//                   cores (v_mfma_f64_16x16x4f64), LDS-staged 64x64x16 tiles,
+//                   four 64-wide waves per workgroup, each owning a 32x32 block.
+// * view_gather / view_scatter : one generic strided data-movement kernel
+//                   pair; every permutation, block extraction, symmetrisation
+//                   and axpy of the contraction engine is one of these.
+// * reductions    : deterministic two-pass dot products and max-abs.
+// * elementwise   : orbital-energy denominators (Jacobi / Davidson
+//                   preconditioners), packed-metric weights.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+namespace nm {
+
+// --------------------------------------------------------------------- GEMM
+// Tile: BM x BN x BK = 64 x 64 x 16, 256 threads = 4 waves arranged 2 x 2.
+// LDS holds A as As[k][m] and B as Bs[k][n] so that the MFMA operand of lane
+// l (row/col l % 16, k = l / 16) is read from consecutive addresses.
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda,
+    int64_t sA, const double* __restrict__ B, int64_t ldb, int64_t sB, double beta,
+    double* __restrict__ C, int64_t ldc, int64_t sC) {
+  __shared__ double As[BK][BM + PAD];
+  __shared__ double Bs[BK][BN + PAD];
+  const int64_t bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int m, k;
+      if (!TA) { m = e >> 4; k = e & 15; } else { k = e >> 6; m = e & 63; }
+      const int gm = m0 + m, gk = k0 + k;
+      double val = 0.0;
+      if (gm < M && gk < K) val = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[k][m] = val;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int k, n;
+      if (!TB) { k = e >> 6; n = e & 63; } else { n = e >> 4; k = e & 15; }
+      const int gn = n0 + n, gk = k0 + k;
+      double val = 0.0;
+      if (gn < N && gk < K) val = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      Bs[k][n] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm * 32 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lk][wn * 32 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of v_mfma_f64_16x16x4f64: lane l, element v -> row l/16 + 4 v, col l % 16.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * 32 + i * 16 + lk + 4 * v;
+        const int gn = n0 + wn * 32 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          double* c = C + (int64_t)gm * ldc + gn;
+          const double r = alpha * acc[i][j][v];
+          *c = (beta == 0.0) ? r : r + beta * (*c);
+        }
+      }
+}
+
+int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
+             const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,
+             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC) {
+  if (M <= 0 || N <= 0 || batch <= 0) return 0;
+  if (K <= 0) {  // C = beta C
+    return -1;
+  }
+  if (batch > 32768) {   // grid.z limit: launch in chunks
+    for (int b0 = 0; b0 < batch; b0 += 32768) {
+      const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
+      int rc = gemm_f64(s, ta, tb, M, N, K, nb, alpha, A + (int64_t)b0 * sA, lda, sA,
+                        B + (int64_t)b0 * sB, ldb, sB, beta, C + (int64_t)b0 * sC, ldc, sC);
+      if (rc) return rc;
+    }
+    return 0;
+  }
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+  dim3 block(256);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ------------------------------------------------------------ strided views
+// out[obase + sum_d i_d ostr_d] (=|+=) alpha * sum_red in[ibase + sum_d i_d istr_d
+//                                                       + sum_r j_r rstr_r]
+__global__ void view_gather_kernel(double* __restrict__ out, const double* __restrict__ in,
+                                   ViewSpec v, double alpha, double beta, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, oo = v.obase, io = v.ibase;
+    for (int d = v.nd - 1; d >= 0; --d) {
+      const int64_t q = rem / v.dims[d];
+      const int64_t i = rem - q * v.dims[d];
+      rem = q;
+      oo += i * v.ostr[d];
+      io += i * v.istr[d];
+    }
+    double acc = 0.0;
+    if (v.nr == 0) {
+      acc = in[io];
+    } else if (v.nr == 1) {
+      for (int64_t j = 0; j < v.rdims[0]; ++j) acc += in[io + j * v.rstr[0]];
+    } else {
+      for (int64_t j0 = 0; j0 < v.rdims[0]; ++j0)
+        for (int64_t j1 = 0; j1 < v.rdims[1]; ++j1)
+          acc += in[io + j0 * v.rstr[0] + j1 * v.rstr[1]];
+    }
+    out[oo] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * out[oo];
+  }
+}
+
+// in[ibase + ...] += alpha * out[obase + ...]; requires the map
+// (i, j) -> input offset to be injective (no two threads hit one element).
+__global__ void view_scatter_kernel(double* __restrict__ in, const double* __restrict__ out,
+                                    ViewSpec v, double alpha, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, oo = v.obase, io = v.ibase;
+    for (int d = v.nd - 1; d >= 0; --d) {
+      const int64_t q = rem / v.dims[d];
+      const int64_t i = rem - q * v.dims[d];
+      rem = q;
+      oo += i * v.ostr[d];
+      io += i * v.istr[d];
+    }
+    const double val = alpha * out[oo];
+    if (v.nr == 0) {
+      in[io] += val;
+    } else if (v.nr == 1) {
+      for (int64_t j = 0; j < v.rdims[0]; ++j) in[io + j * v.rstr[0]] += val;
+    } else {
+      for (int64_t j0 = 0; j0 < v.rdims[0]; ++j0)
+        for (int64_t j1 = 0; j1 < v.rdims[1]; ++j1)
+          in[io + j0 * v.rstr[0] + j1 * v.rstr[1]] += val;
+    }
+  }
+}
+
+static int grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v, double alpha,
+                double beta) {
+  int64_t total = 1;
+  for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
+  if (total == 0) return 0;
+  hipLaunchKernelGGL(view_gather_kernel, dim3(grid_for(total)), dim3(256), 0, s, out, in, v,
+                     alpha, beta, total);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int view_scatter(hipStream_t s, double* in, const double* out, const ViewSpec& v, double alpha) {
+  int64_t total = 1;
+  for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
+  if (total == 0) return 0;
+  hipLaunchKernelGGL(view_scatter_kernel, dim3(grid_for(total)), dim3(256), 0, s, in, out, v,
+                     alpha, total);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ------------------------------------------------------------- elementwise
+__global__ void fill_kernel(double* x, double val, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = val;
+}
+
+int fill(hipStream_t s, double* x, double val, int64_t n) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, val, n);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// y = a x + b y
+__global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = (b == 0.0) ? a * x[e] : a * x[e] + b * y[e];
+}
+
+int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, b, n);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Amplitude-shaped vector: [o*v singles][o*o*v*v doubles t2[i][j][a][b]].
+// y = x / (shift - D) with D the orbital-energy difference (preconditioner);
+// the sign convention: mode 0 -> y = -x / D (Jacobi step), mode 1 -> y = x / (shift - D).
+__global__ void denom_kernel(double* y, const double* x, const double* eps, int o, int v,
+                             double shift, int mode, double floor_abs) {
+  const int64_t nov = (int64_t)o * v, n2 = nov * nov;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nov + n2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double D;
+    if (e < nov) {
+      const int i = (int)(e / v), a = (int)(e % v);
+      D = eps[o + a] - eps[i];
+    } else {
+      int64_t r = e - nov;
+      const int b = (int)(r % v); r /= v;
+      const int a = (int)(r % v); r /= v;
+      const int j = (int)(r % o);
+      const int i = (int)(r / o);
+      D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
+    }
+    double d = (mode == 0) ? -D : shift - D;
+    if (fabs(d) < floor_abs) d = (d < 0.0) ? -floor_abs : floor_abs;
+    y[e] = x[e] / d;
+  }
+}
+
+int apply_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o,
+                      int v, double shift, int mode) {
+  const int64_t n = (int64_t)o * v * (1 + (int64_t)o * v);
+  hipLaunchKernelGGL(denom_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, eps, o, v, shift,
+                     mode, 1e-3);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Packed-metric weights on the doubles block: w = 1/2 (1 + delta_(ia),(jb)).
+// mode 0: y = w x (seed of a packed functional on the full tensor);
+// mode 1: y[ijab] = x[ijab] + x[jiba] - delta x (full-tensor gradient -> packed gradient);
+// mode 2: y <- symmetric part of y in place (x unused): keeps vectors in the
+//         space of doubles with x2[i][j][a][b] == x2[j][i][b][a].
+__global__ void metric_kernel(double* y, const double* x, int o, int v, int mode) {
+  const int64_t nov = (int64_t)o * v, n2 = nov * nov;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nov + n2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nov) {
+      if (mode != 2) y[e] = x[e];
+      continue;
+    }
+    int64_t r = e - nov;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    const bool diag = (i == j) && (a == b);
+    if (mode == 2) {  // in place: x2 <- (x2 + x2^T)/2, one thread per unordered pair
+      const int64_t P = (int64_t)i * v + a, Q = (int64_t)j * v + b;
+      if (P < Q) {
+        const int64_t t = nov + (((int64_t)j * o + i) * v + b) * v + a;
+        const double m = 0.5 * (y[e] + y[t]);
+        y[e] = m;
+        y[t] = m;
+      }
+      continue;
+    }
+    if (mode == 0) {
+      y[e] = diag ? x[e] : 0.5 * x[e];
+    } else {
+      const int64_t t = nov + (((int64_t)j * o + i) * v + b) * v + a;
+      y[e] = diag ? x[e] : x[e] + x[t];
+    }
+  }
+}
+
+int apply_metric(hipStream_t s, double* y, const double* x, int o, int v, int mode) {
+  const int64_t n = (int64_t)o * v * (1 + (int64_t)o * v);
+  hipLaunchKernelGGL(metric_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, o, v, mode);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// --------------------------------------------------------------- reductions
+// Pass 1: per-block partial sums (wavefront shuffles, then LDS across waves).
+__device__ inline double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+__device__ inline double wave_max(double x) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  return x;
+}
+
+// Packed-metric dot: sum singles + 1/2 sum doubles + 1/2 sum diagonal doubles
+// when `packed` != 0 (amplitude-shaped vectors), plain dot otherwise.
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double* x, const double* y,
+                                                          int64_t n, int o, int v, int packed,
+                                                          double* part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const int64_t nov = (int64_t)o * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double w = 1.0;
+    if (packed && e >= nov) {
+      int64_t r = e - nov;
+      const int b = (int)(r % v); r /= v;
+      const int a = (int)(r % v); r /= v;
+      const int j = (int)(r % o);
+      const int i = (int)(r / o);
+      w = (i == j && a == b) ? 1.0 : 0.5;
+    }
+    acc += w * x[e] * y[e];
+  }
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void absmax_partial_kernel(const double* x, int64_t n,
+                                                             double* part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double a = fabs(x[e]);
+    acc = (a > acc || a != a) ? a : acc;  // propagate NaN
+  }
+  acc = wave_max(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Pass 2: one block folds the partials (fixed order: deterministic).
+__global__ __launch_bounds__(256) void fold_kernel(const double* part, int np, int op,
+                                                   double* out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < np; e += 256) acc = op ? fmax(acc, part[e]) : acc + part[e];
+  acc = op ? wave_max(acc) : wave_sum(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    *out = op ? fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))
+              : red[0] + red[1] + red[2] + red[3];
+}
+
+constexpr int kReduceBlocks = 1024;
+
+int dot(hipStream_t s, const double* x, const double* y, int64_t n, int o, int v, int packed,
+        double* scratch, double* out_dev) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kReduceBlocks), dim3(256), 0, s, x, y, n, o, v,
+                     packed, scratch);
+  hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(256), 0, s, scratch, kReduceBlocks, 0, out_dev);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int absmax(hipStream_t s, const double* x, int64_t n, double* scratch, double* out_dev) {
+  hipLaunchKernelGGL(absmax_partial_kernel, dim3(kReduceBlocks), dim3(256), 0, s, x, n, scratch);
+  hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(256), 0, s, scratch, kReduceBlocks, 1, out_dev);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int reduce_scratch_doubles() { return kReduceBlocks; }
+
+}  // namespace nm

@@ -1,0 +1,144 @@
+"""GPU parity: the library (through its C ABI) against the fp64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import ccsd
+from oracle import response as rs
+
+from gpu_helpers import T, oracle_state, say, to_full, to_packed
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_13264_amd as nm
+    return nm
+
+
+CONTRACTIONS = [
+    ("ijcd,acbd->ijab", [(3, 5, 7, 9), (13, 7, 11, 9)], (3, 5, 13, 11)),       # ladder
+    ("pP,PQRS->pQRS", [(7, 7), (7, 6, 5, 4)], (7, 6, 5, 4)),                  # index transform
+    ("qQ,pQRS->pqRS", [(6, 6), (5, 6, 4, 3)], (5, 6, 4, 3)),                  # batched (promoted)
+    ("pqrS,sS->pqrs", [(4, 5, 6, 7), (3, 7)], (4, 5, 6, 3)),                  # transposed B
+    ("kicd,adkc->ia", [(3, 4, 5, 6), (7, 6, 3, 5)], (4, 7)),                  # split-K shaped
+    ("ia,jb->ijab", [(3, 5), (4, 6)], (3, 4, 5, 6)),                          # outer product
+    ("ijab,iajb->", [(3, 4, 5, 6), (3, 5, 4, 6)], ()),                        # full contraction
+    ("iiaa,ia->ia", [(3, 3, 5, 5), (3, 5)], (3, 5)),                          # diagonal + batch
+    ("zik,zkj->zij", [(5, 33, 17), (5, 17, 70)], (5, 33, 70)),               # explicit batch
+    ("ak,kx->ax", [(70, 4100), (4100, 3)], (70, 3)),                         # long K, split
+]
+
+
+@pytest.mark.parametrize("spec,shapes,oshape", CONTRACTIONS)
+def test_contract_matches_torch(nm, spec, shapes, oshape):
+    say(f"[contract] {spec}")
+    rng = np.random.default_rng(len(spec))
+    A = T(rng.normal(size=shapes[0]))
+    B = T(rng.normal(size=shapes[1]))
+    C0 = rng.normal(size=oshape) if oshape else rng.normal(size=(1,))
+    C = T(C0.reshape(oshape) if oshape else C0)
+    la, rest = spec.split(",")
+    lb, lc = rest.split("->")
+    Ac, Bc = A.cpu(), B.cpu()
+    if la == "iiaa":
+        Ac = torch.einsum("iiaa->ia", Ac)
+        ref = torch.einsum("ia,ia->ia", Ac, Bc)
+    else:
+        ref = torch.einsum(spec, Ac, Bc)
+    ref = 0.7 * ref + 0.3 * torch.as_tensor(C0.reshape(oshape) if oshape else C0[0])
+    nm.contract(spec, 0.7, A, B, 0.3, C)
+    torch.cuda.synchronize()
+    err = (C.cpu().reshape(ref.shape) - ref).abs().max().item()
+    assert err < 1e-11 * max(1.0, ref.abs().max().item())
+
+
+@pytest.mark.parametrize("o,v", [(1, 4), (2, 3), (3, 5), (4, 12)])
+def test_residual_matches_oracle(nm, o, v):
+    say(f"[residual] o={o} v={v}")
+    naux = 3 * (o + v)
+    sysd = synth.make_system(o, v, naux, synth.exact_check_seed(o, v))
+    h, g = rs.system_hamiltonian(sysd["eps"], sysd["B"], o)
+    t1, t2 = synth.random_amplitudes(o, v, seed=5, scale=0.1)
+    om1, om2 = ccsd.residual(torch.as_tensor(t1), torch.as_tensor(t2), h, g)
+    ref = np.concatenate([om1.numpy().ravel(), om2.numpy().ravel()])
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    out = torch.zeros(ref.size, dtype=torch.float64, device="cuda")
+    ctx.residual(T(np.concatenate([t1.ravel(), t2.ravel()])), out)
+    torch.cuda.synchronize()
+    assert np.abs(out.cpu().numpy() - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 5)])
+def test_jacobian_transforms_match_oracle(nm, o, v):
+    say(f"[jacobian] o={o} v={v}")
+    naux = 3 * (o + v)
+    st = oracle_state(o, v, naux, synth.exact_check_seed(o, v), 2)
+    sysd = st["sys"]
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    ctx.ground()
+    x = np.random.default_rng(3).normal(size=st["x"].numel())
+    y = torch.zeros(o * v + (o * v) ** 2, dtype=torch.float64, device="cuda")
+    ctx.apply_jacobian(nm.CC_RIGHT, T(to_full(x, o, v)), y)
+    ref = rs.right_transform(st["x"], torch.as_tensor(x), st["h"], st["g"], o, v).numpy()
+    assert np.abs(to_packed(y.cpu().numpy(), o, v) - ref).max() < 1e-9
+    ctx.apply_jacobian(nm.CC_LEFT, T(to_full(x, o, v)), y)
+    ref = rs.left_transform(st["x"], torch.as_tensor(x), st["h"], st["g"], o, v).numpy()
+    assert np.abs(to_packed(y.cpu().numpy(), o, v) - ref).max() < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 5, 18, None), (2, 4, 18, None), (4, 12, 48, 2301)])
+def test_pipeline_matches_oracle(nm, o, v, naux, seed):
+    say(f"[pipeline] o={o} v={v} naux={naux}")
+    seed = synth.exact_check_seed(o, v) if seed is None else seed
+    nroots = 2
+    st = oracle_state(o, v, naux, seed, nroots)
+    sysd = st["sys"]
+    n = o + v
+    dirs = synth.make_directions(n, naux, seed + 17, 2)
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    e, it, rc = ctx.ground()
+    assert rc == 0
+    e_hf_ref = float(ccsd.energy(torch.zeros(o, v, dtype=torch.float64),
+                                 torch.zeros(o, o, v, v, dtype=torch.float64), st["h"], st["g"]))
+    assert abs((e + e_hf_ref) - st["E0"]) < 1e-9
+    w, _, rc = ctx.eom(nm.CC_BOTH, nroots)
+    assert rc == 0
+    assert np.abs(np.array(w) - st["omega"].numpy()).max() < 1e-9
+    Nf = o * v + (o * v) ** 2
+    buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+    for k in range(nroots):
+        R = to_packed(ctx.export(nm._lib.CC_R, k + 1, 0, buf).cpu().numpy(), o, v)
+        L = to_packed(ctx.export(nm._lib.CC_L, k + 1, 0, buf).cpu().numpy(), o, v)
+        assert np.abs(R - st["R"][k].numpy()).max() < 1e-7
+        assert np.abs(L - st["L"][k].numpy()).max() < 1e-7
+        assert abs(ctx.export_r0(k + 1) - float(st["R0"][k])) < 1e-8
+    for (i, j) in [(0, 1), (1, 0)]:
+        m = rs.multipliers(st, i, j, relaxed=True)
+        ctx.multipliers(i + 1, j + 1)
+        eta = to_packed(ctx.export(nm._lib.CC_ETA_T, i + 1, j + 1, buf).cpu().numpy(), o, v)
+        assert np.abs(eta - m["eta_t"].numpy()).max() < 1e-7
+        zeta = to_packed(ctx.export(nm._lib.CC_ZETA, i + 1, j + 1, buf).cpu().numpy(), o, v)
+        assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7
+        kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
+        ek = ctx.export(nm._lib.CC_ETA_K, i + 1, j + 1, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(ek - m["eta_kappa"].numpy()).max() < 1e-7
+        kb = ctx.export(nm._lib.CC_KAPPA, i + 1, j + 1, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(kb - m["kappa_bar"].numpy()).max() < 1e-7
+        D1 = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        ctx.densities(i + 1, j + 1, D1)
+        Dref, dref = rs.effective_densities(st, m, j)
+        Dg = D1.cpu().numpy()
+        assert np.abs(0.5 * (Dg + Dg.T) - Dref.numpy()).max() < 1e-7
+        F = ctx.nacme(i + 1, j + 1, T(dirs["dh"]), T(dirs["dB"]))
+        for q in range(2):
+            dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+            Fo = rs.coupling_direct(st, m, j, dirs["dh"][q], dg)
+            assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
+    ctx.close()
