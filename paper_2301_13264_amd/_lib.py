@@ -66,6 +66,8 @@ def lib():
         L.nm_contract.argtypes = [ctypes.c_char_p, D, P, L64, P, L64, D, P, L64, P]
         L.nm_eig_host.argtypes = [I, PD, PD, PD, PD]
         L.nm_version.restype = ctypes.c_char_p
+        L.cc_stats.argtypes = [P, PD, I]
+        L.cc_stats.restype = ctypes.c_int
         for name in ("cc_create", "cc_ground", "eom_solve", "multipliers", "densities", "nacme",
                      "cc_apply_jacobian", "cc_residual", "cc_export", "cc_set_guess",
                      "nm_contract", "nm_eig_host"):
@@ -77,7 +79,7 @@ def lib():
 EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multipliers",
             "densities", "nacme", "cc_apply_jacobian", "cc_residual", "cc_export",
             "cc_set_guess", "cc_last_error", "cc_destroy", "nm_contract", "nm_eig_host",
-            "nm_version"]
+            "nm_version", "cc_stats"]
 
 
 def default_opts(**kw) -> Opts:
@@ -170,6 +172,13 @@ class Context:
         x = ctypes.c_double()
         self._check(lib().cc_export(self._h, CC_R0, k, 0, ctypes.byref(x)))
         return x.value
+
+    def stats(self):
+        out = (ctypes.c_double * 6)()
+        self._check(lib().cc_stats(self._h, out, 6))
+        keys = ["residuals", "right_transforms", "left_transforms", "gemm_flops",
+                "peak_bytes", "reserved_bytes"]
+        return dict(zip(keys, list(out)))
 
     def set_guess(self, what, idx, src):
         self._check(lib().cc_set_guess(self._h, what, idx, _ptr(src)))

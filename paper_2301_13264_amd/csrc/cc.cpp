@@ -76,6 +76,7 @@ struct cc_ctx {
   std::map<std::pair<int, int>, nm::PairData> pairs;
   std::string err;
   bool sticky = false;
+  int64_t n_right = 0, n_left = 0, n_residual = 0;
 };
 
 namespace nm {
@@ -241,6 +242,7 @@ static Tensor T2of(Ctx& c, double* x) {
 
 // Residual at amplitudes x -> out (amplitude-shaped).
 static void residual(Ctx& c, double* x, double* out) {
+  ++c.n_residual;
   ArenaScope sc(c.eng->arena());
   Graph G(*c.eng);
   ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.g);
@@ -282,6 +284,7 @@ struct Tape {
 
   // y = A x
   void right(const double* x, double* y) {
+    ++c.n_right;
     const int n0 = G.size();
     Arena::Mark mk = c.eng->arena().mark();
     const int r1 = G.leaf(T1of(c, const_cast<double*>(x))), r2 = G.leaf(T2of(c, const_cast<double*>(x)));
@@ -295,6 +298,7 @@ struct Tape {
 
   // y = x^T A (packed-gradient convention, amplitude-shaped)
   void left(const double* x, double* y) {
+    ++c.n_left;
     Arena::Mark mk = c.eng->arena().mark();
     double* seed = c.eng->arena().alloc(c.N);
     kc(apply_metric(c.s, seed, x, c.o, c.v, 0), "metric");
@@ -388,7 +392,7 @@ struct Ritz {
 // Lowest-nroots eigenpairs of a non-symmetric operator on amplitude-shaped
 // vectors (biorthonormal metric), preconditioned by orbital-energy differences.
 static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*)>& T,
-                     std::vector<double*>& out) {
+                     std::vector<double*>& out, const std::vector<double*>* guess = nullptr) {
   const int64_t N = c.N, nov = (int64_t)c.o * c.v;
   const int nb = nroots + std::max(0, c.opts.davidson_block);
   const int maxm = std::max(c.opts.davidson_max, 2 * nb + 2);
@@ -430,14 +434,21 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     return true;
   };
 
-  // initial guess: singles unit vectors at the smallest e_a - e_i
-  {
+  // initial guess: given vectors (e.g. the right states for the left
+  // problem), then singles unit vectors at the smallest e_a - e_i
+  if (guess)
+    for (double* gv : *guess) {
+      if (m >= nb) break;
+      copy_d(c, Rs, gv, N);
+      add(Rs, nullptr);
+    }
+  if (m < nb) {
     std::vector<std::pair<double, int64_t>> d;
     for (int i = 0; i < c.o; ++i)
       for (int a = 0; a < c.v; ++a) d.push_back({c.eps_h[c.o + a] - c.eps_h[i], (int64_t)i * c.v + a});
     std::sort(d.begin(), d.end());
     const double one = 1.0;
-    for (int k = 0; k < nb && k < (int)d.size(); ++k) {
+    for (int k = 0; k < (int)d.size() && m < nb; ++k) {
       kc(fill(c.s, Rs, 0.0, N), "fill");
       hip_check(hipMemcpyAsync(Rs + d[k].second, &one, sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
       sync(c);
@@ -509,7 +520,9 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       }
       continue;
     }
-    for (int k = 0; k < nk; ++k) {
+    // corrections only for the wanted roots; the extra Ritz vectors stay in
+    // the subspace (and survive restarts) as ballast
+    for (int k = 0; k < std::min(nk, nroots); ++k) {
       if (rn[k] < c.opts.tol_eom) continue;
       copy_d(c, Rs, AX + (int64_t)k * N, N);
       axpby_(c, Rs, X + (int64_t)k * N, -res.w[k], 1.0, N);
@@ -624,7 +637,8 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
     if (!r.converged) status = CC_NOT_CONVERGED;
   }
   if (side & CC_LEFT) {
-    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.left(x, y); }, c.L);
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.left(x, y); }, c.L,
+                      c.have_right ? &c.R : nullptr);
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_l = r.w;
     c.have_left = true;
@@ -1280,6 +1294,15 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
   } catch (const Error& e) {
     return e.code;
   }
+}
+
+int cc_stats(const cc_ctx* c, double* out, int n) {
+  if (!c || !out || n < 1) return CC_ERR_ARG;
+  const double v[6] = {(double)c->n_residual, (double)c->n_right, (double)c->n_left,
+                       (double)c->eng->gemm_flops(), (double)c->eng->arena().peak_bytes(),
+                       (double)c->eng->arena().reserved_bytes()};
+  for (int k = 0; k < n && k < 6; ++k) out[k] = v[k];
+  return CC_OK;
 }
 
 int nm_eig_host(int m, const double* G, double* wr, double* wi, double* V) {

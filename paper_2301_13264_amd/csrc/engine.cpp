@@ -2,6 +2,9 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <set>
 
@@ -208,15 +211,17 @@ static void scatter_into(hipStream_t s, double alpha, const DView& src, const DV
   kcheck(view_scatter(s, dst.p, src.p, vs, alpha), "view_scatter");
 }
 
-void Engine::linear(double alpha, const DView& A, const DView& C) {
+void Engine::linear(double alpha, const DView& A, const DView& C, bool overwrite) {
   // forward reduction if every C label is in A, else broadcast
   bool all_in = true;
   for (int k = 0; k < C.nd; ++k)
     if (find_lab(A, C.lab[k]) < 0) all_in = false;
-  if (all_in)
-    gather_into(s_, alpha, A, C, 1.0);
-  else
+  if (all_in) {
+    gather_into(s_, alpha, A, C, overwrite ? 0.0 : 1.0);
+  } else {
+    if (overwrite) throw Error(-1, "broadcast term cannot overwrite");
     scatter_into(s_, alpha, A, C);
+  }
 }
 
 static DView packed_view(Arena& ar, const DView& src, const std::string& order, hipStream_t s) {
@@ -296,6 +301,12 @@ static bool as_matrix(const DView& v, const std::string& batch, const std::strin
   return true;
 }
 
+static bool trace_on() {
+  static int t = -1;
+  if (t < 0) t = std::getenv("NACME_TRACE") ? 1 : 0;
+  return t == 1;
+}
+
 static int64_t prod_of(const DView& v, const std::string& s) {
   int64_t p = 1;
   for (char c : s) p *= v.dims[find_lab(v, c)];
@@ -306,7 +317,7 @@ static std::string labels_of(const DView& v) { return std::string(v.lab, v.lab +
 
 __global__ void scalar_axpy_kernel(double* y, const double* x, double a) { *y += a * (*x); }
 
-void Engine::contract(double alpha, const DView& A, const DView& B, const DView& C) {
+void Engine::contract(double alpha, const DView& A, const DView& B, const DView& C, bool overwrite) {
   std::string sb, sm, sn, sk;
   for (int k = 0; k < A.nd; ++k) {
     const char c = A.lab[k];
@@ -342,6 +353,7 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     const double* pb = contiguous_in(B, ord) ? B.p : packed_view(arena_, B, ord, s_).p;
     double* tmp = scalar_slot(63);
     kcheck(dot(s_, pa, pb, K, 1, 1, 0, red_, tmp), "dot");
+    if (overwrite) kcheck(fill(s_, C.p, 0.0, 1), "fill");
     hipLaunchKernelGGL(scalar_axpy_kernel, dim3(1), dim3(1), 0, s_, C.p, tmp, alpha);
     kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "scalar axpy");
     arena_.rewind(mk);
@@ -371,20 +383,28 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     };
     int64_t ld, bs;
     // only promote when the unpromoted layout would need a copy
-    auto direct_ok = [&](const std::string& b, const std::string& m, const std::string& n) {
-      return (as_matrix(A, b, m, sk, ld, bs) || as_matrix(A, b, sk, m, ld, bs)) &&
-             (as_matrix(B, b, sk, n, ld, bs) || as_matrix(B, b, n, sk, ld, bs)) &&
-             as_matrix(C, b, m, n, ld, bs);
+    // ba / bb: batch labels as seen by A / B (empty for the broadcast operand)
+    auto direct_ok = [&](const std::string& ba, const std::string& bb, const std::string& bc,
+                         const std::string& m, const std::string& n) {
+      return (as_matrix(A, ba, m, sk, ld, bs) || as_matrix(A, ba, sk, m, ld, bs)) &&
+             (as_matrix(B, bb, sk, n, ld, bs) || as_matrix(B, bb, n, sk, ld, bs)) &&
+             as_matrix(C, bc, m, n, ld, bs);
     };
-    if (!direct_ok("", sm, sn)) {
+    // copies the unpromoted layout would need (doubles)
+    int64_t copy_cost = 0;
+    if (!(as_matrix(A, "", sm, sk, ld, bs) || as_matrix(A, "", sk, sm, ld, bs))) copy_cost += M0 * K;
+    if (!(as_matrix(B, "", sk, sn, ld, bs) || as_matrix(B, "", sn, sk, ld, bs))) copy_cost += K * N0;
+    if (!as_matrix(C, "", sm, sn, ld, bs)) copy_cost += M0 * N0;
+    // promote only when it saves a large copy and leaves a GEMM-shaped batch
+    if (copy_cost > (int64_t)1 << 22) {
       for (size_t len = cand.size(); len > 0 && pb_lab.empty(); --len) {
         const std::string pre = cand.substr(0, len);
-        if (direct_ok(pre, sm, strip(sn, pre))) pb_lab = pre;
+        if (N0 / prod_of(B, pre) >= 16 && direct_ok("", pre, pre, sm, strip(sn, pre))) pb_lab = pre;
       }
       if (pb_lab.empty())
         for (size_t len = candA.size(); len > 0 && pa_lab.empty(); --len) {
           const std::string pre = candA.substr(0, len);
-          if (direct_ok(pre, strip(sm, pre), sn)) pa_lab = pre;
+          if (M0 / prod_of(A, pre) >= 16 && direct_ok(pre, "", pre, strip(sm, pre), sn)) pa_lab = pre;
         }
     }
     if (!pb_lab.empty()) {
@@ -436,7 +456,12 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     ldc = N;
     sC = M * N;
   }
-  const double a_ = direct ? alpha : 1.0, b_ = direct ? 1.0 : 0.0;
+  const double a_ = direct ? alpha : 1.0, b_ = (direct && !overwrite) ? 1.0 : 0.0;
+  std::chrono::steady_clock::time_point t0;
+  if (trace_on()) {
+    (void)hipStreamSynchronize(s_);
+    t0 = std::chrono::steady_clock::now();
+  }
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) throw Error(-1, "GEMM dimension overflow");
 
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * nb;
@@ -447,14 +472,12 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
     ns = (K + kc - 1) / kc;
     double* part = arena_.alloc(ns * M * N);
-    for (int64_t z = 0; z < ns; ++z) {
-      const int64_t k0 = z * kc, kl = std::min(kc, K - k0);
-      const double* az = ta ? pa + k0 * lda : pa + k0;
-      const double* bz = tb ? pb + k0 : pb + k0 * ldb;
-      kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kl, 1, 1.0, az, lda, 0, bz, ldb, 0, 0.0,
-                      part + z * M * N, N, 0),
-             "gemm(splitk)");
-    }
+    // one launch: K chunks on grid.z, the last chunk possibly shorter
+    const int64_t klast = K - (ns - 1) * kc;
+    kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kc, (int)ns, 1.0, pa, lda,
+                    ta ? kc * lda : kc, pb, ldb, tb ? kc : kc * ldb, 0.0, part, N, M * N,
+                    (int)klast),
+           "gemm(splitk)");
     const int64_t tot = M * N;
     const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
     hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc, ldc, part, (int)M,
@@ -465,7 +488,16 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
                     pc, ldc, sC),
            "gemm");
   }
-  if (!direct) gather_into(s_, alpha, cbuf, C, 1.0);
+  if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
+  if (trace_on()) {
+    (void)hipStreamSynchronize(s_);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[contract] %s,%s->%s b=%s m=%s n=%s k=%s nb=%lld M=%lld N=%lld K=%lld ta=%d tb=%d "
+                 "packA=%d packB=%d direct=%d bcast=%d%d %.3f ms\n",
+                 labels_of(A).c_str(), labels_of(B).c_str(), labels_of(C).c_str(), sb.c_str(), sm.c_str(),
+                 sn.c_str(), sk.c_str(), (long long)nb, (long long)M, (long long)N, (long long)K, ta, tb,
+                 pa != A.p, pb != B.p, direct, bcastA, bcastB, ms);
+  }
   arena_.rewind(mk);
 }
 
@@ -518,16 +550,32 @@ DView Graph::out_view(const Term& tm, const Tensor& t) const {
 
 int Graph::node(const std::vector<int64_t>& shape, const std::vector<Term>& terms) {
   Node n;
-  n.val = make_tensor(e_.arena(), shape, true, e_.stream());
+  // The first term may overwrite the (uninitialised) output when it covers
+  // the whole node and is not a broadcast.
+  bool first_overwrites = false;
+  if (!terms.empty() && terms[0].obox.empty()) {
+    const Term& t0 = terms[0];
+    if (t0.bilinear) {
+      first_overwrites = true;
+    } else {
+      first_overwrites = true;
+      for (char ch : t0.olab)
+        if (t0.a.lab.find(ch) == std::string::npos) first_overwrites = false;
+    }
+  }
+  n.val = make_tensor(e_.arena(), shape, !first_overwrites, e_.stream());
   n.terms = terms;
+  bool first = true;
   for (const Term& tm : terms) {
     DView C = out_view(tm, n.val);
     DView A = view_of(tm.a, nodes_.at(tm.a.node).val);
+    const bool ow = first && first_overwrites;
+    first = false;
     if (tm.bilinear) {
       DView B = view_of(tm.b, nodes_.at(tm.b.node).val);
-      e_.contract(tm.alpha, A, B, C);
+      e_.contract(tm.alpha, A, B, C, ow);
     } else {
-      e_.linear(tm.alpha, A, C);
+      e_.linear(tm.alpha, A, C, ow);
     }
   }
   nodes_.push_back(n);

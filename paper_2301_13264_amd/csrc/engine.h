@@ -105,8 +105,9 @@ class Engine {
   Arena& arena() { return arena_; }
 
   // primitives on views
-  void contract(double alpha, const DView& A, const DView& B, const DView& C);  // C += alpha A.B
-  void linear(double alpha, const DView& A, const DView& C);                    // C += alpha sum A
+  // C (+)= alpha A.B ; C (+)= alpha sum A.  overwrite: C = ... (C's old values ignored)
+  void contract(double alpha, const DView& A, const DView& B, const DView& C, bool overwrite = false);
+  void linear(double alpha, const DView& A, const DView& C, bool overwrite = false);
   double* scratch_reduce();
   double* scalar_slot(int k);   // small device scalars
   uint64_t gemm_flops() const { return flops_; }

@@ -23,7 +23,7 @@ struct ViewSpec {
 
 int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,
-             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC);
+             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast = 0);
 int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v, double alpha,
                 double beta);
 int view_scatter(hipStream_t s, double* in, const double* out, const ViewSpec& v, double alpha);

@@ -28,7 +28,7 @@ template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda,
     int64_t sA, const double* __restrict__ B, int64_t ldb, int64_t sB, double beta,
-    double* __restrict__ C, int64_t ldc, int64_t sC) {
+    double* __restrict__ C, int64_t ldc, int64_t sC, int Klast) {
   __shared__ double As[BK][BM + PAD];
   __shared__ double Bs[BK][BN + PAD];
   const int64_t bz = blockIdx.z;
@@ -36,6 +36,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   B += bz * sB;
   C += bz * sC;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const int lr = lane & 15, lk = lane >> 4;
@@ -99,9 +100,148 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
       }
 }
 
+// Large-tile variant: 128 x 128 x 16 per workgroup, each wave a 64 x 64 block
+// (4 x 4 MFMA tiles, 64 fp64 accumulators per lane).  The next K tile is
+// prefetched into registers while the current one is consumed from LDS
+// (double-buffered), so one barrier per K tile suffices.
+//
+// LDS layouts follow the global layout of each operand so that both the
+// stores and the MFMA operand reads are free of bank conflicts:
+//  * an operand whose K index is contiguous in memory (A row-major, B
+//    transposed) is kept as [row][k] with a row stride of 17 doubles (34
+//    banks): the 16 lanes of an MFMA operand read hit 16 distinct bank pairs;
+//  * an operand whose M/N index is contiguous (A transposed, B row-major) is
+//    kept as [k][row] with a row stride of 144 doubles (a 32-bank shift
+//    between successive k rows, so the two half-waves read disjoint banks).
+// Tiles are ordered so that the M tiles sharing one B column tile run back to
+// back on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+constexpr int LBM = 128, LBN = 128, LBK = 16;
+constexpr int LKS = LBK + 1;     // [row][k] stride
+constexpr int LRS = 128 + 16;    // [k][row] stride
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_big_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda,
+    int64_t sA, const double* __restrict__ B, int64_t ldb, int64_t sB, double beta,
+    double* __restrict__ C, int64_t ldc, int64_t sC, int Klast) {
+  constexpr int ASZ = TA ? LBK * LRS : LBM * LKS;
+  constexpr int BSZ = TB ? LBN * LKS : LBK * LRS;
+  __shared__ double As[2][ASZ];
+  __shared__ double Bs[2][BSZ];
+  const int64_t bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy;
+  int bid = blockIdx.x + gx * blockIdx.y;
+  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int tm = bid % gy, tn = bid / gy;
+  const int m0 = tm * LBM, n0 = tn * LBN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // Per-thread load pattern (8 elements of each operand per K tile):
+  //  K-contiguous operand : row = (tid >> 4) + 16 r, k = tid & 15
+  //  row-contiguous operand: k = (tid >> 7) + 2 r,   row = tid & 127
+  const int a_row0 = TA ? (tid & 127) : (tid >> 4);
+  const int a_k0 = TA ? (tid >> 7) : (tid & 15);
+  const int b_row0 = TB ? (tid >> 4) : (tid & 127);
+  const int b_k0 = TB ? (tid & 15) : (tid >> 7);
+  const double* pa = TA ? A + (int64_t)a_k0 * lda + (m0 + a_row0) : A + (int64_t)(m0 + a_row0) * lda + a_k0;
+  const double* pb = TB ? B + (int64_t)(n0 + b_row0) * ldb + b_k0 : B + (int64_t)b_k0 * ldb + (n0 + b_row0);
+  const int64_t a_rstep = TA ? 2 * lda : 16 * lda;   // pointer step between r
+  const int64_t b_rstep = TB ? 16 * ldb : 2 * ldb;
+  const int64_t a_kstep = TA ? (int64_t)LBK * lda : LBK;   // step per K tile
+  const int64_t b_kstep = TB ? LBK : (int64_t)LBK * ldb;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  double ra[8], rb[8];
+  auto gload = [&](int t) {
+    const int kb = t * LBK;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int row = TA ? a_row0 : a_row0 + 16 * r;
+      const int k = TA ? a_k0 + 2 * r : a_k0;
+      const bool ok = (m0 + row < M) && (kb + k < K);
+      ra[r] = ok ? pa[t * a_kstep + r * a_rstep] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int row = TB ? b_row0 + 16 * r : b_row0;
+      const int k = TB ? b_k0 : b_k0 + 2 * r;
+      const bool ok = (n0 + row < N) && (kb + k < K);
+      rb[r] = ok ? pb[t * b_kstep + r * b_rstep] : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (TA) As[buf][(a_k0 + 2 * r) * LRS + a_row0] = ra[r];
+      else As[buf][(a_row0 + 16 * r) * LKS + a_k0] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (TB) Bs[buf][(b_row0 + 16 * r) * LKS + b_k0] = rb[r];
+      else Bs[buf][(b_k0 + 2 * r) * LRS + b_row0] = rb[r];
+    }
+  };
+  const int nk = (K + LBK - 1) / LBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) gload(t + 1);
+    const double* as = As[cur];
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int kk = 0; kk < LBK; kk += 4) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 64 + i * 16 + lr, k = kk + lk;
+        a[i] = TA ? as[k * LRS + row] : as[row * LKS + k];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wn * 64 + j * 16 + lr, k = kk + lk;
+        bb[j] = TB ? bs[row * LKS + k] : bs[k * LRS + row];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * 64 + i * 16 + lk + 4 * v;
+        const int gn = n0 + wn * 64 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          double* c = C + (int64_t)gm * ldc + gn;
+          const double r = alpha * acc[i][j][v];
+          *c = (beta == 0.0) ? r : r + beta * (*c);
+        }
+      }
+}
+
 int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,
-             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC) {
+             int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (K <= 0) {  // C = beta C
     return -1;
@@ -110,21 +250,35 @@ int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, do
     for (int b0 = 0; b0 < batch; b0 += 32768) {
       const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
       int rc = gemm_f64(s, ta, tb, M, N, K, nb, alpha, A + (int64_t)b0 * sA, lda, sA,
-                        B + (int64_t)b0 * sB, ldb, sB, beta, C + (int64_t)b0 * sC, ldc, sC);
+                        B + (int64_t)b0 * sB, ldb, sB, beta, C + (int64_t)b0 * sC, ldc, sC,
+                        b0 + nb == batch ? Klast : 0);
       if (rc) return rc;
     }
     return 0;
   }
+  if (M >= LBM && N >= LBN) {
+    dim3 grid((N + LBN - 1) / LBN, (M + LBM - 1) / LBM, batch);
+    dim3 block(256);
+    if (!ta && !tb)
+      hipLaunchKernelGGL((gemm_f64_big_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
+    else if (!ta && tb)
+      hipLaunchKernelGGL((gemm_f64_big_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
+    else if (ta && !tb)
+      hipLaunchKernelGGL((gemm_f64_big_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
+    else
+      hipLaunchKernelGGL((gemm_f64_big_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
   dim3 block(256);
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
   else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
   else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -31,6 +31,13 @@ CONTRACTIONS = [
     ("iiaa,ia->ia", [(3, 3, 5, 5), (3, 5)], (3, 5)),                          # diagonal + batch
     ("zik,zkj->zij", [(5, 33, 17), (5, 17, 70)], (5, 33, 70)),               # explicit batch
     ("ak,kx->ax", [(70, 4100), (4100, 3)], (70, 3)),                         # long K, split
+    ("ik,kj->ij", [(300, 70), (70, 260)], (300, 260)),                       # 128-tile, ragged
+    ("ki,kj->ij", [(70, 300), (70, 260)], (300, 260)),                       # 128-tile, A^T
+    ("ik,jk->ij", [(300, 70), (260, 70)], (300, 260)),                       # 128-tile, B^T
+    ("ki,jk->ij", [(70, 300), (260, 70)], (300, 260)),                       # 128-tile, both
+    ("zik,zkj->zij", [(3, 130, 41), (3, 41, 140)], (3, 130, 140)),           # 128-tile, batch
+    ("ijcd,cdab->ijab", [(4, 33, 13, 11), (13, 11, 12, 15)], (4, 33, 12, 15)),  # ladder, 128-tile
+    ("ik,kj->ij", [(256, 64), (64, 1024)], (256, 1024)),                     # 8-divisible grid
 ]
 
 
