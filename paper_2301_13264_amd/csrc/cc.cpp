@@ -64,6 +64,7 @@ struct cc_ctx {
   std::unique_ptr<nm::Engine> eng;
   std::vector<void*> owned;
   nm::Tensor eps, f, g, I;
+  nm::Tensor W, Wov;   // W[c][d][a][b] = (ac|bd), Wov[c][d][k][b] = (kc|bd)
   std::vector<double> eps_h;
   double* t = nullptr;
   bool have_guess = false;
@@ -146,71 +147,112 @@ static void axpby_(Ctx& c, double* y, const double* x, double a, double b, int64
 
 // ------------------------------------------------------------ residual graph
 struct ResNodes {
-  int t1, t2, f, g;
+  int t1, t2, f, g, w, wov;
   int om1, om2;
   int first;  // first non-leaf node of the residual
 };
 
-// Omega(t; f, g) of closed-shell CCSD in the T1-transformed form:
-// ghat = (X (x) Y (x) X (x) Y) g with X = 1 - t~, Y = 1 + t~^T (t~[a,i] = t_ai),
-// Fhat = X (f + sum_kc t_kc (2 g_pqkc - g_pckq)) Y^T; singles and doubles
-// projections as in the oracle's residual.
+// Omega(t; f, g) of closed-shell CCSD in the T1-transformed form.  The
+// transformed integrals are ghat = (X (x) Y (x) X (x) Y) g with X = 1 - t~ on
+// creator indices (1, 3) and Y = 1 + t~^T on annihilator indices (2, 4),
+// t~[a,i] = t_ai.  X is the identity on occupied creators and Y on virtual
+// annihilators, so each block of ghat only needs the transforms of its
+// virtual creators and occupied annihilators.  They are applied annihilators
+// first (shrinking an n-range to o) and only for the blocks the equations
+// use:
+//   Go  = Y_2 g            [n][o][n][n]
+//   Goo = Y_4 Go           [n][o][n][o]
+//   Gvo = Y_4 g[:,V,:,:]   [n][v][n][o]
+// then X_1 / X_3 on the virtual creators of each block.  The vvvv block only
+// enters the particle-particle ladder; that term is evaluated on the bare
+// integrals W[cd][ab] = (ac|bd) with the creator transforms written out:
+//   sum_cd t_ij^cd ghat_acbd = sum_cd t_ij^cd g_acbd - sum_k t_ak Y1_ijkb
+//       - sum_l t_bl Y1_jila + sum_kl t_ak t_bl Z_ijkl,
+//   Y1_ijkb = sum_cd t_ij^cd g_kcbd,  Z_ijkl = sum_cd t_ij^cd g_kcld,
+// so that derivatives of the residual contain one ladder GEMM, not two.
+// The transformed Fock matrix is Fhat = X (f + 2 J(t1) - K(t1)) Y^T with
+// J(t1)_pq = sum_k Go[k,k,p,q] - J_pq and K(t1)_pq = sum_k Go[p,k,k,q] - K_pq.
+// The singles and doubles projections are those of the oracle's residual.
 static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2,
-                               const Tensor& F, const Tensor& Gi) {
+                               const Tensor& F, const Tensor& Gi, const Tensor& Wt,
+                               const Tensor& Wov) {
   const int64_t o = c.o, v = c.v, n = c.n;
-  const Range O{0, o}, V{o, v}, A{0, n};
+  const Range O{0, o}, V{o, v}, A{0, n}, Vl{0, v};
   ResNodes r;
   r.t1 = G.leaf(T1);
   r.t2 = G.leaf(T2);
   r.f = G.leaf(F);
   r.g = G.leaf(Gi);
+  r.w = G.leaf(Wt);
+  r.wov = G.leaf(Wov);
   r.first = G.size();
   const int t1 = r.t1, t2 = r.t2, f = r.f, g = r.g;
-  // one-index T1 transformations of g (creators: X, annihilators: Y)
-  const int g1 = G.node({n, n, n, n}, {lin(1, op(g, "pqrs"), "pqrs"),
-                                       mul(-1, op(t1, "ka"), op(g, "kqrs", {O, A, A, A}), "aqrs", {V, A, A, A})});
-  const int g2 = G.node({n, n, n, n}, {lin(1, op(g1, "pqrs"), "pqrs"),
-                                       mul(1, op(t1, "qc"), op(g1, "pcrs", {A, V, A, A}), "pqrs", {A, O, A, A})});
-  const int g3 = G.node({n, n, n, n}, {lin(1, op(g2, "pqrs"), "pqrs"),
-                                       mul(-1, op(t1, "ka"), op(g2, "pqks", {A, A, O, A}), "pqas", {A, A, V, A})});
-  const int gg = G.node({n, n, n, n}, {lin(1, op(g3, "pqrs"), "pqrs"),
-                                       mul(1, op(g3, "pqrc", {A, A, A, V}), op(t1, "sc"), "pqrs", {A, A, A, O})});
+  // annihilator transforms
+  const int Go = G.node({n, o, n, n}, {lin(1, op(g, "pirs", {A, O, A, A}), "pirs"),
+                                       mul(1, op(t1, "ic"), op(g, "pcrs", {A, V, A, A}), "pirs")});
+  const int Goo = G.node({n, o, n, o}, {lin(1, op(Go, "pirj", {A, O, A, O}), "pirj"),
+                                        mul(1, op(Go, "pirc", {A, O, A, V}), op(t1, "jc"), "pirj")});
+  const int Gvo = G.node({n, v, n, o}, {lin(1, op(g, "pbrj", {A, V, A, O}), "pbrj"),
+                                        mul(1, op(g, "pbrc", {A, V, A, V}), op(t1, "jc"), "pbrj")});
+  // creator transforms of the blocks used below
+  const int Hv = G.node({v, o, n, o}, {lin(1, op(Goo, "airj", {V, O, A, O}), "airj"),
+                                       mul(-1, op(t1, "ka"), op(Goo, "kirj", {O, O, A, O}), "airj")});
+  const int gvovo = G.node({v, o, v, o}, {lin(1, op(Hv, "aibj", {Vl, O, V, O}), "aibj"),
+                                          mul(-1, op(Hv, "aikj", {Vl, O, O, O}), op(t1, "kb"), "aibj")});
+  const int goovv = G.node({o, o, v, v}, {lin(1, op(Go, "kiac", {O, O, V, V}), "kiac"),
+                                          mul(-1, op(Go, "kilc", {O, O, O, V}), op(t1, "la"), "kiac")});
+  const int gvoov = G.node({v, o, o, v}, {lin(1, op(Go, "aikc", {V, O, O, V}), "aikc"),
+                                          mul(-1, op(t1, "la"), op(Go, "likc", {O, O, O, V}), "aikc")});
+  const int gvvov = G.node({v, v, o, v}, {lin(1, op(g, "adkc", {V, V, O, V}), "adkc"),
+                                          mul(-1, op(t1, "la"), op(g, "ldkc", {O, V, O, V}), "adkc")});
+  const int gvvoo = G.node({v, v, o, o}, {lin(1, op(Gvo, "acki", {V, Vl, O, O}), "acki"),
+                                          mul(-1, op(t1, "la"), op(Gvo, "lcki", {O, Vl, O, O}), "acki")});
+  const Op g_ovov = op(g, "kcld", {O, V, O, V});
   // transformed Fock matrix
   const int fp = G.node({n, n}, {lin(1, op(f, "pq"), "pq"),
-                                 mul(2, op(g, "pqkc", {A, A, O, V}), op(t1, "kc"), "pq"),
-                                 mul(-1, op(g, "pckq", {A, V, O, A}), op(t1, "kc"), "pq")});
+                                 lin(2, op(Go, "kkpq", {O, O, A, A}), "pq"),
+                                 lin(-2, op(g, "kkpq", {O, O, A, A}), "pq"),
+                                 lin(-1, op(Go, "pkkq", {A, O, O, A}), "pq"),
+                                 lin(1, op(g, "pkkq", {A, O, O, A}), "pq")});
   const int f1 = G.node({n, n}, {lin(1, op(fp, "pq"), "pq"),
                                  mul(-1, op(t1, "ka"), op(fp, "kq", {O, A}), "aq", {V, A})});
   const int Fh = G.node({n, n}, {lin(1, op(f1, "pq"), "pq"),
                                  mul(1, op(f1, "pc", {A, V}), op(t1, "qc"), "pq", {A, O})});
   const int u = G.node({o, o, v, v}, {lin(2, op(t2, "ijab"), "ijab"), lin(-1, op(t2, "ijba"), "ijab")});
   // singles
-  r.om1 = G.node({o, v}, {mul(1, op(u, "kicd"), op(gg, "adkc", {V, V, O, V}), "ia"),
-                          mul(-1, op(u, "klac"), op(gg, "kilc", {O, O, O, V}), "ia"),
+  r.om1 = G.node({o, v}, {mul(1, op(u, "kicd"), op(gvvov, "adkc"), "ia"),
+                          mul(-1, op(u, "klac"), op(Go, "kilc", {O, O, O, V}), "ia"),
                           mul(1, op(u, "ikac"), op(Fh, "kc", {O, V}), "ia"),
                           lin(1, op(Fh, "ai", {V, O}), "ia")});
+  // ladder pieces on bare integrals
+  const int Y1 = G.node({o, o, o, v}, {mul(1, op(t2, "ijcd"), op(r.wov, "cdkb"), "ijkb")});
+  const int Z = G.node({o, o, o, o}, {mul(1, op(t2, "ijcd"), g_ovov, "ijkl")});
+  const int Zt = G.node({o, o, v, o}, {mul(1, op(t1, "ka"), op(Z, "ijkl"), "ijal")});
   // doubles
-  const int W = G.node({o, o, o, o}, {lin(1, op(gg, "kilj", {O, O, O, O}), "kilj"),
-                                      mul(1, op(t2, "ijcd"), op(gg, "kcld", {O, V, O, V}), "kilj")});
-  const int Xc = G.node({o, o, v, v}, {lin(1, op(gg, "kiac", {O, O, V, V}), "kiac"),
-                                       mul(-0.5, op(t2, "liad"), op(gg, "kdlc", {O, V, O, V}), "kiac")});
-  const int Lvoov = G.node({v, o, o, v}, {lin(2, op(gg, "aikc", {V, O, O, V}), "aikc"),
-                                          lin(-1, op(gg, "acki", {V, V, O, O}), "aikc")});
-  const int Lovov = G.node({o, v, o, v}, {lin(2, op(gg, "ldkc", {O, V, O, V}), "ldkc"),
-                                          lin(-1, op(gg, "lckd", {O, V, O, V}), "ldkc")});
+  const int W = G.node({o, o, o, o}, {lin(1, op(Goo, "kilj", {O, O, O, O}), "kilj"),
+                                      mul(1, op(t2, "ijcd"), g_ovov, "kilj")});
+  const int Xc = G.node({o, o, v, v}, {lin(1, op(goovv, "kiac"), "kiac"),
+                                       mul(-0.5, op(t2, "liad"), op(g, "kdlc", {O, V, O, V}), "kiac")});
+  const int Lvoov = G.node({v, o, o, v}, {lin(2, op(gvoov, "aikc"), "aikc"),
+                                          lin(-1, op(gvvoo, "acki"), "aikc")});
+  const int Lovov = G.node({o, v, o, v}, {lin(2, op(g, "ldkc", {O, V, O, V}), "ldkc"),
+                                          lin(-1, op(g, "lckd", {O, V, O, V}), "ldkc")});
   const int Xd = G.node({v, o, o, v}, {lin(1, op(Lvoov, "aikc"), "aikc"),
                                        mul(0.5, op(u, "ilad"), op(Lovov, "ldkc"), "aikc")});
   const int Ev = G.node({v, v}, {lin(1, op(Fh, "bc", {V, V}), "bc"),
-                                 mul(-1, op(u, "klbd"), op(gg, "ldkc", {O, V, O, V}), "bc")});
+                                 mul(-1, op(u, "klbd"), op(g, "ldkc", {O, V, O, V}), "bc")});
   const int Eo = G.node({o, o}, {lin(1, op(Fh, "kj", {O, O}), "kj"),
-                                 mul(1, op(u, "ljcd"), op(gg, "kdlc", {O, V, O, V}), "kj")});
+                                 mul(1, op(u, "ljcd"), op(g, "kdlc", {O, V, O, V}), "kj")});
   const int P = G.node({o, o, v, v}, {mul(-0.5, op(t2, "kjbc"), op(Xc, "kiac"), "ijab"),
                                       mul(-1, op(t2, "kibc"), op(Xc, "kjac"), "ijab"),
                                       mul(0.5, op(u, "jkbc"), op(Xd, "aikc"), "ijab"),
                                       mul(1, op(t2, "ijac"), op(Ev, "bc"), "ijab"),
                                       mul(-1, op(t2, "ikab"), op(Eo, "kj"), "ijab")});
-  r.om2 = G.node({o, o, v, v}, {lin(1, op(gg, "aibj", {V, O, V, O}), "ijab"),
-                                mul(1, op(t2, "ijcd"), op(gg, "acbd", {V, V, V, V}), "ijab"),
+  r.om2 = G.node({o, o, v, v}, {mul(1, op(t2, "ijcd"), op(r.w, "cdab"), "ijab"),
+                                lin(1, op(gvovo, "aibj"), "ijab"),
+                                mul(-1, op(t1, "ka"), op(Y1, "ijkb"), "ijab"),
+                                mul(-1, op(Y1, "jila"), op(t1, "lb"), "ijab"),
+                                mul(1, op(Zt, "ijal"), op(t1, "lb"), "ijab"),
                                 mul(1, op(t2, "klab"), op(W, "kilj"), "ijab"),
                                 lin(1, op(P, "ijab"), "ijab"),
                                 lin(1, op(P, "jiba"), "ijab")});
@@ -245,7 +287,7 @@ static void residual(Ctx& c, double* x, double* out) {
   ++c.n_residual;
   ArenaScope sc(c.eng->arena());
   Graph G(*c.eng);
-  ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.g);
+  ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.g, c.W, c.Wov);
   const int64_t nov = (int64_t)c.o * c.v;
   copy_d(c, out, G.val(r.om1).p, nov);
   copy_d(c, out + nov, G.val(r.om2).p, c.N - nov);
@@ -278,7 +320,7 @@ struct Tape {
   Graph G;
   ResNodes r;
   explicit Tape(Ctx& cc) : c(cc), base(cc.eng->arena().mark()), G(*cc.eng) {
-    r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g);
+    r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g, c.W, c.Wov);
   }
   ~Tape() { c.eng->arena().rewind(base); }
 
@@ -847,10 +889,16 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
       ArenaScope s2(ar);
       auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}, {tp.r.om1, wz}, {tp.r.om2, wz + nov}},
-                          {tp.r.f, tp.r.g});
+                          {tp.r.f, tp.r.g, tp.r.w, tp.r.wov});
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
       if (!P.Gbar) P.Gbar = palloc(c, n4(c));
       copy_d(c, P.Gbar, adj[tp.r.g].p, n4(c));
+      // the ladder's integral copies are blocks of g: fold their adjoints back
+      Graph Gd(*c.eng);
+      const int gb = Gd.leaf(tview(P.Gbar, {c.n, c.n, c.n, c.n}));
+      const Range O{0, c.o}, V{c.o, c.v};
+      c.eng->linear(1.0, full_view(adj[tp.r.w], "cdab"), Gd.view(op(gb, "acbd", {V, V, V, V})));
+      c.eng->linear(1.0, full_view(adj[tp.r.wov], "cdkb"), Gd.view(op(gb, "kcbd", {O, V, V, V})));
     }
   }
   if (c.opts.relaxed) {
@@ -1067,6 +1115,22 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
     nm::kc(nm::gemm_f64(c->s, true, false, (int)nn, (int)nn, naux, 1, 1.0, B, nn, 0, B, nn, 0, 0.0, c->g.p,
                         nn, 0),
            "eri build");
+    {
+      // GEMM-ready copies of the all-virtual and one-occupied blocks
+      const int64_t vv = (int64_t)v * v;
+      c->W = nm::tview(nm::palloc(*c, vv * vv), {v, v, v, v});
+      c->Wov = nm::tview(nm::palloc(*c, vv * v * o), {v, v, o, v});
+      nm::Graph G(*c->eng);
+      const int gl = G.leaf(c->g);
+      const nm::Range Oo{0, o}, Vv{o, v};
+      nm::DView src = nm::full_view(c->g, "acbd");
+      (void)src;
+      nm::Term tw = nm::lin(1, nm::op(gl, "acbd", {Vv, Vv, Vv, Vv}), "cdab");
+      nm::Term to = nm::lin(1, nm::op(gl, "kcbd", {Oo, Vv, Vv, Vv}), "cdkb");
+      const int iw = G.leaf(c->W), io = G.leaf(c->Wov);
+      c->eng->linear(1.0, G.view(tw.a), nm::full_view(G.val(iw), "cdab"), true);
+      c->eng->linear(1.0, G.view(to.a), nm::full_view(G.val(io), "cdkb"), true);
+    }
     c->t = nm::palloc(*c, c->N);
     nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
     nm::sync(*c);

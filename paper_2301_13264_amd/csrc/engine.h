@@ -144,6 +144,8 @@ class Graph {
   // when the arena is rewound by the caller).
   void truncate(int n) { nodes_.resize(n); }
   Engine& engine() { return e_; }
+  // strided view of an operand (box + labels) of an existing node
+  DView view(const Op& o) const { return view_of(o, nodes_.at(o.node).val); }
 
  private:
   DView view_of(const Op& op, const Tensor& t) const;
