@@ -39,16 +39,34 @@ def log(msg):
 
 
 def run_step(nm, torch, inp, cfg, opts):
+    """One pass of the path; every library call ends with a stream sync, so the
+    host clock between calls gives the per-stage split."""
+    st = {}
+    t = time.perf_counter()
+
+    def lap(name):
+        nonlocal t
+        now = time.perf_counter()
+        st[name] = st.get(name, 0.0) + (now - t)
+        t = now
+
     ctx = nm.Context(cfg["o"], cfg["v"], cfg["naux"], inp["eps"], inp["B"], opts)
+    lap("integrals")
     e, it, rc0 = ctx.ground()
+    lap("ground")
     w, itw, rc1 = ctx.eom(nm.CC_BOTH, cfg["nroots"])
+    lap("eom")
     F = {}
     for (i, j) in [(1, 2), (2, 1)]:
         ctx.multipliers(i, j)
+        lap("multipliers")
         ctx.densities(i, j)
+        lap("densities")
         F[(i, j)] = ctx.nacme(i, j, inp["dh"], inp["dB"])
+        lap("nacme")
     torch.cuda.synchronize()
-    return ctx, dict(e_corr=e, omega=w, ground_iters=it, eom_iters=itw, F=F, rc=(rc0, rc1))
+    return ctx, dict(e_corr=e, omega=w, ground_iters=it, eom_iters=itw, F=F, rc=(rc0, rc1),
+                     stage_s=st)
 
 
 def main():
@@ -165,6 +183,7 @@ def main():
         config=dict(workload="thymine_dz: o=33 v=127 naux=640, 2 roots, 45 directions, "
                              f"DF scale {SIGMA_B:.5f}", global_batch=1, parallelism="none"),
         time_to_nacme_s=ms / 1000.0,
+        stage_s=out["stage_s"],
         omega=out["omega"], e_corr=out["e_corr"],
         jacobian_transforms_per_s=dict(right=1000.0 / tr["right"], left=1000.0 / tr["left"]),
         jacobian_transform_ms=tr,

@@ -78,6 +78,7 @@ struct cc_ctx {
   std::string err;
   bool sticky = false;
   int64_t n_right = 0, n_left = 0, n_residual = 0;
+  double* rows_part = nullptr;   // partial sums of multi-row dot products
 };
 
 namespace nm {
@@ -143,6 +144,51 @@ static double amax(Ctx& c, const double* x, int64_t n) {
 }
 static void axpby_(Ctx& c, double* y, const double* x, double a, double b, int64_t n) {
   kc(axpby(c.s, y, x, a, b, n), "axpby");
+}
+
+static DView mat_view(const double* p, int64_t rows, int64_t cols, const char* lab) {
+  DView v;
+  v.p = const_cast<double*>(p);
+  v.nd = 2;
+  v.dims[0] = rows; v.dims[1] = cols;
+  v.str[0] = cols; v.str[1] = 1;
+  v.lab[0] = lab[0]; v.lab[1] = lab[1];
+  return v;
+}
+static DView vec_view(const double* p, int64_t n, char lab) {
+  DView v;
+  v.p = const_cast<double*>(p);
+  v.nd = 1;
+  v.dims[0] = n;
+  v.str[0] = 1;
+  v.lab[0] = lab;
+  return v;
+}
+
+// h[k] = <V_k, x> for the m rows of V ([m][n] contiguous), in one GEMV and one
+// copy to the host; `packed` selects the biorthonormal metric on
+// amplitude-shaped vectors.  work: n + m doubles.
+static void dots_rows(Ctx& c, const double* V, int m, const double* x, int64_t n, bool packed,
+                      double* work, std::vector<double>& h) {
+  h.assign(m, 0.0);
+  if (m == 0) return;
+  const double* xx = x;
+  if (packed) {
+    kc(apply_metric(c.s, work, x, c.o, c.v, 0), "metric");
+    xx = work;
+  }
+  double* hd = work + n;
+  kc(rows_dot(c.s, V, m, n, xx, c.rows_part, hd), "rows_dot");
+  hip_check(hipMemcpyAsync(h.data(), hd, m * sizeof(double), hipMemcpyDeviceToHost, c.s), "D2H");
+  sync(c);
+}
+
+// x -= sum_k h[k] V_k (one GEMM); hd: m device doubles.
+static void sub_rows(Ctx& c, const double* V, int m, const std::vector<double>& h, double* x, int64_t n,
+                     double* hd) {
+  if (m == 0) return;
+  hip_check(hipMemcpyAsync(hd, h.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+  kc(rows_axpy(c.s, V, m, n, hd, -1.0, x), "rows_axpy");
 }
 
 // ------------------------------------------------------------ residual graph
@@ -447,20 +493,22 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   double* Rs = ar.alloc(N);
   double* ydev = ar.alloc((int64_t)nb * maxm);
   std::vector<double> G((size_t)maxm * maxm, 0.0);
+  double* work = ar.alloc(N + 2 * maxm);
+  double* hd = work + N + maxm;
+  std::vector<double> h;
   int m = 0;
 
   // add x (and optionally its image ax) to the subspace after biorthonormal
-  // Gram-Schmidt; returns false if x is (numerically) in the span.
+  // Gram-Schmidt (two passes, block GEMVs); false if x is in the span.
   auto add = [&](double* x, double* ax) -> bool {
     if (!ax) kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
     double n0 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
     if (!(n0 > 0)) return false;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int k = 0; k < m; ++k) {
-        const double h = dot_bio(c, V + (int64_t)k * N, x);
-        axpby_(c, x, V + (int64_t)k * N, -h, 1.0, N);
-        if (ax) axpby_(c, ax, W + (int64_t)k * N, -h, 1.0, N);
-      }
+    for (int pass = 0; pass < 2 && m > 0; ++pass) {
+      dots_rows(c, V, m, x, N, true, work, h);
+      sub_rows(c, V, m, h, x, N, hd);
+      if (ax) sub_rows(c, W, m, h, ax, N, hd);
+    }
     const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
     if (n1 < 1e-4 * n0 || n1 < 1e-14) return false;
     axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
@@ -469,10 +517,10 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     else
       T(V + (int64_t)m * N, W + (int64_t)m * N);
     ++m;
-    for (int k = 0; k < m; ++k) {
-      G[(size_t)k * maxm + (m - 1)] = dot_bio(c, V + (int64_t)k * N, W + (int64_t)(m - 1) * N);
-      G[(size_t)(m - 1) * maxm + k] = dot_bio(c, V + (int64_t)(m - 1) * N, W + (int64_t)k * N);
-    }
+    dots_rows(c, V, m, W + (int64_t)(m - 1) * N, N, true, work, h);
+    for (int k = 0; k < m; ++k) G[(size_t)k * maxm + (m - 1)] = h[k];
+    dots_rows(c, W, m, V + (int64_t)(m - 1) * N, N, true, work, h);
+    for (int k = 0; k < m; ++k) G[(size_t)(m - 1) * maxm + k] = h[k];
     return true;
   };
 
@@ -738,7 +786,9 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   auto dotf = [&](const double* p, const double* q) {
     return packed ? dot_bio(c, p, q) : dot_plain(c, p, q, n);
   };
-  std::vector<double> G((size_t)maxm * maxm), bv(maxm);
+  std::vector<double> G((size_t)maxm * maxm), bv(maxm), h;
+  double* work = ar.alloc(n + 2 * maxm);
+  double* hd = work + n + maxm;
   int m = 0;
   precond(r, b);
   int status = CC_NOT_CONVERGED;
@@ -747,20 +797,19 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   for (it = 1; it <= maxit && m < maxm; ++it) {
     if (packed) kc(apply_metric(c.s, r, r, c.o, c.v, 2), "symmetrise");
     const double n0 = std::sqrt(std::max(0.0, dotf(r, r)));
-    for (int pass = 0; pass < 2; ++pass)
-      for (int k = 0; k < m; ++k) {
-        const double h = dotf(V + (int64_t)k * n, r);
-        axpby_(c, r, V + (int64_t)k * n, -h, 1.0, n);
-      }
+    for (int pass = 0; pass < 2 && m > 0; ++pass) {
+      dots_rows(c, V, m, r, n, packed, work, h);
+      sub_rows(c, V, m, h, r, n, hd);
+    }
     const double n1 = std::sqrt(std::max(0.0, dotf(r, r)));
     if (!(n1 > 1e-14 * std::max(n0, 1e-300))) break;
     axpby_(c, V + (int64_t)m * n, r, 1.0 / n1, 0.0, n);
     T(V + (int64_t)m * n, W + (int64_t)m * n);
     ++m;
-    for (int k = 0; k < m; ++k) {
-      G[(size_t)k * maxm + m - 1] = dotf(V + (int64_t)k * n, W + (int64_t)(m - 1) * n);
-      G[(size_t)(m - 1) * maxm + k] = dotf(V + (int64_t)(m - 1) * n, W + (int64_t)k * n);
-    }
+    dots_rows(c, V, m, W + (int64_t)(m - 1) * n, n, packed, work, h);
+    for (int k = 0; k < m; ++k) G[(size_t)k * maxm + m - 1] = h[k];
+    dots_rows(c, W, m, V + (int64_t)(m - 1) * n, n, packed, work, h);
+    for (int k = 0; k < m; ++k) G[(size_t)(m - 1) * maxm + k] = h[k];
     bv[m - 1] = dotf(V + (int64_t)(m - 1) * n, b);
     std::vector<double> Gm((size_t)m * m), cvec(bv.begin(), bv.begin() + m);
     for (int a = 0; a < m; ++a)
@@ -1133,6 +1182,7 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
     }
     c->t = nm::palloc(*c, c->N);
     nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
+    c->rows_part = nm::palloc(*c, nm::rows_scratch_doubles());
     nm::sync(*c);
     *out = c;
     return CC_OK;

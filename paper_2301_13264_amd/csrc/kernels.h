@@ -6,6 +6,7 @@
 namespace nm {
 
 constexpr int kMaxViewDims = 6;
+constexpr int kMaxRows = 128;   // subspace rows handled by rows_dot / rows_axpy
 
 // A strided map between an output box and an input tensor:
 // out[obase + sum_d i_d ostr_d]  <->  in[ibase + sum_d i_d istr_d + sum_r j_r rstr_r]
@@ -36,5 +37,10 @@ int dot(hipStream_t s, const double* x, const double* y, int64_t n, int o, int v
         double* scratch, double* out_dev);
 int absmax(hipStream_t s, const double* x, int64_t n, double* scratch, double* out_dev);
 int reduce_scratch_doubles();
+int rows_dot(hipStream_t s, const double* V, int m, int64_t n, const double* x, double* part,
+             double* out);
+int rows_scratch_doubles();
+int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h, double alpha,
+              double* x);
 
 }  // namespace nm

@@ -568,4 +568,89 @@ int absmax(hipStream_t s, const double* x, int64_t n, double* scratch, double* o
 
 int reduce_scratch_doubles() { return kReduceBlocks; }
 
+// ------------------------------------------------------- multi-row vectors
+// out[k] = sum_e V[k][e] x[e] for the m <= kMaxRows rows of V (row-major,
+// row stride n).  Every block covers a contiguous chunk of e, reads x once and
+// keeps m partial sums per thread; partials [block][k] are folded in a fixed
+// order by a second kernel (deterministic).
+constexpr int kRowBlocks = 512;
+
+constexpr int kRowGroup = 8;   // rows accumulated in registers at a time
+
+__global__ __launch_bounds__(256) void rows_dot_partial_kernel(const double* __restrict__ V,
+                                                               int m, int64_t n,
+                                                               const double* __restrict__ x,
+                                                               double* part) {
+  __shared__ double red[4][kRowGroup];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = blockIdx.x * chunk;
+  const int64_t e1 = e0 + chunk < n ? e0 + chunk : n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int g0 = 0; g0 < m; g0 += kRowGroup) {
+    double acc[kRowGroup];
+#pragma unroll
+    for (int k = 0; k < kRowGroup; ++k) acc[k] = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const double xe = x[e];
+#pragma unroll
+      for (int k = 0; k < kRowGroup; ++k)
+        if (g0 + k < m) acc[k] += V[(int64_t)(g0 + k) * n + e] * xe;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowGroup; ++k) {
+      double a = acc[k];
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+      if (lane == 0) red[wid][k] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRowGroup && g0 + threadIdx.x < m) {
+      const int k = threadIdx.x;
+      part[(int64_t)blockIdx.x * kMaxRows + g0 + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void rows_fold_kernel(const double* part, int nb, int m, double* out) {
+  const int k = threadIdx.x;
+  if (k >= m) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * kMaxRows + k];
+  out[k] = acc;
+}
+
+int rows_dot(hipStream_t s, const double* V, int m, int64_t n, const double* x, double* part,
+             double* out) {
+  if (m <= 0) return 0;
+  if (m > kMaxRows) return -1;
+  hipLaunchKernelGGL(rows_dot_partial_kernel, dim3(kRowBlocks), dim3(256), 0, s, V, m, n, x, part);
+  hipLaunchKernelGGL(rows_fold_kernel, dim3(1), dim3(kMaxRows), 0, s, part, kRowBlocks, m, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int rows_scratch_doubles() { return kRowBlocks * kMaxRows; }
+
+// x[e] += alpha * sum_k h[k] V[k][e]   (h on the device)
+__global__ __launch_bounds__(256) void rows_axpy_kernel(const double* __restrict__ V, int m,
+                                                        int64_t n, const double* __restrict__ h,
+                                                        double alpha, double* __restrict__ x) {
+  __shared__ double hs[kMaxRows];
+  if (threadIdx.x < m) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += hs[k] * V[(int64_t)k * n + e];
+    x[e] += alpha * acc;
+  }
+}
+
+int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h, double alpha,
+              double* x) {
+  if (m <= 0) return 0;
+  if (m > kMaxRows) return -1;
+  hipLaunchKernelGGL(rows_axpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, V, m, n, h, alpha, x);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 }  // namespace nm
