@@ -66,7 +66,10 @@ extern "C" {
 #define CC_LEFT 2
 #define CC_BOTH 3
 
-#define CC_FP64 0
+#define CC_FP64 0          /* every contraction in fp64                          */
+#define CC_FP32_REFINE 1   /* large contractions with fp32 operands on the FP32
+                              matrix cores inside the solvers, fp64 residuals
+                              and fp64 final iterations (iterative refinement) */
 
 /* Export / guess selectors. */
 #define CC_T 1        /* ground amplitudes (amplitude-shaped)                 */
@@ -83,7 +86,7 @@ extern "C" {
 typedef struct cc_ctx cc_ctx;
 
 typedef struct {
-  int precision;       /* CC_FP64                                              */
+  int precision;       /* CC_FP64 or CC_FP32_REFINE                            */
   int relaxed;         /* 1: orbital-relaxed (kappa-bar solved), 0: fixed      */
                        /*    reference (kappa-bar = 0)                         */
   double tol_ground;   /* max |Omega_mu| of the ground state                   */
@@ -93,10 +96,12 @@ typedef struct {
   int diis_dim;        /* DIIS history of the ground-state solver              */
   int davidson_block;  /* extra trial vectors beyond nroots                    */
   int davidson_max;    /* subspace size before a restart                       */
+  double mixed_min_flops; /* CC_FP32_REFINE: contractions with fewer flops     */
+                          /* stay fp64 (default 1e9)                           */
 } cc_opts;
 
 /* Defaults: FP64, relaxed, tolerances 1e-10 / 1e-9 / 1e-9, maxit 200,
- * diis_dim 8, davidson_block 2, davidson_max 48.                               */
+ * diis_dim 8, davidson_block 2, davidson_max 48, mixed_min_flops 1e9.          */
 void cc_default_opts(cc_opts* opts);
 
 /* Creates a context.  eps[n]: canonical orbital energies (device); B[naux][n][n]
@@ -157,10 +162,20 @@ void cc_destroy(cc_ctx* ctx);
 
 /* Engine surface.  C = alpha * einsum(spec)(A, B) + beta * C on device
  * arrays; spec "ab,bc->ac" (lowercase letters, <= 6 per operand, repeated
- * letters inside one operand select a diagonal).  dims* give the shapes.    */
+ * letters inside one operand select a diagonal).  dims* give the shapes.
+ * precision: CC_FP64, or CC_FP32_REFINE to run the contraction with fp32
+ * operands (fp32 accumulation, fp64 result) whatever its size.              */
 int nm_contract(const char* spec, double alpha, const double* A, const int64_t* dimsA,
                 const double* B, const int64_t* dimsB, double beta, double* C,
-                const int64_t* dimsC, void* stream);
+                const int64_t* dimsC, int precision, void* stream);
+/* Kernel surface: one launch of the matrix-core GEMM used by the engine,
+ * C[M][N] = alpha op(A) op(B) + beta C (row-major, leading dimensions lda,
+ * ldb, ldc; ta / tb select A stored [K][M] / B stored [N][K]).  precision
+ * CC_FP64: A, B double; CC_FP32_REFINE: A, B float (fp32 accumulation).
+ * Asynchronous on `stream`.                                                 */
+int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
+            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,
+            void* stream);
 /* Host-only: eigen-decomposition of a real m x m row-major matrix used for
  * Davidson subspaces; wr, wi [m]; V [m][m] real parts of unit eigenvectors
  * (row k = vector k, phase chosen so its largest component is real).       */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnacme.so")
 
 CC_OK, CC_NOT_CONVERGED = 0, 1
 CC_RIGHT, CC_LEFT, CC_BOTH = 1, 2, 3
-CC_FP64 = 0
+CC_FP64, CC_FP32_REFINE = 0, 1
 CC_T, CC_R, CC_L, CC_R0, CC_ZETA, CC_KAPPA, CC_D1, CC_ETA_T, CC_ETA_K, CC_DTRANS = range(1, 11)
 
 ERRORS = {-1: "argument", -2: "call order", -3: "HIP", -4: "out of memory",
@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
                 ("tol_ground", ctypes.c_double), ("tol_eom", ctypes.c_double),
                 ("tol_mult", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("diis_dim", ctypes.c_int), ("davidson_block", ctypes.c_int),
-                ("davidson_max", ctypes.c_int)]
+                ("davidson_max", ctypes.c_int), ("mixed_min_flops", ctypes.c_double)]
 
 
 _lib = None
@@ -63,10 +63,13 @@ def lib():
         L.cc_last_error.restype = ctypes.c_char_p
         L.cc_destroy.argtypes = [P]
         L.cc_destroy.restype = None
-        L.nm_contract.argtypes = [ctypes.c_char_p, D, P, L64, P, L64, D, P, L64, P]
+        L.nm_contract.argtypes = [ctypes.c_char_p, D, P, L64, P, L64, D, P, L64, I, P]
         L.nm_eig_host.argtypes = [I, PD, PD, PD, PD]
         L.nm_version.restype = ctypes.c_char_p
         L.cc_stats.argtypes = [P, PD, I]
+        L.nm_gemm.argtypes = [I, I, I, I, I, I, D, P, ctypes.c_int64, P, ctypes.c_int64, D, P,
+                              ctypes.c_int64, P]
+        L.nm_gemm.restype = ctypes.c_int
         L.cc_stats.restype = ctypes.c_int
         for name in ("cc_create", "cc_ground", "eom_solve", "multipliers", "densities", "nacme",
                      "cc_apply_jacobian", "cc_residual", "cc_export", "cc_set_guess",
@@ -79,7 +82,7 @@ def lib():
 EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multipliers",
             "densities", "nacme", "cc_apply_jacobian", "cc_residual", "cc_export",
             "cc_set_guess", "cc_last_error", "cc_destroy", "nm_contract", "nm_eig_host",
-            "nm_version", "cc_stats"]
+            "nm_version", "cc_stats", "nm_gemm"]
 
 
 def default_opts(**kw) -> Opts:
@@ -184,12 +187,31 @@ class Context:
         self._check(lib().cc_set_guess(self._h, what, idx, _ptr(src)))
 
 
-def contract(spec: str, alpha, A, B, beta, C, stream=None):
+def contract(spec: str, alpha, A, B, beta, C, stream=None, precision=0):
     dims = lambda t: (ctypes.c_int64 * max(t.dim(), 1))(*t.shape)  # noqa: E731
     rc = lib().nm_contract(spec.encode(), alpha, _ptr(A), dims(A), _ptr(B), dims(B), beta,
-                           _ptr(C), dims(C), _stream_ptr(stream))
+                           _ptr(C), dims(C), precision, _stream_ptr(stream))
     if rc != CC_OK:
         raise CCError(rc, f"nm_contract({spec})")
+    return C
+
+
+def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None):
+    """One matrix-core GEMM launch C = alpha A B + beta C (2-D row-major
+    device tensors; A, B float64 for precision 0, float32 for precision 1)."""
+    import torch
+    want = torch.float64 if precision == 0 else torch.float32
+    for t in (A, B):
+        if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+            raise ValueError("bad GEMM operand")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise ValueError("GEMM shape mismatch")
+    rc = lib().nm_gemm(precision, 0, 0, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), K,
+                       ctypes.c_void_p(B.data_ptr()), N, beta, _ptr(C), N, _stream_ptr(stream))
+    if rc != CC_OK:
+        raise CCError(rc, "nm_gemm")
     return C
 
 

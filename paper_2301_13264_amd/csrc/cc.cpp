@@ -121,6 +121,12 @@ struct ArenaScope {
   ~ArenaScope() { a.rewind(m); }
 };
 
+// Mixed precision: solvers run their operator applications with fp32
+// operands until the residual falls below kMixedSwitch, then finish with fp64
+// operators and fp64 residuals.
+constexpr double kMixedSwitch = 1e-5;
+static bool mixed(const Ctx& c) { return c.opts.precision == CC_FP32_REFINE; }
+
 static Tensor tview(double* p, std::vector<int64_t> shape) {
   Tensor t;
   t.p = p;
@@ -366,7 +372,12 @@ struct Tape {
   Graph G;
   ResNodes r;
   explicit Tape(Ctx& cc) : c(cc), base(cc.eng->arena().mark()), G(*cc.eng) {
+    // the recorded primal values are always fp64; only the derivative sweeps
+    // may run with fp32 operands
+    const bool lp = c.eng->lowp();
+    c.eng->set_lowp(false);
     r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g, c.W, c.Wov);
+    c.eng->set_lowp(lp);
   }
   ~Tape() { c.eng->arena().rewind(base); }
 
@@ -416,12 +427,20 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
   int it = 0;
   double err = 0.0;
   int status = CC_NOT_CONVERGED;
+  bool lowp = mixed(c);
+  c.eng->set_lowp(lowp);
   for (it = 1; it <= c.opts.maxit; ++it) {
     residual(c, c.t, r);
     err = amax(c, r, N);
     if (!std::isfinite(err)) throw Error(-5, "non-finite CCSD residual");
     if (verbose()) std::fprintf(stderr, "[ground] it %d max|Omega| %.3e\n", it, err);
-    if (err < c.opts.tol_ground) {
+    if (lowp && err < kMixedSwitch) {
+      // iterative refinement: the remaining iterations use fp64 residuals
+      lowp = false;
+      c.eng->set_lowp(false);
+      continue;
+    }
+    if (!lowp && err < c.opts.tol_ground) {
       status = CC_OK;
       break;
     }
@@ -461,6 +480,7 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
       }
     }
   }
+  c.eng->set_lowp(false);
   if (it > c.opts.maxit) it = c.opts.maxit;
   c.ecorr = energy(c, c.t);
   if (e_out) *e_out = c.ecorr;
@@ -497,6 +517,8 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   double* hd = work + N + maxm;
   std::vector<double> h;
   int m = 0;
+  bool lowp = mixed(c);
+  c.eng->set_lowp(lowp);
 
   // add x (and optionally its image ax) to the subspace after biorthonormal
   // Gram-Schmidt (two passes, block GEMVs); false if x is in the span.
@@ -593,6 +615,19 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       for (int k = 0; k < nk; ++k) std::fprintf(stderr, " w%d=%.12f r=%.2e", k, res.w[k], rn[k]);
       std::fprintf(stderr, "\n");
     }
+    if (lowp && (worst < kMixedSwitch || it == c.opts.maxit / 2)) {
+      // fp64 phase: restart from the Ritz vectors with fp64 images
+      lowp = false;
+      c.eng->set_lowp(false);
+      m = 0;
+      std::fill(G.begin(), G.end(), 0.0);
+      double* tmpx = ar.alloc(N);
+      for (int k = 0; k < nk; ++k) {
+        copy_d(c, tmpx, X + (int64_t)k * N, N);
+        add(tmpx, nullptr);
+      }
+      continue;
+    }
     if (worst < c.opts.tol_eom) {
       res.converged = true;
       break;
@@ -620,6 +655,8 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       if (m < maxm) add(Rs, nullptr);
     }
   }
+  c.eng->set_lowp(false);
+  if (lowp) res.converged = false;   // never accept a mixed-precision answer
   // normalise and hand out the nroots lowest Ritz vectors
   for (int k = 0; k < nroots; ++k) {
     const double xn = std::sqrt(dot_bio(c, X + (int64_t)k * N, X + (int64_t)k * N));
@@ -832,6 +869,53 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   return status;
 }
 
+// T(x) = b by iterative refinement when the context runs mixed precision:
+// r = b - T(x) with the fp64 operator, correction from T(d) = r solved with
+// fp32-operand operator applications to 1e-4 relative, x += d; repeat until
+// the fp64 residual meets tol.  Plain linsolve otherwise.
+static int linsolve_refined(Ctx& c, int64_t n, bool packed,
+                            const std::function<void(const double*, double*)>& T,
+                            const std::function<void(double*, const double*)>& precond,
+                            const double* b, double* x, double tol, int maxit, int* iters) {
+  if (!mixed(c)) {
+    c.eng->set_lowp(false);
+    return linsolve(c, n, packed, T, precond, b, x, tol, maxit, iters);
+  }
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  double* r = ar.alloc(n);
+  double* d = ar.alloc(n);
+  auto nrm = [&](const double* p) {
+    return std::sqrt(std::max(0.0, packed ? dot_bio(c, p, p) : dot_plain(c, p, p, n)));
+  };
+  const double bn = nrm(b);
+  kc(fill(c.s, x, 0.0, n), "fill");
+  copy_d(c, r, b, n);
+  int total = 0, status = CC_NOT_CONVERGED;
+  for (int outer = 0; outer < 12 && total < maxit; ++outer) {
+    if (outer > 0) {
+      c.eng->set_lowp(false);
+      T(x, r);                          // fp64 operator
+      axpby_(c, r, b, 1.0, -1.0, n);    // r = b - T x
+    }
+    const double rn = nrm(r);
+    if (verbose()) std::fprintf(stderr, "[refine] outer %d |r| %.3e\n", outer, rn);
+    if (!std::isfinite(rn)) throw Error(-5, "non-finite refinement residual");
+    if (rn < tol * std::max(1.0, bn)) {
+      status = CC_OK;
+      break;
+    }
+    c.eng->set_lowp(true);
+    int it = 0;
+    linsolve(c, n, packed, T, precond, r, d, 1e-4 * std::min(1.0, rn), maxit - total, &it);
+    total += it;
+    axpby_(c, x, d, 1.0, 1.0, n);
+  }
+  c.eng->set_lowp(false);
+  if (iters) *iters = total;
+  return status;
+}
+
 // ------------------------------------------------------ orbital rotation
 // Integrals of exp(kappa) H exp(-kappa) to first order in kappa (exact for
 // derivatives at kappa = 0): h + K h + h K^T, g + sum of one-index K
@@ -929,7 +1013,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       auto pre = [&](double* y, const double* x) {
         kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
       };
-      const int st = linsolve(c, N, true, T, pre, b, P.zeta, c.opts.tol_mult, c.opts.maxit, &it_z);
+      const int st = linsolve_refined(c, N, true, T, pre, b, P.zeta, c.opts.tol_mult, c.opts.maxit, &it_z);
       if (st != CC_OK) status = st;
     }
     // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j)
@@ -993,7 +1077,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       kc(apply_denominator(c.s, big, big, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
       copy_d(c, y, big, nov);
     };
-    const int st = linsolve(c, nov, false, T, pre1, b, P.kbar, c.opts.tol_mult, c.opts.maxit, &it_k);
+    const int st = linsolve_refined(c, nov, false, T, pre1, b, P.kbar, c.opts.tol_mult, c.opts.maxit, &it_k);
     if (st != CC_OK) status = st;
   } else {
     kc(fill(c.s, P.kbar, 0.0, nov), "fill");
@@ -1117,6 +1201,7 @@ void cc_default_opts(cc_opts* o) {
   o->diis_dim = 8;
   o->davidson_block = 2;
   o->davidson_max = 48;
+  o->mixed_min_flops = 1e9;
 }
 
 const char* nm_version(void) { return "nacme-mi355x 0.1 (gfx950, fp64)"; }
@@ -1134,9 +1219,11 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
     const int64_t nov = (int64_t)o * v;
     c->N = nov + nov * nov;
     if (opts) c->opts = *opts; else cc_default_opts(&c->opts);
-    if (c->opts.precision != CC_FP64) throw Error(CC_ERR_ARG, "only CC_FP64 is available");
+    if (c->opts.precision != CC_FP64 && c->opts.precision != CC_FP32_REFINE)
+      throw Error(CC_ERR_ARG, "unknown precision mode");
     c->s = (hipStream_t)stream;
     c->eng.reset(new nm::Engine(c->s));
+    c->eng->set_lowp_min_flops(c->opts.mixed_min_flops);
     const int64_t n = c->n, nn = n * n;
     c->eps = nm::tview(nm::palloc(*c, n), {n});
     nm::copy_d(*c, c->eps.p, eps, n);
@@ -1373,7 +1460,8 @@ int cc_set_guess(cc_ctx* c, int what, int idx, const double* src) {
 }
 
 int nm_contract(const char* spec, double alpha, const double* A, const int64_t* dA, const double* B,
-                const int64_t* dB, double beta, double* C, const int64_t* dC, void* stream) {
+                const int64_t* dB, double beta, double* C, const int64_t* dC, int precision,
+                void* stream) {
   if (!spec || !A || !B || !C || !dA || !dB || !dC) return CC_ERR_ARG;
   try {
     std::string s(spec);
@@ -1384,6 +1472,9 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
     hipStream_t st = (hipStream_t)stream;
     static thread_local std::unique_ptr<nm::Engine> eng;
     if (!eng || eng->stream() != st) eng.reset(new nm::Engine(st));
+    if (precision != CC_FP64 && precision != CC_FP32_REFINE) return CC_ERR_ARG;
+    eng->set_lowp(precision == CC_FP32_REFINE);
+    eng->set_lowp_min_flops(0.0);   // the test surface applies the mode to any size
     std::vector<int64_t> sa(dA, dA + la.size()), sb(dB, dB + lb.size()), sc(dC, dC + lc.size());
     nm::ArenaScope scope(eng->arena());
     nm::Graph G(*eng);
@@ -1417,6 +1508,23 @@ int cc_stats(const cc_ctx* c, double* out, int n) {
                        (double)c->eng->arena().reserved_bytes()};
   for (int k = 0; k < n && k < 6; ++k) out[k] = v[k];
   return CC_OK;
+}
+
+int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
+            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,
+            void* stream) {
+  if (!A || !B || !C || M < 0 || N < 0 || K < 1) return CC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (precision == CC_FP64)
+    rc = nm::gemm_f64(st, ta != 0, tb != 0, M, N, K, 1, alpha, (const double*)A, lda, 0,
+                      (const double*)B, ldb, 0, beta, C, ldc, 0);
+  else if (precision == CC_FP32_REFINE)
+    rc = nm::gemm_f32acc(st, ta != 0, tb != 0, M, N, K, alpha, (const float*)A, lda,
+                         (const float*)B, ldb, beta, C, ldc);
+  else
+    return CC_ERR_ARG;
+  return rc == 0 ? CC_OK : CC_ERR_HIP;
 }
 
 int nm_eig_host(int m, const double* G, double* wr, double* wi, double* V) {

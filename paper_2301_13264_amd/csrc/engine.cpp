@@ -360,6 +360,60 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     return;
   }
 
+  // Mixed-precision path for large plain (unbatched) contractions: pack both
+  // operands to fp32 in GEMM order, multiply on the FP32 matrix cores.
+  if (lowp_ && sb.empty() && K >= 4 && M0 * N0 >= 16 &&
+      2.0 * (double)M0 * (double)N0 * (double)K >= lowp_min_flops_) {
+    auto pack32 = [&](const DView& src, const std::string& order, int64_t& cnt) -> float* {
+      ViewSpec vs;
+      vs.nd = (int)order.size();
+      int64_t st = 1;
+      for (int k = vs.nd - 1; k >= 0; --k) {
+        const int j = find_lab(src, order[k]);
+        vs.dims[k] = src.dims[j];
+        vs.ostr[k] = st;
+        vs.istr[k] = src.str[j];
+        st *= src.dims[j];
+      }
+      cnt = st;
+      float* buf = (float*)arena_.alloc((st + 1) / 2);
+      kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
+      return buf;
+    };
+    int64_t na, nbb;
+    const float* a32 = pack32(A, sm + sk, na);
+    const float* b32 = pack32(B, sk + sn, nbb);
+    int64_t ldc, sC;
+    const bool direct = as_matrix(C, "", sm, sn, ldc, sC);
+    double* pc;
+    DView cbuf;
+    if (direct) {
+      pc = C.p;
+    } else {
+      const std::string ord = sm + sn;
+      cbuf.nd = (int)ord.size();
+      int64_t st = 1;
+      for (int k = cbuf.nd - 1; k >= 0; --k) {
+        const char ch = ord[k];
+        const int ja = find_lab(A, ch);
+        cbuf.lab[k] = ch;
+        cbuf.dims[k] = ja >= 0 ? A.dims[ja] : B.dims[find_lab(B, ch)];
+        cbuf.str[k] = st;
+        st *= cbuf.dims[k];
+      }
+      cbuf.p = arena_.alloc(st);
+      pc = cbuf.p;
+      ldc = N0;
+    }
+    kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)K, direct ? alpha : 1.0, a32, K, b32, N0,
+                       (direct && !overwrite) ? 1.0 : 0.0, pc, ldc),
+           "gemm fp32");
+    if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
+    lowp_flops_ += (uint64_t)(2.0 * (double)M0 * (double)N0 * (double)K);
+    arena_.rewind(mk);
+    return;
+  }
+
   // Promote outer labels shared by C and B (N labels) or by C and A (M labels)
   // to a batch dimension with a broadcast (stride 0) other operand.
   std::string pb_lab, pa_lab;   // promoted labels

@@ -112,6 +112,13 @@ class Engine {
   double* scalar_slot(int k);   // small device scalars
   uint64_t gemm_flops() const { return flops_; }
   void reset_flops() { flops_ = 0; }
+  // Mixed precision: unbatched contractions of at least lowp_min_flops run
+  // with fp32 operands on the FP32 matrix cores (fp32 accumulation, fp64
+  // result) while set_lowp(true) is in effect.
+  void set_lowp(bool on) { lowp_ = on; }
+  void set_lowp_min_flops(double f) { lowp_min_flops_ = f; }
+  bool lowp() const { return lowp_; }
+  uint64_t lowp_flops() const { return lowp_flops_; }
 
  private:
   hipStream_t s_;
@@ -119,6 +126,9 @@ class Engine {
   double* red_ = nullptr;
   double* scal_ = nullptr;
   uint64_t flops_ = 0;
+  bool lowp_ = false;
+  double lowp_min_flops_ = 1e9;
+  uint64_t lowp_flops_ = 0;
 };
 
 class Graph {

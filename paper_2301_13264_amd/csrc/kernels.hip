@@ -16,6 +16,10 @@
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Output row of accumulator element v for lane group lk (= lane / 16) of the
+// fp32 16x16x4 MFMA (measured: 4 lk + v; the fp64 16x16x4 MFMA uses lk + 4 v).
+#define F32_ROW(lk, v) (4 * (lk) + (v))
+
 namespace nm {
 
 // --------------------------------------------------------------------- GEMM
@@ -249,6 +253,166 @@ __global__ __launch_bounds__(NT) void gemm_f64_big_kernel(
       }
 }
 
+
+// FP32 variant of the large-tile kernel for the mixed-precision path: fp32
+// operands (packed by the caller), v_mfma_f32_16x16x4f32 with fp32
+// accumulation, fp64 epilogue C = alpha * acc + beta * C.  Same tiling, LDS
+// strides (17 / 144 floats keep the operand reads conflict-free: 17 r and
+// 144 k spread the 64 lanes over distinct banks) and XCD-grouped tile order.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(512) void gemm_f32acc_big_kernel(
+    int M, int N, int K, double alpha, const float* __restrict__ A, int64_t lda,
+    const float* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc) {
+  constexpr int NT = 512, WM = 4, TR = LBM / WM, FI = TR / 16;
+  constexpr int PER = (LBM * LBK) / NT, RSTEP = NT / 16, KSTEP = NT / 128;
+  constexpr int ASZ = TA ? LBK * LRS : LBM * LKS;
+  constexpr int BSZ = TB ? LBN * LKS : LBK * LRS;
+  __shared__ float As[2][ASZ];
+  __shared__ float Bs[2][BSZ];
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy;
+  int bid = blockIdx.x + gx * blockIdx.y;
+  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int tm = bid % gy, tn = bid / gy;
+  const int m0 = tm * LBM, n0 = tn * LBN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int a_row0 = TA ? (tid & 127) : (tid >> 4);
+  const int a_k0 = TA ? (tid >> 7) : (tid & 15);
+  const int b_row0 = TB ? (tid >> 4) : (tid & 127);
+  const int b_k0 = TB ? (tid & 15) : (tid >> 7);
+  const float* pa = TA ? A + (int64_t)a_k0 * lda + (m0 + a_row0) : A + (int64_t)(m0 + a_row0) * lda + a_k0;
+  const float* pb = TB ? B + (int64_t)(n0 + b_row0) * ldb + b_k0 : B + (int64_t)b_k0 * ldb + (n0 + b_row0);
+  const int64_t a_rstep = TA ? KSTEP * lda : RSTEP * lda;
+  const int64_t b_rstep = TB ? RSTEP * ldb : KSTEP * ldb;
+  const int64_t a_kstep = TA ? (int64_t)LBK * lda : LBK;
+  const int64_t b_kstep = TB ? LBK : (int64_t)LBK * ldb;
+  v4f acc[FI][4];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  float ra[PER], rb[PER];
+  auto gload = [&](int t) {
+    const int kb = t * LBK;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int row = TA ? a_row0 : a_row0 + RSTEP * r;
+      const int k = TA ? a_k0 + KSTEP * r : a_k0;
+      const bool ok = (m0 + row < M) && (kb + k < K);
+      ra[r] = ok ? pa[t * a_kstep + r * a_rstep] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int row = TB ? b_row0 + RSTEP * r : b_row0;
+      const int k = TB ? b_k0 : b_k0 + KSTEP * r;
+      const bool ok = (n0 + row < N) && (kb + k < K);
+      rb[r] = ok ? pb[t * b_kstep + r * b_rstep] : 0.f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      if (TA) As[buf][(a_k0 + KSTEP * r) * LRS + a_row0] = ra[r];
+      else As[buf][(a_row0 + RSTEP * r) * LKS + a_k0] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      if (TB) Bs[buf][(b_row0 + RSTEP * r) * LKS + b_k0] = rb[r];
+      else Bs[buf][(b_k0 + KSTEP * r) * LRS + b_row0] = rb[r];
+    }
+  };
+  const int nk = (K + LBK - 1) / LBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) gload(t + 1);
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+#pragma unroll
+    for (int kk = 0; kk < LBK; kk += 4) {
+      float a[FI], bb[4];
+#pragma unroll
+      for (int i = 0; i < FI; ++i) {
+        const int row = wm * TR + i * 16 + lr, k = kk + lk;
+        a[i] = TA ? as[k * LRS + row] : as[row * LKS + k];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wn * 64 + j * 16 + lr, k = kk + lk;
+        bb[j] = TB ? bs[row * LKS + k] : bs[k * LRS + row];
+      }
+#pragma unroll
+      for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * TR + i * 16 + F32_ROW(lk, v);
+        const int gn = n0 + wn * 64 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          double* c = C + (int64_t)gm * ldc + gn;
+          const double r = alpha * (double)acc[i][j][v];
+          *c = (beta == 0.0) ? r : r + beta * (*c);
+        }
+      }
+}
+
+int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const float* A,
+                int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+  if (M <= 0 || N <= 0) return 0;
+  if (K <= 0) return -1;
+  dim3 grid((N + LBN - 1) / LBN, (M + LBM - 1) / LBM, 1);
+#define NM_F32(TA_, TB_) \
+  hipLaunchKernelGGL((gemm_f32acc_big_kernel<TA_, TB_>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc)
+  if (!ta && !tb) NM_F32(false, false);
+  else if (!ta && tb) NM_F32(false, true);
+  else if (ta && !tb) NM_F32(true, false);
+  else NM_F32(true, true);
+#undef NM_F32
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// out (float) = in (double) through a strided view (packing for the fp32 path)
+__global__ void view_gather_f32_kernel(float* __restrict__ out, const double* __restrict__ in,
+                                       ViewSpec v, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, oo = v.obase, io = v.ibase;
+    for (int d = v.nd - 1; d >= 0; --d) {
+      const int64_t q = rem / v.dims[d];
+      const int64_t i = rem - q * v.dims[d];
+      rem = q;
+      oo += i * v.ostr[d];
+      io += i * v.istr[d];
+    }
+    out[oo] = (float)in[io];
+  }
+}
+
+int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec& v) {
+  int64_t total = 1;
+  for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
+  if (total == 0) return 0;
+  int64_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(view_gather_f32_kernel, dim3((int)g), dim3(256), 0, s, out, in, v, total);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,

@@ -149,3 +149,59 @@ def test_pipeline_matches_oracle(nm, o, v, naux, seed):
             Fo = rs.coupling_direct(st, m, j, dirs["dh"][q], dg)
             assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
     ctx.close()
+
+
+@pytest.mark.parametrize("spec,shapes,oshape", [
+    ("ik,kj->ij", [(300, 70), (70, 260)], (300, 260)),
+    ("ki,jk->ij", [(70, 300), (260, 70)], (300, 260)),
+    ("ijcd,cdab->ijab", [(4, 33, 13, 11), (13, 11, 12, 15)], (4, 33, 12, 15)),
+])
+def test_contract_fp32_operands(nm, spec, shapes, oshape):
+    """Mixed-precision contraction (fp32 operands and accumulation): error at
+    the level of fp32 rounding of the products."""
+    say(f"[contract fp32] {spec}")
+    rng = np.random.default_rng(3)
+    A = T(rng.normal(size=shapes[0]))
+    B = T(rng.normal(size=shapes[1]))
+    C = torch.zeros(oshape, dtype=torch.float64, device="cuda")
+    nm.contract(spec, 1.0, A, B, 0.0, C, precision=1)
+    torch.cuda.synchronize()
+    ref = torch.einsum(spec, A.cpu(), B.cpu())
+    k = np.prod(shapes[0]) * np.prod(shapes[1]) / np.prod(oshape) if oshape else 1
+    err = (C.cpu() - ref).abs().max().item()
+    assert err < 1e-5 * np.sqrt(k) * ref.abs().max().item()
+    assert err > 0.0   # the fp32 path really ran
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 4, 18, None), (4, 12, 48, 2301)])
+def test_mixed_precision_pipeline_matches_oracle(nm, o, v, naux, seed):
+    """CC_FP32_REFINE with every unbatched contraction forced onto fp32
+    operands: the refined energies, states and couplings meet the fp64
+    tolerances against the oracle."""
+    say(f"[mixed pipeline] o={o} v={v}")
+    seed = synth.exact_check_seed(o, v) if seed is None else seed
+    nroots = 2
+    st = oracle_state(o, v, naux, seed, nroots)
+    sysd = st["sys"]
+    dirs = synth.make_directions(o + v, naux, seed + 17, 2)
+    opts = nm.default_opts(precision=1, mixed_min_flops=0.0)
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]), opts)
+    e, _, rc = ctx.ground()
+    assert rc == 0
+    e_hf_ref = float(ccsd.energy(torch.zeros(o, v, dtype=torch.float64),
+                                 torch.zeros(o, o, v, v, dtype=torch.float64), st["h"], st["g"]))
+    assert abs((e + e_hf_ref) - st["E0"]) < 1e-9
+    w, _, rc = ctx.eom(nm.CC_BOTH, nroots)
+    assert rc == 0
+    assert np.abs(np.array(w) - st["omega"].numpy()).max() < 1e-9
+    for (i, j) in [(0, 1), (1, 0)]:
+        m = rs.multipliers(st, i, j, relaxed=True)
+        _, rc = ctx.multipliers(i + 1, j + 1)
+        assert rc == 0
+        ctx.densities(i + 1, j + 1)
+        F = ctx.nacme(i + 1, j + 1, T(dirs["dh"]), T(dirs["dB"]))
+        for q in range(2):
+            dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+            Fo = rs.coupling_direct(st, m, j, dirs["dh"][q], dg)
+            assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
+    ctx.close()
