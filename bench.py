@@ -9,10 +9,13 @@ factor, derivative integrals):
   cc_create (integral build) -> cc_ground -> eom_solve(both sides)
   -> multipliers, densities, nacme for the ordered pairs (1,2) and (2,1).
 
-Besides the step time, the run measures the Jacobian transforms per second,
-the ladder contraction's roofline fraction (HIP events on the stream the
-kernel runs on) and a CPU baseline (the fp64 oracle's residual at the same
-size on the host cores).
+The timed steps run the mixed-precision path (fp32-operand matrix-core
+contractions inside the solvers, fp64 residuals and fp64 final iterations);
+one step of the plain fp64 path runs beside it for the speed-up and the
+coupling agreement.  The run also measures the Jacobian transforms per
+second, the ladder GEMM's roofline fraction in both precisions (HIP events
+on the stream the kernel runs on) and a CPU baseline (the fp64 oracle's
+residual at the same size on the host cores).
 """
 from __future__ import annotations
 
@@ -25,8 +28,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks (dense): FP64 matrix 78.6 TFLOP/s, HBM 8 TB/s.
+# MI355X published peaks (dense matrix cores): FP64 78.6 TFLOP/s, FP32
+# 157.3 TFLOP/s; HBM 8 TB/s.
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 WORKLOAD = dict(name="thymine_dz", o=33, v=127, naux=640, nroots=2, ndir=45, seed=4301)
 # DF factor scale: the recipe's N(0, 0.05) gives no convergent CCSD at this
 # size (ground-state iterations overflow from the MP2 start); the scale is
@@ -76,6 +81,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--transforms", type=int, default=6)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed",
+                    help="precision of the timed steps")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the step in the other precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -96,25 +105,46 @@ def main():
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
     inp = dict(eps=T(sysd["eps"]), B=T(sysd["B"]), dh=T(dirs["dh"]), dB=T(dirs["dB"]))
     torch.cuda.synchronize()
-    opts = nm.default_opts()
+    prec = nm.CC_FP32_REFINE if args.precision == "mixed" else nm.CC_FP64
+    opts = nm.default_opts(precision=prec)
 
     for w in range(args.warmup):
-        log(f"[bench] warmup step {w + 1}/{args.warmup}")
+        log(f"[bench] warmup step {w + 1}/{args.warmup} ({args.precision})")
         ctx, _ = run_step(nm, torch, inp, cfg, opts)
         ctx.close()
     torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} step(s)")
+    log(f"[bench] timing {args.steps} step(s) ({args.precision})")
     t0 = time.perf_counter()
     ctx = None
     for s in range(args.steps):
         if ctx is not None:
             ctx.close()
         ctx, out = run_step(nm, torch, inp, cfg, opts)
-        log(f"[bench] step {s + 1} done: omega={out['omega']} F12[0]={out['F'][(1, 2)][0]:.6e}")
+        log(f"[bench] step {s + 1} done: omega={out['omega']} F12[0]={out['F'][(1, 2)][0]:.6e} "
+            f"stages={ {k: round(x, 2) for k, x in out['stage_s'].items()} }")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = 1000.0 * (t1 - t0) / args.steps
     stats = ctx.stats()
+
+    other = None
+    if not args.no_compare:
+        oname = "fp64" if args.precision == "mixed" else "mixed"
+        oprec = nm.CC_FP64 if args.precision == "mixed" else nm.CC_FP32_REFINE
+        log(f"[bench] one step in {oname} for comparison")
+        c0 = time.perf_counter()
+        octx, oout = run_step(nm, torch, inp, cfg, nm.default_opts(precision=oprec))
+        c1 = time.perf_counter()
+        octx.close()
+        dF = max(float(np.max(np.abs(np.asarray(out["F"][k]) - np.asarray(oout["F"][k]))))
+                 for k in out["F"])
+        dw = max(abs(a - b) for a, b in zip(out["omega"], oout["omega"]))
+        other = dict(precision=oname, time_to_nacme_s=c1 - c0, stage_s=oout["stage_s"],
+                     max_abs_dF=dF, max_abs_domega=dw,
+                     d_e_corr=abs(out["e_corr"] - oout["e_corr"]),
+                     ground_iters=oout["ground_iters"], eom_iters=oout["eom_iters"])
+        log(f"[bench] {oname}: {c1 - c0:.2f} s, max|dF| = {dF:.3e} "
+            f"stages={ {k: round(x, 2) for k, x in oout['stage_s'].items()} }")
 
     # Jacobian transforms/s at the converged amplitudes (HIP events, stream of the library)
     N = cfg["o"] * cfg["v"] + (cfg["o"] * cfg["v"]) ** 2
@@ -133,23 +163,33 @@ def main():
         tr[name] = ev0.elapsed_time(ev1) / args.transforms
     ctx.close()
 
-    # Ladder contraction roofline: Y[ij,ab] = sum_cd t[ij,cd] W[cd,ab] on the FP64 matrix cores
+    # Ladder GEMM roofline: Y[ij][ab] = sum_cd t[ij][cd] W[cd][ab], one launch of
+    # the matrix-core GEMM (M = o^2, N = K = v^2) in each operand precision.
     o, v = cfg["o"], cfg["v"]
-    A = torch.randn(o, o, v, v, dtype=torch.float64, device=dev)
-    Bv = torch.randn(v, v, v, v, dtype=torch.float64, device=dev)
-    C = torch.zeros(o, o, v, v, dtype=torch.float64, device=dev)
-    nm.contract("ijcd,cdab->ijab", 1.0, A, Bv, 0.0, C)
-    nl = 10
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(st)
-    for _ in range(nl):
-        nm.contract("ijcd,cdab->ijab", 1.0, A, Bv, 0.0, C)
-    ev1.record(st)
-    ev1.synchronize()
-    ladder_ms = ev0.elapsed_time(ev1) / nl
     ladder_flop = 2.0 * o * o * v ** 4
-    ladder_tf = ladder_flop / (ladder_ms * 1e-3) / 1e12
-    del A, Bv, C
+    roof = {}
+    for pname, pcode, dt, peak in [("fp64", 0, torch.float64, PEAK_FP64_TFLOPS),
+                                   ("fp32", 1, torch.float32, PEAK_FP32_TFLOPS)]:
+        A = torch.randn(o * o, v * v, dtype=dt, device=dev)
+        Bv = torch.randn(v * v, v * v, dtype=dt, device=dev)
+        C = torch.zeros(o * o, v * v, dtype=torch.float64, device=dev)
+        nm.gemm(pcode, A, Bv, C, stream=st)
+        nl = 10
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        for _ in range(nl):
+            nm.gemm(pcode, A, Bv, C, stream=st)
+        ev1.record(st)
+        ev1.synchronize()
+        lms = ev0.elapsed_time(ev1) / nl
+        tf = ladder_flop / (lms * 1e-3) / 1e12
+        roof[pname] = dict(bound="mfma", achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak,
+                           traffic=None, launch_ms=lms, flop_per_launch=ladder_flop)
+        del A, Bv, C
+    roof["fp64"]["kernel"] = "gemm_f64_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp64 operands)"
+    roof["fp32"]["kernel"] = ("gemm_f32acc_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp32 "
+                              "operands, fp32 accumulation)")
+    main_roof = roof["fp32"] if args.precision == "mixed" else roof["fp64"]
 
     # CPU baseline: the oracle's residual at the same size on the host cores
     cpu = None
@@ -178,11 +218,16 @@ def main():
     res = dict(
         metric="time-to-NACME vector & Jacobian transforms/s (TFLOP/s, % MFMA peak) at <=1e-6 au",
         value=value, unit="NACME vectors/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+        ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32+f64" if args.precision == "mixed" else "f64",
         data="synthetic",
         config=dict(workload="thymine_dz: o=33 v=127 naux=640, 2 roots, 45 directions, "
                              f"DF scale {SIGMA_B:.5f}", global_batch=1, parallelism="none"),
+        precision=args.precision,
         time_to_nacme_s=ms / 1000.0,
+        compare=other,
+        speedup_vs_fp64=(other["time_to_nacme_s"] / (ms / 1000.0)
+                         if other and args.precision == "mixed" else None),
         stage_s=out["stage_s"],
         omega=out["omega"], e_corr=out["e_corr"],
         jacobian_transforms_per_s=dict(right=1000.0 / tr["right"], left=1000.0 / tr["left"]),
@@ -191,10 +236,9 @@ def main():
                          left=stats["left_transforms"]),
         step_gemm_tflops=stats["gemm_flops"] / (ms / 1000.0) / 1e12,
         device_work_area_gb=stats["peak_bytes"] / 1e9,
-        roofline=dict(bound="mfma", achieved=ladder_tf, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                      frac=ladder_tf / PEAK_FP64_TFLOPS, traffic=None,
-                      kernel="gemm_f64_kernel (ladder Y[ij,ab] = sum_cd t[ij,cd] W[cd,ab])",
-                      flop_per_launch=ladder_flop, launch_ms=ladder_ms),
+        roofline=main_roof,
+        ladder_roofline=roof,
+        lowp_gemm_flops=stats.get("lowp_flops"),
         cpu_baseline=cpu,
     )
     print(json.dumps(res), flush=True)

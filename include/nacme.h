@@ -153,9 +153,10 @@ int cc_residual(cc_ctx* ctx, const double* t, double* omega);
 int cc_export(cc_ctx* ctx, int what, int idx, int jdx, double* dst);
 /* Sets a starting guess: CC_T (amplitudes for cc_ground).                    */
 int cc_set_guess(cc_ctx* ctx, int what, int idx, const double* src);
-/* Counters since cc_create (host out[n], n <= 6): residual evaluations,
+/* Counters since cc_create (host out[n], n <= 7): residual evaluations,
  * right transforms, left transforms, algorithmic GEMM flops issued,
- * peak and reserved bytes of the library's device work area.               */
+ * peak and reserved bytes of the library's device work area, and the part
+ * of the GEMM flops issued with fp32 operands.                             */
 int cc_stats(const cc_ctx* ctx, double* out, int n);
 const char* cc_last_error(const cc_ctx* ctx);
 void cc_destroy(cc_ctx* ctx);

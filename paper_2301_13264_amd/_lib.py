@@ -177,10 +177,10 @@ class Context:
         return x.value
 
     def stats(self):
-        out = (ctypes.c_double * 6)()
-        self._check(lib().cc_stats(self._h, out, 6))
+        out = (ctypes.c_double * 7)()
+        self._check(lib().cc_stats(self._h, out, 7))
         keys = ["residuals", "right_transforms", "left_transforms", "gemm_flops",
-                "peak_bytes", "reserved_bytes"]
+                "peak_bytes", "reserved_bytes", "lowp_flops"]
         return dict(zip(keys, list(out)))
 
     def set_guess(self, what, idx, src):

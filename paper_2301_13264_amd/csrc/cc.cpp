@@ -295,8 +295,11 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
                                  mul(-1, op(u, "klbd"), op(g, "ldkc", {O, V, O, V}), "bc")});
   const int Eo = G.node({o, o}, {lin(1, op(Fh, "kj", {O, O}), "kj"),
                                  mul(1, op(u, "ljcd"), op(g, "kdlc", {O, V, O, V}), "kj")});
-  const int P = G.node({o, o, v, v}, {mul(-0.5, op(t2, "kjbc"), op(Xc, "kiac"), "ijab"),
-                                      mul(-1, op(t2, "kibc"), op(Xc, "kjac"), "ijab"),
+  // Q_ijab = sum_kc t_kjbc Xc_kiac; the exchange partner sum_kc t_kibc Xc_kjac
+  // is Q with i and j swapped, added as a permutation instead of a second GEMM
+  const int Q = G.node({o, o, v, v}, {mul(1, op(t2, "kjbc"), op(Xc, "kiac"), "ijab")});
+  const int P = G.node({o, o, v, v}, {lin(-0.5, op(Q, "ijab"), "ijab"),
+                                      lin(-1, op(Q, "jiab"), "ijab"),
                                       mul(0.5, op(u, "jkbc"), op(Xd, "aikc"), "ijab"),
                                       mul(1, op(t2, "ijac"), op(Ev, "bc"), "ijab"),
                                       mul(-1, op(t2, "ikab"), op(Eo, "kj"), "ijab")});
@@ -1266,6 +1269,10 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
       const int iw = G.leaf(c->W), io = G.leaf(c->Wov);
       c->eng->linear(1.0, G.view(tw.a), nm::full_view(G.val(iw), "cdab"), true);
       c->eng->linear(1.0, G.view(to.a), nm::full_view(G.val(io), "cdkb"), true);
+      // W[cd][ab] = (ac|bd) = (ca|db) = W[ab][cd] for real orbitals and a
+      // factor symmetric in p, q
+      c->W.pair_sym = true;
+      c->W.constant = c->Wov.constant = c->g.constant = true;
     }
     c->t = nm::palloc(*c, c->N);
     nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
@@ -1503,10 +1510,11 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
 
 int cc_stats(const cc_ctx* c, double* out, int n) {
   if (!c || !out || n < 1) return CC_ERR_ARG;
-  const double v[6] = {(double)c->n_residual, (double)c->n_right, (double)c->n_left,
+  const double v[7] = {(double)c->n_residual, (double)c->n_right, (double)c->n_left,
                        (double)c->eng->gemm_flops(), (double)c->eng->arena().peak_bytes(),
-                       (double)c->eng->arena().reserved_bytes()};
-  for (int k = 0; k < n && k < 6; ++k) out[k] = v[k];
+                       (double)c->eng->arena().reserved_bytes(),
+                       (double)c->eng->lowp_flops()};
+  for (int k = 0; k < n && k < 7; ++k) out[k] = v[k];
   return CC_OK;
 }
 
@@ -1520,8 +1528,8 @@ int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, co
     rc = nm::gemm_f64(st, ta != 0, tb != 0, M, N, K, 1, alpha, (const double*)A, lda, 0,
                       (const double*)B, ldb, 0, beta, C, ldc, 0);
   else if (precision == CC_FP32_REFINE)
-    rc = nm::gemm_f32acc(st, ta != 0, tb != 0, M, N, K, alpha, (const float*)A, lda,
-                         (const float*)B, ldb, beta, C, ldc);
+    rc = nm::gemm_f32acc(st, ta != 0, tb != 0, M, N, K, 1, alpha, (const float*)A, lda, 0,
+                         (const float*)B, ldb, 0, beta, C, ldc, 0);
   else
     return CC_ERR_ARG;
   return rc == 0 ? CC_OK : CC_ERR_HIP;

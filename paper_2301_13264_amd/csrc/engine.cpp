@@ -95,6 +95,7 @@ DView full_view(const Tensor& t, const std::string& lab) {
   DView v;
   v.p = t.p;
   v.nd = t.nd;
+  v.constant = t.constant;
   strides_of(t, v.str);
   for (int k = 0; k < t.nd; ++k) {
     v.dims[k] = t.d[k];
@@ -128,7 +129,43 @@ static bool contiguous_in(const DView& v, const std::string& order) {
   return true;
 }
 
+static bool trace_on() { return std::getenv("NACME_TRACE") != nullptr; }
+
+// NACME_TRACE: every contraction and linear term is timed on its own (stream
+// synchronised before and after) and printed to stderr with its labels and
+// extents, so that the cost of each term of a graph can be read off.
+struct TermTrace {
+  hipStream_t s;
+  bool on;
+  std::string what;
+  std::chrono::steady_clock::time_point t0;
+  static std::string desc(const DView& v) {
+    std::string r(v.lab, v.lab + v.nd);
+    r += "(";
+    for (int k = 0; k < v.nd; ++k) r += (k ? "," : "") + std::to_string(v.dims[k]);
+    return r + ")";
+  }
+  TermTrace(hipStream_t st, const char* kind, const DView& a, const DView* b, const DView& c)
+      : s(st), on(trace_on()) {
+    if (!on) return;
+    what = std::string(kind) + " " + desc(a) + (b ? " " + desc(*b) : "") + " -> " + desc(c);
+    (void)hipStreamSynchronize(s);
+    t0 = std::chrono::steady_clock::now();
+  }
+  ~TermTrace() {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[term] %s %.4f ms\n", what.c_str(), ms);
+  }
+};
+
 // ------------------------------------------------------------------ Engine
+Engine::~Engine() {
+  for (auto& kv : f32_cache_) (void)hipFree(kv.second);
+}
+
 Engine::Engine(hipStream_t s) : s_(s) {
   red_ = arena_.alloc(reduce_scratch_doubles());
   scal_ = arena_.alloc(64);
@@ -212,6 +249,7 @@ static void scatter_into(hipStream_t s, double alpha, const DView& src, const DV
 }
 
 void Engine::linear(double alpha, const DView& A, const DView& C, bool overwrite) {
+  TermTrace trace(s_, "lin", A, nullptr, C);
   // forward reduction if every C label is in A, else broadcast
   bool all_in = true;
   for (int k = 0; k < C.nd; ++k)
@@ -251,6 +289,27 @@ __global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, i
     double* c = C + m * ldc + n;
     *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * (*c));
   }
+}
+
+// K split of a single large-tile GEMM.  A workgroup of 128 x 128 output
+// takes about `us_per_k` microseconds per unit of K when the device is full
+// and 512 workgroups (two per CU) run at once, so a grid of `tiles`
+// workgroups finishes in ceil(tiles / 512) rounds; splitting K into ns chunks
+// trades rounds against chunk length plus the fold of ns partial products
+// (16 bytes per element and chunk at about 4 TB/s).
+constexpr double kF64UsPerK = 0.23, kF32UsPerK = 0.13;
+static int64_t big_split(int64_t tiles, int64_t K, int64_t MN, double us_per_k) {
+  int64_t best = 1;
+  double tbest = 1e300;
+  for (int64_t ns = 1; ns <= 256; ++ns) {
+    const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
+    if (ns > 1 && kc < 512) break;
+    const double rounds = (double)((tiles * ns + 511) / 512);
+    const double t = rounds * (double)kc * us_per_k +
+                     (ns > 1 ? (double)ns * (double)MN * 16.0 / 4e6 : 0.0);
+    if (t < tbest * 0.98) { tbest = t; best = ns; }
+  }
+  return best;
 }
 
 // Can `v` be read as a (batched) row-major matrix rows x cols with a leading
@@ -301,12 +360,6 @@ static bool as_matrix(const DView& v, const std::string& batch, const std::strin
   return true;
 }
 
-static bool trace_on() {
-  static int t = -1;
-  if (t < 0) t = std::getenv("NACME_TRACE") ? 1 : 0;
-  return t == 1;
-}
-
 static int64_t prod_of(const DView& v, const std::string& s) {
   int64_t p = 1;
   for (char c : s) p *= v.dims[find_lab(v, c)];
@@ -317,7 +370,79 @@ static std::string labels_of(const DView& v) { return std::string(v.lab, v.lab +
 
 __global__ void scalar_axpy_kernel(double* y, const double* x, double a) { *y += a * (*x); }
 
-void Engine::contract(double alpha, const DView& A, const DView& B, const DView& C, bool overwrite) {
+// The same values with the labels of the two index halves exchanged (valid
+// for pair-symmetric tensors).
+static DView swap_halves(const DView& v) {
+  DView w = v;
+  const int h = v.nd / 2;
+  for (int k = 0; k < v.nd; ++k) w.lab[k] = v.lab[(k + h) % v.nd];
+  return w;
+}
+static bool halves_match(const DView& v) {
+  if (!v.pair_sym || v.nd % 2 != 0 || v.nd == 0) return false;
+  for (int k = 0; k < v.nd; ++k)
+    if (v.dims[k] != v.dims[(k + v.nd / 2) % v.nd]) return false;
+  return true;
+}
+
+// fp32 copy of `src` laid out row-major in label order `order`; constant
+// sources are converted once and kept (up to 8 GB), others go to the arena.
+static ViewSpec pack_spec(const DView& src, const std::string& order, int64_t& count) {
+  ViewSpec vs;
+  vs.nd = (int)order.size();
+  int64_t st = 1;
+  for (int k = vs.nd - 1; k >= 0; --k) {
+    const int j = find_lab(src, order[k]);
+    vs.dims[k] = src.dims[j];
+    vs.ostr[k] = st;
+    vs.istr[k] = src.str[j];
+    st *= src.dims[j];
+  }
+  count = st;
+  return vs;
+}
+
+const float* Engine::packed_f32(const DView& src, const std::string& order) {
+  int64_t cnt = 0;
+  const ViewSpec vs = pack_spec(src, order, cnt);
+  if (src.constant) {
+    std::string key = std::to_string((uintptr_t)src.p);
+    for (int k = 0; k < vs.nd; ++k)
+      key += ":" + std::to_string(vs.dims[k]) + "/" + std::to_string(vs.istr[k]);
+    auto it = f32_cache_.find(key);
+    if (it != f32_cache_.end()) return it->second;
+    const size_t bytes = (size_t)cnt * sizeof(float);
+    if (f32_cache_bytes_ + bytes <= ((size_t)8 << 30)) {
+      float* buf = nullptr;
+      if (hipMalloc((void**)&buf, bytes) == hipSuccess) {
+        kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
+        f32_cache_[key] = buf;
+        f32_cache_bytes_ += bytes;
+        return buf;
+      }
+      (void)hipGetLastError();
+    }
+  }
+  float* buf = (float*)arena_.alloc((cnt + 1) / 2);
+  kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
+  return buf;
+}
+
+void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const DView& C,
+                      bool overwrite) {
+  TermTrace trace(s_, lowp_ ? "mul32" : "mul", A_in, &B_in, C);
+  // A pair-symmetric operand whose contracted labels sit in its leading half
+  // is relabelled so that they sit in the trailing half (B: leading), which
+  // turns a transposed GEMM operand into a plain one.
+  DView A = A_in, B = B_in;
+  auto in_half = [](const DView& v, const DView& other, bool lead) {
+    const int h = v.nd / 2;
+    for (int k = lead ? 0 : h; k < (lead ? h : v.nd); ++k)
+      if (find_lab(other, v.lab[k]) < 0) return false;
+    return true;
+  };
+  if (halves_match(B) && in_half(B, A, false) && !in_half(B, A, true)) B = swap_halves(B);
+  if (halves_match(A) && in_half(A, B, true) && !in_half(A, B, false)) A = swap_halves(A);
   std::string sb, sm, sn, sk;
   for (int k = 0; k < A.nd; ++k) {
     const char c = A.lab[k];
@@ -360,37 +485,25 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     return;
   }
 
-  // Mixed-precision path for large plain (unbatched) contractions: pack both
-  // operands to fp32 in GEMM order, multiply on the FP32 matrix cores.
-  if (lowp_ && sb.empty() && K >= 4 && M0 * N0 >= 16 &&
-      2.0 * (double)M0 * (double)N0 * (double)K >= lowp_min_flops_) {
-    auto pack32 = [&](const DView& src, const std::string& order, int64_t& cnt) -> float* {
-      ViewSpec vs;
-      vs.nd = (int)order.size();
-      int64_t st = 1;
-      for (int k = vs.nd - 1; k >= 0; --k) {
-        const int j = find_lab(src, order[k]);
-        vs.dims[k] = src.dims[j];
-        vs.ostr[k] = st;
-        vs.istr[k] = src.str[j];
-        st *= src.dims[j];
-      }
-      cnt = st;
-      float* buf = (float*)arena_.alloc((st + 1) / 2);
-      kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
-      return buf;
-    };
-    int64_t na, nbb;
-    const float* a32 = pack32(A, sm + sk, na);
-    const float* b32 = pack32(B, sk + sn, nbb);
+  // Mixed-precision path for large contractions: pack both operands to fp32
+  // in [batch][rows][k] / [batch][k][cols] order and multiply on the FP32
+  // matrix cores (fp32 accumulation, fp64 result); products with few output
+  // tiles and a long K are split over K like the fp64 path.
+  // (batched products only when each product fills most of a 128 x 128 tile)
+  if (lowp_ && K >= 4 && M0 * N0 >= 16 && (sb.empty() || (M0 >= 96 && N0 >= 96)) &&
+      2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K >= lowp_min_flops_) {
+    if (M0 > INT32_MAX || N0 > INT32_MAX || K > INT32_MAX || nb0 > INT32_MAX)
+      throw Error(-1, "GEMM dimension overflow");
+    const float* a32 = packed_f32(A, sb + sm + sk);
+    const float* b32 = packed_f32(B, sb + sk + sn);
     int64_t ldc, sC;
-    const bool direct = as_matrix(C, "", sm, sn, ldc, sC);
+    const bool direct = as_matrix(C, sb, sm, sn, ldc, sC);
     double* pc;
     DView cbuf;
     if (direct) {
       pc = C.p;
     } else {
-      const std::string ord = sm + sn;
+      const std::string ord = sb + sm + sn;
       cbuf.nd = (int)ord.size();
       int64_t st = 1;
       for (int k = cbuf.nd - 1; k >= 0; --k) {
@@ -404,12 +517,37 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
       cbuf.p = arena_.alloc(st);
       pc = cbuf.p;
       ldc = N0;
+      sC = M0 * N0;
     }
-    kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)K, direct ? alpha : 1.0, a32, K, b32, N0,
-                       (direct && !overwrite) ? 1.0 : 0.0, pc, ldc),
-           "gemm fp32");
+    const double a_ = direct ? alpha : 1.0, b_ = (direct && !overwrite) ? 1.0 : 0.0;
+    const int64_t tiles = ((M0 + 127) / 128) * ((N0 + 127) / 128) * nb0;
+    int64_t ns = 1;
+    if (nb0 == 1 && tiles < 256 && K >= 2048) {
+      ns = std::min<int64_t>(std::max<int64_t>(1, 512 / tiles), K / 512);
+      ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
+    } else if (nb0 == 1) {
+      ns = big_split(tiles, K, M0 * N0, kF32UsPerK);
+    }
+    if (ns > 1) {
+      const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
+      ns = (K + kc - 1) / kc;
+      const int64_t klast = K - (ns - 1) * kc;
+      double* part = arena_.alloc(ns * M0 * N0);
+      kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)kc, (int)ns, 1.0, a32, K, kc,
+                         b32, N0, kc * N0, 0.0, part, N0, M0 * N0, (int)klast),
+             "gemm fp32 (split K)");
+      const int64_t tot = M0 * N0;
+      const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+      hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc, ldc, part, (int)M0,
+                         (int)N0, (int)ns, a_, b_);
+      kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+    } else {
+      kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)K, (int)nb0, a_, a32, K, M0 * K,
+                         b32, N0, K * N0, b_, pc, ldc, sC),
+             "gemm fp32");
+    }
     if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
-    lowp_flops_ += (uint64_t)(2.0 * (double)M0 * (double)N0 * (double)K);
+    lowp_flops_ += (uint64_t)(2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K);
     arena_.rewind(mk);
     return;
   }
@@ -511,18 +649,20 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
     sC = M * N;
   }
   const double a_ = direct ? alpha : 1.0, b_ = (direct && !overwrite) ? 1.0 : 0.0;
-  std::chrono::steady_clock::time_point t0;
-  if (trace_on()) {
-    (void)hipStreamSynchronize(s_);
-    t0 = std::chrono::steady_clock::now();
-  }
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) throw Error(-1, "GEMM dimension overflow");
 
-  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * nb;
-  if (nb == 1 && tiles < 512 && K >= 4096) {
+  const bool big = M >= 128 && N >= 128;   // gemm_f64 then runs 128 x 128 tiles
+  const int64_t tiles = big ? ((M + 127) / 128) * ((N + 127) / 128) * nb
+                            : ((M + 63) / 64) * ((N + 63) / 64) * nb;
+  int64_t ns = 1;
+  if (nb == 1 && big) {
+    ns = big_split(tiles, K, M * N, kF64UsPerK);
+  } else if (nb == 1 && tiles < 512 && K >= 4096) {
     // split K so that the grid fills the device; partials folded in order
-    int64_t ns = std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), K / 1024);
+    ns = std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), K / 1024);
     ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
+  }
+  if (ns > 1) {
     const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
     ns = (K + kc - 1) / kc;
     double* part = arena_.alloc(ns * M * N);
@@ -543,15 +683,6 @@ void Engine::contract(double alpha, const DView& A, const DView& B, const DView&
            "gemm");
   }
   if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
-  if (trace_on()) {
-    (void)hipStreamSynchronize(s_);
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    std::fprintf(stderr, "[contract] %s,%s->%s b=%s m=%s n=%s k=%s nb=%lld M=%lld N=%lld K=%lld ta=%d tb=%d "
-                 "packA=%d packB=%d direct=%d bcast=%d%d %.3f ms\n",
-                 labels_of(A).c_str(), labels_of(B).c_str(), labels_of(C).c_str(), sb.c_str(), sm.c_str(),
-                 sn.c_str(), sk.c_str(), (long long)nb, (long long)M, (long long)N, (long long)K, ta, tb,
-                 pa != A.p, pb != B.p, direct, bcastA, bcastB, ms);
-  }
   arena_.rewind(mk);
 }
 
@@ -590,6 +721,8 @@ DView Graph::view_of(const Op& o, const Tensor& t) const {
     }
   }
   v.p = t.p + base;
+  v.pair_sym = t.pair_sym && o.box.empty() && v.nd == t.nd;
+  v.constant = t.constant;
   return v;
 }
 

@@ -61,6 +61,11 @@ struct Tensor {
   double* p = nullptr;
   int nd = 0;
   int64_t d[kMaxViewDims] = {0};
+  // values unchanged when the first and second halves of the indices are
+  // swapped (a symmetric matrix of index pairs, e.g. (ac|bd) as [cd][ab])
+  bool pair_sym = false;
+  // never written after creation (integrals): fp32 packings may be cached
+  bool constant = false;
   int64_t size() const {
     int64_t s = 1;
     for (int k = 0; k < nd; ++k) s *= d[k];
@@ -93,6 +98,8 @@ struct Node {
 struct DView {
   double* p = nullptr;
   int nd = 0;
+  bool pair_sym = false;   // see Tensor::pair_sym (whole tensors only)
+  bool constant = false;   // view of a Tensor::constant tensor
   int64_t dims[kMaxViewDims] = {0};
   int64_t str[kMaxViewDims] = {0};
   char lab[kMaxViewDims] = {0};
@@ -101,6 +108,9 @@ struct DView {
 class Engine {
  public:
   Engine(hipStream_t s);
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
   hipStream_t stream() const { return s_; }
   Arena& arena() { return arena_; }
 
@@ -129,6 +139,10 @@ class Engine {
   bool lowp_ = false;
   double lowp_min_flops_ = 1e9;
   uint64_t lowp_flops_ = 0;
+  // fp32 packings of constant operands, keyed by source view and order
+  std::map<std::string, float*> f32_cache_;
+  size_t f32_cache_bytes_ = 0;
+  const float* packed_f32(const DView& src, const std::string& order);
 };
 
 class Graph {

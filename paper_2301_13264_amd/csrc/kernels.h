@@ -28,8 +28,9 @@ int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, do
 int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v, double alpha,
                 double beta);
 int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec& v);
-int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const float* A,
-                int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc);
+int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
+                const float* A, int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB,
+                double beta, double* C, int64_t ldc, int64_t sC, int Klast = 0);
 int view_scatter(hipStream_t s, double* in, const double* out, const ViewSpec& v, double alpha);
 int fill(hipStream_t s, double* x, double val, int64_t n);
 int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n);

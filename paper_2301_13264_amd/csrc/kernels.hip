@@ -126,7 +126,7 @@ constexpr int LKS = LBK + 1;     // [row][k] stride
 constexpr int LRS = 128 + 16;    // [k][row] stride
 
 template <bool TA, bool TB, int NT>
-__global__ __launch_bounds__(NT) void gemm_f64_big_kernel(
+__global__ __launch_bounds__(NT, 4) void gemm_f64_big_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda,
     int64_t sA, const double* __restrict__ B, int64_t ldb, int64_t sB, double beta,
     double* __restrict__ C, int64_t ldc, int64_t sC, int Klast) {
@@ -262,15 +262,23 @@ __global__ __launch_bounds__(NT) void gemm_f64_big_kernel(
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(512) void gemm_f32acc_big_kernel(
-    int M, int N, int K, double alpha, const float* __restrict__ A, int64_t lda,
-    const float* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc) {
+__global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
+    int M, int N, int K, double alpha, const float* __restrict__ A, int64_t lda, int64_t sA,
+    const float* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int Klast) {
   constexpr int NT = 512, WM = 4, TR = LBM / WM, FI = TR / 16;
   constexpr int PER = (LBM * LBK) / NT, RSTEP = NT / 16, KSTEP = NT / 128;
   constexpr int ASZ = TA ? LBK * LRS : LBM * LKS;
   constexpr int BSZ = TB ? LBN * LKS : LBK * LRS;
   __shared__ float As[2][ASZ];
   __shared__ float Bs[2][BSZ];
+  // grid.z: batch entries, or K chunks of a split-K product (the last chunk
+  // Klast long when Klast > 0)
+  const int64_t bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy;
   int bid = blockIdx.x + gx * blockIdx.y;
@@ -372,18 +380,165 @@ __global__ __launch_bounds__(512) void gemm_f32acc_big_kernel(
       }
 }
 
-int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const float* A,
-                int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc) {
-  if (M <= 0 || N <= 0) return 0;
+int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
+                const float* A, int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB,
+                double beta, double* C, int64_t ldc, int64_t sC, int Klast) {
+  if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (K <= 0) return -1;
-  dim3 grid((N + LBN - 1) / LBN, (M + LBM - 1) / LBM, 1);
+  if (batch > 32768) {   // grid.z limit: launch in chunks
+    for (int b0 = 0; b0 < batch; b0 += 32768) {
+      const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
+      int rc = gemm_f32acc(s, ta, tb, M, N, K, nb, alpha, A + (int64_t)b0 * sA, lda, sA,
+                           B + (int64_t)b0 * sB, ldb, sB, beta, C + (int64_t)b0 * sC, ldc, sC,
+                           b0 + nb == batch ? Klast : 0);
+      if (rc) return rc;
+    }
+    return 0;
+  }
+  dim3 grid((N + LBN - 1) / LBN, (M + LBM - 1) / LBM, batch);
 #define NM_F32(TA_, TB_) \
-  hipLaunchKernelGGL((gemm_f32acc_big_kernel<TA_, TB_>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc)
+  hipLaunchKernelGGL((gemm_f32acc_big_kernel<TA_, TB_>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast)
   if (!ta && !tb) NM_F32(false, false);
   else if (!ta && tb) NM_F32(false, true);
   else if (ta && !tb) NM_F32(true, false);
   else NM_F32(true, true);
 #undef NM_F32
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ------------------------------------------------------ tiled strided copy
+// A strided copy without summed labels runs as 64 x 64 tiles of two of its
+// dimensions: X, the input's fastest, and Y, the output's fastest; every
+// other dimension is a batch index decoded once per workgroup.  When X != Y
+// the tile passes through LDS (row stride 65 doubles: the transposed reads of
+// one wave fall in distinct banks), so loads run along X and stores along Y,
+// both coalesced.  When X == Y, Y is the output's next-fastest dimension and
+// each lane stores what it loaded.
+struct TileSpec {
+  int64_t nx = 1, ny = 1, isx = 0, isy = 0, osx = 0, osy = 0;
+  int64_t tx = 1, ty = 1;
+  int nb = 0;
+  int64_t bdims[kMaxViewDims] = {0}, bistr[kMaxViewDims] = {0}, bostr[kMaxViewDims] = {0};
+};
+
+template <typename TO, bool TRANS>
+__global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
+                                                        const double* __restrict__ in,
+                                                        TileSpec t, double alpha, double beta) {
+  __shared__ double tile[TRANS ? 64 * 65 : 1];
+  int64_t b = blockIdx.x;
+  const int64_t txi = b % t.tx;
+  b /= t.tx;
+  const int64_t tyi = b % t.ty;
+  b /= t.ty;
+  int64_t ib = 0, ob = 0;
+  for (int d = t.nb - 1; d >= 0; --d) {
+    const int64_t q = b / t.bdims[d];
+    const int64_t i = b - q * t.bdims[d];
+    b = q;
+    ib += i * t.bistr[d];
+    ob += i * t.bostr[d];
+  }
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int64_t x0 = txi * 64, y0 = tyi * 64;
+  if (TRANS) {
+#pragma unroll 4
+    for (int r = row; r < 64; r += 4) {
+      const int64_t x = x0 + lane, y = y0 + r;
+      if (x < t.nx && y < t.ny) tile[r * 65 + lane] = in[ib + x * t.isx + y * t.isy];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = row; r < 64; r += 4) {
+      const int64_t y = y0 + lane, x = x0 + r;
+      if (x < t.nx && y < t.ny) {
+        const double val = alpha * tile[lane * 65 + r];
+        TO* o = out + ob + x * t.osx + y * t.osy;
+        *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int r = row; r < 64; r += 4) {
+      const int64_t x = x0 + lane, y = y0 + r;
+      if (x < t.nx && y < t.ny) {
+        const double val = alpha * in[ib + x * t.isx + y * t.isy];
+        TO* o = out + ob + x * t.osx + y * t.osy;
+        *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+      }
+    }
+  }
+}
+
+// Plans a tiled copy for `v`; false when the view has summed labels or the
+// tiles would be mostly empty (the generic kernel then runs).
+static bool plan_tiles(const ViewSpec& v, TileSpec& t, bool& trans) {
+  if (v.nr != 0) return false;
+  int nd = 0;
+  int64_t dims[kMaxViewDims], is[kMaxViewDims], os[kMaxViewDims];
+  for (int d = 0; d < v.nd; ++d) {
+    if (v.dims[d] == 1) continue;
+    // merge with the previous kept dimension when both maps nest
+    if (nd > 0 && is[nd - 1] == v.istr[d] * v.dims[d] && os[nd - 1] == v.ostr[d] * v.dims[d]) {
+      dims[nd - 1] *= v.dims[d];
+      is[nd - 1] = v.istr[d];
+      os[nd - 1] = v.ostr[d];
+      continue;
+    }
+    dims[nd] = v.dims[d];
+    is[nd] = v.istr[d];
+    os[nd] = v.ostr[d];
+    ++nd;
+  }
+  if (nd < 2) return false;
+  int X = 0, Y = 0;
+  for (int d = 1; d < nd; ++d) {
+    if (is[d] < is[X]) X = d;
+    if (os[d] < os[Y]) Y = d;
+  }
+  trans = X != Y;
+  if (!trans) {
+    Y = -1;
+    for (int d = 0; d < nd; ++d)
+      if (d != X && (Y < 0 || os[d] < os[Y])) Y = d;
+  }
+  t.nx = dims[X];
+  t.isx = is[X];
+  t.osx = os[X];
+  t.ny = dims[Y];
+  t.isy = is[Y];
+  t.osy = os[Y];
+  t.tx = (t.nx + 63) / 64;
+  t.ty = (t.ny + 63) / 64;
+  t.nb = 0;
+  int64_t nbatch = 1;
+  for (int d = 0; d < nd; ++d) {
+    if (d == X || d == Y) continue;
+    t.bdims[t.nb] = dims[d];
+    t.bistr[t.nb] = is[d];
+    t.bostr[t.nb] = os[d];
+    ++t.nb;
+    nbatch *= dims[d];
+  }
+  const double fill = (double)(t.nx * t.ny) / (double)(t.tx * 64 * t.ty * 64);
+  const double blocks = (double)t.tx * (double)t.ty * (double)nbatch;
+  return fill >= 1.0 / 16.0 && blocks < (double)(1 << 24);
+}
+
+template <typename TO>
+static int tile_copy(hipStream_t s, TO* out, const double* in, const ViewSpec& v, double alpha,
+                     double beta) {
+  TileSpec t;
+  bool trans = false;
+  if (!plan_tiles(v, t, trans)) return 1;
+  int64_t blocks = t.tx * t.ty;
+  for (int d = 0; d < t.nb; ++d) blocks *= t.bdims[d];
+  if (trans)
+    hipLaunchKernelGGL((tile_copy_kernel<TO, true>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       out + v.obase, in + v.ibase, t, alpha, beta);
+  else
+    hipLaunchKernelGGL((tile_copy_kernel<TO, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       out + v.obase, in + v.ibase, t, alpha, beta);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -408,6 +563,8 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
   int64_t total = 1;
   for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
   if (total == 0) return 0;
+  const int rc = tile_copy<float>(s, out, in, v, 1.0, 0.0);
+  if (rc <= 0) return rc;
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(view_gather_f32_kernel, dim3((int)g), dim3(256), 0, s, out, in, v, total);
@@ -525,6 +682,8 @@ int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v,
   int64_t total = 1;
   for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
   if (total == 0) return 0;
+  const int rc = tile_copy<double>(s, out, in, v, alpha, beta);
+  if (rc <= 0) return rc;
   hipLaunchKernelGGL(view_gather_kernel, dim3(grid_for(total)), dim3(256), 0, s, out, in, v,
                      alpha, beta, total);
   return hipGetLastError() == hipSuccess ? 0 : -3;

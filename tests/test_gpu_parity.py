@@ -155,6 +155,9 @@ def test_pipeline_matches_oracle(nm, o, v, naux, seed):
     ("ik,kj->ij", [(300, 70), (70, 260)], (300, 260)),
     ("ki,jk->ij", [(70, 300), (260, 70)], (300, 260)),
     ("ijcd,cdab->ijab", [(4, 33, 13, 11), (13, 11, 12, 15)], (4, 33, 12, 15)),
+    ("ak,kx->ax", [(70, 4100), (4100, 3)], (70, 3)),                         # split K
+    ("kicd,adkc->ia", [(5, 33, 20, 31), (127, 31, 5, 20)], (33, 127)),       # split K, packed
+    ("zik,zkj->zij", [(3, 130, 41), (3, 41, 140)], (3, 130, 140)),           # batched
 ])
 def test_contract_fp32_operands(nm, spec, shapes, oshape):
     """Mixed-precision contraction (fp32 operands and accumulation): error at
@@ -171,6 +174,28 @@ def test_contract_fp32_operands(nm, spec, shapes, oshape):
     err = (C.cpu() - ref).abs().max().item()
     assert err < 1e-5 * np.sqrt(k) * ref.abs().max().item()
     assert err > 0.0   # the fp32 path really ran
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (130, 257, 19), (1089, 640, 300)])
+def test_gemm_kernel_surface(nm, prec, M, N, K):
+    """nm_gemm, the single-launch GEMM the bench times: ragged edges in every
+    dimension, fp64 operands exact to rounding, fp32 operands to fp32
+    rounding of the products."""
+    say(f"[nm_gemm] prec={prec} {M}x{N}x{K}")
+    rng = np.random.default_rng(M + N + K)
+    dt = torch.float64 if prec == 0 else torch.float32
+    A = torch.as_tensor(rng.normal(size=(M, K)), device="cuda").to(dt)
+    B = torch.as_tensor(rng.normal(size=(K, N)), device="cuda").to(dt)
+    C0 = torch.as_tensor(rng.normal(size=(M, N)), device="cuda")
+    C = C0.clone()
+    nm.gemm(prec, A, B, C, alpha=0.5, beta=-2.0)
+    torch.cuda.synchronize()
+    ref = 0.5 * (A.double().cpu() @ B.double().cpu()) - 2.0 * C0.cpu()
+    err = (C.cpu() - ref).abs().max().item()
+    tol = (1e-13 if prec == 0 else 1e-6) * np.sqrt(K) * max(1.0, ref.abs().max().item())
+    assert err < tol
 
 
 @pytest.mark.parametrize("o,v,naux,seed", [(2, 4, 18, None), (4, 12, 48, 2301)])
