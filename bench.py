@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--transforms", type=int, default=6)
+    ap.add_argument("--transforms", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed",
                     help="precision of the timed steps")
     ap.add_argument("--no-compare", action="store_true",
@@ -127,6 +127,31 @@ def main():
     ms = 1000.0 * (t1 - t0) / args.steps
     stats = ctx.stats()
 
+    # Jacobian transforms/s at the converged amplitudes (HIP events on the
+    # library's stream): k vectors per batched call, fp64 and fp32 operands;
+    # the marginal cost per vector excludes the per-call linearisation.
+    N = cfg["o"] * cfg["v"] + (cfg["o"] * cfg["v"]) ** 2
+    st = torch.cuda.current_stream()
+    tr = {}
+    for pname, pcode in [("fp64", nm.CC_FP64), ("fp32", nm.CC_FP32_REFINE)]:
+        for side, sname in [(nm.CC_RIGHT, "right"), (nm.CC_LEFT, "left")]:
+            per_call = {}
+            for k in (1, 4):
+                X = torch.randn(k, N, dtype=torch.float64, device=dev) * 1e-2
+                Y = torch.zeros_like(X)
+                ctx.apply_jacobian_block(side, X, Y, precision=pcode)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(st)
+                for _ in range(args.transforms):
+                    ctx.apply_jacobian_block(side, X, Y, precision=pcode)
+                ev1.record(st)
+                ev1.synchronize()
+                per_call[k] = ev0.elapsed_time(ev1) / args.transforms
+                del X, Y
+            tr[f"{sname}_{pname}"] = dict(ms_per_call_k1=per_call[1], ms_per_call_k4=per_call[4],
+                                          ms_per_vector_k4=(per_call[4] - per_call[1]) / 3.0)
+    ctx.close()
+
     other = None
     if not args.no_compare:
         oname = "fp64" if args.precision == "mixed" else "mixed"
@@ -145,23 +170,6 @@ def main():
                      ground_iters=oout["ground_iters"], eom_iters=oout["eom_iters"])
         log(f"[bench] {oname}: {c1 - c0:.2f} s, max|dF| = {dF:.3e} "
             f"stages={ {k: round(x, 2) for k, x in oout['stage_s'].items()} }")
-
-    # Jacobian transforms/s at the converged amplitudes (HIP events, stream of the library)
-    N = cfg["o"] * cfg["v"] + (cfg["o"] * cfg["v"]) ** 2
-    X = torch.randn(N, dtype=torch.float64, device=dev)
-    Y = torch.zeros_like(X)
-    st = torch.cuda.current_stream()
-    tr = {}
-    for side, name in [(nm.CC_RIGHT, "right"), (nm.CC_LEFT, "left")]:
-        ctx.apply_jacobian(side, X, Y)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(st)
-        for _ in range(args.transforms):
-            ctx.apply_jacobian(side, X, Y)
-        ev1.record(st)
-        ev1.synchronize()
-        tr[name] = ev0.elapsed_time(ev1) / args.transforms
-    ctx.close()
 
     # Ladder GEMM roofline: Y[ij][ab] = sum_cd t[ij][cd] W[cd][ab], one launch of
     # the matrix-core GEMM (M = o^2, N = K = v^2) in each operand precision.
@@ -230,7 +238,7 @@ def main():
                          if other and args.precision == "mixed" else None),
         stage_s=out["stage_s"],
         omega=out["omega"], e_corr=out["e_corr"],
-        jacobian_transforms_per_s=dict(right=1000.0 / tr["right"], left=1000.0 / tr["left"]),
+        jacobian_transforms_per_s={k: 1000.0 / x["ms_per_vector_k4"] for k, x in tr.items()},
         jacobian_transform_ms=tr,
         step_counts=dict(residuals=stats["residuals"], right=stats["right_transforms"],
                          left=stats["left_transforms"]),

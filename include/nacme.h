@@ -101,7 +101,8 @@ typedef struct {
 } cc_opts;
 
 /* Defaults: FP64, relaxed, tolerances 1e-10 / 1e-9 / 1e-9, maxit 200,
- * diis_dim 8, davidson_block 2, davidson_max 48, mixed_min_flops 1e9.          */
+ * diis_dim 8, davidson_block 2, davidson_max 120 (at most 128),
+ * mixed_min_flops 1e9.                                                        */
 void cc_default_opts(cc_opts* opts);
 
 /* Creates a context.  eps[n]: canonical orbital energies (device); B[naux][n][n]
@@ -146,6 +147,13 @@ int nacme(cc_ctx* ctx, int i, int j, int nq, const double* dh, const double* dB,
 /* Y = A X (side CC_RIGHT) or Y = X^T A (side CC_LEFT) at the current ground
  * amplitudes; X, Y amplitude-shaped device vectors.                          */
 int cc_apply_jacobian(cc_ctx* ctx, int side, const double* X, double* Y);
+/* Batched transforms (Sec. II B): Y[z] = A X[z] (CC_RIGHT) or X[z]^T A
+ * (CC_LEFT) for k vectors stored [k][N] (N = o v + o^2 v^2, device), all k
+ * pushed through each contraction together.  precision CC_FP64, or
+ * CC_FP32_REFINE for the fp32-operand contractions the mixed-precision
+ * solvers use (results then carry fp32 rounding).                          */
+int cc_apply_jacobian_block(cc_ctx* ctx, int side, int k, const double* X, double* Y,
+                            int precision);
 /* omega = Omega(t) for amplitudes t (device, amplitude-shaped).              */
 int cc_residual(cc_ctx* ctx, const double* t, double* omega);
 /* Copies a stored quantity (selectors above) to dst (device; CC_R0 host).

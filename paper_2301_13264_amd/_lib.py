@@ -71,6 +71,8 @@ def lib():
                               ctypes.c_int64, P]
         L.nm_gemm.restype = ctypes.c_int
         L.cc_stats.restype = ctypes.c_int
+        L.cc_apply_jacobian_block.argtypes = [P, I, I, P, P, I]
+        L.cc_apply_jacobian_block.restype = ctypes.c_int
         for name in ("cc_create", "cc_ground", "eom_solve", "multipliers", "densities", "nacme",
                      "cc_apply_jacobian", "cc_residual", "cc_export", "cc_set_guess",
                      "nm_contract", "nm_eig_host"):
@@ -82,7 +84,7 @@ def lib():
 EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multipliers",
             "densities", "nacme", "cc_apply_jacobian", "cc_residual", "cc_export",
             "cc_set_guess", "cc_last_error", "cc_destroy", "nm_contract", "nm_eig_host",
-            "nm_version", "cc_stats", "nm_gemm"]
+            "nm_version", "cc_stats", "nm_gemm", "cc_apply_jacobian_block"]
 
 
 def default_opts(**kw) -> Opts:
@@ -163,6 +165,13 @@ class Context:
 
     def apply_jacobian(self, side, X, Y):
         self._check(lib().cc_apply_jacobian(self._h, side, _ptr(X), _ptr(Y)))
+
+    def apply_jacobian_block(self, side, X, Y, precision=0):
+        """Y[z] = A X[z] (or X[z]^T A) for the k rows of X ([k][N] device)."""
+        if X.dim() != 2 or tuple(Y.shape) != tuple(X.shape):
+            raise ValueError("X and Y must be [k][N]")
+        self._check(lib().cc_apply_jacobian_block(self._h, side, X.shape[0], _ptr(X), _ptr(Y),
+                                                  precision))
 
     def residual(self, t, out):
         self._check(lib().cc_residual(self._h, _ptr(t), _ptr(out)))

@@ -114,6 +114,15 @@ static void copy_d(Ctx& c, double* dst, const double* src, int64_t n) {
     hip_check(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c.s), "memcpy D2D");
 }
 
+// rows k of `len` doubles: dst[k * ldd ...] = src[k * lds ...]
+static void copy_rows(Ctx& c, double* dst, int64_t ldd, const double* src, int64_t lds, int64_t len,
+                      int64_t rows) {
+  if (len <= 0 || rows <= 0) return;
+  hip_check(hipMemcpy2DAsync(dst, ldd * sizeof(double), src, lds * sizeof(double), len * sizeof(double),
+                             rows, hipMemcpyDeviceToDevice, c.s),
+            "memcpy2D D2D");
+}
+
 struct ArenaScope {
   Arena& a;
   Arena::Mark m;
@@ -125,6 +134,10 @@ struct ArenaScope {
 // operands until the residual falls below kMixedSwitch, then finish with fp64
 // operators and fp64 residuals.
 constexpr double kMixedSwitch = 1e-5;
+// Eigensolver switch point: fp32-operand images carry about 1e-7 relative
+// rounding, so the fp32 phase is run until the residual norm reaches 1e-7
+// or stalls.
+constexpr double kEigSwitch = 1e-7;
 static bool mixed(const Ctx& c) { return c.opts.precision == CC_FP32_REFINE; }
 
 static Tensor tview(double* p, std::vector<int64_t> shape) {
@@ -398,6 +411,49 @@ struct Tape {
     c.eng->arena().rewind(mk);
   }
 
+  // Y[k] = A X[k] for k vectors stored [k][N], in one pass of the graph with
+  // a batch index on every tangent (shared primal operands, k-fold GEMMs).
+  void right_block(const double* X, double* Y, int k) {
+    if (k == 1) return right(X, Y);
+    c.n_right += k;
+    const int n0 = G.size();
+    Arena::Mark mk = c.eng->arena().mark();
+    const int64_t nov = (int64_t)c.o * c.v, nd = c.N - nov;
+    Tensor b1 = make_tensor(c.eng->arena(), {k, c.o, c.v}, false, c.s);
+    Tensor b2 = make_tensor(c.eng->arena(), {k, c.o, c.o, c.v, c.v}, false, c.s);
+    copy_rows(c, b1.p, nov, X, c.N, nov, k);
+    copy_rows(c, b2.p, nd, X + nov, c.N, nd, k);
+    const int r1 = G.leaf(b1), r2 = G.leaf(b2);
+    auto tan = G.jvp({{r.t1, r1}, {r.t2, r2}}, r.first, k);
+    copy_rows(c, Y, c.N, G.val(tan.at(r.om1)).p, nov, nov, k);
+    copy_rows(c, Y + nov, c.N, G.val(tan.at(r.om2)).p, nd, nd, k);
+    G.truncate(n0);
+    c.eng->arena().rewind(mk);
+  }
+
+  // Y[k] = X[k]^T A for k vectors stored [k][N] (one reverse sweep).
+  void left_block(const double* X, double* Y, int k) {
+    if (k == 1) return left(X, Y);
+    c.n_left += k;
+    Arena::Mark mk = c.eng->arena().mark();
+    const int64_t nov = (int64_t)c.o * c.v, nd = c.N - nov;
+    double* tmp = c.eng->arena().alloc(c.N);
+    double* s1 = c.eng->arena().alloc((int64_t)k * nov);
+    double* s2 = c.eng->arena().alloc((int64_t)k * nd);
+    for (int z = 0; z < k; ++z) {
+      kc(apply_metric(c.s, tmp, X + (int64_t)z * c.N, c.o, c.v, 0), "metric");
+      copy_d(c, s1 + z * nov, tmp, nov);
+      copy_d(c, s2 + z * nd, tmp + nov, nd);
+    }
+    auto adj = G.vjp({{r.om1, s1}, {r.om2, s2}}, {r.t1, r.t2}, k);
+    for (int z = 0; z < k; ++z) {
+      copy_d(c, tmp, adj[r.t1].p + z * nov, nov);
+      copy_d(c, tmp + nov, adj[r.t2].p + z * nd, nd);
+      kc(apply_metric(c.s, Y + (int64_t)z * c.N, tmp, c.o, c.v, 1), "metric");
+    }
+    c.eng->arena().rewind(mk);
+  }
+
   // y = x^T A (packed-gradient convention, amplitude-shaped)
   void left(const double* x, double* y) {
     ++c.n_left;
@@ -502,11 +558,12 @@ struct Ritz {
 
 // Lowest-nroots eigenpairs of a non-symmetric operator on amplitude-shaped
 // vectors (biorthonormal metric), preconditioned by orbital-energy differences.
-static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*)>& T,
+// T(X, Y, k) applies the operator to k vectors stored [k][N] at once.
+static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*, int)>& T,
                      std::vector<double*>& out, const std::vector<double*>* guess = nullptr) {
   const int64_t N = c.N, nov = (int64_t)c.o * c.v;
   const int nb = nroots + std::max(0, c.opts.davidson_block);
-  const int maxm = std::max(c.opts.davidson_max, 2 * nb + 2);
+  const int maxm = std::min(kMaxRows, std::max(c.opts.davidson_max, 2 * nb + 2));
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
   double* V = ar.alloc((int64_t)maxm * N);
@@ -523,9 +580,11 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   bool lowp = mixed(c);
   c.eng->set_lowp(lowp);
 
-  // add x (and optionally its image ax) to the subspace after biorthonormal
-  // Gram-Schmidt (two passes, block GEMVs); false if x is in the span.
-  auto add = [&](double* x, double* ax) -> bool {
+  // biorthonormal Gram-Schmidt of x against the basis (two passes, block
+  // GEMVs), stored as basis row m (its image, when given, as W row m);
+  // false if x is in the span.  Rows without an image get one from flush().
+  auto orth = [&](double* x, double* ax) -> bool {
+    if (m >= maxm) return false;
     if (!ax) kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
     double n0 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
     if (!(n0 > 0)) return false;
@@ -537,16 +596,20 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
     if (n1 < 1e-4 * n0 || n1 < 1e-14) return false;
     axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
-    if (ax)
-      axpby_(c, W + (int64_t)m * N, ax, 1.0 / n1, 0.0, N);
-    else
-      T(V + (int64_t)m * N, W + (int64_t)m * N);
+    if (ax) axpby_(c, W + (int64_t)m * N, ax, 1.0 / n1, 0.0, N);
     ++m;
-    dots_rows(c, V, m, W + (int64_t)(m - 1) * N, N, true, work, h);
-    for (int k = 0; k < m; ++k) G[(size_t)k * maxm + (m - 1)] = h[k];
-    dots_rows(c, W, m, V + (int64_t)(m - 1) * N, N, true, work, h);
-    for (int k = 0; k < m; ++k) G[(size_t)(m - 1) * maxm + k] = h[k];
     return true;
+  };
+  // images of basis rows [m0, m) that have none, in one block application,
+  // then the new rows and columns of the projected matrix G = V^T A V
+  auto flush = [&](int m0, int mimg) {
+    if (mimg < m) T(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
+    for (int j = m0; j < m; ++j) {
+      dots_rows(c, V, m, W + (int64_t)j * N, N, true, work, h);
+      for (int k = 0; k < m; ++k) G[(size_t)k * maxm + j] = h[k];
+      dots_rows(c, W, m, V + (int64_t)j * N, N, true, work, h);
+      for (int k = 0; k < m; ++k) G[(size_t)j * maxm + k] = h[k];
+    }
   };
 
   // initial guess: given vectors (e.g. the right states for the left
@@ -555,7 +618,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     for (double* gv : *guess) {
       if (m >= nb) break;
       copy_d(c, Rs, gv, N);
-      add(Rs, nullptr);
+      orth(Rs, nullptr);
     }
   if (m < nb) {
     std::vector<std::pair<double, int64_t>> d;
@@ -567,9 +630,15 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       kc(fill(c.s, Rs, 0.0, N), "fill");
       hip_check(hipMemcpyAsync(Rs + d[k].second, &one, sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
       sync(c);
-      add(Rs, nullptr);
+      orth(Rs, nullptr);
     }
   }
+  flush(0, 0);
+  // fp32-operand phase: ends when the residual reaches kEigSwitch or stops
+  // improving (the fp32 rounding floor); the fp64 phase restarts from the
+  // Ritz vectors with fp64 images
+  double best_lowp = 1e300;
+  int stall = 0;
   Ritz res;
   for (int it = 1; it <= c.opts.maxit; ++it) {
     res.iters = it;
@@ -618,17 +687,24 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       for (int k = 0; k < nk; ++k) std::fprintf(stderr, " w%d=%.12f r=%.2e", k, res.w[k], rn[k]);
       std::fprintf(stderr, "\n");
     }
-    if (lowp && (worst < kMixedSwitch || it == c.opts.maxit / 2)) {
+    if (lowp) {
+      if (worst < 0.7 * best_lowp) {
+        best_lowp = worst;
+        stall = 0;
+      } else {
+        ++stall;
+      }
+    }
+    if (lowp && (worst < kEigSwitch || stall >= 3 || it >= c.opts.maxit / 2)) {
       // fp64 phase: restart from the Ritz vectors with fp64 images
       lowp = false;
       c.eng->set_lowp(false);
       m = 0;
       std::fill(G.begin(), G.end(), 0.0);
-      double* tmpx = ar.alloc(N);
-      for (int k = 0; k < nk; ++k) {
-        copy_d(c, tmpx, X + (int64_t)k * N, N);
-        add(tmpx, nullptr);
-      }
+      double* tmpx = ar.alloc((int64_t)nk * N);
+      copy_d(c, tmpx, X, (int64_t)nk * N);
+      for (int k = 0; k < nk; ++k) orth(tmpx + (int64_t)k * N, nullptr);
+      flush(0, 0);
       continue;
     }
     if (worst < c.opts.tol_eom) {
@@ -639,24 +715,25 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     if (m + nk > maxm) {
       m = 0;
       std::fill(G.begin(), G.end(), 0.0);
-      double* tmpx = ar.alloc(N);
-      double* tmpa = ar.alloc(N);
-      for (int k = 0; k < nk; ++k) {
-        copy_d(c, tmpx, X + (int64_t)k * N, N);
-        copy_d(c, tmpa, AX + (int64_t)k * N, N);
-        add(tmpx, tmpa);
-      }
+      double* tmpx = ar.alloc((int64_t)nk * N);
+      double* tmpa = ar.alloc((int64_t)nk * N);
+      copy_d(c, tmpx, X, (int64_t)nk * N);
+      copy_d(c, tmpa, AX, (int64_t)nk * N);
+      for (int k = 0; k < nk; ++k) orth(tmpx + (int64_t)k * N, tmpa + (int64_t)k * N);
+      flush(0, m);
       continue;
     }
-    // corrections only for the wanted roots; the extra Ritz vectors stay in
-    // the subspace (and survive restarts) as ballast
+    // corrections only for the wanted roots (one block application); the
+    // extra Ritz vectors stay in the subspace (and survive restarts) as ballast
+    const int m0 = m;
     for (int k = 0; k < std::min(nk, nroots); ++k) {
       if (rn[k] < c.opts.tol_eom) continue;
       copy_d(c, Rs, AX + (int64_t)k * N, N);
       axpby_(c, Rs, X + (int64_t)k * N, -res.w[k], 1.0, N);
       kc(apply_denominator(c.s, Rs, Rs, c.eps.p, c.o, c.v, res.w[k], 1), "precondition");
-      if (m < maxm) add(Rs, nullptr);
+      orth(Rs, nullptr);
     }
+    flush(m0, m0);
   }
   c.eng->set_lowp(false);
   if (lowp) res.converged = false;   // never accept a mixed-precision answer
@@ -758,7 +835,7 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
   int status = CC_OK, itsum = 0;
   Tape tp(c);
   if (side & CC_RIGHT) {
-    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.right(x, y); }, c.R);
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.right_block(x, y, k); }, c.R);
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_r = r.w;
     c.have_right = true;
@@ -767,8 +844,8 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
     if (!r.converged) status = CC_NOT_CONVERGED;
   }
   if (side & CC_LEFT) {
-    Ritz r = davidson(c, nroots, [&](const double* x, double* y) { tp.left(x, y); }, c.L,
-                      c.have_right ? &c.R : nullptr);
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.left_block(x, y, k); },
+                      c.L, c.have_right ? &c.R : nullptr);
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_l = r.w;
     c.have_left = true;
@@ -1203,7 +1280,7 @@ void cc_default_opts(cc_opts* o) {
   o->maxit = 200;
   o->diis_dim = 8;
   o->davidson_block = 2;
-  o->davidson_max = 48;
+  o->davidson_max = 120;
   o->mixed_min_flops = 1e9;
 }
 
@@ -1392,6 +1469,25 @@ int cc_apply_jacobian(cc_ctx* c, int side, const double* X, double* Y) {
     nm::sync(*c);
     return CC_OK;
   } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_apply_jacobian_block(cc_ctx* c, int side, int k, const double* X, double* Y, int precision) {
+  ABI_GUARD(c);
+  if (c->stage < 1) { c->err = "cc_apply_jacobian_block before cc_ground"; return CC_ERR_STATE; }
+  if (!X || !Y || k < 1 || (side != CC_RIGHT && side != CC_LEFT) ||
+      (precision != CC_FP64 && precision != CC_FP32_REFINE))
+    return CC_ERR_ARG;
+  try {
+    nm::Tape tp(*c);
+    c->eng->set_lowp(precision == CC_FP32_REFINE);
+    if (side == CC_RIGHT) tp.right_block(X, Y, k); else tp.left_block(X, Y, k);
+    c->eng->set_lowp(false);
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    c->eng->set_lowp(false);
     return fail(c, e);
   }
 }

@@ -36,10 +36,22 @@ double* Arena::alloc(int64_t ndouble) {
         peak_ = std::max(peak_, live_);
         return p;
       }
+      // chunks after the current one are unused: take the first that fits
+      for (size_t k = cur_ + 1; k < chunks_.size(); ++k) {
+        if (chunks_[k].cap >= bytes) {
+          std::swap(chunks_[cur_ + 1], chunks_[k]);
+          ++cur_;
+          chunks_[cur_].top = 0;
+          break;
+        }
+      }
+      if (chunks_[cur_].top + bytes <= chunks_[cur_].cap) continue;
+      // none fits: release the unused ones (after the device has finished
+      // with whatever they held) so that capacity is not stranded
       if (cur_ + 1 < chunks_.size()) {
-        ++cur_;
-        chunks_[cur_].top = 0;
-        continue;
+        (void)hipDeviceSynchronize();
+        for (size_t k = cur_ + 1; k < chunks_.size(); ++k) (void)hipFree(chunks_[k].base);
+        chunks_.resize(cur_ + 1);
       }
     }
     size_t cap = std::max(bytes, (size_t)1 << 30);
@@ -769,7 +781,28 @@ int Graph::node(const std::vector<int64_t>& shape, const std::vector<Term>& term
   return (int)nodes_.size() - 1;
 }
 
-std::map<int, int> Graph::jvp(const std::map<int, int>& seeds, int first) {
+// Batched derivatives: tangents / adjoints of `nb` directions at once carry
+// a leading batch index with label kBatchLabel on the derivative operand and
+// on the output of every term (the primal operand is shared by the batch).
+static constexpr char kBatchLabel = 'Z';
+static Op batched_op(Op o, int64_t nb) {
+  if (nb <= 0) return o;
+  o.lab.insert(o.lab.begin(), kBatchLabel);
+  if (!o.box.empty()) o.box.insert(o.box.begin(), Range{0, nb});
+  return o;
+}
+static Term batched_out(Term t, int64_t nb) {
+  if (nb <= 0) return t;
+  t.olab.insert(t.olab.begin(), kBatchLabel);
+  if (!t.obox.empty()) t.obox.insert(t.obox.begin(), Range{0, nb});
+  return t;
+}
+static std::vector<int64_t> batched_shape(std::vector<int64_t> s, int64_t nb) {
+  if (nb > 0) s.insert(s.begin(), nb);
+  return s;
+}
+
+std::map<int, int> Graph::jvp(const std::map<int, int>& seeds, int first, int64_t batch) {
   std::map<int, int> tan = seeds;
   const int end = (int)nodes_.size();
   for (int k = first; k < end; ++k) {
@@ -782,28 +815,31 @@ std::map<int, int> Graph::jvp(const std::map<int, int>& seeds, int first) {
       if (tm.bilinear) {
         auto ib = tan.find(tm.b.node);
         if (ia != tan.end()) {
-          Term x = tm;
+          Term x = batched_out(tm, batch);
+          x.a = batched_op(tm.a, batch);
           x.a.node = ia->second;
           tt.push_back(x);
         }
         if (ib != tan.end()) {
-          Term x = tm;
+          Term x = batched_out(tm, batch);
+          x.b = batched_op(tm.b, batch);
           x.b.node = ib->second;
           tt.push_back(x);
         }
       } else if (ia != tan.end()) {
-        Term x = tm;
+        Term x = batched_out(tm, batch);
+        x.a = batched_op(tm.a, batch);
         x.a.node = ia->second;
         tt.push_back(x);
       }
     }
-    if (!tt.empty()) tan[k] = node(nk.val.shape(), tt);
+    if (!tt.empty()) tan[k] = node(batched_shape(nk.val.shape(), batch), tt);
   }
   return tan;
 }
 
 std::map<int, Tensor> Graph::vjp(const std::map<int, const double*>& seeds,
-                                 const std::vector<int>& wrt) {
+                                 const std::vector<int>& wrt, int64_t batch) {
   const int n = (int)nodes_.size();
   std::vector<char> needs(n, 0);
   for (int w : wrt) needs.at(w) = 1;
@@ -818,7 +854,8 @@ std::map<int, Tensor> Graph::vjp(const std::map<int, const double*>& seeds,
   }
   std::vector<Tensor> adj(n);
   auto get_adj = [&](int k) -> Tensor& {
-    if (!adj[k].p) adj[k] = make_tensor(e_.arena(), nodes_[k].val.shape(), true, e_.stream());
+    if (!adj[k].p)
+      adj[k] = make_tensor(e_.arena(), batched_shape(nodes_[k].val.shape(), batch), true, e_.stream());
     return adj[k];
   };
   for (auto& kv : seeds) {
@@ -830,21 +867,21 @@ std::map<int, Tensor> Graph::vjp(const std::map<int, const double*>& seeds,
     if (!adj[k].p || nodes_[k].leaf) continue;
     const Node& nk = nodes_[k];
     for (const Term& tm : nk.terms) {
-      DView Cb = out_view(tm, adj[k]);
+      DView Cb = out_view(batched_out(tm, batch), adj[k]);
       if (tm.bilinear) {
         const bool na = needs[tm.a.node], nb = needs[tm.b.node];
         if (na) {
-          DView Ab = view_of(tm.a, get_adj(tm.a.node));
+          DView Ab = view_of(batched_op(tm.a, batch), get_adj(tm.a.node));
           DView B = view_of(tm.b, nodes_[tm.b.node].val);
           e_.contract(tm.alpha, Cb, B, Ab);
         }
         if (nb) {
-          DView Bb = view_of(tm.b, get_adj(tm.b.node));
+          DView Bb = view_of(batched_op(tm.b, batch), get_adj(tm.b.node));
           DView A = view_of(tm.a, nodes_[tm.a.node].val);
           e_.contract(tm.alpha, A, Cb, Bb);
         }
       } else if (needs[tm.a.node]) {
-        DView Ab = view_of(tm.a, get_adj(tm.a.node));
+        DView Ab = view_of(batched_op(tm.a, batch), get_adj(tm.a.node));
         e_.linear(tm.alpha, Cb, Ab);
       }
     }

@@ -156,13 +156,17 @@ class Graph {
 
   // Tangents of every node from `first` on, given tangents of some nodes
   // (node -> tangent node).  Returns the completed map (absent = zero).
-  std::map<int, int> jvp(const std::map<int, int>& seeds, int first = 0);
+  // batch > 0: `batch` directions at once; every tangent node (seeds too)
+  // has shape [batch] + the shape of its primal node.
+  std::map<int, int> jvp(const std::map<int, int>& seeds, int first = 0, int64_t batch = 0);
 
   // Reverse sweep.  seeds: node -> device tensor (same shape) holding the
   // adjoint of a scalar functional; returns adjoints of `wrt` nodes (device
   // tensors allocated in the arena; zero-filled when unreachable).
+  // batch > 0: `batch` functionals at once, seeds and adjoints of shape
+  // [batch] + the node's shape.
   std::map<int, Tensor> vjp(const std::map<int, const double*>& seeds,
-                            const std::vector<int>& wrt);
+                            const std::vector<int>& wrt, int64_t batch = 0);
 
   // Truncate the tape to `n` nodes (values of removed nodes are released
   // when the arena is rewound by the caller).

@@ -230,3 +230,42 @@ def test_mixed_precision_pipeline_matches_oracle(nm, o, v, naux, seed):
             Fo = rs.coupling_direct(st, m, j, dirs["dh"][q], dg)
             assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
     ctx.close()
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 5), (4, 12)])
+def test_block_transforms_match_single(nm, o, v):
+    """Batched right/left transforms of k vectors equal k single transforms
+    (fp64), and the fp32-operand variant stays within fp32 rounding; the
+    singles and doubles parts are checked against the oracle."""
+    say(f"[block jacobian] o={o} v={v}")
+    naux = 3 * (o + v)
+    st = oracle_state(o, v, naux, synth.exact_check_seed(o, v), 2)
+    sysd = st["sys"]
+    # every contraction qualifies for fp32 operands in the precision=1 calls
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]), nm.default_opts(mixed_min_flops=0.0))
+    ctx.ground()
+    k = 3
+    Nf = o * v + (o * v) ** 2
+    rng = np.random.default_rng(11)
+    xs = [rng.normal(size=st["x"].numel()) for _ in range(k)]
+    X = torch.stack([T(to_full(x, o, v)) for x in xs])
+    for side, fn in [(nm.CC_RIGHT, rs.right_transform), (nm.CC_LEFT, rs.left_transform)]:
+        Y = torch.zeros_like(X)
+        ctx.apply_jacobian_block(side, X, Y)
+        y1 = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+        for z in range(k):
+            ctx.apply_jacobian(side, X[z].contiguous(), y1)
+            torch.cuda.synchronize()
+            ref = y1.cpu().numpy()
+            got = Y[z].cpu().numpy()
+            assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+            orc = fn(st["x"], torch.as_tensor(xs[z]), st["h"], st["g"], o, v).numpy()
+            assert np.abs(to_packed(got, o, v) - orc).max() < 1e-9
+        Y32 = torch.zeros_like(X)
+        ctx.apply_jacobian_block(side, X, Y32, precision=1)
+        torch.cuda.synchronize()
+        scale = Y.abs().max().item()
+        d32 = (Y32 - Y).abs().max().item()
+        assert d32 < 1e-5 * max(1.0, scale)
+        assert d32 > 0.0   # the fp32 contractions really ran
+    ctx.close()
