@@ -185,6 +185,59 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
 int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
             int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,
             void* stream);
+/* ---- learned initial guess --------------------------------------------- */
+/* A three-layer perceptron y = W3^T s(W2^T s(W1^T x + b1) + b2) + b3 with
+ * SiLU s(u) = u / (1 + exp(-u)) and row-major W[in][out], trained on the
+ * amplitudes the method itself produces (learned guesses for the solvers).
+ * fp32 master parameters updated by Adam (beta 0.9 / 0.999, eps 1e-8); every
+ * product uses the bfloat16 rounding of the parameters with fp32
+ * accumulation.  Loss: half the mean squared error over all outputs.
+ * Parameters are flattened W1, b1, W2, b2, W3, b3.  Arrays X [n][n_in],
+ * T and Y [n][n_out] are fp32 DEVICE pointers; parameter and gradient
+ * copies are HOST arrays of mlp_num_params floats.  Work runs on the stream
+ * given to mlp_create; calls return after it has finished.                  */
+typedef struct nm_mlp nm_mlp;
+/* N(0, 1/fan_in) weights from `seed`, zero biases.  -1 bad sizes, -4 OOM.  */
+int mlp_create(nm_mlp** net, int n_in, int width, int n_out, uint64_t seed, void* stream);
+int64_t mlp_num_params(const nm_mlp* net);
+int mlp_dims(const nm_mlp* net, int* n_in, int* width, int* n_out);
+/* Sets the master parameters (host src), their bfloat16 working copy, and
+ * resets the optimiser state.                                              */
+int mlp_set_params(nm_mlp* net, const float* src);
+/* dst (host) <- master parameters, or their bfloat16 working copy.          */
+int mlp_get_params(nm_mlp* net, float* dst, int working);
+/* Y = net(X) for n rows.                                                     */
+int mlp_forward(nm_mlp* net, int64_t n, const float* X, float* Y);
+/* Loss of (X, T) over n rows (host *loss) and its gradient with respect to
+ * the parameters (kept for mlp_adam_step; copied to host grad if non-NULL). */
+int mlp_loss_grad(nm_mlp* net, int64_t n, const float* X, const float* T, double* loss,
+                  float* grad);
+/* One Adam update with step size lr from the last gradient.                 */
+int mlp_adam_step(nm_mlp* net, float lr);
+/* `steps` Adam updates on minibatches of `batch` rows drawn uniformly (with
+ * replacement, from `seed`) out of the n rows of (X, T); *last_loss: loss
+ * of the last minibatch before its update.                                  */
+int mlp_train(nm_mlp* net, int64_t n, const float* X, const float* T, int64_t batch, int steps,
+              float lr, uint64_t seed, double* last_loss);
+const char* mlp_last_error(const nm_mlp* net);
+void mlp_destroy(nm_mlp* net);
+
+/* Doubles-amplitude guess from the network.  For every doubles index
+ * (i, j, a, b), row-major, the 8 features are e_i, e_j, e_a, e_b,
+ * D = e_a + e_b - e_i - e_j, (ia|jb), (ib|ja) and the MP2 amplitude
+ * -(ia|jb)/D, each standardised as (f - mu[k]) / sd[k] (mu, sd host [8];
+ * NULL = 0 and 1).  The network output z' gives the amplitude
+ * t = -((ia|jb) + scale z') / D, so z' = 0 is the MP2 guess the amplitude
+ * solver otherwise starts from (Sec. II A).
+ * cc_t2_features: F (device fp32 [o^2 v^2][8]).
+ * cc_t2_target:   Z (device fp32 [o^2 v^2]) = (-D t - (ia|jb)) / scale from
+ *                 the converged ground amplitudes (after cc_ground).
+ * cc_guess_t2:    sets the starting amplitudes of the next cc_ground to
+ *                 t1 = 0 and the network's doubles (net: n_in 8, n_out 1). */
+int cc_t2_features(cc_ctx* ctx, const float* mu, const float* sd, float* F);
+int cc_t2_target(cc_ctx* ctx, float scale, float* Z);
+int cc_guess_t2(cc_ctx* ctx, nm_mlp* net, const float* mu, const float* sd, float scale);
+
 /* Host-only: eigen-decomposition of a real m x m row-major matrix used for
  * Davidson subspaces; wr, wi [m]; V [m][m] real parts of unit eigenvectors
  * (row k = vector k, phase chosen so its largest component is real).       */

@@ -4,4 +4,4 @@ The computation lives in libnacme.so (C ABI, include/nacme.h); this package
 only builds and binds it.
 """
 from ._lib import (CC_BOTH, CC_FP32_REFINE, CC_FP64, CC_LEFT, CC_RIGHT,  # noqa: F401
-                   CCError, Context, contract, default_opts, eig_host, gemm, lib)
+                   CCError, MLP, Context, contract, default_opts, eig_host, gemm, lib)

@@ -73,6 +73,30 @@ def lib():
         L.cc_stats.restype = ctypes.c_int
         L.cc_apply_jacobian_block.argtypes = [P, I, I, P, P, I]
         L.cc_apply_jacobian_block.restype = ctypes.c_int
+        PF = ctypes.POINTER(ctypes.c_float)
+        F = ctypes.c_float
+        U64 = ctypes.c_uint64
+        L.mlp_create.argtypes = [ctypes.POINTER(P), I, I, I, U64, P]
+        L.mlp_num_params.argtypes = [P]
+        L.mlp_num_params.restype = ctypes.c_int64
+        L.mlp_dims.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.mlp_set_params.argtypes = [P, PF]
+        L.mlp_get_params.argtypes = [P, PF, I]
+        L.mlp_forward.argtypes = [P, ctypes.c_int64, P, P]
+        L.mlp_loss_grad.argtypes = [P, ctypes.c_int64, P, P, PD, PF]
+        L.mlp_adam_step.argtypes = [P, F]
+        L.mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int64, I, F, U64, PD]
+        L.mlp_last_error.argtypes = [P]
+        L.mlp_last_error.restype = ctypes.c_char_p
+        L.mlp_destroy.argtypes = [P]
+        L.mlp_destroy.restype = None
+        L.cc_t2_features.argtypes = [P, PF, PF, P]
+        L.cc_t2_target.argtypes = [P, F, P]
+        L.cc_guess_t2.argtypes = [P, P, PF, PF, F]
+        for name in ("mlp_create", "mlp_dims", "mlp_set_params", "mlp_get_params", "mlp_forward",
+                     "mlp_loss_grad", "mlp_adam_step", "mlp_train", "cc_t2_features",
+                     "cc_t2_target", "cc_guess_t2"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("cc_create", "cc_ground", "eom_solve", "multipliers", "densities", "nacme",
                      "cc_apply_jacobian", "cc_residual", "cc_export", "cc_set_guess",
                      "nm_contract", "nm_eig_host"):
@@ -84,7 +108,10 @@ def lib():
 EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multipliers",
             "densities", "nacme", "cc_apply_jacobian", "cc_residual", "cc_export",
             "cc_set_guess", "cc_last_error", "cc_destroy", "nm_contract", "nm_eig_host",
-            "nm_version", "cc_stats", "nm_gemm", "cc_apply_jacobian_block"]
+            "nm_version", "cc_stats", "nm_gemm", "cc_apply_jacobian_block", "mlp_create",
+            "mlp_num_params", "mlp_dims", "mlp_set_params", "mlp_get_params", "mlp_forward",
+            "mlp_loss_grad", "mlp_adam_step", "mlp_train", "mlp_last_error", "mlp_destroy",
+            "cc_t2_features", "cc_t2_target", "cc_guess_t2"]
 
 
 def default_opts(**kw) -> Opts:
@@ -98,6 +125,12 @@ def default_opts(**kw) -> Opts:
 def _ptr(t):
     if not t.is_cuda or t.dtype != __import__("torch").float64 or not t.is_contiguous():
         raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    if not t.is_cuda or t.dtype != __import__("torch").float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -173,6 +206,20 @@ class Context:
         self._check(lib().cc_apply_jacobian_block(self._h, side, X.shape[0], _ptr(X), _ptr(Y),
                                                   precision))
 
+    def t2_features(self, F, mu=None, sd=None):
+        """F (device float32 [o^2 v^2][8]) <- standardised doubles features."""
+        self._check(lib().cc_t2_features(self._h, _fvec(mu), _fvec(sd), _fptr(F)))
+        return F
+
+    def t2_target(self, Z, scale=1.0):
+        """Z (device float32 [o^2 v^2]) <- (-D t - (ia|jb)) / scale."""
+        self._check(lib().cc_t2_target(self._h, scale, _fptr(Z)))
+        return Z
+
+    def guess_t2(self, net, mu=None, sd=None, scale=1.0):
+        """Start the next ground-state solve from the network's amplitudes."""
+        self._check(lib().cc_guess_t2(self._h, net._h, _fvec(mu), _fvec(sd), scale))
+
     def residual(self, t, out):
         self._check(lib().cc_residual(self._h, _ptr(t), _ptr(out)))
 
@@ -222,6 +269,77 @@ def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None):
     if rc != CC_OK:
         raise CCError(rc, "nm_gemm")
     return C
+
+
+def _fvec(x):
+    if x is None:
+        return None
+    arr = (ctypes.c_float * len(x))(*[float(v) for v in x])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """Three-layer SiLU perceptron trained on the GPU (include/nacme.h)."""
+
+    def __init__(self, n_in, width, n_out, seed=0, stream=None):
+        self._h = ctypes.c_void_p()
+        rc = lib().mlp_create(ctypes.byref(self._h), n_in, width, n_out, seed, _stream_ptr(stream))
+        if rc != CC_OK:
+            raise CCError(rc, "mlp_create failed")
+        self.n_in, self.width, self.n_out = n_in, width, n_out
+        self.num_params = int(lib().mlp_num_params(self._h))
+
+    def _check(self, rc):
+        if rc < 0:
+            raise CCError(rc, lib().mlp_last_error(self._h).decode())
+        return rc
+
+    def get_params(self, working=False):
+        import numpy as np
+        out = np.zeros(self.num_params, dtype=np.float32)
+        self._check(lib().mlp_get_params(
+            self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(working)))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        arr = np.ascontiguousarray(p, dtype=np.float32)
+        if arr.size != self.num_params:
+            raise ValueError("parameter count mismatch")
+        self._check(lib().mlp_set_params(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def forward(self, X, Y):
+        self._check(lib().mlp_forward(self._h, X.shape[0], _fptr(X), _fptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T, want_grad=True):
+        import numpy as np
+        loss = ctypes.c_double()
+        g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None
+        self._check(lib().mlp_loss_grad(self._h, X.shape[0], _fptr(X), _fptr(T), ctypes.byref(loss),
+                                        gp))
+        return loss.value, g
+
+    def adam_step(self, lr):
+        self._check(lib().mlp_adam_step(self._h, lr))
+
+    def train(self, X, T, batch, steps, lr, seed=0):
+        loss = ctypes.c_double()
+        self._check(lib().mlp_train(self._h, X.shape[0], _fptr(X), _fptr(T), batch, steps, lr, seed,
+                                    ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self._h:
+            lib().mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def eig_host(G):

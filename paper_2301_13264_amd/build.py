@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnacme.so")
-SOURCES = ["kernels.hip", "engine.cpp", "linalg.cpp", "cc.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "linalg.cpp", "cc.cpp", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions anywhere in the device code

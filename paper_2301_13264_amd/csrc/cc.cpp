@@ -797,6 +797,65 @@ __global__ void signed_max_partial(const double* x, int o, int v, int64_t n, dou
   }
 }
 
+// ------------------------------------------------ learned doubles guess
+// Features of doubles index e = ((i o + j) v + a) v + b: e_i, e_j, e_a, e_b,
+// D, (ia|jb), (ib|ja), -(ia|jb)/D, standardised with mu and 1/sd.
+__global__ void t2_features_kernel(const double* __restrict__ g, const double* __restrict__ eps,
+                                   int o, int v, const float* __restrict__ mu,
+                                   const float* __restrict__ isd, float* __restrict__ F) {
+  const int64_t n = o + v, tot = (int64_t)o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    const double ei = eps[i], ej = eps[j], ea = eps[o + a], eb = eps[o + b];
+    const double D = ea + eb - ei - ej;
+    const double giajb = g[((i * n + o + a) * n + j) * n + o + b];
+    const double gibja = g[((i * n + o + b) * n + j) * n + o + a];
+    const double f[8] = {ei, ej, ea, eb, D, giajb, gibja, -giajb / D};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) F[e * 8 + k] = (float)((f[k] - (double)mu[k]) * (double)isd[k]);
+  }
+}
+
+// z = (-D t - (ia|jb)) / scale (target) or t = -((ia|jb) + scale z) / D (guess)
+__global__ void t2_map_kernel(const double* __restrict__ g, const double* __restrict__ eps, int o,
+                              int v, double* __restrict__ t2, float* __restrict__ z, double scale,
+                              int to_amplitudes) {
+  const int64_t n = o + v, tot = (int64_t)o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    const double D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
+    const double giajb = g[((i * n + o + a) * n + j) * n + o + b];
+    if (to_amplitudes)
+      t2[e] = -(giajb + scale * (double)z[e]) / D;
+    else
+      z[e] = (float)((-D * t2[e] - giajb) / scale);
+  }
+}
+
+static float* feature_norm(Ctx& c, const float* mu, const float* sd) {
+  float h[16];
+  for (int k = 0; k < 8; ++k) {
+    h[k] = mu ? mu[k] : 0.0f;
+    const float s = sd ? sd[k] : 1.0f;
+    if (!(s > 0.0f)) throw Error(-1, "feature scales must be positive");
+    h[8 + k] = 1.0f / s;
+  }
+  float* d = (float*)c.eng->arena().alloc(8);
+  hip_check(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, c.s), "H2D");
+  sync(c);
+  return d;
+}
+
 static double signed_max(Ctx& c, const double* x) {
   const int nbk = 256;
   ArenaScope sc(c.eng->arena());
@@ -1554,6 +1613,72 @@ int cc_set_guess(cc_ctx* c, int what, int idx, const double* src) {
   if (!src || what != CC_T) return CC_ERR_ARG;
   try {
     nm::copy_d(*c, c->t, src, c->N);
+    c->have_guess = true;
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_t2_features(cc_ctx* c, const float* mu, const float* sd, float* F) {
+  ABI_GUARD(c);
+  if (!F) return CC_ERR_ARG;
+  try {
+    nm::ArenaScope sc(c->eng->arena());
+    const float* nrm = nm::feature_norm(*c, mu, sd);
+    const int64_t tot = (int64_t)c->o * c->o * c->v * c->v;
+    const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(nm::t2_features_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o,
+                       c->v, nrm, nrm + 8, F);
+    nm::hip_check(hipGetLastError(), "t2 features");
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_t2_target(cc_ctx* c, float scale, float* Z) {
+  ABI_GUARD(c);
+  if (c->stage < 1) { c->err = "cc_t2_target before cc_ground"; return CC_ERR_STATE; }
+  if (!Z || !(scale > 0.0f)) return CC_ERR_ARG;
+  try {
+    const int64_t tot = (int64_t)c->o * c->o * c->v * c->v, nov = (int64_t)c->o * c->v;
+    const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o, c->v,
+                       c->t + nov, Z, (double)scale, 0);
+    nm::hip_check(hipGetLastError(), "t2 target");
+    nm::sync(*c);
+    return CC_OK;
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int cc_guess_t2(cc_ctx* c, nm_mlp* net, const float* mu, const float* sd, float scale) {
+  ABI_GUARD(c);
+  int ni = 0, no = 0;
+  if (!net || mlp_dims(net, &ni, nullptr, &no) != CC_OK || ni != 8 || no != 1 || !(scale > 0.0f))
+    return CC_ERR_ARG;
+  try {
+    nm::ArenaScope sc(c->eng->arena());
+    const int64_t tot = (int64_t)c->o * c->o * c->v * c->v, nov = (int64_t)c->o * c->v;
+    float* F = (float*)c->eng->arena().alloc(tot * 4);
+    float* Z = (float*)c->eng->arena().alloc((tot + 1) / 2);
+    const int rc = cc_t2_features(c, mu, sd, F);
+    if (rc != CC_OK) return rc;
+    if (mlp_forward(net, tot, F, Z) != CC_OK) {
+      c->err = std::string("network evaluation failed: ") + mlp_last_error(net);
+      return CC_ERR_HIP;
+    }
+    nm::kc(nm::fill(c->s, c->t, 0.0, nov), "fill");
+    const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o, c->v,
+                       c->t + nov, Z, (double)scale, 1);
+    nm::hip_check(hipGetLastError(), "t2 guess");
+    // the network sees (i, a) and (j, b) in order: restore t_ij^ab = t_ji^ba
+    nm::kc(nm::apply_metric(c->s, c->t, c->t, c->o, c->v, 2), "symmetrise");
     c->have_guess = true;
     nm::sync(*c);
     return CC_OK;

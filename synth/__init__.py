@@ -127,3 +127,21 @@ def random_hamiltonian(n: int, naux: int, seed: int, sigma: float = 0.1):
     h = 0.5 * (h + h.T)
     B = symmetric_factor(naux, n, sigma, rng)
     return h, B
+
+
+def perturbed_factor(B: np.ndarray, seed: int, scale: float = 0.01) -> np.ndarray:
+    """A perturbed geometry of the learned-guess workload: the factor of an
+    orbital rotation U = exp(K) of the same system, B[P] -> U^T B[P] U, with
+    K antisymmetric and K_pq ~ N(0, scale^2) for p < q.  (A rotation of the
+    auxiliary index alone would leave the integrals unchanged.)  The orbital
+    energies stay as they are, so the perturbed system is again canonical."""
+    from scipy.linalg import expm
+    n = B.shape[1]
+    rng = np.random.default_rng(seed)
+    K = np.zeros((n, n))
+    iu = np.triu_indices(n, 1)
+    K[iu] = rng.normal(scale=scale, size=iu[0].size)
+    K = K - K.T
+    U = expm(K)
+    out = np.einsum("pq,Ppr,rs->Pqs", U, B, U, optimize=True)
+    return np.ascontiguousarray(0.5 * (out + out.transpose(0, 2, 1)))
