@@ -74,6 +74,60 @@ def run_step(nm, torch, inp, cfg, opts):
                      stage_s=st)
 
 
+# HBM traffic of one ladder GEMM launch (M = o^2 = 1089, N = K = v^2 = 16129),
+# from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of `bench.py --roofline-only`
+# (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
+# ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
+# None until taken for the current kernels.
+LADDER_TRAFFIC_BYTES = {"fp64": None, "fp32": None}
+
+
+def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
+    """Ladder GEMM roofline: Y[ij][ab] = sum_cd t[ij][cd] W[cd][ab], one launch of
+    the matrix-core GEMM (M = o^2, N = K = v^2) per operand precision, timed
+    with HIP events on the stream the kernel is launched on."""
+    o, v = cfg["o"], cfg["v"]
+    ladder_flop = 2.0 * o * o * v ** 4
+    roof = {}
+    for pname, pcode, dt, peak in [("fp64", 0, torch.float64, PEAK_FP64_TFLOPS),
+                                   ("fp32", 1, torch.float32, PEAK_FP32_TFLOPS)]:
+        A = torch.randn(o * o, v * v, dtype=dt, device=dev)
+        Bv = torch.randn(v * v, v * v, dtype=dt, device=dev)
+        C = torch.zeros(o * o, v * v, dtype=torch.float64, device=dev)
+        nm.gemm(pcode, A, Bv, C, stream=st)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        for _ in range(nl):
+            nm.gemm(pcode, A, Bv, C, stream=st)
+        ev1.record(st)
+        ev1.synchronize()
+        lms = ev0.elapsed_time(ev1) / nl
+        tf = ladder_flop / (lms * 1e-3) / 1e12
+        roof[pname] = dict(bound="mfma", achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak,
+                           traffic=LADDER_TRAFFIC_BYTES[pname], launch_ms=lms,
+                           flop_per_launch=ladder_flop,
+                           algorithmic_bytes=(A.numel() + Bv.numel()) * A.element_size()
+                           + 8 * C.numel())
+        del A, Bv, C
+    roof["fp64"]["kernel"] = "gemm_f64_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp64 operands)"
+    roof["fp32"]["kernel"] = ("gemm_f32acc_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp32 "
+                              "operands, fp32 accumulation)")
+    return roof
+
+
+def roofline_only(nm, torch, cfg, dev):
+    """The ladder launches alone, plus a 1 GiB device copy that calibrates the
+    HBM byte counters (for rocprofv3 --pmc runs)."""
+    st = torch.cuda.current_stream()
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    roof = ladder_roofline(nm, torch, cfg, dev, st, nl=3)
+    print(json.dumps(dict(mode="roofline-only", copy_bytes=src.numel() * 8, ladder=roof)),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +139,8 @@ def main():
                     help="precision of the timed steps")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the step in the other precision")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the ladder GEMM launches and a copy calibration (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -99,6 +155,9 @@ def main():
 
     cfg = WORKLOAD
     dev = torch.device("cuda:0")
+    if args.roofline_only:
+        roofline_only(nm, torch, cfg, dev)
+        return
     sysd = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=SIGMA_B)
     dirs = synth.make_directions(cfg["o"] + cfg["v"], cfg["naux"], cfg["seed"], cfg["ndir"],
                                  sigma_b=SIGMA_B)
@@ -171,32 +230,8 @@ def main():
         log(f"[bench] {oname}: {c1 - c0:.2f} s, max|dF| = {dF:.3e} "
             f"stages={ {k: round(x, 2) for k, x in oout['stage_s'].items()} }")
 
-    # Ladder GEMM roofline: Y[ij][ab] = sum_cd t[ij][cd] W[cd][ab], one launch of
-    # the matrix-core GEMM (M = o^2, N = K = v^2) in each operand precision.
     o, v = cfg["o"], cfg["v"]
-    ladder_flop = 2.0 * o * o * v ** 4
-    roof = {}
-    for pname, pcode, dt, peak in [("fp64", 0, torch.float64, PEAK_FP64_TFLOPS),
-                                   ("fp32", 1, torch.float32, PEAK_FP32_TFLOPS)]:
-        A = torch.randn(o * o, v * v, dtype=dt, device=dev)
-        Bv = torch.randn(v * v, v * v, dtype=dt, device=dev)
-        C = torch.zeros(o * o, v * v, dtype=torch.float64, device=dev)
-        nm.gemm(pcode, A, Bv, C, stream=st)
-        nl = 10
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(st)
-        for _ in range(nl):
-            nm.gemm(pcode, A, Bv, C, stream=st)
-        ev1.record(st)
-        ev1.synchronize()
-        lms = ev0.elapsed_time(ev1) / nl
-        tf = ladder_flop / (lms * 1e-3) / 1e12
-        roof[pname] = dict(bound="mfma", achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak,
-                           traffic=None, launch_ms=lms, flop_per_launch=ladder_flop)
-        del A, Bv, C
-    roof["fp64"]["kernel"] = "gemm_f64_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp64 operands)"
-    roof["fp32"]["kernel"] = ("gemm_f32acc_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp32 "
-                              "operands, fp32 accumulation)")
+    roof = ladder_roofline(nm, torch, cfg, dev, st)
     main_roof = roof["fp32"] if args.precision == "mixed" else roof["fp64"]
 
     # CPU baseline: the oracle's residual at the same size on the host cores

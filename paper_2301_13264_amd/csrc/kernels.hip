@@ -121,6 +121,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 //    between successive k rows, so the two half-waves read disjoint banks).
 // Tiles are ordered so that the M tiles sharing one B column tile run back to
 // back on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+// Workgroups are dealt round-robin over the 8 XCDs (workgroup b runs on XCD
+// b % 8).  XCD x is given a contiguous range of tile indices (a bijection on
+// [0, total) for any total), so that tiles sharing operand panels run on the
+// same XCD at the same time and meet in its L2.
+__device__ inline int xcd_tile(int b, int total) {
+  const int per = total >> 3, rem = total & 7;
+  const int x = b & 7, s = b >> 3;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + s;
+}
+
 constexpr int LBM = 128, LBN = 128, LBK = 16;
 constexpr int LKS = LBK + 1;     // [row][k] stride
 constexpr int LRS = 128 + 16;    // [k][row] stride
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(NT, 4) void gemm_f64_big_kernel(
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy;
   int bid = blockIdx.x + gx * blockIdx.y;
-  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  bid = xcd_tile(bid, total);
   const int tm = bid % gy, tn = bid / gy;
   const int m0 = tm * LBM, n0 = tn * LBN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy;
   int bid = blockIdx.x + gx * blockIdx.y;
-  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  bid = xcd_tile(bid, total);
   const int tm = bid % gy, tn = bid / gy;
   const int m0 = tm * LBM, n0 = tn * LBN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
