@@ -1232,6 +1232,30 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
   return status;
 }
 
+// A <- (A + A^T) / 2 for a square m x m matrix, in 64 x 64 tile pairs
+// (tile (bi, bj) with bi <= bj and its mirror) staged through LDS so that every
+// read and write runs along rows.
+__global__ __launch_bounds__(256) void pair_sym_kernel(double* __restrict__ A, int64_t m) {
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  __shared__ double s1[64][65], s2[64][65];
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int64_t r0 = bi * 64, c0 = bj * 64;
+  for (int r = row; r < 64; r += 4) {
+    const int64_t gr = r0 + r, gc = c0 + lane;
+    s1[r][lane] = (gr < m && gc < m) ? A[gr * m + gc] : 0.0;      // A[r0 + r][c0 + l]
+    const int64_t hr = c0 + r, hc = r0 + lane;
+    s2[r][lane] = (hr < m && hc < m) ? A[hr * m + hc] : 0.0;      // A[c0 + r][r0 + l]
+  }
+  __syncthreads();
+  for (int r = row; r < 64; r += 4) {
+    const int64_t gr = r0 + r, gc = c0 + lane;
+    if (gr < m && gc < m) A[gr * m + gc] = 0.5 * (s1[r][lane] + s2[lane][r]);
+    const int64_t hr = c0 + r, hc = r0 + lane;
+    if (hr < m && hc < m) A[hr * m + hc] = 0.5 * (s2[r][lane] + s1[lane][r]);
+  }
+}
+
 // D_eff = dPhi/df + kappa-bar embedded in the vo block; the two-electron
 // density Gamma = dPhi/dg + 2 D_eff(pq) delta_rs(occ) - D_eff(ps) delta_qr(occ)
 // so that F^q = sum D_eff dh^q + sum Gamma dg^q.
@@ -1283,6 +1307,13 @@ static void densities_impl(Ctx& c, int i1, int j1) {
     dst.str[0] = n * n * n; dst.str[1] = 1; dst.str[2] = n * n + n;   // Gam[p][k][k][q]
     c.eng->linear(-1.0, src, dst);
   }
+  // only the part of Gamma symmetric under (pq) <-> (rs) meets the symmetric
+  // dg^q; keeping that part lets the coupling GEMM read Gamma untransposed
+  {
+    const int64_t m = (int64_t)c.n * c.n, t = (m + 63) / 64;
+    hipLaunchKernelGGL(pair_sym_kernel, dim3((unsigned)t, (unsigned)t), dim3(256), 0, c.s, P.Gam, m);
+    hip_check(hipGetLastError(), "pair symmetrisation");
+  }
   P.have_dens = true;
 }
 
@@ -1297,9 +1328,10 @@ static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const d
     const double* dhq = dh + (int64_t)q * nn;
     const double* dBq = dB + (int64_t)q * naux * nn;
     const double f1 = dot_plain(c, P.Deff, dhq, nn);
-    // Z[P][pq] = sum_rs dB[P][rs] Gamma[pq][rs];  F2 = sum_P,pq Z[P][pq] dB[P][pq]
-    kc(gemm_f64(c.s, false, true, (int)naux, (int)nn, (int)nn, 1, 1.0, dBq, nn, 0, P.Gam, nn, 0, 0.0, Z,
-                nn, 0),
+    // Z[P][pq] = sum_rs dB[P][rs] Gamma[rs][pq] (Gamma symmetric over the pair
+    // exchange);  F2 = sum_P,pq Z[P][pq] dB[P][pq]
+    kc(gemm_f64(c.s, false, false, (int)naux, (int)nn, (int)nn, 1, 1.0, dBq, nn, 0, P.Gam, nn, 0, 0.0,
+                Z, nn, 0),
        "nacme gemm");
     const double f2 = dot_plain(c, Z, dBq, naux * nn);
     F[q] = f1 + f2;

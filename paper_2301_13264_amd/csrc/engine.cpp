@@ -666,29 +666,35 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
   const bool big = M >= 128 && N >= 128;   // gemm_f64 then runs 128 x 128 tiles
   const int64_t tiles = big ? ((M + 127) / 128) * ((N + 127) / 128) * nb
                             : ((M + 63) / 64) * ((N + 63) / 64) * nb;
+  // K split of one product (pointers of batch entry b): split-K GEMM in one
+  // launch (K chunks on grid.z, the last possibly shorter), partials folded
+  // in a fixed order
   int64_t ns = 1;
-  if (nb == 1 && big) {
-    ns = big_split(tiles, K, M * N, kF64UsPerK);
-  } else if (nb == 1 && tiles < 512 && K >= 4096) {
-    // split K so that the grid fills the device; partials folded in order
+  if (big) {
+    if (nb == 1) ns = big_split(tiles, K, M * N, kF64UsPerK);
+  } else if (tiles < 512 && K >= 4096) {
     ns = std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), K / 1024);
     ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
   }
+  // a few batch entries that leave the device idle are run one by one,
+  // each split over K
+  if (nb > 64) ns = 1;
   if (ns > 1) {
     const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
     ns = (K + kc - 1) / kc;
     double* part = arena_.alloc(ns * M * N);
-    // one launch: K chunks on grid.z, the last chunk possibly shorter
     const int64_t klast = K - (ns - 1) * kc;
-    kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kc, (int)ns, 1.0, pa, lda,
-                    ta ? kc * lda : kc, pb, ldb, tb ? kc : kc * ldb, 0.0, part, N, M * N,
-                    (int)klast),
-           "gemm(splitk)");
-    const int64_t tot = M * N;
-    const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc, ldc, part, (int)M,
-                       (int)N, (int)ns, a_, b_);
-    kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+    for (int64_t b = 0; b < nb; ++b) {
+      kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kc, (int)ns, 1.0, pa + b * sA, lda,
+                      ta ? kc * lda : kc, pb + b * sB, ldb, tb ? kc : kc * ldb, 0.0, part, N, M * N,
+                      (int)klast),
+             "gemm(splitk)");
+      const int64_t tot = M * N;
+      const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+      hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc + b * sC, ldc, part,
+                         (int)M, (int)N, (int)ns, a_, b_);
+      kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+    }
   } else {
     kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)K, (int)nb, a_, pa, lda, sA, pb, ldb, sB, b_,
                     pc, ldc, sC),
