@@ -31,6 +31,8 @@ def _right_state_at(st, j, h, g, t_init):
     o, v = st["o"], st["v"]
     t1, t2, _, _ = ccsd.solve_ground(h, g, o, tol=1e-12, t_init=t_init)
     x = ccsd.pack(t1, t2)
+    if j == response.GROUND:      # exp(T)|HF>, intermediate normalisation
+        return t1, t2, x, 1.0, torch.zeros_like(x)
     A = response.dense_jacobian(x, h, g, o, v).numpy()
     w, vr = scipy.linalg.eig(A)
     k = int(np.argmin(np.abs(w - float(st["omega"][j]))))
@@ -98,7 +100,8 @@ class CIStates:
 
     def ket0(self, j):
         st = self.st
-        return self.ket(st["t1"], st["t2"], st["R0"][j], st["R"][j])
+        _, R0, R = response.right_state(st, j)
+        return self.ket(st["t1"], st["t2"], R0, R)
 
 
 def fd_relaxed(st, i, j, dh, dg, delta=1e-4, ci: CIStates | None = None):
@@ -130,8 +133,10 @@ def transition_density_ci(st, i, j, ci: CIStates | None = None):
 
 
 def hellmann_feynman_two_electron(st, i, j, dh, dg, ci: CIStates | None = None):
-    """For exact (o = 1) states: <psi_i^L| H^q |psi_j^R> / (omega_j - omega_i)."""
+    """For exact (o = 1) states: <psi_i^L| H^q |psi_j^R> / (omega_j - omega_i)
+    (omega = 0 for the ground state)."""
     ci = ci or CIStates(st)
     b, c = ci.bra(i), ci.ket0(j)
     Hc = ci.ds.H(np.asarray(dh), np.asarray(dg), c)
-    return float(np.sum(b * Hc)) / float(st["omega"][j] - st["omega"][i])
+    wj = response.right_state(st, j)[0]
+    return float(np.sum(b * Hc)) / float(wj - st["omega"][i])

@@ -170,6 +170,18 @@ def hf_hessian(h, g, o, v):
 
 
 # ------------------------------------------------------------ multipliers
+GROUND = -1   # index of the CC ground state when it is the right state of a pair
+
+
+def right_state(st: dict, j: int):
+    """(omega_j, R0_j, R_j) of the right state j of a pair.  The ground state
+    exp(T)|HF> (Sec. II C, j = 0) has R0 = 1, R = 0 and no EOM condition, so
+    every gamma term of the Lagrangian vanishes with it."""
+    if j == GROUND:
+        return 0.0, 1.0, torch.zeros_like(st["x"])
+    return st["omega"][j], st["R0"][j], st["R"][j]
+
+
 def lagrangian_hamiltonian_part(x, gamma, zeta, Rj, h, g, o, v):
     """gamma . A(t; h, g) R_j + zeta . Omega(t; h, g)."""
     return (torch.dot(gamma, right_transform(x, Rj, h, g, o, v))
@@ -177,7 +189,7 @@ def lagrangian_hamiltonian_part(x, gamma, zeta, Rj, h, g, o, v):
 
 
 def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
-    """Multipliers of the ordered excited-state pair (i, j), i != j.
+    """Multipliers of the ordered pair (i, j), i != j excited, or j = GROUND.
 
     gamma = L_i/(omega_j - omega_i) and xi = -omega_j gamma.R_j (Sec. II B);
     t-stationarity A^T zeta = -eta_t with
@@ -188,10 +200,11 @@ def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
     """
     o, v, h, g, x = st["o"], st["v"], st["h"], st["g"], st["x"]
     n = o + v
-    om, R, L, R0 = st["omega"], st["R"], st["L"], st["R0"]
-    Li, Rj, R0j = L[i], R[j], R0[j]
-    gamma = Li / (om[j] - om[i])
-    xi = -om[j] * torch.dot(gamma, Rj)
+    om, L = st["omega"], st["L"]
+    Li = L[i]
+    wj, R0j, Rj = right_state(st, j)
+    gamma = torch.zeros_like(Li) if j == GROUND else Li / (wj - om[i])
+    xi = -wj * torch.dot(gamma, Rj)
     # eta_t
     zero = torch.zeros_like(x)
     eta_o = grad(lambda d: overlap(d, Li, R0j, Rj, o, v))(zero)
@@ -224,7 +237,7 @@ def coupling_direct(st: dict, mult: dict, j: int, dh, dg) -> float:
     """F^q = gamma.(A(t; H^q) R_j) + zeta.Omega(t; H^q) + kappa_bar.F^q_ai (Sec. II C)."""
     o, v, x = st["o"], st["v"], st["x"]
     dh, dg = as_t(dh), as_t(dg)
-    val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"], st["R"][j],
+    val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"], right_state(st, j)[2],
                                       dh, dg, o, v)
     val = val + torch.sum(mult["kappa_bar"] * fock_ai(dh, dg, o))
     return float(val)
@@ -243,7 +256,7 @@ def effective_densities(st: dict, mult: dict, j: int):
 
     def functional(h, g):
         val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"],
-                                          st["R"][j], h, g, o, v)
+                                          right_state(st, j)[2], h, g, o, v)
         return val + torch.sum(mult["kappa_bar"] * fock_ai(h, g, o))
 
     h0 = torch.zeros((n, n), dtype=DT)

@@ -209,3 +209,56 @@ def test_gauge_invariant_product_two_electrons():
     mij = rs.multipliers(st, 0, 1)
     mji = rs.multipliers(st, 1, 0)
     assert rs.coupling_direct(st, mij, 1, dh, dg) * rs.coupling_direct(st, mji, 0, dh, dg) <= 0
+
+
+# ----------------------------------------------- ground-state right state
+GROUND = rs.GROUND
+
+
+@pytest.mark.parametrize("o,v", [(1, 5), (2, 3), (3, 9)])
+def test_ground_pair_zeta_closed_form(o, v):
+    """j = ground state: the solved t-multipliers equal -L_i / omega_i
+    (= L_i / (E0 - E_i)); only kappa-bar needs a solve."""
+    st = solved(o, v)
+    for i in range(2):
+        m = rs.multipliers(st, i, GROUND, relaxed=True)
+        ref = -st["L"][i] / st["omega"][i]
+        assert torch.abs(m["zeta"] - ref).max() < 1e-10 * max(1.0, float(ref.abs().max()))
+        assert torch.abs(m["gamma"]).max() == 0.0
+
+
+def test_ground_pair_two_electron_closed_form():
+    """Exact states: F_i0 = <psi_i^L|H^q|psi_0^R>/(E0 - E_i), and the orbital
+    response vanishes for two electrons."""
+    st = solved(1, 6)
+    ci = fd.CIStates(st)
+    for i in range(3):
+        m = rs.multipliers(st, i, GROUND, relaxed=True)
+        assert torch.abs(m["kappa_bar"]).max() < 1e-10
+        for dh, dg in directions(st, 2):
+            F = rs.coupling_direct(st, m, GROUND, dh, dg)
+            assert abs(F - fd.hellmann_feynman_two_electron(st, i, GROUND, dh, dg, ci)) < 1e-9
+
+
+@pytest.mark.parametrize("o,v", [(1, 10), (3, 9)])
+def test_ground_pair_unrelaxed_matches_finite_difference(o, v):
+    st = solved(o, v)
+    (dh, dg), = directions(st, 1)
+    for i in range(2):
+        m = rs.multipliers(st, i, GROUND, relaxed=False)
+        F = rs.coupling_direct(st, m, GROUND, dh, dg)
+        Fr = fd.richardson(lambda d: fd.fd_unrelaxed(st, i, GROUND, dh, dg, delta=d), 1e-4)
+        assert abs(F - Fr) < 1e-7 * max(1.0, abs(F))
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 9)])
+def test_ground_pair_relaxed_matches_finite_difference(o, v):
+    st = solved(o, v)
+    ci = fd.CIStates(st)
+    (dh, dg), = directions(st, 1)
+    m = rs.multipliers(st, 0, GROUND, relaxed=True)
+    F = rs.coupling_direct(st, m, GROUND, dh, dg)
+    Fr = fd.richardson(lambda d: fd.fd_relaxed(st, 0, GROUND, dh, dg, delta=d, ci=ci), 1e-4)
+    assert abs(F - Fr) < 1e-7 * max(1.0, abs(F))
+    D, d = rs.effective_densities(st, m, GROUND)
+    assert abs(rs.coupling_from_densities(D, d, dh, dg) - F) < 1e-12 * max(1.0, abs(F))
