@@ -124,11 +124,14 @@ int cc_ground(cc_ctx* ctx, double* e_corr, int* iters);
  * -6 if a requested root is complex.                                        */
 int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
 
-/* Multipliers of the ordered pair (i, j), 1 <= i != j <= nroots:
- * gamma = L_i/(omega_j - omega_i), xi = 0 (Sec. II B); zeta-bar from
- * A^T zeta = -eta_t (eq. amplituderelax) and, when relaxed, kappa-bar from
- * (A^HF)^T kappa = -eta_kappa (eq. orbitalrelax).  iters: host [2] or NULL
- * (zeta and kappa iterations).                                               */
+/* Multipliers of the ordered pair (i, j), 1 <= i <= nroots, 0 <= j <=
+ * nroots, i != j: gamma = L_i/(omega_j - omega_i), xi = 0 (Sec. II B); zeta-bar
+ * from A^T zeta = -eta_t (eq. amplituderelax) and, when relaxed, kappa-bar
+ * from (A^HF)^T kappa = -eta_kappa (eq. orbitalrelax).  j = 0 couples the
+ * excited left state i to the CC ground state exp(T)|HF> (R0 = 1, R = 0):
+ * gamma = 0 and zeta = -L_i/omega_i in closed form (Sec. II C); only
+ * kappa-bar is solved.  densities() and nacme() then give F_i0.  iters: host
+ * [2] or NULL (zeta and kappa iterations).                                   */
 int multipliers(cc_ctx* ctx, int i, int j, int* iters);
 
 /* Effective densities of the pair (i, j): D_eff (n x n) and the two-electron

@@ -1099,53 +1099,78 @@ static PairData& pair_of(Ctx& c, int i, int j) {
 static int64_t n4(Ctx& c) { return (int64_t)c.n * c.n * c.n * c.n; }
 
 static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
+  // j1 = 0: the right state is the ground state exp(T)|HF> (R0 = 1, R = 0, no
+  // EOM condition, so gamma = 0), and A^T zeta = -L_i has the closed-form
+  // solution zeta = -L_i / omega_i (L_i is a left eigenvector) (Sec. II C)
+  const bool ground = (j1 == 0);
   const int i = i1 - 1, j = j1 - 1;
   const int64_t N = c.N, nov = (int64_t)c.o * c.v, nn = (int64_t)c.n * c.n;
   PairData& P = pair_of(c, i1, j1);
-  const double wi = c.omega_r[i], wj = c.omega_r[j];
-  axpby_(c, P.gamma, c.L[i], 1.0 / (wj - wi), 0.0, N);
+  const double wi = c.omega_r[i];
+  const double R0j = ground ? 1.0 : c.R0[j];
+  if (ground)
+    kc(fill(c.s, P.gamma, 0.0, N), "fill");
+  else
+    axpby_(c, P.gamma, c.L[i], 1.0 / (c.omega_r[j] - wi), 0.0, N);
   Arena& ar = c.eng->arena();
   int status = CC_OK;
   int it_z = 0, it_k = 0;
   {
     Tape tp(c);
     // JVP along R_j, kept on the tape
-    const int r1 = tp.G.leaf(T1of(c, c.R[j])), r2 = tp.G.leaf(T2of(c, c.R[j]));
-    auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
-    const int ar1 = tan.at(tp.r.om1), ar2 = tan.at(tp.r.om2);
+    int ar1 = -1, ar2 = -1;
+    if (!ground) {
+      const int r1 = tp.G.leaf(T1of(c, c.R[j])), r2 = tp.G.leaf(T2of(c, c.R[j]));
+      auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
+      ar1 = tan.at(tp.r.om1);
+      ar2 = tan.at(tp.r.om2);
+    }
     ArenaScope sc(ar);
     double* wg = ar.alloc(N);     // metric-weighted gamma
     kc(apply_metric(c.s, wg, P.gamma, c.o, c.v, 0), "metric");
     double* tmp = ar.alloc(N);
     // F-matrix term: d/dt [gamma . A(t) R_j]
-    {
+    if (!ground) {
       ArenaScope s2(ar);
       auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}}, {tp.r.t1, tp.r.t2});
       copy_d(c, tmp, adj[tp.r.t1].p, nov);
       copy_d(c, tmp + nov, adj[tp.r.t2].p, N - nov);
       kc(apply_metric(c.s, P.eta_t, tmp, c.o, c.v, 1), "metric");
+    } else {
+      kc(fill(c.s, P.eta_t, 0.0, N), "fill");
     }
     // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
     {
       ArenaScope s2(ar);
       Graph Gs(*c.eng);
-      const int l2 = Gs.leaf(T2of(c, c.L[i])), rr1 = Gs.leaf(T1of(c, c.R[j]));
-      const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
-                                          mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
-      axpby_(c, P.eta_t, c.L[i], c.R0[j], 1.0, N);
-      axpby_(c, P.eta_t, Gs.val(sn).p, 1.0, 1.0, nov);
+      const double* sv = nullptr;
+      if (!ground) {
+        const int l2 = Gs.leaf(T2of(c, c.L[i])), rr1 = Gs.leaf(T1of(c, c.R[j]));
+        const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
+                                            mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
+        sv = Gs.val(sn).p;
+      }
+      axpby_(c, P.eta_t, c.L[i], R0j, 1.0, N);
+      if (sv) axpby_(c, P.eta_t, sv, 1.0, 1.0, nov);
       // transition density D_pq = <L_i| E_pq |R_j>: seeds L_i on A R_j,
       // R0_j L_i + s on Omega (singles), wrt f
       double* wl = ar.alloc(N);
       kc(apply_metric(c.s, wl, c.L[i], c.o, c.v, 0), "metric");
       double* sp = ar.alloc(N);
-      axpby_(c, sp, wl, c.R0[j], 0.0, N);
-      axpby_(c, sp, Gs.val(sn).p, 1.0, 1.0, nov);
-      auto adj = tp.G.vjp({{ar1, wl}, {ar2, wl + nov}, {tp.r.om1, sp}, {tp.r.om2, sp + nov}}, {tp.r.f});
+      axpby_(c, sp, wl, R0j, 0.0, N);
+      if (sv) axpby_(c, sp, sv, 1.0, 1.0, nov);
+      std::map<int, const double*> seeds{{tp.r.om1, sp}, {tp.r.om2, sp + nov}};
+      if (!ground) {
+        seeds[ar1] = wl;
+        seeds[ar2] = wl + nov;
+      }
+      auto adj = tp.G.vjp(seeds, {tp.r.f});
       copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
     }
     // zeta: A^T zeta = -eta_t
-    {
+    if (ground) {
+      axpby_(c, P.zeta, c.L[i], -1.0 / wi, 0.0, N);
+    } else {
       double* b = ar.alloc(N);
       axpby_(c, b, P.eta_t, -1.0, 0.0, N);
       auto T = [&](const double* x, double* y) { tp.left(x, y); };
@@ -1160,8 +1185,12 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       double* wz = ar.alloc(N);
       kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
       ArenaScope s2(ar);
-      auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}, {tp.r.om1, wz}, {tp.r.om2, wz + nov}},
-                          {tp.r.f, tp.r.g, tp.r.w, tp.r.wov});
+      std::map<int, const double*> seeds{{tp.r.om1, wz}, {tp.r.om2, wz + nov}};
+      if (!ground) {
+        seeds[ar1] = wg;
+        seeds[ar2] = wg + nov;
+      }
+      auto adj = tp.G.vjp(seeds, {tp.r.f, tp.r.g, tp.r.w, tp.r.wov});
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
       if (!P.Gbar) P.Gbar = palloc(c, n4(c));
       copy_d(c, P.Gbar, adj[tp.r.g].p, n4(c));
@@ -1503,8 +1532,8 @@ int eom_solve(cc_ctx* c, int side, int nroots, double* omega, int* iters) {
 int multipliers(cc_ctx* c, int i, int j, int* iters) {
   ABI_GUARD(c);
   if (!c->gauged) { c->err = "multipliers before right and left EOM states"; return CC_ERR_STATE; }
-  if (i < 1 || j < 1 || i > c->nroots || j > c->nroots || i == j) {
-    c->err = "pair indices must satisfy 1 <= i != j <= nroots";
+  if (i < 1 || j < 0 || i > c->nroots || j > c->nroots || i == j) {
+    c->err = "pair indices must satisfy 1 <= i <= nroots, 0 <= j <= nroots, i != j";
     return CC_ERR_ARG;
   }
   try {

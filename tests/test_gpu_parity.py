@@ -151,6 +151,43 @@ def test_pipeline_matches_oracle(nm, o, v, naux, seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 5, 18, None), (2, 4, 18, None), (4, 12, 48, 2301)])
+def test_ground_pair_couplings_match_oracle(nm, o, v, naux, seed):
+    """F_i0: excited left state i, CC ground state on the right (j = 0)."""
+    say(f"[ground pair] o={o} v={v}")
+    seed = synth.exact_check_seed(o, v) if seed is None else seed
+    st = oracle_state(o, v, naux, seed, 2)
+    sysd = st["sys"]
+    n = o + v
+    dirs = synth.make_directions(n, naux, seed + 17, 2)
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    ctx.ground()
+    ctx.eom(nm.CC_BOTH, 2)
+    Nf = o * v + (o * v) ** 2
+    buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+    for i in range(2):
+        m = rs.multipliers(st, i, rs.GROUND, relaxed=True)
+        ctx.multipliers(i + 1, 0)
+        zeta = to_packed(ctx.export(nm._lib.CC_ZETA, i + 1, 0, buf).cpu().numpy(), o, v)
+        assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7
+        kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
+        ek = ctx.export(nm._lib.CC_ETA_K, i + 1, 0, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(ek - m["eta_kappa"].numpy()).max() < 1e-7
+        kb = ctx.export(nm._lib.CC_KAPPA, i + 1, 0, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(kb - m["kappa_bar"].numpy()).max() < 1e-7
+        D1 = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        ctx.densities(i + 1, 0, D1)
+        Dref, _ = rs.effective_densities(st, m, rs.GROUND)
+        Dg = D1.cpu().numpy()
+        assert np.abs(0.5 * (Dg + Dg.T) - Dref.numpy()).max() < 1e-7
+        F = ctx.nacme(i + 1, 0, T(dirs["dh"]), T(dirs["dB"]))
+        for q in range(2):
+            dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+            Fo = rs.coupling_direct(st, m, rs.GROUND, dirs["dh"][q], dg)
+            assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
+    ctx.close()
+
+
 @pytest.mark.parametrize("spec,shapes,oshape", [
     ("ik,kj->ij", [(300, 70), (70, 260)], (300, 260)),
     ("ki,jk->ij", [(70, 300), (260, 70)], (300, 260)),
