@@ -140,3 +140,32 @@ def hellmann_feynman_two_electron(st, i, j, dh, dg, ci: CIStates | None = None):
     Hc = ci.ds.H(np.asarray(dh), np.asarray(dg), c)
     wj = response.right_state(st, j)[0]
     return float(np.sum(b * Hc)) / float(wj - st["omega"][i])
+
+
+def _state_energy_at(st, j, h, g):
+    """E_j = E0 + omega_j (E0 for the ground state) of the system (h, g),
+    the root nearest omega_j(0)."""
+    o, v = st["o"], st["v"]
+    t1, t2, E0, _ = ccsd.solve_ground(h, g, o, tol=1e-12, t_init=(st["t1"], st["t2"]))
+    if j == response.GROUND:
+        return E0
+    x = ccsd.pack(t1, t2)
+    w = scipy.linalg.eigvals(response.dense_jacobian(x, h, g, o, v).numpy())
+    k = int(np.argmin(np.abs(w - float(st["omega"][j]))))
+    return E0 + float(w[k].real)
+
+
+def fd_energy_gradient(st, j, dh, dg, delta=1e-4, relaxed=True):
+    """Central difference of E_j along (dh, dg); relaxed: Hartree-Fock
+    re-solved at lam (the energy is invariant to the orbital rotation)."""
+    o, v = st["o"], st["v"]
+    dh, dg = as_t(dh), as_t(dg)
+    vals = []
+    for lam in (delta, -delta):
+        h = st["h"] + lam * dh
+        g = st["g"] + lam * dg
+        if relaxed:
+            h, g = response.rotate(h, g, solve_hf(h, g, o, v), o, v)
+        vals.append(_state_energy_at(st, j, h, g))
+    return (vals[0] - vals[1]) / (2.0 * delta)
+

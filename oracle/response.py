@@ -274,6 +274,76 @@ def coupling_from_densities(D, d, dh, dg) -> float:
     return float(torch.sum(D * as_t(dh)) + 0.5 * torch.sum(d * as_t(dg)))
 
 
+# ------------------------------------------ state energies and their gradients
+def energy_lagrangian_part(x, Lj, zeta, Rj, h, g, o, v):
+    """E0(t; h, g) + L_j . A(t; h, g) R_j + zeta . Omega(t; h, g); the L_j term
+    is absent for the ground state (Lj None).  At the solution this equals
+    E_j = E0 + omega_j, because L_j . R_j = 1 and A R_j = omega_j R_j."""
+    val = energy_vec(x, h, g, o, v) + torch.dot(zeta, omega_vec(x, h, g, o, v))
+    if Lj is not None:
+        val = val + torch.dot(Lj, right_transform(x, Rj, h, g, o, v))
+    return val
+
+
+def gradient_multipliers(st: dict, j: int, relaxed: bool = True) -> dict:
+    """Multipliers of the energy of state j (j = GROUND: E0; else E0 + omega_j)
+    as a Lagrangian in the same stationarity conditions as the coupling
+    (Sec. II B): A^T zeta = -(dE0/dt + d/dt [L_j . A(t) R_j]) and
+    (A^HF)^T kappa_bar = -d/dkappa [E0 + L_j . A R_j + zeta . Omega]."""
+    o, v, h, g, x = st["o"], st["v"], st["h"], st["g"], st["x"]
+    if j == GROUND:
+        Lj = Rj = None
+        eta_t = eta(x, h, g, o, v)
+    else:
+        Lj, Rj = st["L"][j], st["R"][j]
+        eta_t = eta(x, h, g, o, v) + grad(
+            lambda y: torch.dot(Lj, right_transform(y, Rj, h, g, o, v)))(x)
+    A = st.get("A")
+    if A is None:
+        A = dense_jacobian(x, h, g, o, v)
+        st["A"] = A
+    zeta = torch.linalg.solve(A.T, -eta_t)
+    out = dict(L=Lj, R=Rj, eta_t=eta_t, zeta=zeta)
+    if relaxed:
+        k0 = torch.zeros((o, v), dtype=DT)
+        eta_k = grad(lambda k: energy_lagrangian_part(
+            x, Lj, zeta, Rj, *rotate(h, g, k, o, v), o, v))(k0)
+        AHF = hf_hessian(h, g, o, v)
+        kbar = torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
+        out.update(eta_kappa=eta_k, kappa_bar=kbar)
+    else:
+        out["kappa_bar"] = torch.zeros((o, v), dtype=DT)
+    return out
+
+
+def energy_gradient(st: dict, mult: dict, dh, dg) -> float:
+    """dE_j/dlam along (dh, dg): the Hamiltonian-linear part of the energy
+    Lagrangian evaluated with (dh, dg), plus kappa_bar . F^q_ai."""
+    o, v, x = st["o"], st["v"], st["x"]
+    dh, dg = as_t(dh), as_t(dg)
+    val = energy_lagrangian_part(x, mult["L"], mult["zeta"], mult["R"], dh, dg, o, v)
+    return float(val + torch.sum(mult["kappa_bar"] * fock_ai(dh, dg, o)))
+
+
+def gradient_densities(st: dict, mult: dict):
+    """(D[n,n], d[n,n,n,n]) with dE_j/dlam = sum D dh + 1/2 sum d dg."""
+    o, v, x = st["o"], st["v"], st["x"]
+    n = o + v
+
+    def functional(h, g):
+        val = energy_lagrangian_part(x, mult["L"], mult["zeta"], mult["R"], h, g, o, v)
+        return val + torch.sum(mult["kappa_bar"] * fock_ai(h, g, o))
+
+    Dh, Dg = grad(functional, argnums=(0, 1))(torch.zeros((n, n), dtype=DT),
+                                              torch.zeros((n, n, n, n), dtype=DT))
+    Dh = 0.5 * (Dh + Dh.T)
+    d = 2.0 * Dg
+    d = 0.5 * (d + d.permute(2, 3, 0, 1))
+    d = 0.5 * (d + d.permute(1, 0, 2, 3))
+    d = 0.5 * (d + d.permute(0, 1, 3, 2))
+    return Dh, d
+
+
 # -------------------------------------------------------------- pipeline
 def ground_and_eom(h, g, o: int, nroots: int, tol: float = 1e-11, t_init=None):
     """Solve CCSD and the lowest nroots right/left EOM states (dense)."""

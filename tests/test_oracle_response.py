@@ -262,3 +262,44 @@ def test_ground_pair_relaxed_matches_finite_difference(o, v):
     assert abs(F - Fr) < 1e-7 * max(1.0, abs(F))
     D, d = rs.effective_densities(st, m, GROUND)
     assert abs(rs.coupling_from_densities(D, d, dh, dg) - F) < 1e-12 * max(1.0, abs(F))
+
+
+# ------------------------------------------------ state-energy gradients
+@pytest.mark.parametrize("o,v,relaxed", [(1, 6, True), (2, 3, True), (3, 9, True), (3, 9, False)])
+def test_energy_gradient_matches_finite_difference(o, v, relaxed):
+    """dE_j/dlam of the ground (j = GROUND) and excited states from the
+    energy Lagrangian equals the Richardson-extrapolated central difference of
+    the re-solved energies; density route = direct route."""
+    st = solved(o, v)
+    (dh, dg), = directions(st, 1)
+    for j in (GROUND, 0, 1):
+        m = rs.gradient_multipliers(st, j, relaxed=relaxed)
+        G = rs.energy_gradient(st, m, dh, dg)
+        Gr = fd.richardson(lambda d: fd.fd_energy_gradient(st, j, dh, dg, delta=d, relaxed=relaxed),
+                           1e-4)
+        assert abs(G - Gr) < 1e-7 * max(1.0, abs(G))
+        D, d = rs.gradient_densities(st, m)
+        assert abs(rs.coupling_from_densities(D, d, dh, dg) - G) < 1e-11 * max(1.0, abs(G))
+
+
+def test_energy_gradient_is_hellmann_feynman_for_two_electrons():
+    """CCSD is FCI for two electrons and orbital rotations are redundant:
+    dE_j/dlam = <psi_j^L|H^q|psi_j^R> for the (exact) excited and ground states."""
+    st = solved(1, 5)
+    ci = fd.CIStates(st)
+    for dh, dg in directions(st, 2):
+        for j in (GROUND, 0, 2):
+            m = rs.gradient_multipliers(st, j, relaxed=True)
+            G = rs.energy_gradient(st, m, dh, dg)
+            c = ci.ket0(j)
+            if j == GROUND:
+                b = ci.ds.exp_excite(st["t1"].numpy(), st["t2"].numpy(), ci.ds.hf(), sign=-1.0,
+                                     transpose=True)
+                lam = ci.ds.dual_vector(
+                    -torch.linalg.solve(st["A"].T, st["eta"]).numpy(), ci.M, ci.S)
+                b = b + ci.ds.exp_excite(st["t1"].numpy(), st["t2"].numpy(), lam, sign=-1.0,
+                                         transpose=True)
+            else:
+                b = ci.bra(j)
+            hf = float(np.sum(b * ci.ds.H(np.asarray(dh), np.asarray(dg), c)))
+            assert abs(G - hf) < 1e-9 * max(1.0, abs(G))
