@@ -124,14 +124,21 @@ int cc_ground(cc_ctx* ctx, double* e_corr, int* iters);
  * -6 if a requested root is complex.                                        */
 int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
 
-/* Multipliers of the ordered pair (i, j), 1 <= i <= nroots, 0 <= j <=
- * nroots, i != j: gamma = L_i/(omega_j - omega_i), xi = 0 (Sec. II B); zeta-bar
- * from A^T zeta = -eta_t (eq. amplituderelax) and, when relaxed, kappa-bar
- * from (A^HF)^T kappa = -eta_kappa (eq. orbitalrelax).  j = 0 couples the
- * excited left state i to the CC ground state exp(T)|HF> (R0 = 1, R = 0):
- * gamma = 0 and zeta = -L_i/omega_i in closed form (Sec. II C); only
- * kappa-bar is solved.  densities() and nacme() then give F_i0.  iters: host
- * [2] or NULL (zeta and kappa iterations).                                   */
+/* Multipliers of the ordered pair (i, j), 0 <= i, j <= nroots:
+ *  - 1 <= i != j: coupling F_ij; gamma = L_i/(omega_j - omega_i), xi = 0
+ *    (Sec. II B); zeta-bar from A^T zeta = -eta_t (eq. amplituderelax) and,
+ *    when relaxed, kappa-bar from (A^HF)^T kappa = -eta_kappa (eq.
+ *    orbitalrelax);
+ *  - j = 0 < i: coupling F_i0 of the excited left state i with the CC ground
+ *    state exp(T)|HF> (R0 = 1, R = 0): gamma = 0 and zeta = -L_i/omega_i in
+ *    closed form (Sec. II C); only kappa-bar is solved;
+ *  - i = j: gradient of the state energy E_j = E0 + omega_j (E0 for j = 0)
+ *    from the same stationarity conditions, with dE0/dt + F(L_j) R_j in
+ *    place of eta_t and no overlap term; then densities(j, j) and
+ *    nacme(j, j, ...) give dE_j/dlambda^q (branching-plane vectors:
+ *    g^q = dE_2^q - dE_1^q, h^q = (E_2 - E_1) F_12^q).
+ * Pair (0, 0) needs only cc_ground; every other pair needs both EOM sides.
+ * iters: host [2] or NULL (zeta and kappa iterations).                       */
 int multipliers(cc_ctx* ctx, int i, int j, int* iters);
 
 /* Effective densities of the pair (i, j): D_eff (n x n) and the two-electron
@@ -140,7 +147,8 @@ int multipliers(cc_ctx* ctx, int i, int j, int* iters);
  * D1 (device [n][n], may be NULL) receives D_eff.                            */
 int densities(cc_ctx* ctx, int i, int j, double* D1);
 
-/* Derivative coupling F_ij^q for nq perturbation directions (Sec. II C):
+/* Derivative coupling F_ij^q (or, for i = j, the energy gradient
+ * dE_j/dlambda^q) for nq perturbation directions (Sec. II C):
  * dh[nq][n][n] one-electron derivatives, dB[nq][naux][n][n] derivative
  * factors with dg^q_pqrs = sum_P dB[q][P][p][q'] dB[q][P][r][s] (device).
  * F: host [nq].                                                              */

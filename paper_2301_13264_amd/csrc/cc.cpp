@@ -328,7 +328,7 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
 }
 
 // E_corr = 2 sum f_ia t_ai + sum (t_aibj + t_ai t_bj)(2 g_iajb - g_ibja).
-struct EnergyNodes { int t1, t2, e; };
+struct EnergyNodes { int t1, t2, f, g, e; };
 static EnergyNodes energy_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2) {
   const int64_t o = c.o, v = c.v;
   const Range O{0, o}, V{o, v};
@@ -336,6 +336,8 @@ static EnergyNodes energy_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor
   r.t1 = G.leaf(T1);
   r.t2 = G.leaf(T2);
   const int f = G.leaf(c.f), g = G.leaf(c.g);
+  r.f = f;
+  r.g = g;
   const int tau = G.node({o, o, v, v}, {lin(1, op(r.t2, "ijab"), "ijab"),
                                         mul(1, op(r.t1, "ia"), op(r.t1, "jb"), "ijab")});
   const int Lb = G.node({o, v, o, v}, {lin(2, op(g, "iajb", {O, V, O, V}), "iajb"),
@@ -1098,17 +1100,37 @@ static PairData& pair_of(Ctx& c, int i, int j) {
 
 static int64_t n4(Ctx& c) { return (int64_t)c.n * c.n * c.n * c.n; }
 
+// Hartree-Fock energy in terms of the Fock and Coulomb leaves,
+// E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji): its derivatives.
+__global__ void ehf_terms_kernel(double* Fbar, double* Gbar, int64_t n, int o) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)o * o) return;
+  const int64_t i = e / o, j = e - (e / o) * o;
+  Gbar[((i * n + i) * n + j) * n + j] -= 2.0;
+  Gbar[((i * n + j) * n + j) * n + i] += 1.0;
+  if (j == 0) Fbar[i * n + i] += 2.0;
+}
+
+// Multipliers of one Lagrangian, selected by the pair (i1, j1):
+//  * i1 != j1 >= 1: coupling F_ij, Phi = zeta.Omega + gamma.(A R_j), overlap
+//    of <L_i| with the right state j (Sec. II B);
+//  * j1 = 0 < i1: coupling F_i0 with the CC ground state exp(T)|HF> (R0 = 1,
+//    R = 0, no EOM condition, gamma = 0); A^T zeta = -L_i has the closed-form
+//    solution zeta = -L_i / omega_i (L_i is a left eigenvector) (Sec. II C);
+//  * i1 = j1: gradient of the state energy E_j = E0 + L_j.(A R_j) (E0 alone
+//    for j1 = 0): Phi = E0 + zeta.Omega + L_j.(A R_j), no overlap term, so
+//    eta_t = dE0/dt + F(L_j) R_j and eta_kappa = d Phi / d kappa.
 static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
-  // j1 = 0: the right state is the ground state exp(T)|HF> (R0 = 1, R = 0, no
-  // EOM condition, so gamma = 0), and A^T zeta = -L_i has the closed-form
-  // solution zeta = -L_i / omega_i (L_i is a left eigenvector) (Sec. II C)
-  const bool ground = (j1 == 0);
+  const bool grad_mode = (i1 == j1);
+  const bool has_right = (j1 > 0);
   const int i = i1 - 1, j = j1 - 1;
   const int64_t N = c.N, nov = (int64_t)c.o * c.v, nn = (int64_t)c.n * c.n;
   PairData& P = pair_of(c, i1, j1);
-  const double wi = c.omega_r[i];
-  const double R0j = ground ? 1.0 : c.R0[j];
-  if (ground)
+  const double wi = (i1 > 0) ? c.omega_r[i] : 0.0;
+  const double R0j = has_right ? c.R0[j] : 1.0;
+  if (grad_mode && has_right)
+    copy_d(c, P.gamma, c.L[j], N);
+  else if (!has_right)
     kc(fill(c.s, P.gamma, 0.0, N), "fill");
   else
     axpby_(c, P.gamma, c.L[i], 1.0 / (c.omega_r[j] - wi), 0.0, N);
@@ -1119,7 +1141,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
     Tape tp(c);
     // JVP along R_j, kept on the tape
     int ar1 = -1, ar2 = -1;
-    if (!ground) {
+    if (has_right) {
       const int r1 = tp.G.leaf(T1of(c, c.R[j])), r2 = tp.G.leaf(T2of(c, c.R[j]));
       auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
       ar1 = tan.at(tp.r.om1);
@@ -1130,7 +1152,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
     kc(apply_metric(c.s, wg, P.gamma, c.o, c.v, 0), "metric");
     double* tmp = ar.alloc(N);
     // F-matrix term: d/dt [gamma . A(t) R_j]
-    if (!ground) {
+    if (has_right) {
       ArenaScope s2(ar);
       auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}}, {tp.r.t1, tp.r.t2});
       copy_d(c, tmp, adj[tp.r.t1].p, nov);
@@ -1139,12 +1161,26 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
     } else {
       kc(fill(c.s, P.eta_t, 0.0, N), "fill");
     }
-    // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
-    {
+    if (grad_mode) {
+      // dE0/dt (packed-gradient convention), added to eta_t
+      ArenaScope s2(ar);
+      Graph Ge(*c.eng);
+      EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
+      double* one = c.eng->scalar_slot(62);
+      kc(fill(c.s, one, 1.0, 1), "fill");
+      auto adj = Ge.vjp({{en.e, one}}, {en.t1, en.t2});
+      copy_d(c, tmp, adj[en.t1].p, nov);
+      copy_d(c, tmp + nov, adj[en.t2].p, N - nov);
+      double* et = ar.alloc(N);
+      kc(apply_metric(c.s, et, tmp, c.o, c.v, 1), "metric");
+      axpby_(c, P.eta_t, et, 1.0, 1.0, N);
+      kc(fill(c.s, P.dtrans, 0.0, nn), "fill");
+    } else {
+      // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
       ArenaScope s2(ar);
       Graph Gs(*c.eng);
       const double* sv = nullptr;
-      if (!ground) {
+      if (has_right) {
         const int l2 = Gs.leaf(T2of(c, c.L[i])), rr1 = Gs.leaf(T1of(c, c.R[j]));
         const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
                                             mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
@@ -1160,7 +1196,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       axpby_(c, sp, wl, R0j, 0.0, N);
       if (sv) axpby_(c, sp, sv, 1.0, 1.0, nov);
       std::map<int, const double*> seeds{{tp.r.om1, sp}, {tp.r.om2, sp + nov}};
-      if (!ground) {
+      if (has_right) {
         seeds[ar1] = wl;
         seeds[ar2] = wl + nov;
       }
@@ -1168,7 +1204,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
     }
     // zeta: A^T zeta = -eta_t
-    if (ground) {
+    if (!grad_mode && !has_right) {
       axpby_(c, P.zeta, c.L[i], -1.0 / wi, 0.0, N);
     } else {
       double* b = ar.alloc(N);
@@ -1180,13 +1216,13 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       const int st = linsolve_refined(c, N, true, T, pre, b, P.zeta, c.opts.tol_mult, c.opts.maxit, &it_z);
       if (st != CC_OK) status = st;
     }
-    // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j)
+    // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j) (+ E0)
     {
       double* wz = ar.alloc(N);
       kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
       ArenaScope s2(ar);
       std::map<int, const double*> seeds{{tp.r.om1, wz}, {tp.r.om2, wz + nov}};
-      if (!ground) {
+      if (has_right) {
         seeds[ar1] = wg;
         seeds[ar2] = wg + nov;
       }
@@ -1201,6 +1237,21 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       c.eng->linear(1.0, full_view(adj[tp.r.w], "cdab"), Gd.view(op(gb, "acbd", {V, V, V, V})));
       c.eng->linear(1.0, full_view(adj[tp.r.wov], "cdkb"), Gd.view(op(gb, "kcbd", {O, V, V, V})));
     }
+    if (grad_mode) {
+      // + dE0/d(f, g): correlation energy by the energy graph, E_HF by hand
+      ArenaScope s2(ar);
+      Graph Ge(*c.eng);
+      EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
+      double* one = c.eng->scalar_slot(62);
+      kc(fill(c.s, one, 1.0, 1), "fill");
+      auto adj = Ge.vjp({{en.e, one}}, {en.f, en.g});
+      axpby_(c, P.Fbar, adj[en.f].p, 1.0, 1.0, nn);
+      axpby_(c, P.Gbar, adj[en.g].p, 1.0, 1.0, n4(c));
+      const int64_t oo = (int64_t)c.o * c.o;
+      hipLaunchKernelGGL(ehf_terms_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
+                         P.Fbar, P.Gbar, (int64_t)c.n, c.o);
+      hip_check(hipGetLastError(), "HF energy terms");
+    }
   }
   if (c.opts.relaxed) {
     ArenaScope sc(ar);
@@ -1213,6 +1264,9 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       ArenaScope s2(ar);
       auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.gr, P.Gbar}}, {rn.kap});
       copy_d(c, P.eta_k, adj[rn.kap].p, nov);
+    }
+    if (!grad_mode) {
+      ArenaScope s2(ar);
       Graph Gd(*c.eng);
       const int d = Gd.leaf(tview(P.dtrans, {c.n, c.n}));
       const Range O{0, c.o}, V{c.o, c.v};
@@ -1531,9 +1585,12 @@ int eom_solve(cc_ctx* c, int side, int nroots, double* omega, int* iters) {
 
 int multipliers(cc_ctx* c, int i, int j, int* iters) {
   ABI_GUARD(c);
-  if (!c->gauged) { c->err = "multipliers before right and left EOM states"; return CC_ERR_STATE; }
-  if (i < 1 || j < 0 || i > c->nroots || j > c->nroots || i == j) {
-    c->err = "pair indices must satisfy 1 <= i <= nroots, 0 <= j <= nroots, i != j";
+  if (c->stage < 1 || (!c->gauged && !(i == 0 && j == 0))) {
+    c->err = "multipliers before the ground state (pair (0, 0)) or the right and left EOM states";
+    return CC_ERR_STATE;
+  }
+  if (i < 0 || j < 0 || i > c->nroots || j > c->nroots || (i == 0 && j != 0)) {
+    c->err = "pair indices must satisfy 0 <= i, j <= nroots with i >= 1 unless i = j = 0";
     return CC_ERR_ARG;
   }
   try {

@@ -188,6 +188,55 @@ def test_ground_pair_couplings_match_oracle(nm, o, v, naux, seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 5, 18, None), (2, 4, 18, None), (4, 12, 48, 2301)])
+def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
+    """dE_j/dlambda (pairs (j, j)) of the ground and two excited states, and the
+    branching-plane vectors built from them, against the oracle."""
+    say(f"[energy gradients] o={o} v={v}")
+    seed = synth.exact_check_seed(o, v) if seed is None else seed
+    st = oracle_state(o, v, naux, seed, 2)
+    sysd = st["sys"]
+    n = o + v
+    dirs = synth.make_directions(n, naux, seed + 17, 2)
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    ctx.ground()
+    # the ground-state gradient needs no EOM states
+    ctx.multipliers(0, 0)
+    w, _, _ = ctx.eom(nm.CC_BOTH, 2)
+    Nf = o * v + (o * v) ** 2
+    buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+    grads = {}
+    for jj, jo in [(0, rs.GROUND), (1, 0), (2, 1)]:
+        m = rs.gradient_multipliers(st, jo, relaxed=True)
+        if jj > 0:
+            ctx.multipliers(jj, jj)
+        zeta = to_packed(ctx.export(nm._lib.CC_ZETA, jj, jj, buf).cpu().numpy(), o, v)
+        assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7
+        kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
+        kb = ctx.export(nm._lib.CC_KAPPA, jj, jj, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(kb - m["kappa_bar"].numpy()).max() < 1e-7
+        ctx.densities(jj, jj)
+        G = ctx.nacme(jj, jj, T(dirs["dh"]), T(dirs["dB"]))
+        for q in range(2):
+            dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+            Go = rs.energy_gradient(st, m, dirs["dh"][q], dg)
+            assert abs(G[q] - Go) < 1e-7 * max(1.0, abs(Go))
+        grads[jj] = np.asarray(G)
+    # branching plane: g = grad(E2 - E1), h = (E2 - E1) F_12
+    ctx.multipliers(1, 2)
+    ctx.densities(1, 2)
+    F12 = np.asarray(ctx.nacme(1, 2, T(dirs["dh"]), T(dirs["dB"])))
+    for q in range(2):
+        dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+        g_ref = (rs.energy_gradient(st, rs.gradient_multipliers(st, 1), dirs["dh"][q], dg)
+                 - rs.energy_gradient(st, rs.gradient_multipliers(st, 0), dirs["dh"][q], dg))
+        assert abs((grads[2][q] - grads[1][q]) - g_ref) < 1e-7 * max(1.0, abs(g_ref))
+        h_ref = float(st["omega"][1] - st["omega"][0]) * rs.coupling_direct(
+            st, rs.multipliers(st, 0, 1), 1, dirs["dh"][q], dg)
+        assert abs((w[1] - w[0]) * F12[q] - h_ref) < 1e-7 * max(1.0, abs(h_ref))
+    ctx.close()
+
+
 @pytest.mark.parametrize("spec,shapes,oshape", [
     ("ik,kj->ij", [(300, 70), (70, 260)], (300, 260)),
     ("ki,jk->ij", [(70, 300), (260, 70)], (300, 260)),
