@@ -51,6 +51,7 @@ struct PairData {
   double* Gbar = nullptr;    // [n]^4   d Phi / d g
   double* Deff = nullptr;    // [n][n]
   double* Gam = nullptr;     // [n]^4   two-electron density (1/2 d_eff)
+  double* Gp = nullptr;      // [m][m]  Gam over unordered pairs p <= q, m = n(n+1)/2
   bool have_mult = false, have_dens = false;
 };
 
@@ -200,6 +201,41 @@ static void dots_rows(Ctx& c, const double* V, int m, const double* x, int64_t n
   kc(rows_dot(c.s, V, m, n, xx, c.rows_part, hd), "rows_dot");
   hip_check(hipMemcpyAsync(h.data(), hd, m * sizeof(double), hipMemcpyDeviceToHost, c.s), "D2H");
   sync(c);
+}
+
+// H[r][k] = <V_k, X_r> for R vectors X [R][n] (rows of V read once per four
+// vectors); `packed` selects the biorthonormal metric.  work: R n + R m.
+static void dots_rows_multi(Ctx& c, const double* V, int m, const double* X, int R, int64_t n,
+                            bool packed, double* work, std::vector<double>& H) {
+  H.assign((size_t)R * m, 0.0);
+  if (m == 0 || R == 0) return;
+  const double* xx = X;
+  if (packed) {
+    for (int r = 0; r < R; ++r)
+      kc(apply_metric(c.s, work + (int64_t)r * n, X + (int64_t)r * n, c.o, c.v, 0), "metric");
+    xx = work;
+  }
+  double* hd = work + (int64_t)R * n;
+  for (int r0 = 0; r0 < R; r0 += kMaxRhs) {
+    const int rr = std::min(kMaxRhs, R - r0);
+    kc(rows_dot_multi(c.s, V, m, n, xx + (int64_t)r0 * n, n, rr, c.rows_part, hd + (int64_t)r0 * m),
+       "rows_dot_multi");
+  }
+  hip_check(hipMemcpyAsync(H.data(), hd, H.size() * sizeof(double), hipMemcpyDeviceToHost, c.s), "D2H");
+  sync(c);
+}
+
+// X_r -= sum_k H[r][k] V_k for R vectors X [R][n]; hd: R m device doubles.
+static void sub_rows_multi(Ctx& c, const double* V, int m, const std::vector<double>& H, double* X,
+                           int R, int64_t n, double* hd) {
+  if (m == 0 || R == 0) return;
+  hip_check(hipMemcpyAsync(hd, H.data(), (size_t)R * m * sizeof(double), hipMemcpyHostToDevice, c.s),
+            "H2D");
+  for (int r0 = 0; r0 < R; r0 += kMaxRhs) {
+    const int rr = std::min(kMaxRhs, R - r0);
+    kc(rows_axpy_multi(c.s, V, m, n, hd + (int64_t)r0 * m, -1.0, X + (int64_t)r0 * n, n, rr),
+       "rows_axpy_multi");
+  }
 }
 
 // x -= sum_k h[k] V_k (one GEMM); hd: m device doubles.
@@ -577,7 +613,11 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   std::vector<double> G((size_t)maxm * maxm, 0.0);
   double* work = ar.alloc(N + 2 * maxm);
   double* hd = work + N + maxm;
-  std::vector<double> h;
+  // block buffers: corrections [nb][N], metric work and projections
+  double* Cblk = ar.alloc((int64_t)nb * N);
+  double* workm = ar.alloc((int64_t)nb * N + (int64_t)nb * maxm);
+  double* hdm = ar.alloc((int64_t)nb * maxm);
+  std::vector<double> h, H;
   int m = 0;
   bool lowp = mixed(c);
   c.eng->set_lowp(lowp);
@@ -606,12 +646,15 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   // then the new rows and columns of the projected matrix G = V^T A V
   auto flush = [&](int m0, int mimg) {
     if (mimg < m) T(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
-    for (int j = m0; j < m; ++j) {
-      dots_rows(c, V, m, W + (int64_t)j * N, N, true, work, h);
-      for (int k = 0; k < m; ++k) G[(size_t)k * maxm + j] = h[k];
-      dots_rows(c, W, m, V + (int64_t)j * N, N, true, work, h);
-      for (int k = 0; k < m; ++k) G[(size_t)j * maxm + k] = h[k];
-    }
+    const int r = m - m0;
+    if (r <= 0) return;
+    // columns G[k][j] = <V_k, W_j> and rows G[j][k] = <W_k, V_j>, j >= m0
+    dots_rows_multi(c, V, m, W + (int64_t)m0 * N, r, N, true, workm, H);
+    for (int jj = 0; jj < r; ++jj)
+      for (int k = 0; k < m; ++k) G[(size_t)k * maxm + m0 + jj] = H[(size_t)jj * m + k];
+    dots_rows_multi(c, W, m, V + (int64_t)m0 * N, r, N, true, workm, H);
+    for (int jj = 0; jj < r; ++jj)
+      for (int k = 0; k < m; ++k) G[(size_t)(m0 + jj) * maxm + k] = H[(size_t)jj * m + k];
   };
 
   // initial guess: given vectors (e.g. the right states for the left
@@ -728,12 +771,33 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     // corrections only for the wanted roots (one block application); the
     // extra Ritz vectors stay in the subspace (and survive restarts) as ballast
     const int m0 = m;
+    int r = 0;
+    std::vector<double> n0;
     for (int k = 0; k < std::min(nk, nroots); ++k) {
       if (rn[k] < c.opts.tol_eom) continue;
-      copy_d(c, Rs, AX + (int64_t)k * N, N);
-      axpby_(c, Rs, X + (int64_t)k * N, -res.w[k], 1.0, N);
-      kc(apply_denominator(c.s, Rs, Rs, c.eps.p, c.o, c.v, res.w[k], 1), "precondition");
-      orth(Rs, nullptr);
+      double* x = Cblk + (int64_t)r * N;
+      copy_d(c, x, AX + (int64_t)k * N, N);
+      axpby_(c, x, X + (int64_t)k * N, -res.w[k], 1.0, N);
+      kc(apply_denominator(c.s, x, x, c.eps.p, c.o, c.v, res.w[k], 1), "precondition");
+      kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
+      n0.push_back(std::sqrt(std::max(0.0, dot_bio(c, x, x))));
+      ++r;
+    }
+    // block Gram-Schmidt against the basis (two passes), then within the block
+    for (int pass = 0; pass < 2 && m0 > 0 && r > 0; ++pass) {
+      dots_rows_multi(c, V, m0, Cblk, r, N, true, workm, H);
+      sub_rows_multi(c, V, m0, H, Cblk, r, N, hdm);
+    }
+    for (int a = 0; a < r && m < maxm; ++a) {
+      double* x = Cblk + (int64_t)a * N;
+      for (int pass = 0; pass < 2 && m > m0; ++pass) {
+        dots_rows(c, V + (int64_t)m0 * N, m - m0, x, N, true, work, h);
+        sub_rows(c, V + (int64_t)m0 * N, m - m0, h, x, N, hd);
+      }
+      const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+      if (!(n0[a] > 0) || n1 < 1e-4 * n0[a] || n1 < 1e-14) continue;
+      axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
+      ++m;
     }
     flush(m0, m0);
   }
@@ -886,7 +950,11 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
     c.R.clear();
     c.L.clear();
     c.have_right = c.have_left = c.gauged = false;
-    c.pairs.clear();
+    // pairs that involve excited states are stale; the ground-state gradient
+    // (pair (0, 0)) depends on the amplitudes only
+    for (auto it = c.pairs.begin(); it != c.pairs.end();) {
+      if (it->first.first != 0 || it->first.second != 0) it = c.pairs.erase(it); else ++it;
+    }
     for (int k = 0; k < nroots; ++k) {
       c.R.push_back(palloc(c, c.N));
       c.L.push_back(palloc(c, c.N));
@@ -1315,27 +1383,47 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
   return status;
 }
 
-// A <- (A + A^T) / 2 for a square m x m matrix, in 64 x 64 tile pairs
-// (tile (bi, bj) with bi <= bj and its mirror) staged through LDS so that every
-// read and write runs along rows.
-__global__ __launch_bounds__(256) void pair_sym_kernel(double* __restrict__ A, int64_t m) {
-  const int64_t bi = blockIdx.y, bj = blockIdx.x;
-  if (bi > bj) return;
-  __shared__ double s1[64][65], s2[64][65];
-  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-  const int64_t r0 = bi * 64, c0 = bj * 64;
-  for (int r = row; r < 64; r += 4) {
-    const int64_t gr = r0 + r, gc = c0 + lane;
-    s1[r][lane] = (gr < m && gc < m) ? A[gr * m + gc] : 0.0;      // A[r0 + r][c0 + l]
-    const int64_t hr = c0 + r, hc = r0 + lane;
-    s2[r][lane] = (hr < m && hc < m) ? A[hr * m + hc] : 0.0;      // A[c0 + r][r0 + l]
+// Index k of the unordered pair p <= q (row-major upper triangle of n x n)
+// and its multiplicity among the ordered pairs (2 off the diagonal).
+__device__ inline void pair_of_index(int64_t k, int64_t n, int64_t& p, int64_t& q) {
+  // rows p hold n - p entries; find p with start(p) <= k < start(p + 1)
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (mid * n - mid * (mid - 1) / 2 <= k) lo = mid; else hi = mid - 1;
   }
-  __syncthreads();
-  for (int r = row; r < 64; r += 4) {
-    const int64_t gr = r0 + r, gc = c0 + lane;
-    if (gr < m && gc < m) A[gr * m + gc] = 0.5 * (s1[r][lane] + s2[lane][r]);
-    const int64_t hr = c0 + r, hc = r0 + lane;
-    if (hr < m && hc < m) A[hr * m + hc] = 0.5 * (s2[r][lane] + s1[lane][r]);
+  p = lo;
+  q = p + (k - (p * n - p * (p - 1) / 2));
+}
+
+// Gp[k][l] = (Gam[p][q][r][s] + Gam[q][p][r][s] + Gam[p][q][s][r] + Gam[q][p][s][r]) / 4
+// for k = (p <= q), l = (r <= s): the part of Gam that meets integrals
+// symmetric in p <-> q and r <-> s.
+__global__ void pack_pairs_kernel(const double* __restrict__ Gam, int64_t n, int64_t m,
+                                  double* __restrict__ Gp) {
+  const int64_t tot = m * m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / m, l = e - (e / m) * m;
+    int64_t p, q, r, s;
+    pair_of_index(k, n, p, q);
+    pair_of_index(l, n, r, s);
+    const int64_t pq = p * n + q, qp = q * n + p, rs = r * n + s, sr = s * n + r, nn = n * n;
+    Gp[e] = 0.25 * (Gam[pq * nn + rs] + Gam[qp * nn + rs] + Gam[pq * nn + sr] + Gam[qp * nn + sr]);
+  }
+}
+
+// U[row][k] = mult(k) * dB[row][p][q] for the rows of the direction factors
+// (row = (q, P)), k = (p <= q), mult = 2 off the diagonal
+__global__ void pack_factor_kernel(const double* __restrict__ dB, int64_t rows, int64_t n, int64_t m,
+                                   double* __restrict__ U) {
+  const int64_t tot = rows * m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / m, k = e - (e / m) * m;
+    int64_t p, q;
+    pair_of_index(k, n, p, q);
+    U[e] = (p == q ? 1.0 : 2.0) * dB[row * n * n + p * n + q];
   }
 }
 
@@ -1390,34 +1478,49 @@ static void densities_impl(Ctx& c, int i1, int j1) {
     dst.str[0] = n * n * n; dst.str[1] = 1; dst.str[2] = n * n + n;   // Gam[p][k][k][q]
     c.eng->linear(-1.0, src, dst);
   }
-  // only the part of Gamma symmetric under (pq) <-> (rs) meets the symmetric
-  // dg^q; keeping that part lets the coupling GEMM read Gamma untransposed
+  // the directions' integrals are symmetric in p <-> q and r <-> s: keep Gam
+  // over unordered index pairs for the coupling contraction
   {
-    const int64_t m = (int64_t)c.n * c.n, t = (m + 63) / 64;
-    hipLaunchKernelGGL(pair_sym_kernel, dim3((unsigned)t, (unsigned)t), dim3(256), 0, c.s, P.Gam, m);
-    hip_check(hipGetLastError(), "pair symmetrisation");
+    const int64_t n = c.n, m = n * (n + 1) / 2;
+    if (!P.Gp) P.Gp = palloc(c, m * m);
+    const int g = (int)std::min<int64_t>((m * m + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_pairs_kernel, dim3(g), dim3(256), 0, c.s, P.Gam, n, m, P.Gp);
+    hip_check(hipGetLastError(), "pair packing");
   }
   P.have_dens = true;
 }
 
+// F^q = sum_pq D_eff dh^q + sum_P sum_(pq),(rs) dB^P_pq Gam_pqrs dB^P_rs.  With
+// u^P[k] = mult(k) dB^P[p][q] over unordered pairs k = (p <= q) the second
+// term is sum_P u^P . (Gp u^P): one GEMM [rows = directions x naux] x [m] x [m]
+// per chunk of directions (m = n(n+1)/2, a quarter of the n^2 x n^2 flops),
+// then one dot product per direction.
 static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const double* dB,
                        double* F) {
   PairData& P = c.pairs.at({i1, j1});
-  const int64_t n = c.n, nn = n * n, naux = c.naux;
+  const int64_t n = c.n, nn = n * n, naux = c.naux, m = n * (n + 1) / 2;
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
-  double* Z = ar.alloc(naux * nn);
-  for (int q = 0; q < nq; ++q) {
-    const double* dhq = dh + (int64_t)q * nn;
-    const double* dBq = dB + (int64_t)q * naux * nn;
-    const double f1 = dot_plain(c, P.Deff, dhq, nn);
-    // Z[P][pq] = sum_rs dB[P][rs] Gamma[rs][pq] (Gamma symmetric over the pair
-    // exchange);  F2 = sum_P,pq Z[P][pq] dB[P][pq]
-    kc(gemm_f64(c.s, false, false, (int)naux, (int)nn, (int)nn, 1, 1.0, dBq, nn, 0, P.Gam, nn, 0, 0.0,
-                Z, nn, 0),
+  // directions per chunk: U and Z of about 3 GB each at most
+  const int64_t per_dir = naux * m;
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(3.0e9 / 8.0) / per_dir));
+  double* U = ar.alloc((int64_t)chunk * per_dir);
+  double* Z = ar.alloc((int64_t)chunk * per_dir);
+  for (int q0 = 0; q0 < nq; q0 += chunk) {
+    const int kq = std::min(chunk, nq - q0);
+    const int64_t rows = (int64_t)kq * naux;
+    const int g = (int)std::min<int64_t>((rows * m + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_factor_kernel, dim3(g), dim3(256), 0, c.s, dB + (int64_t)q0 * naux * nn,
+                       rows, n, m, U);
+    hip_check(hipGetLastError(), "factor packing");
+    kc(gemm_f64(c.s, false, false, (int)rows, (int)m, (int)m, 1, 1.0, U, m, 0, P.Gp, m, 0, 0.0, Z,
+                m, 0),
        "nacme gemm");
-    const double f2 = dot_plain(c, Z, dBq, naux * nn);
-    F[q] = f1 + f2;
+    for (int q = 0; q < kq; ++q) {
+      const double f1 = dot_plain(c, P.Deff, dh + (int64_t)(q0 + q) * nn, nn);
+      const double f2 = dot_plain(c, Z + (int64_t)q * per_dir, U + (int64_t)q * per_dir, per_dir);
+      F[q0 + q] = f1 + f2;
+    }
   }
 }
 
@@ -1705,7 +1808,10 @@ int cc_export(cc_ctx* c, int what, int idx, int jdx, double* dst) {
       }
       default: {
         auto it = c->pairs.find({idx, jdx});
-        if (it == c->pairs.end() || !it->second.have_mult) return CC_ERR_STATE;
+        if (it == c->pairs.end() || !it->second.have_mult) {
+          c->err = "cc_export of a pair quantity before multipliers of that pair";
+          return CC_ERR_STATE;
+        }
         nm::PairData& P = it->second;
         if (what == CC_ZETA) nm::copy_d(*c, dst, P.zeta, c->N);
         else if (what == CC_KAPPA) nm::copy_d(*c, dst, P.kbar, nov);
@@ -1713,7 +1819,7 @@ int cc_export(cc_ctx* c, int what, int idx, int jdx, double* dst) {
         else if (what == CC_ETA_K) nm::copy_d(*c, dst, P.eta_k, nov);
         else if (what == CC_DTRANS) nm::copy_d(*c, dst, P.dtrans, nn);
         else if (what == CC_D1) {
-          if (!P.have_dens) return CC_ERR_STATE;
+          if (!P.have_dens) { c->err = "cc_export of D_eff before densities"; return CC_ERR_STATE; }
           nm::copy_d(*c, dst, P.Deff, nn);
         } else return CC_ERR_ARG;
       }

@@ -7,6 +7,7 @@ namespace nm {
 
 constexpr int kMaxViewDims = 6;
 constexpr int kMaxRows = 128;   // subspace rows handled by rows_dot / rows_axpy
+constexpr int kMaxRhs = 4;      // right-hand sides of rows_dot_multi / rows_axpy_multi
 
 // A strided map between an output box and an input tensor:
 // out[obase + sum_d i_d ostr_d]  <->  in[ibase + sum_d i_d istr_d + sum_r j_r rstr_r]
@@ -44,6 +45,12 @@ int reduce_scratch_doubles();
 int rows_dot(hipStream_t s, const double* V, int m, int64_t n, const double* x, double* part,
              double* out);
 int rows_scratch_doubles();
+// out[r][k] = <V_k, X_r> for R <= kMaxRhs vectors X_r = X + r ldx (device out)
+int rows_dot_multi(hipStream_t s, const double* V, int m, int64_t n, const double* X, int64_t ldx,
+                   int R, double* part, double* out);
+// X_r += alpha sum_k H[r][k] V_k (H device [R][m])
+int rows_axpy_multi(hipStream_t s, const double* V, int m, int64_t n, const double* H, double alpha,
+                    double* X, int64_t ldx, int R);
 int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h, double alpha,
               double* x);
 

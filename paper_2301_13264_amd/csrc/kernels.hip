@@ -961,7 +961,124 @@ int rows_dot(hipStream_t s, const double* V, int m, int64_t n, const double* x, 
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int rows_scratch_doubles() { return kRowBlocks * kMaxRows; }
+int rows_scratch_doubles() { return kRowBlocks * kMaxRows * kMaxRhs; }
+
+// Several right-hand sides at once (R <= kMaxRhs vectors X[r] = X + r ldx):
+// part[b][r][k] = sum over block b's chunk of V[k][e] X[r][e]; every row of V
+// is read once for all R vectors.
+template <int R>
+__global__ __launch_bounds__(256) void rows_dot_multi_partial_kernel(
+    const double* __restrict__ V, int m, int64_t n, const double* __restrict__ X, int64_t ldx,
+    double* part) {
+  __shared__ double red[4][R][kRowGroup];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = blockIdx.x * chunk;
+  const int64_t e1 = e0 + chunk < n ? e0 + chunk : n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int g0 = 0; g0 < m; g0 += kRowGroup) {
+    double acc[R][kRowGroup];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < kRowGroup; ++k) acc[r][k] = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      double xe[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) xe[r] = X[(int64_t)r * ldx + e];
+#pragma unroll
+      for (int k = 0; k < kRowGroup; ++k)
+        if (g0 + k < m) {
+          const double vk = V[(int64_t)(g0 + k) * n + e];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r][k] += vk * xe[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < kRowGroup; ++k) {
+        double a = acc[r][k];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+        if (lane == 0) red[wid][r][k] = a;
+      }
+    __syncthreads();
+    if (threadIdx.x < R * kRowGroup) {
+      const int r = threadIdx.x / kRowGroup, k = threadIdx.x % kRowGroup;
+      if (g0 + k < m)
+        part[((int64_t)blockIdx.x * kMaxRhs + r) * kMaxRows + g0 + k] =
+            red[0][r][k] + red[1][r][k] + red[2][r][k] + red[3][r][k];
+    }
+    __syncthreads();
+  }
+}
+
+// out[r][k] = sum_b part[b][r][k]
+__global__ void rows_fold_multi_kernel(const double* part, int nb, int m, int R, double* out) {
+  const int t = threadIdx.x, r = t / kMaxRows, k = t % kMaxRows;
+  if (r >= R || k >= m) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[((int64_t)b * kMaxRhs + r) * kMaxRows + k];
+  out[r * m + k] = acc;
+}
+
+int rows_dot_multi(hipStream_t s, const double* V, int m, int64_t n, const double* X, int64_t ldx,
+                   int R, double* part, double* out) {
+  if (m <= 0 || R <= 0) return 0;
+  if (m > kMaxRows || R > kMaxRhs) return -1;
+#define NM_RD(RR) \
+  hipLaunchKernelGGL(rows_dot_multi_partial_kernel<RR>, dim3(kRowBlocks), dim3(256), 0, s, V, m, n, X, ldx, part)
+  switch (R) {
+    case 1: NM_RD(1); break;
+    case 2: NM_RD(2); break;
+    case 3: NM_RD(3); break;
+    default: NM_RD(4); break;
+  }
+#undef NM_RD
+  hipLaunchKernelGGL(rows_fold_multi_kernel, dim3(1), dim3(kMaxRows * kMaxRhs), 0, s, part,
+                     kRowBlocks, m, R, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// X[r][e] += alpha * sum_k H[r][k] V[k][e] for R vectors (H [R][m] on the
+// device); every row of V is read once for all R vectors.
+template <int R>
+__global__ __launch_bounds__(256) void rows_axpy_multi_kernel(const double* __restrict__ V, int m,
+                                                              int64_t n, const double* __restrict__ H,
+                                                              double alpha, double* __restrict__ X,
+                                                              int64_t ldx) {
+  __shared__ double hs[R][kMaxRows];
+  for (int t = threadIdx.x; t < R * m; t += blockDim.x) hs[t / m][t % m] = H[t];
+  __syncthreads();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double vk = V[(int64_t)k * n + e];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += hs[r][k] * vk;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) X[(int64_t)r * ldx + e] += alpha * acc[r];
+  }
+}
+
+int rows_axpy_multi(hipStream_t s, const double* V, int m, int64_t n, const double* H, double alpha,
+                    double* X, int64_t ldx, int R) {
+  if (m <= 0 || R <= 0) return 0;
+  if (m > kMaxRows || R > kMaxRhs) return -1;
+#define NM_RA(RR) \
+  hipLaunchKernelGGL(rows_axpy_multi_kernel<RR>, dim3(grid_for(n)), dim3(256), 0, s, V, m, n, H, alpha, X, ldx)
+  switch (R) {
+    case 1: NM_RA(1); break;
+    case 2: NM_RA(2); break;
+    case 3: NM_RA(3); break;
+    default: NM_RA(4); break;
+  }
+#undef NM_RA
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 // x[e] += alpha * sum_k h[k] V[k][e]   (h on the device)
 __global__ __launch_bounds__(256) void rows_axpy_kernel(const double* __restrict__ V, int m,
