@@ -66,6 +66,10 @@ struct cc_ctx {
   std::vector<void*> owned;
   nm::Tensor eps, f, g, I;
   nm::Tensor W, Wov;   // W[c][d][a][b] = (ac|bd), Wov[c][d][k][b] = (kc|bd)
+  // virtual slices of g with the transformed index outermost, so that the
+  // annihilator transforms and their derivatives are plain GEMMs:
+  // Gc[c][p][r][s] = (p c|r s), Gvc[c][p][b][r] = (p b|r c)  (c, b virtual)
+  nm::Tensor Gc, Gvc;
   std::vector<double> eps_h;
   double* t = nullptr;
   bool have_guess = false;
@@ -248,7 +252,7 @@ static void sub_rows(Ctx& c, const double* V, int m, const std::vector<double>& 
 
 // ------------------------------------------------------------ residual graph
 struct ResNodes {
-  int t1, t2, f, g, w, wov;
+  int t1, t2, f, g, w, wov, gc, gvc;
   int om1, om2;
   int first;  // first non-leaf node of the residual
 };
@@ -261,9 +265,9 @@ struct ResNodes {
 // virtual creators and occupied annihilators.  They are applied annihilators
 // first (shrinking an n-range to o) and only for the blocks the equations
 // use:
-//   Go  = Y_2 g            [n][o][n][n]
+//   Go  = Y_2 g            stored [i][p][r][s]  (index 2 outermost)
 //   Goo = Y_4 Go           [n][o][n][o]
-//   Gvo = Y_4 g[:,V,:,:]   [n][v][n][o]
+//   Gvo = Y_4 g[:,V,:,:]   stored [j][p][b][r]  (index 4 outermost)
 // then X_1 / X_3 on the virtual creators of each block.  The vvvv block only
 // enters the particle-particle ladder; that term is evaluated on the bare
 // integrals W[cd][ab] = (ac|bd) with the creator transforms written out:
@@ -286,34 +290,36 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
   r.g = G.leaf(Gi);
   r.w = G.leaf(Wt);
   r.wov = G.leaf(Wov);
+  r.gc = G.leaf(c.Gc);
+  r.gvc = G.leaf(c.Gvc);
   r.first = G.size();
   const int t1 = r.t1, t2 = r.t2, f = r.f, g = r.g;
   // annihilator transforms
-  const int Go = G.node({n, o, n, n}, {lin(1, op(g, "pirs", {A, O, A, A}), "pirs"),
-                                       mul(1, op(t1, "ic"), op(g, "pcrs", {A, V, A, A}), "pirs")});
-  const int Goo = G.node({n, o, n, o}, {lin(1, op(Go, "pirj", {A, O, A, O}), "pirj"),
-                                        mul(1, op(Go, "pirc", {A, O, A, V}), op(t1, "jc"), "pirj")});
-  const int Gvo = G.node({n, v, n, o}, {lin(1, op(g, "pbrj", {A, V, A, O}), "pbrj"),
-                                        mul(1, op(g, "pbrc", {A, V, A, V}), op(t1, "jc"), "pbrj")});
+  const int Go = G.node({o, n, n, n}, {lin(1, op(g, "pirs", {A, O, A, A}), "iprs"),
+                                       mul(1, op(t1, "ic"), op(r.gc, "cprs"), "iprs")});
+  const int Goo = G.node({n, o, n, o}, {lin(1, op(Go, "iprj", {O, A, A, O}), "pirj"),
+                                        mul(1, op(Go, "iprc", {O, A, A, V}), op(t1, "jc"), "pirj")});
+  const int Gvo = G.node({o, n, v, n}, {lin(1, op(g, "pbrj", {A, V, A, O}), "jpbr"),
+                                        mul(1, op(t1, "jc"), op(r.gvc, "cpbr"), "jpbr")});
   // creator transforms of the blocks used below
   const int Hv = G.node({v, o, n, o}, {lin(1, op(Goo, "airj", {V, O, A, O}), "airj"),
                                        mul(-1, op(t1, "ka"), op(Goo, "kirj", {O, O, A, O}), "airj")});
   const int gvovo = G.node({v, o, v, o}, {lin(1, op(Hv, "aibj", {Vl, O, V, O}), "aibj"),
                                           mul(-1, op(Hv, "aikj", {Vl, O, O, O}), op(t1, "kb"), "aibj")});
-  const int goovv = G.node({o, o, v, v}, {lin(1, op(Go, "kiac", {O, O, V, V}), "kiac"),
-                                          mul(-1, op(Go, "kilc", {O, O, O, V}), op(t1, "la"), "kiac")});
-  const int gvoov = G.node({v, o, o, v}, {lin(1, op(Go, "aikc", {V, O, O, V}), "aikc"),
-                                          mul(-1, op(t1, "la"), op(Go, "likc", {O, O, O, V}), "aikc")});
+  const int goovv = G.node({o, o, v, v}, {lin(1, op(Go, "ikac", {O, O, V, V}), "kiac"),
+                                          mul(-1, op(Go, "iklc", {O, O, O, V}), op(t1, "la"), "kiac")});
+  const int gvoov = G.node({v, o, o, v}, {lin(1, op(Go, "iakc", {O, V, O, V}), "aikc"),
+                                          mul(-1, op(t1, "la"), op(Go, "ilkc", {O, O, O, V}), "aikc")});
   const int gvvov = G.node({v, v, o, v}, {lin(1, op(g, "adkc", {V, V, O, V}), "adkc"),
                                           mul(-1, op(t1, "la"), op(g, "ldkc", {O, V, O, V}), "adkc")});
-  const int gvvoo = G.node({v, v, o, o}, {lin(1, op(Gvo, "acki", {V, Vl, O, O}), "acki"),
-                                          mul(-1, op(t1, "la"), op(Gvo, "lcki", {O, Vl, O, O}), "acki")});
+  const int gvvoo = G.node({v, v, o, o}, {lin(1, op(Gvo, "iack", {O, V, Vl, O}), "acki"),
+                                          mul(-1, op(t1, "la"), op(Gvo, "ilck", {O, O, Vl, O}), "acki")});
   const Op g_ovov = op(g, "kcld", {O, V, O, V});
   // transformed Fock matrix
   const int fp = G.node({n, n}, {lin(1, op(f, "pq"), "pq"),
                                  lin(2, op(Go, "kkpq", {O, O, A, A}), "pq"),
                                  lin(-2, op(g, "kkpq", {O, O, A, A}), "pq"),
-                                 lin(-1, op(Go, "pkkq", {A, O, O, A}), "pq"),
+                                 lin(-1, op(Go, "kpkq", {O, A, O, A}), "pq"),
                                  lin(1, op(g, "pkkq", {A, O, O, A}), "pq")});
   const int f1 = G.node({n, n}, {lin(1, op(fp, "pq"), "pq"),
                                  mul(-1, op(t1, "ka"), op(fp, "kq", {O, A}), "aq", {V, A})});
@@ -322,7 +328,7 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
   const int u = G.node({o, o, v, v}, {lin(2, op(t2, "ijab"), "ijab"), lin(-1, op(t2, "ijba"), "ijab")});
   // singles
   r.om1 = G.node({o, v}, {mul(1, op(u, "kicd"), op(gvvov, "adkc"), "ia"),
-                          mul(-1, op(u, "klac"), op(Go, "kilc", {O, O, O, V}), "ia"),
+                          mul(-1, op(u, "klac"), op(Go, "iklc", {O, O, O, V}), "ia"),
                           mul(1, op(u, "ikac"), op(Fh, "kc", {O, V}), "ia"),
                           lin(1, op(Fh, "ai", {V, O}), "ia")});
   // ladder pieces on bare integrals
@@ -1150,6 +1156,39 @@ static RotNodes rotation_graph(Graph& G, Ctx& c, const Tensor& kappa) {
   return r;
 }
 
+// The Fock matrix of exp(kappa) H exp(-kappa) to first order in kappa from
+// the blocks of g it needs (one occupied index), for the A^HF transforms of
+// the kappa-bar equations: with J_pq = sum_k g_pqkk and X_pq = sum_k g_pkkq,
+//   J(kappa) = J + K J + J K^T + sum_kt K_kt (g_pqtk + g_pqkt),
+//   X(kappa) = X + K X + X K^T + sum_kt K_kt (g_ptkq + g_pktq),
+//   F(kappa) = h(kappa) + 2 J(kappa) - X(kappa),  h(kappa) = h + K h + h K^T,
+// the same first-order Fock matrix as rotation_graph's without its n^4 node.
+static RotNodes fock_rotation_graph(Graph& G, Ctx& c, const Tensor& kappa) {
+  const int64_t o = c.o, v = c.v, n = c.n;
+  const Range O{0, o}, V{o, v}, A{0, n};
+  RotNodes r;
+  r.kap = G.leaf(kappa);
+  const int fl = G.leaf(c.f), gl = G.leaf(c.g);
+  r.gr = -1;
+  const int J = G.node({n, n}, {lin(1, op(gl, "pqkk", {A, A, O, O}), "pq")});
+  const int X = G.node({n, n}, {lin(1, op(gl, "pkkq", {A, O, O, A}), "pq")});
+  const int h = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"), lin(-2, op(J, "pq"), "pq"),
+                                lin(1, op(X, "pq"), "pq")});
+  const int K = G.node({n, n}, {lin(1, op(r.kap, "ia"), "ai", {V, O}), lin(-1, op(r.kap, "ia"), "ia", {O, V})});
+  const int Ko = G.node({o, n}, {lin(1, op(K, "kt", {O, A}), "kt")});
+  r.fr = G.node({n, n}, {lin(1, op(h, "pq"), "pq"), mul(1, op(K, "pt"), op(h, "tq"), "pq"),
+                         mul(1, op(h, "pt"), op(K, "qt"), "pq"),
+                         lin(2, op(J, "pq"), "pq"), mul(2, op(K, "pt"), op(J, "tq"), "pq"),
+                         mul(2, op(J, "pt"), op(K, "qt"), "pq"),
+                         mul(2, op(Ko, "kt"), op(gl, "pqtk", {A, A, A, O}), "pq"),
+                         mul(2, op(Ko, "kt"), op(gl, "pqkt", {A, A, O, A}), "pq"),
+                         lin(-1, op(X, "pq"), "pq"), mul(-1, op(K, "pt"), op(X, "tq"), "pq"),
+                         mul(-1, op(X, "pt"), op(K, "qt"), "pq"),
+                         mul(-1, op(Ko, "kt"), op(gl, "ptkq", {A, A, O, A}), "pq"),
+                         mul(-1, op(Ko, "kt"), op(gl, "pktq", {A, O, A, A}), "pq")});
+  return r;
+}
+
 // ------------------------------------------------------------- multipliers
 static PairData& pair_of(Ctx& c, int i, int j) {
   PairData& p = c.pairs[{i, j}];
@@ -1294,7 +1333,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
         seeds[ar1] = wg;
         seeds[ar2] = wg + nov;
       }
-      auto adj = tp.G.vjp(seeds, {tp.r.f, tp.r.g, tp.r.w, tp.r.wov});
+      auto adj = tp.G.vjp(seeds, {tp.r.f, tp.r.g, tp.r.w, tp.r.wov, tp.r.gc, tp.r.gvc});
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
       if (!P.Gbar) P.Gbar = palloc(c, n4(c));
       copy_d(c, P.Gbar, adj[tp.r.g].p, n4(c));
@@ -1304,6 +1343,9 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       const Range O{0, c.o}, V{c.o, c.v};
       c.eng->linear(1.0, full_view(adj[tp.r.w], "cdab"), Gd.view(op(gb, "acbd", {V, V, V, V})));
       c.eng->linear(1.0, full_view(adj[tp.r.wov], "cdkb"), Gd.view(op(gb, "kcbd", {O, V, V, V})));
+      const Range Al{0, c.n};
+      c.eng->linear(1.0, full_view(adj[tp.r.gc], "cprs"), Gd.view(op(gb, "pcrs", {Al, V, Al, Al})));
+      c.eng->linear(1.0, full_view(adj[tp.r.gvc], "cpbr"), Gd.view(op(gb, "pbrc", {Al, V, Al, V})));
     }
     if (grad_mode) {
       // + dE0/d(f, g): correlation energy by the energy graph, E_HF by hand
@@ -1345,6 +1387,8 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
     double* b = ar.alloc(nov);
     axpby_(c, b, P.eta_k, -1.0, 0.0, nov);
     double* seed = ar.alloc(nn);
+    Graph Gf(*c.eng);
+    RotNodes fn = fock_rotation_graph(Gf, c, tview(k0, {c.o, c.v}));
     auto T = [&](const double* x, double* y) {
       ArenaScope s2(ar);
       kc(fill(c.s, seed, 0.0, nn), "fill");
@@ -1355,8 +1399,8 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       vs.obase = (int64_t)c.o * c.n;
       vs.istr[0] = c.v; vs.istr[1] = 1;
       kc(view_gather(c.s, seed, x, vs, 1.0, 0.0), "embed");
-      auto adj = G.vjp({{rn.fr, seed}}, {rn.kap});
-      copy_d(c, y, adj[rn.kap].p, nov);
+      auto adj = Gf.vjp({{fn.fr, seed}}, {fn.kap});
+      copy_d(c, y, adj[fn.kap].p, nov);
     };
     // preconditioner: orbital-energy differences on the singles block
     auto pre1 = [&](double* y, const double* x) {
@@ -1623,10 +1667,16 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
       const int iw = G.leaf(c->W), io = G.leaf(c->Wov);
       c->eng->linear(1.0, G.view(tw.a), nm::full_view(G.val(iw), "cdab"), true);
       c->eng->linear(1.0, G.view(to.a), nm::full_view(G.val(io), "cdkb"), true);
+      const nm::Range Aa{0, n};
+      c->Gc = nm::tview(nm::palloc(*c, (int64_t)v * n * n * n), {v, n, n, n});
+      c->Gvc = nm::tview(nm::palloc(*c, (int64_t)v * n * v * n), {v, n, v, n});
+      c->eng->linear(1.0, G.view(nm::op(gl, "pcrs", {Aa, Vv, Aa, Aa})), nm::full_view(c->Gc, "cprs"), true);
+      c->eng->linear(1.0, G.view(nm::op(gl, "pbrc", {Aa, Vv, Aa, Vv})), nm::full_view(c->Gvc, "cpbr"), true);
       // W[cd][ab] = (ac|bd) = (ca|db) = W[ab][cd] for real orbitals and a
       // factor symmetric in p, q
       c->W.pair_sym = true;
       c->W.constant = c->Wov.constant = c->g.constant = true;
+      c->Gc.constant = c->Gvc.constant = true;
     }
     c->t = nm::palloc(*c, c->N);
     nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
