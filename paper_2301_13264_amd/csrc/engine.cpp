@@ -673,8 +673,12 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
   if (big) {
     if (nb == 1) ns = big_split(tiles, K, M * N, kF64UsPerK);
   } else if (tiles < 512 && K >= 4096) {
-    ns = std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), K / 1024);
-    ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
+    // skinny products with a long K (gradients of the integral transforms):
+    // enough K chunks for ~4096 workgroups of at least 512 K each, partials
+    // capped at 2^26 doubles
+    ns = std::min<int64_t>(std::max<int64_t>(1, 4096 / tiles), K / 512);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, ((int64_t)1 << 26) / (M * N)));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, 2048));
   }
   // a few batch entries that leave the device idle are run one by one,
   // each split over K
