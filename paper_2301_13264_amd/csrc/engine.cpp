@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <set>
 
 namespace nm {
@@ -324,6 +326,58 @@ static int64_t big_split(int64_t tiles, int64_t K, int64_t MN, double us_per_k) 
   return best;
 }
 
+// Autotuner of the K split.  The first time a large single product of a given
+// shape (precision, transposes, M, N, K) runs, the split chosen by the model
+// above and its neighbours (1, s/2, 2s) are each timed once with HIP events
+// into a scratch output, and the fastest is kept for the rest of the process;
+// the real product then runs once with that split.  NACME_AUTOTUNE=0 keeps
+// the model's choice.
+static std::mutex g_tune_mu;
+static std::map<std::string, int64_t> g_tune;
+static bool autotune_on() {
+  const char* e = std::getenv("NACME_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+static std::string tune_key(char prec, bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
+  return std::string(1, prec) + (ta ? "T" : "N") + (tb ? "T" : "N") + ":" + std::to_string(M) + "x" +
+         std::to_string(N) + "x" + std::to_string(K);
+}
+// times launch(ns) for each candidate (outputs go to scratch) and returns the best
+static int64_t tune_split(hipStream_t s, const std::string& key, int64_t model, int64_t ns_max,
+                          const std::function<void(int64_t)>& launch) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  std::vector<int64_t> cand{model, 1, std::max<int64_t>(1, model / 2), std::min<int64_t>(ns_max, model * 2)};
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  int64_t best = model;
+  float tbest = 1e30f;
+  for (int64_t c : cand) {
+    hip_check(hipEventRecord(e0, s), "event");
+    launch(c);
+    hip_check(hipEventRecord(e1, s), "event");
+    hip_check(hipEventSynchronize(e1), "event");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+    if (ms < tbest) { tbest = ms; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (std::getenv("NACME_VERBOSE"))
+    std::fprintf(stderr, "[autotune] %s split %lld (model %lld) %.3f ms\n", key.c_str(),
+                 (long long)best, (long long)model, tbest);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+static constexpr double kTuneMinFlops = 2e10;
+
 // Can `v` be read as a (batched) row-major matrix rows x cols with a leading
 // dimension?  cols must be compact with unit innermost stride; rows must be
 // nested uniformly with the last row stride = ld; batch labels nested above.
@@ -540,24 +594,34 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
     } else if (nb0 == 1) {
       ns = big_split(tiles, K, M0 * N0, kF32UsPerK);
     }
-    if (ns > 1) {
-      const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
-      ns = (K + kc - 1) / kc;
-      const int64_t klast = K - (ns - 1) * kc;
-      double* part = arena_.alloc(ns * M0 * N0);
-      kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)kc, (int)ns, 1.0, a32, K, kc,
-                         b32, N0, kc * N0, 0.0, part, N0, M0 * N0, (int)klast),
-             "gemm fp32 (split K)");
-      const int64_t tot = M0 * N0;
-      const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-      hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc, ldc, part, (int)M0,
-                         (int)N0, (int)ns, a_, b_);
-      kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
-    } else {
-      kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)K, (int)nb0, a_, a32, K, M0 * K,
-                         b32, N0, K * N0, b_, pc, ldc, sC),
-             "gemm fp32");
+    auto launch = [&](int64_t nsplit, double* out, int64_t ldo, int64_t so, double aa, double bb) {
+      if (nsplit > 1) {
+        const int64_t kc = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+        const int64_t nsr = (K + kc - 1) / kc;
+        const int64_t klast = K - (nsr - 1) * kc;
+        Arena::Mark pm = arena_.mark();
+        double* part = arena_.alloc(nsr * M0 * N0);
+        kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)kc, (int)nsr, 1.0, a32, K, kc,
+                           b32, N0, kc * N0, 0.0, part, N0, M0 * N0, (int)klast),
+               "gemm fp32 (split K)");
+        const int64_t tot = M0 * N0;
+        const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+        hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, out, ldo, part, (int)M0,
+                           (int)N0, (int)nsr, aa, bb);
+        kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+        arena_.rewind(pm);
+      } else {
+        kcheck(gemm_f32acc(s_, false, false, (int)M0, (int)N0, (int)K, (int)nb0, aa, a32, K, M0 * K,
+                           b32, N0, K * N0, bb, out, ldo, so),
+               "gemm fp32");
+      }
+    };
+    if (nb0 == 1 && autotune_on() && 2.0 * (double)M0 * (double)N0 * (double)K >= kTuneMinFlops) {
+      double* scratch = arena_.alloc(M0 * N0);
+      ns = tune_split(s_, tune_key('s', false, false, M0, N0, K), ns, 256,
+                      [&](int64_t c) { launch(c, scratch, N0, M0 * N0, 1.0, 0.0); });
     }
+    launch(ns, pc, ldc, sC, a_, b_);
     if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
     lowp_flops_ += (uint64_t)(2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K);
     arena_.rewind(mk);
@@ -683,27 +747,38 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
   // a few batch entries that leave the device idle are run one by one,
   // each split over K
   if (nb > 64) ns = 1;
-  if (ns > 1) {
-    const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
-    ns = (K + kc - 1) / kc;
-    double* part = arena_.alloc(ns * M * N);
-    const int64_t klast = K - (ns - 1) * kc;
-    for (int64_t b = 0; b < nb; ++b) {
-      kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kc, (int)ns, 1.0, pa + b * sA, lda,
-                      ta ? kc * lda : kc, pb + b * sB, ldb, tb ? kc : kc * ldb, 0.0, part, N, M * N,
-                      (int)klast),
-             "gemm(splitk)");
-      const int64_t tot = M * N;
-      const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-      hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, pc + b * sC, ldc, part,
-                         (int)M, (int)N, (int)ns, a_, b_);
-      kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+  // the product with K split in `nsplit` chunks into out (ld ldo, batch stride so)
+  auto launch = [&](int64_t nsplit, double* out, int64_t ldo, int64_t so, double aa, double bb) {
+    if (nsplit > 1) {
+      const int64_t kc = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+      const int64_t nsr = (K + kc - 1) / kc;
+      Arena::Mark pm = arena_.mark();
+      double* part = arena_.alloc(nsr * M * N);
+      const int64_t klast = K - (nsr - 1) * kc;
+      for (int64_t b = 0; b < nb; ++b) {
+        kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)kc, (int)nsr, 1.0, pa + b * sA, lda,
+                        ta ? kc * lda : kc, pb + b * sB, ldb, tb ? kc : kc * ldb, 0.0, part, N,
+                        M * N, (int)klast),
+               "gemm(splitk)");
+        const int64_t tot = M * N;
+        const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+        hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, out + b * so, ldo, part,
+                           (int)M, (int)N, (int)nsr, aa, bb);
+        kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+      }
+      arena_.rewind(pm);
+    } else {
+      kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)K, (int)nb, aa, pa, lda, sA, pb, ldb, sB, bb,
+                      out, ldo, so),
+             "gemm");
     }
-  } else {
-    kcheck(gemm_f64(s_, ta, tb, (int)M, (int)N, (int)K, (int)nb, a_, pa, lda, sA, pb, ldb, sB, b_,
-                    pc, ldc, sC),
-           "gemm");
+  };
+  if (nb == 1 && autotune_on() && 2.0 * (double)M * (double)N * (double)K >= kTuneMinFlops) {
+    double* scratch = arena_.alloc(M * N);
+    ns = tune_split(s_, tune_key('d', ta, tb, M, N, K), ns, big ? 256 : 2048,
+                    [&](int64_t c) { launch(c, scratch, N, M * N, 1.0, 0.0); });
   }
+  launch(ns, pc, ldc, sC, a_, b_);
   if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
   arena_.rewind(mk);
 }
