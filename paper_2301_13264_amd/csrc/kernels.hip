@@ -858,7 +858,8 @@ __global__ __launch_bounds__(256) void absmax_partial_kernel(const double* x, in
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double a = fabs(x[e]);
-    acc = (a > acc || a != a) ? a : acc;  // propagate NaN
+    // a NaN counts as +inf: the max reductions below (fmax) would drop it
+    acc = (a != a) ? INFINITY : (a > acc ? a : acc);
   }
   acc = wave_max(acc);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
