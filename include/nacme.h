@@ -170,7 +170,10 @@ int cc_residual(cc_ctx* ctx, const double* t, double* omega);
 /* Copies a stored quantity (selectors above) to dst (device; CC_R0 host).
  * idx: state (CC_R, CC_L, CC_R0) or i (pair quantities); jdx: j.            */
 int cc_export(cc_ctx* ctx, int what, int idx, int jdx, double* dst);
-/* Sets a starting guess: CC_T (amplitudes for cc_ground).                    */
+/* Sets a starting guess: CC_T (amplitudes for the next cc_ground), or CC_R /
+ * CC_L with idx = 1..64 (starting vectors of the next right / left EOM
+ * solve, e.g. the states of a neighbouring geometry; used once).  Every
+ * answer is still judged by the solver's own residual tolerance.            */
 int cc_set_guess(cc_ctx* ctx, int what, int idx, const double* src);
 /* Counters since cc_create (host out[n], n <= 7): residual evaluations,
  * right transforms, left transforms, algorithmic GEMM flops issued,

@@ -73,6 +73,9 @@ struct cc_ctx {
   std::vector<double> eps_h;
   double* t = nullptr;
   bool have_guess = false;
+  // starting vectors of the next right / left EOM solve (cc_set_guess), e.g.
+  // the states of a neighbouring geometry; used once, then dropped
+  std::map<int, double*> guess_R, guess_L;
   int stage = 0;  // 1 ground done
   bool have_right = false, have_left = false, gauged = false;
   double ecorr = 0.0;
@@ -139,9 +142,9 @@ struct ArenaScope {
 // operands until the residual falls below kMixedSwitch, then finish with fp64
 // operators and fp64 residuals.
 constexpr double kMixedSwitch = 1e-5;
-// Eigensolver switch point: fp32-operand images carry about 1e-7 relative
-// rounding, so the fp32 phase is run until the residual norm reaches 1e-7
-// or stalls.
+// Eigensolver: fp32-operand images carry about 1e-7 relative rounding, so the
+// residual norms computed from them level off near 1e-7; at that point (or
+// when they stall) the wanted Ritz vectors get fp64 images.
 constexpr double kEigSwitch = 1e-7;
 static bool mixed(const Ctx& c) { return c.opts.precision == CC_FP32_REFINE; }
 
@@ -625,8 +628,11 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   double* hdm = ar.alloc((int64_t)nb * maxm);
   std::vector<double> h, H;
   int m = 0;
-  bool lowp = mixed(c);
+  const bool lowp = mixed(c);
   c.eng->set_lowp(lowp);
+  // mixed precision: fp64 images of the wanted Ritz vectors, coefficients Z
+  double* AXd = lowp ? ar.alloc((int64_t)nroots * N) : nullptr;
+  double* zdev = lowp ? ar.alloc((int64_t)nroots * maxm) : nullptr;
 
   // biorthonormal Gram-Schmidt of x against the basis (two passes, block
   // GEMVs), stored as basis row m (its image, when given, as W row m);
@@ -685,12 +691,54 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     }
   }
   flush(0, 0);
-  // fp32-operand phase: ends when the residual reaches kEigSwitch or stops
-  // improving (the fp32 rounding floor); the fp64 phase restarts from the
-  // Ritz vectors with fp64 images
+  // Mixed precision: every basis image comes from the fp32-operand operator.
+  // When the residuals reach the fp32 rounding floor (kEigSwitch or a stall),
+  // and again before convergence is accepted, the wanted Ritz vectors
+  // X = Y V get fp64 images AXd and their true residual norms are measured.
+  // The basis images are then corrected by a rank-nroots update,
+  //   W <- W + Z^T D,  D = AXd - Y W,  Z = (Y Y^T)^-1 Y  (so Z Y^T = I),
+  // which makes the images of those Ritz vectors exact and leaves the other
+  // directions of the basis as they were, and G = V^T W gets the same update.
+  // The subspace is kept; later corrections are again imaged in fp32, and
+  // their rounding enters the residual only through coefficients of the size
+  // of the residual at the update, far below the tolerance.  Only a true
+  // (fp64) residual below the tolerance ends the solve.
   double best_lowp = 1e300;
   int stall = 0;
+  bool refreshed = false;
   Ritz res;
+  auto refresh = [&](const std::vector<double>& Y, int nk) -> double {
+    c.eng->set_lowp(false);
+    T(X, AXd, nroots);
+    c.eng->set_lowp(true);
+    double wt = 0.0;
+    for (int k = 0; k < nroots; ++k) {
+      double* xk = X + (int64_t)k * N;
+      double* dk = AXd + (int64_t)k * N;
+      copy_d(c, Rs, dk, N);
+      axpby_(c, Rs, xk, -res.w[k], 1.0, N);
+      const double xn = std::sqrt(dot_bio(c, xk, xk));
+      wt = std::max(wt, std::sqrt(std::max(0.0, dot_bio(c, Rs, Rs))) / xn);
+      axpby_(c, dk, AX + (int64_t)k * N, -1.0, 1.0, N);   // D_k
+    }
+    (void)nk;
+    std::vector<double> S((size_t)nroots * nroots, 0.0), Z(Y.begin(), Y.begin() + (size_t)nroots * m);
+    for (int a = 0; a < nroots; ++a)
+      for (int b = 0; b < nroots; ++b)
+        for (int i = 0; i < m; ++i) S[(size_t)a * nroots + b] += Y[(size_t)a * m + i] * Y[(size_t)b * m + i];
+    if (!lu_solve(S, Z, nroots, m)) throw Error(-5, "singular Ritz coefficient matrix");
+    hip_check(hipMemcpyAsync(zdev, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+    kc(gemm_f64(c.s, true, false, m, (int)N, nroots, 1, 1.0, zdev, m, 0, AXd, N, 0, 1.0, W, N, 0),
+       "image update");
+    dots_rows_multi(c, V, m, AXd, nroots, N, true, workm, H);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        double acc = 0.0;
+        for (int k = 0; k < nroots; ++k) acc += H[(size_t)k * m + a] * Z[(size_t)k * m + b];
+        G[(size_t)a * maxm + b] += acc;
+      }
+    return wt;
+  };
   for (int it = 1; it <= c.opts.maxit; ++it) {
     res.iters = it;
     std::vector<double> Gm((size_t)m * m);
@@ -746,19 +794,21 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
         ++stall;
       }
     }
-    if (lowp && (worst < kEigSwitch || stall >= 3 || it >= c.opts.maxit / 2)) {
-      // fp64 phase: restart from the Ritz vectors with fp64 images
-      lowp = false;
-      c.eng->set_lowp(false);
-      m = 0;
-      std::fill(G.begin(), G.end(), 0.0);
-      double* tmpx = ar.alloc((int64_t)nk * N);
-      copy_d(c, tmpx, X, (int64_t)nk * N);
-      for (int k = 0; k < nk; ++k) orth(tmpx + (int64_t)k * N, nullptr);
-      flush(0, 0);
-      continue;
+    if (lowp && (worst < c.opts.tol_eom || stall >= 3 ||
+                 (!refreshed && (worst < kEigSwitch || it >= c.opts.maxit / 2)))) {
+      const double wt = refresh(Y, nk);
+      refreshed = true;
+      best_lowp = 1e300;
+      stall = 0;
+      if (verbose()) std::fprintf(stderr, "[davidson] it %d fp64 images, true residual %.2e\n", it, wt);
+      if (!std::isfinite(wt)) throw Error(-5, "non-finite Davidson residual");
+      if (wt < c.opts.tol_eom) {
+        res.converged = true;
+        break;
+      }
+      continue;   // Ritz pairs again from the corrected G
     }
-    if (worst < c.opts.tol_eom) {
+    if (!lowp && worst < c.opts.tol_eom) {
       res.converged = true;
       break;
     }
@@ -808,7 +858,6 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     flush(m0, m0);
   }
   c.eng->set_lowp(false);
-  if (lowp) res.converged = false;   // never accept a mixed-precision answer
   // normalise and hand out the nroots lowest Ritz vectors
   for (int k = 0; k < nroots; ++k) {
     const double xn = std::sqrt(dot_bio(c, X + (int64_t)k * N, X + (int64_t)k * N));
@@ -969,8 +1018,17 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
   }
   int status = CC_OK, itsum = 0;
   Tape tp(c);
+  auto guesses = [&](std::map<int, double*>& gm) {
+    std::vector<double*> gv;
+    for (auto& kv : gm)
+      if (kv.first >= 1 && kv.first <= nroots) gv.push_back(kv.second);
+    return gv;
+  };
   if (side & CC_RIGHT) {
-    Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.right_block(x, y, k); }, c.R);
+    std::vector<double*> gr = guesses(c.guess_R);
+    Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.right_block(x, y, k); }, c.R,
+                      gr.empty() ? nullptr : &gr);
+    c.guess_R.clear();
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_r = r.w;
     c.have_right = true;
@@ -979,8 +1037,11 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
     if (!r.converged) status = CC_NOT_CONVERGED;
   }
   if (side & CC_LEFT) {
+    std::vector<double*> gl = guesses(c.guess_L);
+    if (gl.empty() && c.have_right) gl = c.R;
     Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.left_block(x, y, k); },
-                      c.L, c.have_right ? &c.R : nullptr);
+                      c.L, gl.empty() ? nullptr : &gl);
+    c.guess_L.clear();
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_l = r.w;
     c.have_left = true;
@@ -1883,11 +1944,17 @@ int cc_export(cc_ctx* c, int what, int idx, int jdx, double* dst) {
 
 int cc_set_guess(cc_ctx* c, int what, int idx, const double* src) {
   ABI_GUARD(c);
-  (void)idx;
-  if (!src || what != CC_T) return CC_ERR_ARG;
+  if (!src || (what != CC_T && what != CC_R && what != CC_L)) return CC_ERR_ARG;
+  if (what != CC_T && (idx < 1 || idx > 64)) return CC_ERR_ARG;
   try {
-    nm::copy_d(*c, c->t, src, c->N);
-    c->have_guess = true;
+    if (what == CC_T) {
+      nm::copy_d(*c, c->t, src, c->N);
+      c->have_guess = true;
+    } else {
+      auto& gm = (what == CC_R) ? c->guess_R : c->guess_L;
+      if (!gm.count(idx)) gm[idx] = nm::palloc(*c, c->N);
+      nm::copy_d(*c, gm[idx], src, c->N);
+    }
     nm::sync(*c);
     return CC_OK;
   } catch (const Error& e) {

@@ -350,7 +350,10 @@ static int64_t tune_split(hipStream_t s, const std::string& key, int64_t model, 
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return it->second;
   }
-  std::vector<int64_t> cand{model, 1, std::max<int64_t>(1, model / 2), std::min<int64_t>(ns_max, model * 2)};
+  // no split at all only near a small model split: for the skinny long-K
+  // products (model splits in the hundreds) one chunk takes seconds
+  std::vector<int64_t> cand{model, std::max<int64_t>(1, model / 2), std::min<int64_t>(ns_max, model * 2)};
+  if (model <= 16) cand.push_back(1);
   std::sort(cand.begin(), cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   hipEvent_t e0, e1;

@@ -139,3 +139,43 @@ def test_learned_guess_cuts_ground_iterations(nm):
         assert it1 < it0
         ctx.close()
     net.close()
+
+
+def test_eom_warm_start_from_neighbouring_geometry(nm):
+    """EOM starting vectors (cc_set_guess with CC_R / CC_L) taken from the
+    states of a neighbouring geometry: the same roots, in fewer iterations
+    than the cold start from singles unit vectors."""
+    o, v, naux, seed, nroots = 4, 12, 48, 2301, 2
+    base = synth.make_system(o, v, naux, seed)
+    N = o * v + (o * v) ** 2
+    buf = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx = nm.Context(o, v, naux, T(base["eps"]), T(synth.perturbed_factor(base["B"], 960, scale=1e-3)))
+    ctx.ground()
+    ctx.eom(nm.CC_BOTH, nroots)
+    R = [ctx.export(nm._lib.CC_R, k + 1, 0, buf).clone() for k in range(nroots)]
+    L = [ctx.export(nm._lib.CC_L, k + 1, 0, buf).clone() for k in range(nroots)]
+    ctx.close()
+    ctx = nm.Context(o, v, naux, T(base["eps"]), T(synth.perturbed_factor(base["B"], 961, scale=1e-3)))
+    ctx.ground()
+    w0, itr0, rc = ctx.eom(nm.CC_RIGHT, nroots)
+    assert rc == 0
+    wl0, itl0, rc = ctx.eom(nm.CC_LEFT, nroots)
+    assert rc == 0
+    for k in range(nroots):
+        ctx.set_guess(nm._lib.CC_R, k + 1, R[k])
+        ctx.set_guess(nm._lib.CC_L, k + 1, L[k])
+    w1, itr1, rc = ctx.eom(nm.CC_RIGHT, nroots)
+    assert rc == 0
+    wl1, itl1, rc = ctx.eom(nm.CC_LEFT, nroots)
+    assert rc == 0
+    say(f"  right: cold {itr0} iterations, warm {itr1}; left: from R {itl0}, warm {itl1}")
+    assert np.abs(np.array(w1) - np.array(w0)).max() < 1e-9
+    assert np.abs(np.array(wl1) - np.array(wl0)).max() < 1e-9
+    assert itr1 < itr0
+    # the guesses are used once: the next solve starts cold again
+    w2, itr2, rc = ctx.eom(nm.CC_RIGHT, nroots)
+    assert rc == 0 and itr2 > itr1
+    with pytest.raises(nm.CCError) as e:
+        ctx.set_guess(nm._lib.CC_R, 0, R[0])
+    assert e.value.code == -1
+    ctx.close()
