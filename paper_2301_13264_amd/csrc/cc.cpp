@@ -1086,9 +1086,20 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
 // --------------------------------------------------------- linear solver
 // Solves T(x) = b (T: amplitude-shaped or small vectors of length n, metric
 // `packed`) by Galerkin projection on a growing preconditioned subspace.
+// Solves T(x) = b by a Galerkin projection on a growing subspace V with
+// images W = T(V): G y = V^T b with G = V^T W, x = V y, next basis vector
+// from the preconditioned residual.
+//
+// mixed: the images come from the fp32-operand operator.  When the residual
+// reaches the fp32 rounding floor (kEigSwitch relative, or a stall), and
+// before convergence is accepted, x gets an fp64 image and the true residual
+// is measured; the basis images then get the rank-1 correction
+// W <- W + z D with D = T64(x) - W^T y and z = y / (y . y), so that the
+// image of x becomes exact (G gets the same update) and the subspace is
+// kept.  Only a true residual below tol ends the solve.
 static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(const double*, double*)>& T,
                     const std::function<void(double*, const double*)>& precond, const double* b,
-                    double* x, double tol, int maxit, int* iters) {
+                    double* x, double tol, int maxit, int* iters, bool mixed_images = false) {
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
   const int maxm = std::min(maxit, 120);
@@ -1096,17 +1107,23 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   double* W = ar.alloc((int64_t)maxm * n);
   double* r = ar.alloc(n);
   double* y = ar.alloc(maxm);
+  double* ax = mixed_images ? ar.alloc(n) : nullptr;
   auto dotf = [&](const double* p, const double* q) {
     return packed ? dot_bio(c, p, q) : dot_plain(c, p, q, n);
   };
-  std::vector<double> G((size_t)maxm * maxm), bv(maxm), h;
+  std::vector<double> G((size_t)maxm * maxm), bv(maxm), h, cvec;
   double* work = ar.alloc(n + 2 * maxm);
   double* hd = work + n + maxm;
   int m = 0;
+  c.eng->set_lowp(mixed_images);
   precond(r, b);
   int status = CC_NOT_CONVERGED;
   int it = 0;
   const double bn = std::sqrt(std::max(dotf(b, b), 1e-300));
+  const double goal = tol * std::max(1.0, bn);
+  double best = 1e300;
+  int stall = 0;
+  bool refreshed = false;
   for (it = 1; it <= maxit && m < maxm; ++it) {
     if (packed) kc(apply_metric(c.s, r, r, c.o, c.v, 2), "symmetrise");
     const double n0 = std::sqrt(std::max(0.0, dotf(r, r)));
@@ -1124,72 +1141,69 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
     dots_rows(c, W, m, V + (int64_t)(m - 1) * n, n, packed, work, h);
     for (int k = 0; k < m; ++k) G[(size_t)(m - 1) * maxm + k] = h[k];
     bv[m - 1] = dotf(V + (int64_t)(m - 1) * n, b);
-    std::vector<double> Gm((size_t)m * m), cvec(bv.begin(), bv.begin() + m);
-    for (int a = 0; a < m; ++a)
-      for (int bb = 0; bb < m; ++bb) Gm[(size_t)a * m + bb] = G[(size_t)a * maxm + bb];
-    if (!lu_solve(Gm, cvec, m, 1)) throw Error(-5, "singular projected linear system");
-    hip_check(hipMemcpyAsync(y, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-    kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, V, n, 0, 0.0, x, n, 0), "combine");
-    kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, W, n, 0, 0.0, r, n, 0), "combine");
-    axpby_(c, r, b, -1.0, 1.0, n);    // r = T x - b
-    const double rn = std::sqrt(std::max(0.0, dotf(r, r)));
-    if (!std::isfinite(rn)) throw Error(-5, "non-finite linear-solver residual");
-    if (verbose()) std::fprintf(stderr, "[linsolve] it %d m %d |r| %.3e\n", it, m, rn);
-    if (rn < tol * std::max(1.0, bn) ) {
-      status = CC_OK;
-      break;
+    for (int pass = 0;; ++pass) {
+      std::vector<double> Gm((size_t)m * m);
+      cvec.assign(bv.begin(), bv.begin() + m);
+      for (int a = 0; a < m; ++a)
+        for (int bb = 0; bb < m; ++bb) Gm[(size_t)a * m + bb] = G[(size_t)a * maxm + bb];
+      if (!lu_solve(Gm, cvec, m, 1)) throw Error(-5, "singular projected linear system");
+      hip_check(hipMemcpyAsync(y, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+      kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, V, n, 0, 0.0, x, n, 0), "combine");
+      kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, W, n, 0, 0.0, r, n, 0), "combine");
+      axpby_(c, r, b, -1.0, 1.0, n);    // r = T x - b
+      const double rn = std::sqrt(std::max(0.0, dotf(r, r)));
+      if (!std::isfinite(rn)) throw Error(-5, "non-finite linear-solver residual");
+      if (verbose()) std::fprintf(stderr, "[linsolve] it %d m %d |r| %.3e\n", it, m, rn);
+      if (mixed_images) {
+        if (rn < 0.7 * best) { best = rn; stall = 0; } else { ++stall; }
+      }
+      if (!mixed_images || pass >= 2 || !(rn < goal || stall >= 3 || (!refreshed && rn < kEigSwitch * bn))) {
+        if (rn < goal) status = CC_OK;
+        break;
+      }
+      // fp64 image of x: true residual, then the rank-1 image correction
+      c.eng->set_lowp(false);
+      T(x, ax);
+      c.eng->set_lowp(true);
+      refreshed = true;
+      best = 1e300;
+      stall = 0;
+      axpby_(c, ax, b, -1.0, 1.0, n);      // true residual T64 x - b
+      const double rt = std::sqrt(std::max(0.0, dotf(ax, ax)));
+      if (verbose()) std::fprintf(stderr, "[linsolve] it %d fp64 image, true |r| %.3e\n", it, rt);
+      if (!std::isfinite(rt)) throw Error(-5, "non-finite linear-solver residual");
+      axpby_(c, ax, r, -1.0, 1.0, n);      // D = (T64 x - b) - (W^T y - b)
+      double yy = 0.0;
+      for (int k = 0; k < m; ++k) yy += cvec[k] * cvec[k];
+      std::vector<double> z(m);
+      for (int k = 0; k < m; ++k) z[k] = cvec[k] / yy;
+      hip_check(hipMemcpyAsync(y, z.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+      kc(gemm_f64(c.s, false, false, m, (int)n, 1, 1, 1.0, y, 1, 0, ax, n, 0, 1.0, W, n, 0), "image update");
+      dots_rows(c, V, m, ax, n, packed, work, h);
+      for (int a = 0; a < m; ++a)
+        for (int bb = 0; bb < m; ++bb) G[(size_t)a * maxm + bb] += h[a] * z[bb];
+      if (rt < goal) {
+        axpby_(c, r, ax, 1.0, 1.0, n);     // r = true residual (x unchanged)
+        status = CC_OK;
+        break;
+      }
+      // solve again with the corrected images (the true residual next)
     }
+    if (status == CC_OK) break;
     precond(r, r);
   }
+  c.eng->set_lowp(false);
   if (iters) *iters = it;
   return status;
 }
 
-// T(x) = b by iterative refinement when the context runs mixed precision:
-// r = b - T(x) with the fp64 operator, correction from T(d) = r solved with
-// fp32-operand operator applications to 1e-4 relative, x += d; repeat until
-// the fp64 residual meets tol.  Plain linsolve otherwise.
+// T(x) = b in the context's precision: plain fp64 linsolve, or with
+// fp32-operand images and fp64 image corrections (mixed precision).
 static int linsolve_refined(Ctx& c, int64_t n, bool packed,
                             const std::function<void(const double*, double*)>& T,
                             const std::function<void(double*, const double*)>& precond,
                             const double* b, double* x, double tol, int maxit, int* iters) {
-  if (!mixed(c)) {
-    c.eng->set_lowp(false);
-    return linsolve(c, n, packed, T, precond, b, x, tol, maxit, iters);
-  }
-  Arena& ar = c.eng->arena();
-  ArenaScope sc(ar);
-  double* r = ar.alloc(n);
-  double* d = ar.alloc(n);
-  auto nrm = [&](const double* p) {
-    return std::sqrt(std::max(0.0, packed ? dot_bio(c, p, p) : dot_plain(c, p, p, n)));
-  };
-  const double bn = nrm(b);
-  kc(fill(c.s, x, 0.0, n), "fill");
-  copy_d(c, r, b, n);
-  int total = 0, status = CC_NOT_CONVERGED;
-  for (int outer = 0; outer < 12 && total < maxit; ++outer) {
-    if (outer > 0) {
-      c.eng->set_lowp(false);
-      T(x, r);                          // fp64 operator
-      axpby_(c, r, b, 1.0, -1.0, n);    // r = b - T x
-    }
-    const double rn = nrm(r);
-    if (verbose()) std::fprintf(stderr, "[refine] outer %d |r| %.3e\n", outer, rn);
-    if (!std::isfinite(rn)) throw Error(-5, "non-finite refinement residual");
-    if (rn < tol * std::max(1.0, bn)) {
-      status = CC_OK;
-      break;
-    }
-    c.eng->set_lowp(true);
-    int it = 0;
-    linsolve(c, n, packed, T, precond, r, d, 1e-4 * std::min(1.0, rn), maxit - total, &it);
-    total += it;
-    axpby_(c, x, d, 1.0, 1.0, n);
-  }
-  c.eng->set_lowp(false);
-  if (iters) *iters = total;
-  return status;
+  return linsolve(c, n, packed, T, precond, b, x, tol, maxit, iters, mixed(c));
 }
 
 // ------------------------------------------------------ orbital rotation
