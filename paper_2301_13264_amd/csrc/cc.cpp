@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -656,8 +657,16 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   };
   // images of basis rows [m0, m) that have none, in one block application,
   // then the new rows and columns of the projected matrix G = V^T A V
+  double t_apply = 0.0;
   auto flush = [&](int m0, int mimg) {
-    if (mimg < m) T(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
+    if (mimg < m) {
+      const auto t0 = std::chrono::steady_clock::now();
+      T(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
+      if (verbose()) {
+        sync(c);
+        t_apply += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+    }
     const int r = m - m0;
     if (r <= 0) return;
     // columns G[k][j] = <V_k, W_j> and rows G[j][k] = <W_k, V_j>, j >= m0
@@ -739,13 +748,26 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       }
     return wt;
   };
+  // verbose: device time per phase (subspace eigensolve, Ritz vectors,
+  // residuals, corrections and their orthogonalisation, projections)
+  double t_ph[5] = {0, 0, 0, 0, 0};
+  auto t_last = std::chrono::steady_clock::now();
+  auto phase = [&](int k) {
+    if (!verbose()) return;
+    sync(c);
+    const auto now = std::chrono::steady_clock::now();
+    t_ph[k] += std::chrono::duration<double>(now - t_last).count();
+    t_last = now;
+  };
   for (int it = 1; it <= c.opts.maxit; ++it) {
     res.iters = it;
+    phase(4);
     std::vector<double> Gm((size_t)m * m);
     for (int a = 0; a < m; ++a)
       for (int b = 0; b < m; ++b) Gm[(size_t)a * m + b] = G[(size_t)a * maxm + b];
     std::vector<std::complex<double>> w, Vc;
     if (!eig_nonsym(Gm, m, w, Vc)) throw Error(-5, "subspace eigensolver failed");
+    phase(0);
     std::vector<int> ord(m);
     for (int k = 0; k < m; ++k) ord[k] = k;
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
@@ -764,14 +786,20 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       const std::complex<double> ph = std::conj(Vc[(size_t)kk * m + imax]) / std::abs(Vc[(size_t)kk * m + imax]);
       for (int i = 0; i < m; ++i) Y[(size_t)k * m + i] = (Vc[(size_t)kk * m + i] * ph).real();
     }
-    // Ritz vectors and images: X = Y V, AX = Y W
+    // Ritz vectors and images: X = Y V, AX = Y W (one streaming pass over
+    // the basis per block of kMaxRhs vectors)
     hip_check(hipMemcpyAsync(ydev, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-    kc(gemm_f64(c.s, false, false, nk, (int)N, m, 1, 1.0, ydev, m, 0, V, N, 0, 0.0, X, N, 0), "ritz");
-    kc(gemm_f64(c.s, false, false, nk, (int)N, m, 1, 1.0, ydev, m, 0, W, N, 0, 0.0, AX, N, 0), "ritz");
-    std::vector<double> rn(nk);
+    for (int k0 = 0; k0 < nk; k0 += kMaxRhs) {
+      const int kk = std::min(kMaxRhs, nk - k0);
+      kc(rows_axpy_multi(c.s, V, m, N, ydev + (int64_t)k0 * m, 1.0, X + (int64_t)k0 * N, N, kk, true), "ritz");
+      kc(rows_axpy_multi(c.s, W, m, N, ydev + (int64_t)k0 * m, 1.0, AX + (int64_t)k0 * N, N, kk, true), "ritz");
+    }
+    phase(1);
+    std::vector<double> rn(nk, 0.0);
     std::vector<double*> newv;
     double worst = 0.0;
-    for (int k = 0; k < nk; ++k) {
+    // residual norms of the wanted roots (of all Ritz pairs when reporting)
+    for (int k = 0; k < (verbose() ? nk : std::min(nk, nroots)); ++k) {
       double* xk = X + (int64_t)k * N;
       double* axk = AX + (int64_t)k * N;
       copy_d(c, Rs, axk, N);
@@ -781,6 +809,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       if (k < nroots) worst = std::max(worst, rn[k]);
     }
     if (!std::isfinite(worst)) throw Error(-5, "non-finite Davidson residual");
+    phase(2);
     if (verbose()) {
       std::fprintf(stderr, "[davidson] it %d m %d", it, m);
       for (int k = 0; k < nk; ++k) std::fprintf(stderr, " w%d=%.12f r=%.2e", k, res.w[k], rn[k]);
@@ -839,10 +868,18 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       n0.push_back(std::sqrt(std::max(0.0, dot_bio(c, x, x))));
       ++r;
     }
-    // block Gram-Schmidt against the basis (two passes), then within the block
+    // block Gram-Schmidt against the (orthonormal) basis; a second pass only
+    // when the first removed more than half of some vector's squared norm
     for (int pass = 0; pass < 2 && m0 > 0 && r > 0; ++pass) {
       dots_rows_multi(c, V, m0, Cblk, r, N, true, workm, H);
       sub_rows_multi(c, V, m0, H, Cblk, r, N, hdm);
+      bool again = false;
+      for (int a = 0; a < r; ++a) {
+        double p2 = 0.0;
+        for (int k = 0; k < m0; ++k) p2 += H[(size_t)a * m0 + k] * H[(size_t)a * m0 + k];
+        if (p2 > 0.5 * n0[a] * n0[a]) again = true;
+      }
+      if (!again) break;
     }
     for (int a = 0; a < r && m < maxm; ++a) {
       double* x = Cblk + (int64_t)a * N;
@@ -855,9 +892,15 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
       ++m;
     }
+    phase(3);
     flush(m0, m0);
   }
   c.eng->set_lowp(false);
+  if (verbose())
+    std::fprintf(stderr,
+                 "[davidson] %d iterations, %.3f s in operator applications; eig %.3f ritz %.3f residuals %.3f "
+                 "corrections %.3f projections %.3f s\n",
+                 res.iters, t_apply, t_ph[0], t_ph[1], t_ph[2], t_ph[3], t_ph[4] - t_apply);
   // normalise and hand out the nroots lowest Ritz vectors
   for (int k = 0; k < nroots; ++k) {
     const double xn = std::sqrt(dot_bio(c, X + (int64_t)k * N, X + (int64_t)k * N));

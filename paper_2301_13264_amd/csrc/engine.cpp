@@ -58,6 +58,8 @@ double* Arena::alloc(int64_t ndouble) {
     }
     size_t cap = std::max(bytes, (size_t)1 << 30);
     char* base = nullptr;
+    if (std::getenv("NACME_VERBOSE"))
+      std::fprintf(stderr, "[arena] new chunk %.3f GB (%zu held)\n", cap / 1e9, chunks_.size());
     hipError_t e = hipMalloc(&base, cap);
     if (e != hipSuccess) {
       (void)hipGetLastError();

@@ -48,9 +48,9 @@ int rows_scratch_doubles();
 // out[r][k] = <V_k, X_r> for R <= kMaxRhs vectors X_r = X + r ldx (device out)
 int rows_dot_multi(hipStream_t s, const double* V, int m, int64_t n, const double* X, int64_t ldx,
                    int R, double* part, double* out);
-// X_r += alpha sum_k H[r][k] V_k (H device [R][m])
+// X_r += alpha sum_k H[r][k] V_k (H device [R][m]); overwrite: X_r = alpha sum ...
 int rows_axpy_multi(hipStream_t s, const double* V, int m, int64_t n, const double* H, double alpha,
-                    double* X, int64_t ldx, int R);
+                    double* X, int64_t ldx, int R, bool overwrite = false);
 int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h, double alpha,
               double* x);
 

@@ -1046,7 +1046,7 @@ template <int R>
 __global__ __launch_bounds__(256) void rows_axpy_multi_kernel(const double* __restrict__ V, int m,
                                                               int64_t n, const double* __restrict__ H,
                                                               double alpha, double* __restrict__ X,
-                                                              int64_t ldx) {
+                                                              int64_t ldx, int overwrite) {
   __shared__ double hs[R][kMaxRows];
   for (int t = threadIdx.x; t < R * m; t += blockDim.x) hs[t / m][t % m] = H[t];
   __syncthreads();
@@ -1061,16 +1061,19 @@ __global__ __launch_bounds__(256) void rows_axpy_multi_kernel(const double* __re
       for (int r = 0; r < R; ++r) acc[r] += hs[r][k] * vk;
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) X[(int64_t)r * ldx + e] += alpha * acc[r];
+    for (int r = 0; r < R; ++r) {
+      double* xr = X + (int64_t)r * ldx + e;
+      *xr = overwrite ? alpha * acc[r] : *xr + alpha * acc[r];
+    }
   }
 }
 
 int rows_axpy_multi(hipStream_t s, const double* V, int m, int64_t n, const double* H, double alpha,
-                    double* X, int64_t ldx, int R) {
+                    double* X, int64_t ldx, int R, bool overwrite) {
   if (m <= 0 || R <= 0) return 0;
   if (m > kMaxRows || R > kMaxRhs) return -1;
 #define NM_RA(RR) \
-  hipLaunchKernelGGL(rows_axpy_multi_kernel<RR>, dim3(grid_for(n)), dim3(256), 0, s, V, m, n, H, alpha, X, ldx)
+  hipLaunchKernelGGL(rows_axpy_multi_kernel<RR>, dim3(grid_for(n)), dim3(256), 0, s, V, m, n, H, alpha, X, ldx, (int)overwrite)
   switch (R) {
     case 1: NM_RA(1); break;
     case 2: NM_RA(2); break;
