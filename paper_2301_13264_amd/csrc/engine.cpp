@@ -556,6 +556,47 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
     return;
   }
 
+  // A product of a large operand X with a small one F over a short contracted
+  // range (K < 64: the occupied-index sums) is bound by memory, so it runs in
+  // fp64 in both precisions, as a batched GEMM that reads X and updates C in
+  // place with F packed transposed ([n][k], a few KB):
+  //   C_b[n][r] = sum_k F[k][n] X_b[k][r],
+  // b = leading labels of X that also lead C, r = the other labels of X that
+  // C holds (trailing both), n = F's labels in C.  Layouts that do not allow
+  // it fall through to the general paths.
+  if (sb.empty() && K < 64) {
+    const int64_t na = prod_of(A, labels_of(A)), nbv = prod_of(B, labels_of(B));
+    const bool smallB = nbv <= ((int64_t)1 << 16) && na >= ((int64_t)1 << 20);
+    const bool smallA = na <= ((int64_t)1 << 16) && nbv >= ((int64_t)1 << 20);
+    if (smallA || smallB) {
+      const DView& X = smallB ? A : B;
+      const DView& F = smallB ? B : A;
+      std::string kx, rx, nc;
+      for (int d = 0; d < X.nd; ++d) (find_lab(C, X.lab[d]) >= 0 ? rx : kx) += X.lab[d];
+      for (int d = 0; d < C.nd; ++d)
+        if (find_lab(X, C.lab[d]) < 0) nc += C.lab[d];
+      for (int L = std::min(X.nd, C.nd); L >= 0; --L) {
+        const std::string pre(X.lab, X.lab + L);
+        if (std::string(C.lab, C.lab + L) != pre) continue;
+        std::string rest;
+        for (char ch : rx)
+          if (pre.find(ch) == std::string::npos) rest += ch;
+        int64_t ldx, bsx, ldcs, bsc;
+        if (rest.empty() || prod_of(X, rest) < 16 || !as_matrix(X, pre, kx, rest, ldx, bsx) ||
+            !as_matrix(C, pre, nc, rest, ldcs, bsc))
+          continue;
+        const int64_t Mn = prod_of(F, nc), Nr = prod_of(X, rest), nbx = prod_of(X, pre);
+        if (Mn > INT32_MAX || Nr > INT32_MAX || nbx > INT32_MAX) break;
+        const DView Fp = packed_view(arena_, F, nc + kx, s_);
+        kcheck(gemm_f64(s_, false, false, (int)Mn, (int)Nr, (int)K, (int)nbx, alpha, Fp.p, K, 0, X.p,
+                        ldx, bsx, overwrite ? 0.0 : 1.0, C.p, ldcs, bsc),
+               "gemm (small operand)");
+        arena_.rewind(mk);
+        return;
+      }
+    }
+  }
+
   // Mixed-precision path for large contractions: pack both operands to fp32
   // in [batch][rows][k] / [batch][k][cols] order and multiply on the FP32
   // matrix cores (fp32 accumulation, fp64 result); products with few output

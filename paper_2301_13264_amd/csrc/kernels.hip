@@ -266,10 +266,14 @@ __global__ __launch_bounds__(NT, 4) void gemm_f64_big_kernel(
 
 // FP32 variant of the large-tile kernel for the mixed-precision path: fp32
 // operands (packed by the caller), v_mfma_f32_16x16x4f32 with fp32
-// accumulation, fp64 epilogue C = alpha * acc + beta * C.  Same tiling, LDS
-// strides (17 / 144 floats keep the operand reads conflict-free: 17 r and
-// 144 k spread the 64 lanes over distinct banks) and XCD-grouped tile order.
+// accumulation, fp64 epilogue C = alpha * acc + beta * C.  Same 128 x 128
+// tiling and XCD-grouped tile order as the fp64 kernel, with a K step of 32
+// (half the barriers per MFMA of a 16 step; two workgroups of 74 KB LDS fit a
+// CU).  LDS strides: [row][k] 34 floats (2 mod 32: the 16 rows x 2 k of a
+// half-wave's operand read hit 32 distinct banks), [k][row] 144 floats
+// (16 mod 32: 2 k x 16 rows again distinct).
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int FBK = 32, FKS = FBK + 2, FRS = 128 + 16;
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
@@ -277,9 +281,9 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
     const float* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int Klast) {
   constexpr int NT = 512, WM = 4, TR = LBM / WM, FI = TR / 16;
-  constexpr int PER = (LBM * LBK) / NT, RSTEP = NT / 16, KSTEP = NT / 128;
-  constexpr int ASZ = TA ? LBK * LRS : LBM * LKS;
-  constexpr int BSZ = TB ? LBN * LKS : LBK * LRS;
+  constexpr int PER = (LBM * FBK) / NT, RSTEP = NT / FBK, KSTEP = NT / 128;
+  constexpr int ASZ = TA ? FBK * FRS : LBM * FKS;
+  constexpr int BSZ = TB ? LBN * FKS : FBK * FRS;
   __shared__ float As[2][ASZ];
   __shared__ float Bs[2][BSZ];
   // grid.z: batch entries, or K chunks of a split-K product (the last chunk
@@ -298,16 +302,16 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  const int a_row0 = TA ? (tid & 127) : (tid >> 4);
-  const int a_k0 = TA ? (tid >> 7) : (tid & 15);
-  const int b_row0 = TB ? (tid >> 4) : (tid & 127);
-  const int b_k0 = TB ? (tid & 15) : (tid >> 7);
+  const int a_row0 = TA ? (tid & 127) : (tid / FBK);
+  const int a_k0 = TA ? (tid >> 7) : (tid % FBK);
+  const int b_row0 = TB ? (tid / FBK) : (tid & 127);
+  const int b_k0 = TB ? (tid % FBK) : (tid >> 7);
   const float* pa = TA ? A + (int64_t)a_k0 * lda + (m0 + a_row0) : A + (int64_t)(m0 + a_row0) * lda + a_k0;
   const float* pb = TB ? B + (int64_t)(n0 + b_row0) * ldb + b_k0 : B + (int64_t)b_k0 * ldb + (n0 + b_row0);
   const int64_t a_rstep = TA ? KSTEP * lda : RSTEP * lda;
   const int64_t b_rstep = TB ? RSTEP * ldb : KSTEP * ldb;
-  const int64_t a_kstep = TA ? (int64_t)LBK * lda : LBK;
-  const int64_t b_kstep = TB ? LBK : (int64_t)LBK * ldb;
+  const int64_t a_kstep = TA ? (int64_t)FBK * lda : FBK;
+  const int64_t b_kstep = TB ? FBK : (int64_t)FBK * ldb;
   v4f acc[FI][4];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   float ra[PER], rb[PER];
   auto gload = [&](int t) {
-    const int kb = t * LBK;
+    const int kb = t * FBK;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int row = TA ? a_row0 : a_row0 + RSTEP * r;
@@ -334,16 +338,16 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      if (TA) As[buf][(a_k0 + KSTEP * r) * LRS + a_row0] = ra[r];
-      else As[buf][(a_row0 + RSTEP * r) * LKS + a_k0] = ra[r];
+      if (TA) As[buf][(a_k0 + KSTEP * r) * FRS + a_row0] = ra[r];
+      else As[buf][(a_row0 + RSTEP * r) * FKS + a_k0] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      if (TB) Bs[buf][(b_row0 + RSTEP * r) * LKS + b_k0] = rb[r];
-      else Bs[buf][(b_k0 + KSTEP * r) * LRS + b_row0] = rb[r];
+      if (TB) Bs[buf][(b_row0 + RSTEP * r) * FKS + b_k0] = rb[r];
+      else Bs[buf][(b_k0 + KSTEP * r) * FRS + b_row0] = rb[r];
     }
   };
-  const int nk = (K + LBK - 1) / LBK;
+  const int nk = (K + FBK - 1) / FBK;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -353,17 +357,17 @@ __global__ __launch_bounds__(512, 4) void gemm_f32acc_big_kernel(
     const float* as = As[cur];
     const float* bs = Bs[cur];
 #pragma unroll
-    for (int kk = 0; kk < LBK; kk += 4) {
+    for (int kk = 0; kk < FBK; kk += 4) {
       float a[FI], bb[4];
 #pragma unroll
       for (int i = 0; i < FI; ++i) {
         const int row = wm * TR + i * 16 + lr, k = kk + lk;
-        a[i] = TA ? as[k * LRS + row] : as[row * LKS + k];
+        a[i] = TA ? as[k * FRS + row] : as[row * FKS + k];
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = wn * 64 + j * 16 + lr, k = kk + lk;
-        bb[j] = TB ? bs[row * LKS + k] : bs[k * LRS + row];
+        bb[j] = TB ? bs[row * FKS + k] : bs[k * FRS + row];
       }
 #pragma unroll
       for (int i = 0; i < FI; ++i)
