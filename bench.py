@@ -79,7 +79,7 @@ def run_step(nm, torch, inp, cfg, opts):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 1.6324e+10, "fp32": 6.0837e+09}
+LADDER_TRAFFIC_BYTES = {"fp64": 1.6324e+10, "fp32": None}
 
 
 def ladder_roofline(nm, torch, cfg, dev, st, nl=10):

@@ -1170,9 +1170,14 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   for (it = 1; it <= maxit && m < maxm; ++it) {
     if (packed) kc(apply_metric(c.s, r, r, c.o, c.v, 2), "symmetrise");
     const double n0 = std::sqrt(std::max(0.0, dotf(r, r)));
+    // Gram-Schmidt against the orthonormal basis; a second pass only when the
+    // first removed more than half of the squared norm
     for (int pass = 0; pass < 2 && m > 0; ++pass) {
       dots_rows(c, V, m, r, n, packed, work, h);
       sub_rows(c, V, m, h, r, n, hd);
+      double p2 = 0.0;
+      for (int k = 0; k < m; ++k) p2 += h[k] * h[k];
+      if (p2 <= 0.5 * n0 * n0) break;
     }
     const double n1 = std::sqrt(std::max(0.0, dotf(r, r)));
     if (!(n1 > 1e-14 * std::max(n0, 1e-300))) break;
@@ -1191,8 +1196,8 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
         for (int bb = 0; bb < m; ++bb) Gm[(size_t)a * m + bb] = G[(size_t)a * maxm + bb];
       if (!lu_solve(Gm, cvec, m, 1)) throw Error(-5, "singular projected linear system");
       hip_check(hipMemcpyAsync(y, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-      kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, V, n, 0, 0.0, x, n, 0), "combine");
-      kc(gemm_f64(c.s, false, false, 1, (int)n, m, 1, 1.0, y, m, 0, W, n, 0, 0.0, r, n, 0), "combine");
+      kc(rows_axpy_multi(c.s, V, m, n, y, 1.0, x, n, 1, true), "combine");
+      kc(rows_axpy_multi(c.s, W, m, n, y, 1.0, r, n, 1, true), "combine");
       axpby_(c, r, b, -1.0, 1.0, n);    // r = T x - b
       const double rn = std::sqrt(std::max(0.0, dotf(r, r)));
       if (!std::isfinite(rn)) throw Error(-5, "non-finite linear-solver residual");
@@ -1362,6 +1367,16 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
   Arena& ar = c.eng->arena();
   int status = CC_OK;
   int it_z = 0, it_k = 0;
+  // verbose: device time per phase
+  double t_ph[6] = {0, 0, 0, 0, 0, 0};
+  auto t_last = std::chrono::steady_clock::now();
+  auto phase = [&](int k) {
+    if (!verbose()) return;
+    sync(c);
+    const auto now = std::chrono::steady_clock::now();
+    t_ph[k] += std::chrono::duration<double>(now - t_last).count();
+    t_last = now;
+  };
   {
     Tape tp(c);
     // JVP along R_j, kept on the tape
@@ -1372,6 +1387,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       ar1 = tan.at(tp.r.om1);
       ar2 = tan.at(tp.r.om2);
     }
+    phase(0);
     ArenaScope sc(ar);
     double* wg = ar.alloc(N);     // metric-weighted gamma
     kc(apply_metric(c.s, wg, P.gamma, c.o, c.v, 0), "metric");
@@ -1429,6 +1445,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
     }
     // zeta: A^T zeta = -eta_t
+    phase(1);
     if (!grad_mode && !has_right) {
       axpby_(c, P.zeta, c.L[i], -1.0 / wi, 0.0, N);
     } else {
@@ -1442,6 +1459,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       if (st != CC_OK) status = st;
     }
     // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j) (+ E0)
+    phase(2);
     {
       double* wz = ar.alloc(N);
       kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
@@ -1481,6 +1499,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       hip_check(hipGetLastError(), "HF energy terms");
     }
   }
+  phase(3);
   if (c.opts.relaxed) {
     ArenaScope sc(ar);
     Graph G(*c.eng);
@@ -1501,6 +1520,7 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       const int e1 = Gd.node({c.o, c.v}, {lin(-1, op(d, "ai", {V, O}), "ia"), lin(1, op(d, "ia", {O, V}), "ia")});
       axpby_(c, P.eta_k, Gd.val(e1).p, 1.0, 1.0, nov);
     }
+    phase(4);
     // (A^HF)^T kappa_bar = -eta_kappa, A^HF_(ai),(bj) = dF_ai/dkappa_bj
     double* b = ar.alloc(nov);
     axpby_(c, b, P.eta_k, -1.0, 0.0, nov);
@@ -1535,6 +1555,11 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
     kc(fill(c.s, P.kbar, 0.0, nov), "fill");
     kc(fill(c.s, P.eta_k, 0.0, nov), "fill");
   }
+  phase(5);
+  if (verbose())
+    std::fprintf(stderr,
+                 "[multipliers] (%d,%d) tape+jvp %.3f rhs %.3f zeta %.3f dens-adjoint %.3f eta-kappa %.3f "
+                 "kappa %.3f s\n", i1, j1, t_ph[0], t_ph[1], t_ph[2], t_ph[3], t_ph[4], t_ph[5]);
   P.have_mult = true;
   P.have_dens = false;
   if (iters) {
