@@ -74,26 +74,32 @@ def run_step(nm, torch, inp, cfg, opts):
                      stage_s=st)
 
 
-# HBM traffic of one ladder GEMM launch (M = o^2 = 1089, N = K = v^2 = 16129),
-# from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of `bench.py --roofline-only`
+# HBM traffic of one ladder GEMM launch for a block of LADDER_VECTORS trial
+# vectors (M = 2 o^2 = 2178, N = K = v^2 = 16129), from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE of `bench.py --roofline-only`
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 1.6324e+10, "fp32": None}
+LADDER_TRAFFIC_BYTES = {"fp64": None, "fp32": None}
+# trial vectors per ladder launch: the block the EOM solver pushes through each
+# Jacobian transform (the wanted roots)
+LADDER_VECTORS = 2
 
 
 def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
-    """Ladder GEMM roofline: Y[ij][ab] = sum_cd t[ij][cd] W[cd][ab], one launch of
-    the matrix-core GEMM (M = o^2, N = K = v^2) per operand precision, timed
-    with HIP events on the stream the kernel is launched on."""
+    """Ladder GEMM roofline: Y[z ij][ab] = sum_cd X[z ij][cd] W[cd][ab] for a
+    block of LADDER_VECTORS trial vectors z, one launch of the matrix-core GEMM
+    (M = LADDER_VECTORS o^2, N = K = v^2; 2 o^2 v^4 flop per vector) per operand
+    precision, timed with HIP events on the stream the kernel is launched on."""
     o, v = cfg["o"], cfg["v"]
-    ladder_flop = 2.0 * o * o * v ** 4
+    rows = LADDER_VECTORS * o * o
+    ladder_flop = 2.0 * rows * v ** 4
     roof = {}
     for pname, pcode, dt, peak in [("fp64", 0, torch.float64, PEAK_FP64_TFLOPS),
                                    ("fp32", 1, torch.float32, PEAK_FP32_TFLOPS)]:
-        A = torch.randn(o * o, v * v, dtype=dt, device=dev)
+        A = torch.randn(rows, v * v, dtype=dt, device=dev)
         Bv = torch.randn(v * v, v * v, dtype=dt, device=dev)
-        C = torch.zeros(o * o, v * v, dtype=torch.float64, device=dev)
+        C = torch.zeros(rows, v * v, dtype=torch.float64, device=dev)
         nm.gemm(pcode, A, Bv, C, stream=st)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(st)
@@ -109,9 +115,10 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
                            algorithmic_bytes=(A.numel() + Bv.numel()) * A.element_size()
                            + 8 * C.numel())
         del A, Bv, C
-    roof["fp64"]["kernel"] = "gemm_f64_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp64 operands)"
-    roof["fp32"]["kernel"] = ("gemm_f32acc_big_kernel (ladder t2[ij][cd] x W[cd][ab], fp32 "
-                              "operands, fp32 accumulation)")
+    roof["fp64"]["kernel"] = (f"gemm_f64_big_kernel (ladder X[z ij][cd] x W[cd][ab], "
+                              f"{LADDER_VECTORS} trial vectors, fp64 operands)")
+    roof["fp32"]["kernel"] = (f"gemm_f32acc_big_kernel (ladder X[z ij][cd] x W[cd][ab], "
+                              f"{LADDER_VECTORS} trial vectors, fp32 operands, fp32 accumulation)")
     return roof
 
 
