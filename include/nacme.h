@@ -68,8 +68,10 @@ extern "C" {
 
 #define CC_FP64 0          /* every contraction in fp64                          */
 #define CC_FP32_REFINE 1   /* large contractions with fp32 operands on the FP32
-                              matrix cores inside the solvers, fp64 residuals
-                              and fp64 final iterations (iterative refinement) */
+                              matrix cores inside the solvers; the current
+                              solution gets fp64 operator images that correct
+                              the subspace, and only fp64 residuals decide
+                              convergence (iterative refinement)             */
 
 /* Export / guess selectors. */
 #define CC_T 1        /* ground amplitudes (amplitude-shaped)                 */
