@@ -9,13 +9,15 @@ factor, derivative integrals):
   cc_create (integral build) -> cc_ground -> eom_solve(both sides)
   -> multipliers, densities, nacme for the ordered pairs (1,2) and (2,1).
 
-The timed steps run the mixed-precision path (fp32-operand matrix-core
-contractions inside the solvers, fp64 residuals and fp64 final iterations);
-one step of the plain fp64 path runs beside it for the speed-up and the
-coupling agreement.  The run also measures the Jacobian transforms per
-second, the ladder GEMM's roofline fraction in both precisions (HIP events
-on the stream the kernel runs on) and a CPU baseline (the fp64 oracle's
-residual at the same size on the host cores).
+The timed steps run the mixed-precision path (default: the eigen- and linear
+solvers' contractions as bfloat16 pairs with three bf16 matrix-core products,
+the ground state with fp32 operands; fp64 images of the current solutions and
+fp64 residuals decide convergence; --precision mixed uses fp32 operands
+throughout); one step of the plain fp64 path runs beside it for the speed-up
+and the coupling agreement.  The run also measures the Jacobian transforms
+per second, the ladder GEMM's roofline fraction in every precision (HIP
+events on the stream the kernel runs on) and a CPU baseline (the fp64
+oracle's residual at the same size on the host cores).
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ sys.path.insert(0, ROOT)
 # 157.3 TFLOP/s; HBM 8 TB/s.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 WORKLOAD = dict(name="thymine_dz", o=33, v=127, naux=640, nroots=2, ndir=45, seed=4301)
 # DF factor scale: the recipe's N(0, 0.05) gives no convergent CCSD at this
 # size (ground-state iterations overflow from the MP2 start); the scale is
@@ -80,10 +83,17 @@ def run_step(nm, torch, inp, cfg, opts):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.9769e+10, "fp32": 1.8957e+10}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.9769e+10, "fp32": 1.8957e+10, "bf16x3": None}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
+
+# timed-step precision: library mode, dtype label, dominant ladder kernel
+PRECISIONS = {
+    "mixed": ("CC_FP32_REFINE", "f32+f64", "fp32"),
+    "bf16x3": ("CC_BF16X3_REFINE", "bf16x3+f32+f64", "bf16x3"),
+    "fp64": ("CC_FP64", "f64", "fp64"),
+}
 
 
 def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
@@ -115,6 +125,29 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
                            algorithmic_bytes=(A.numel() + Bv.numel()) * A.element_size()
                            + 8 * C.numel())
         del A, Bv, C
+    # bfloat16 pairs: three bf16 products per product, K padded to a multiple
+    # of 32; achieved counts the bf16 matrix-core flops (3 x the ladder's)
+    Kp = (v * v + 31) // 32 * 32
+    A = torch.randn(2, rows, Kp, device=dev).to(torch.bfloat16)
+    Bt = torch.randn(2, v * v, Kp, device=dev).to(torch.bfloat16)
+    C = torch.zeros(rows, v * v, dtype=torch.float64, device=dev)
+    nm.gemm(2, A, Bt, C, stream=st)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for _ in range(nl):
+        nm.gemm(2, A, Bt, C, stream=st)
+    ev1.record(st)
+    ev1.synchronize()
+    lms = ev0.elapsed_time(ev1) / nl
+    tf = 3.0 * ladder_flop / (lms * 1e-3) / 1e12
+    roof["bf16x3"] = dict(bound="mfma", achieved=tf, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                          frac=tf / PEAK_BF16_TFLOPS, traffic=LADDER_TRAFFIC_BYTES["bf16x3"],
+                          launch_ms=lms, flop_per_launch=3.0 * ladder_flop, products_per_flop=3,
+                          algorithmic_bytes=(A.numel() + Bt.numel()) * 2 + 8 * C.numel())
+    del A, Bt, C
+    roof["bf16x3"]["kernel"] = (f"gemm_bf16x3_kernel (ladder X[z ij][cd] x W[cd][ab], "
+                                f"{LADDER_VECTORS} trial vectors, bfloat16 pairs, 3 bf16 products, "
+                                "fp32 accumulation)")
     roof["fp64"]["kernel"] = (f"gemm_f64_big_kernel (ladder X[z ij][cd] x W[cd][ab], "
                               f"{LADDER_VECTORS} trial vectors, fp64 operands)")
     roof["fp32"]["kernel"] = (f"gemm_f32acc_big_kernel (ladder X[z ij][cd] x W[cd][ab], "
@@ -142,7 +175,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--transforms", type=int, default=3)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed",
+    ap.add_argument("--precision", choices=list(PRECISIONS), default="bf16x3",
                     help="precision of the timed steps")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the step in the other precision")
@@ -171,7 +204,7 @@ def main():
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
     inp = dict(eps=T(sysd["eps"]), B=T(sysd["B"]), dh=T(dirs["dh"]), dB=T(dirs["dB"]))
     torch.cuda.synchronize()
-    prec = nm.CC_FP32_REFINE if args.precision == "mixed" else nm.CC_FP64
+    prec = getattr(nm, PRECISIONS[args.precision][0])
     opts = nm.default_opts(precision=prec)
 
     for w in range(args.warmup):
@@ -199,7 +232,8 @@ def main():
     N = cfg["o"] * cfg["v"] + (cfg["o"] * cfg["v"]) ** 2
     st = torch.cuda.current_stream()
     tr = {}
-    for pname, pcode in [("fp64", nm.CC_FP64), ("fp32", nm.CC_FP32_REFINE)]:
+    for pname, pcode in [("fp64", nm.CC_FP64), ("fp32", nm.CC_FP32_REFINE),
+                         ("bf16x3", nm.CC_BF16X3_REFINE)]:
         for side, sname in [(nm.CC_RIGHT, "right"), (nm.CC_LEFT, "left")]:
             per_call = {}
             for k in (1, 4):
@@ -220,8 +254,8 @@ def main():
 
     other = None
     if not args.no_compare:
-        oname = "fp64" if args.precision == "mixed" else "mixed"
-        oprec = nm.CC_FP64 if args.precision == "mixed" else nm.CC_FP32_REFINE
+        oname = "fp64" if args.precision != "fp64" else "mixed"
+        oprec = nm.CC_FP64 if args.precision != "fp64" else nm.CC_FP32_REFINE
         log(f"[bench] one step in {oname} for comparison")
         c0 = time.perf_counter()
         octx, oout = run_step(nm, torch, inp, cfg, nm.default_opts(precision=oprec))
@@ -239,7 +273,7 @@ def main():
 
     o, v = cfg["o"], cfg["v"]
     roof = ladder_roofline(nm, torch, cfg, dev, st)
-    main_roof = roof["fp32"] if args.precision == "mixed" else roof["fp64"]
+    main_roof = roof[PRECISIONS[args.precision][2]]
 
     # CPU baseline: the oracle's residual at the same size on the host cores
     cpu = None
@@ -269,7 +303,7 @@ def main():
         metric="time-to-NACME vector & Jacobian transforms/s (TFLOP/s, % MFMA peak) at <=1e-6 au",
         value=value, unit="NACME vectors/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32+f64" if args.precision == "mixed" else "f64",
+        dtype=PRECISIONS[args.precision][1],
         data="synthetic",
         config=dict(workload="thymine_dz: o=33 v=127 naux=640, 2 roots, 45 directions, "
                              f"DF scale {SIGMA_B:.5f}", global_batch=1, parallelism="none"),
@@ -277,7 +311,7 @@ def main():
         time_to_nacme_s=ms / 1000.0,
         compare=other,
         speedup_vs_fp64=(other["time_to_nacme_s"] / (ms / 1000.0)
-                         if other and args.precision == "mixed" else None),
+                         if other and args.precision != "fp64" else None),
         stage_s=out["stage_s"],
         omega=out["omega"], e_corr=out["e_corr"],
         jacobian_transforms_per_s={k: 1000.0 / x["ms_per_vector_k4"] for k, x in tr.items()},

@@ -72,6 +72,11 @@ extern "C" {
                               solution gets fp64 operator images that correct
                               the subspace, and only fp64 residuals decide
                               convergence (iterative refinement)             */
+#define CC_BF16X3_REFINE 2 /* as CC_FP32_REFINE, with the eigen- and linear
+                              solvers' contractions run as bfloat16 pairs
+                              (hi + lo, three bf16 matrix-core products, fp32
+                              accumulation, ~1e-5 relative); ground state
+                              with fp32 operands                            */
 
 /* Export / guess selectors. */
 #define CC_T 1        /* ground amplitudes (amplitude-shaped)                 */
@@ -88,7 +93,7 @@ extern "C" {
 typedef struct cc_ctx cc_ctx;
 
 typedef struct {
-  int precision;       /* CC_FP64 or CC_FP32_REFINE                            */
+  int precision;       /* CC_FP64, CC_FP32_REFINE or CC_BF16X3_REFINE          */
   int relaxed;         /* 1: orbital-relaxed (kappa-bar solved), 0: fixed      */
                        /*    reference (kappa-bar = 0)                         */
   double tol_ground;   /* max |Omega_mu| of the ground state                   */
@@ -162,9 +167,9 @@ int nacme(cc_ctx* ctx, int i, int j, int nq, const double* dh, const double* dB,
 int cc_apply_jacobian(cc_ctx* ctx, int side, const double* X, double* Y);
 /* Batched transforms (Sec. II B): Y[z] = A X[z] (CC_RIGHT) or X[z]^T A
  * (CC_LEFT) for k vectors stored [k][N] (N = o v + o^2 v^2, device), all k
- * pushed through each contraction together.  precision CC_FP64, or
- * CC_FP32_REFINE for the fp32-operand contractions the mixed-precision
- * solvers use (results then carry fp32 rounding).                          */
+ * pushed through each contraction together.  precision CC_FP64,
+ * CC_FP32_REFINE or CC_BF16X3_REFINE for the low-precision contractions the
+ * mixed-precision solvers use (results then carry that rounding).          */
 int cc_apply_jacobian_block(cc_ctx* ctx, int side, int k, const double* X, double* Y,
                             int precision);
 /* omega = Omega(t) for amplitudes t (device, amplitude-shaped).              */
@@ -188,15 +193,20 @@ void cc_destroy(cc_ctx* ctx);
 /* Engine surface.  C = alpha * einsum(spec)(A, B) + beta * C on device
  * arrays; spec "ab,bc->ac" (lowercase letters, <= 6 per operand, repeated
  * letters inside one operand select a diagonal).  dims* give the shapes.
- * precision: CC_FP64, or CC_FP32_REFINE to run the contraction with fp32
- * operands (fp32 accumulation, fp64 result) whatever its size.              */
+ * precision: CC_FP64, CC_FP32_REFINE to run the contraction with fp32
+ * operands (fp32 accumulation, fp64 result) whatever its size, or
+ * CC_BF16X3_REFINE for bfloat16-pair operands (contracted range >= 32).     */
 int nm_contract(const char* spec, double alpha, const double* A, const int64_t* dimsA,
                 const double* B, const int64_t* dimsB, double beta, double* C,
                 const int64_t* dimsC, int precision, void* stream);
 /* Kernel surface: one launch of the matrix-core GEMM used by the engine,
  * C[M][N] = alpha op(A) op(B) + beta C (row-major, leading dimensions lda,
  * ldb, ldc; ta / tb select A stored [K][M] / B stored [N][K]).  precision
- * CC_FP64: A, B double; CC_FP32_REFINE: A, B float (fp32 accumulation).
+ * CC_FP64: A, B double; CC_FP32_REFINE: A, B float (fp32 accumulation);
+ * CC_BF16X3_REFINE: bfloat16 pairs (uint16 storage), A = hi [M][lda] followed
+ * by lo [M][lda], B given transposed (tb = 1) as hi [N][ldb] then lo; K a
+ * multiple of 32, lda / ldb multiples of 8, 16-byte aligned; each product
+ * formed as three bf16 products with fp32 accumulation.
  * Asynchronous on `stream`.                                                 */
 int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
             int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,

@@ -3,5 +3,6 @@
 The computation lives in libnacme.so (C ABI, include/nacme.h); this package
 only builds and binds it.
 """
-from ._lib import (CC_BOTH, CC_FP32_REFINE, CC_FP64, CC_LEFT, CC_RIGHT,  # noqa: F401
+from ._lib import (CC_BF16X3_REFINE, CC_BOTH, CC_FP32_REFINE, CC_FP64, CC_LEFT,  # noqa: F401
+                   CC_RIGHT,
                    CCError, MLP, Context, contract, default_opts, eig_host, gemm, lib)

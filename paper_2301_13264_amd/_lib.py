@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnacme.so")
 
 CC_OK, CC_NOT_CONVERGED = 0, 1
 CC_RIGHT, CC_LEFT, CC_BOTH = 1, 2, 3
-CC_FP64, CC_FP32_REFINE = 0, 1
+CC_FP64, CC_FP32_REFINE, CC_BF16X3_REFINE = 0, 1, 2
 CC_T, CC_R, CC_L, CC_R0, CC_ZETA, CC_KAPPA, CC_D1, CC_ETA_T, CC_ETA_K, CC_DTRANS = range(1, 11)
 
 ERRORS = {-1: "argument", -2: "call order", -3: "HIP", -4: "out of memory",
@@ -254,8 +254,23 @@ def contract(spec: str, alpha, A, B, beta, C, stream=None, precision=0):
 
 def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None):
     """One matrix-core GEMM launch C = alpha A B + beta C (2-D row-major
-    device tensors; A, B float64 for precision 0, float32 for precision 1)."""
+    device tensors; A, B float64 for precision 0, float32 for precision 1).
+    Precision 2: A [2][M][K] and Bt [2][N][K] bfloat16 pairs (hi, lo) with B
+    given transposed, K a multiple of 32."""
     import torch
+    if precision == 2:
+        for t in (A, B):
+            if not t.is_cuda or t.dtype != torch.bfloat16 or not t.is_contiguous() or t.dim() != 3:
+                raise ValueError("bad GEMM operand")
+        _, M, K = A.shape
+        _, N, K2 = B.shape
+        if K2 != K or tuple(C.shape) != (M, N):
+            raise ValueError("GEMM shape mismatch")
+        rc = lib().nm_gemm(2, 0, 1, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), K,
+                           ctypes.c_void_p(B.data_ptr()), K, beta, _ptr(C), N, _stream_ptr(stream))
+        if rc != CC_OK:
+            raise CCError(rc, "nm_gemm")
+        return C
     want = torch.float64 if precision == 0 else torch.float32
     for t in (A, B):
         if not t.is_cuda or t.dtype != want or not t.is_contiguous():

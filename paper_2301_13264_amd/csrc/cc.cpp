@@ -143,11 +143,18 @@ struct ArenaScope {
 // operands until the residual falls below kMixedSwitch, then finish with fp64
 // operators and fp64 residuals.
 constexpr double kMixedSwitch = 1e-5;
-// Eigensolver: fp32-operand images carry about 1e-7 relative rounding, so the
-// residual norms computed from them level off near 1e-7; at that point (or
-// when they stall) the wanted Ritz vectors get fp64 images.
-constexpr double kEigSwitch = 1e-7;
-static bool mixed(const Ctx& c) { return c.opts.precision == CC_FP32_REFINE; }
+// Eigen- and linear solvers: fp32-operand images carry about 1e-7 relative
+// rounding (bf16 pairs about 1e-5), so the residual norms computed from them
+// level off there; at that point (or when they stall) the current solution
+// gets fp64 images.
+constexpr double kEigSwitch = 1e-7, kEigSwitchBf16 = 1e-5;
+static bool mixed(const Ctx& c) {
+  return c.opts.precision == CC_FP32_REFINE || c.opts.precision == CC_BF16X3_REFINE;
+}
+// the solvers' low-precision operator: bf16 pairs in CC_BF16X3_REFINE (the
+// ground state keeps fp32 operands: its fp64 phase starts at 1e-5)
+static bool solver_bf16(const Ctx& c) { return c.opts.precision == CC_BF16X3_REFINE; }
+static double eig_switch(const Ctx& c) { return solver_bf16(c) ? kEigSwitchBf16 : kEigSwitch; }
 
 static Tensor tview(double* p, std::vector<int64_t> shape) {
   Tensor t;
@@ -631,6 +638,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   int m = 0;
   const bool lowp = mixed(c);
   c.eng->set_lowp(lowp);
+  c.eng->set_bf16(lowp && solver_bf16(c));
   // mixed precision: fp64 images of the wanted Ritz vectors, coefficients Z
   double* AXd = lowp ? ar.alloc((int64_t)nroots * N) : nullptr;
   double* zdev = lowp ? ar.alloc((int64_t)nroots * maxm) : nullptr;
@@ -824,7 +832,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       }
     }
     if (lowp && (worst < c.opts.tol_eom || stall >= 3 ||
-                 (!refreshed && (worst < kEigSwitch || it >= c.opts.maxit / 2)))) {
+                 (!refreshed && (worst < eig_switch(c) || it >= c.opts.maxit / 2)))) {
       const double wt = refresh(Y, nk);
       refreshed = true;
       best_lowp = 1e300;
@@ -896,6 +904,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     flush(m0, m0);
   }
   c.eng->set_lowp(false);
+  c.eng->set_bf16(false);
   if (verbose())
     std::fprintf(stderr,
                  "[davidson] %d iterations, %.3f s in operator applications; eig %.3f ritz %.3f residuals %.3f "
@@ -1159,6 +1168,7 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
   double* hd = work + n + maxm;
   int m = 0;
   c.eng->set_lowp(mixed_images);
+  c.eng->set_bf16(mixed_images && solver_bf16(c));
   precond(r, b);
   int status = CC_NOT_CONVERGED;
   int it = 0;
@@ -1205,7 +1215,8 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
       if (mixed_images) {
         if (rn < 0.7 * best) { best = rn; stall = 0; } else { ++stall; }
       }
-      if (!mixed_images || pass >= 2 || !(rn < goal || stall >= 3 || (!refreshed && rn < kEigSwitch * bn))) {
+      if (!mixed_images || pass >= 2 ||
+          !(rn < goal || stall >= 3 || (!refreshed && rn < eig_switch(c) * bn))) {
         if (rn < goal) status = CC_OK;
         break;
       }
@@ -1241,6 +1252,7 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
     precond(r, r);
   }
   c.eng->set_lowp(false);
+  c.eng->set_bf16(false);
   if (iters) *iters = it;
   return status;
 }
@@ -1763,7 +1775,8 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
     const int64_t nov = (int64_t)o * v;
     c->N = nov + nov * nov;
     if (opts) c->opts = *opts; else cc_default_opts(&c->opts);
-    if (c->opts.precision != CC_FP64 && c->opts.precision != CC_FP32_REFINE)
+    if (c->opts.precision != CC_FP64 && c->opts.precision != CC_FP32_REFINE &&
+        c->opts.precision != CC_BF16X3_REFINE)
       throw Error(CC_ERR_ARG, "unknown precision mode");
     c->s = (hipStream_t)stream;
     c->eng.reset(new nm::Engine(c->s));
@@ -1950,17 +1963,20 @@ int cc_apply_jacobian_block(cc_ctx* c, int side, int k, const double* X, double*
   ABI_GUARD(c);
   if (c->stage < 1) { c->err = "cc_apply_jacobian_block before cc_ground"; return CC_ERR_STATE; }
   if (!X || !Y || k < 1 || (side != CC_RIGHT && side != CC_LEFT) ||
-      (precision != CC_FP64 && precision != CC_FP32_REFINE))
+      (precision != CC_FP64 && precision != CC_FP32_REFINE && precision != CC_BF16X3_REFINE))
     return CC_ERR_ARG;
   try {
     nm::Tape tp(*c);
-    c->eng->set_lowp(precision == CC_FP32_REFINE);
+    c->eng->set_lowp(precision != CC_FP64);
+    c->eng->set_bf16(precision == CC_BF16X3_REFINE);
     if (side == CC_RIGHT) tp.right_block(X, Y, k); else tp.left_block(X, Y, k);
     c->eng->set_lowp(false);
+    c->eng->set_bf16(false);
     nm::sync(*c);
     return CC_OK;
   } catch (const Error& e) {
     c->eng->set_lowp(false);
+    c->eng->set_bf16(false);
     return fail(c, e);
   }
 }
@@ -2123,8 +2139,10 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
     hipStream_t st = (hipStream_t)stream;
     static thread_local std::unique_ptr<nm::Engine> eng;
     if (!eng || eng->stream() != st) eng.reset(new nm::Engine(st));
-    if (precision != CC_FP64 && precision != CC_FP32_REFINE) return CC_ERR_ARG;
-    eng->set_lowp(precision == CC_FP32_REFINE);
+    if (precision != CC_FP64 && precision != CC_FP32_REFINE && precision != CC_BF16X3_REFINE)
+      return CC_ERR_ARG;
+    eng->set_lowp(precision != CC_FP64);
+    eng->set_bf16(precision == CC_BF16X3_REFINE);
     eng->set_lowp_min_flops(0.0);   // the test surface applies the mode to any size
     std::vector<int64_t> sa(dA, dA + la.size()), sb(dB, dB + lb.size()), sc(dC, dC + lc.size());
     nm::ArenaScope scope(eng->arena());
@@ -2174,7 +2192,15 @@ int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, co
   else if (precision == CC_FP32_REFINE)
     rc = nm::gemm_f32acc(st, ta != 0, tb != 0, M, N, K, 1, alpha, (const float*)A, lda, 0,
                          (const float*)B, ldb, 0, beta, C, ldc, 0);
-  else
+  else if (precision == CC_BF16X3_REFINE) {
+    // bfloat16 pairs: A = [hi | lo] each [M][lda], B = [hi | lo] each [N][ldb] (B^T)
+    if (ta || !tb || K % 32 || lda < K || ldb < K) return CC_ERR_ARG;
+    const uint16_t* a = (const uint16_t*)A;
+    const uint16_t* b = (const uint16_t*)B;
+    rc = nm::gemm_bf16x3(st, M, N, K, 1, alpha, a, a + (int64_t)M * lda, lda, 0, b, b + (int64_t)N * ldb,
+                         ldb, 0, beta, C, ldc, 0, 0);
+    if (rc == -1) return CC_ERR_ARG;
+  } else
     return CC_ERR_ARG;
   return rc == 0 ? CC_OK : CC_ERR_HIP;
 }

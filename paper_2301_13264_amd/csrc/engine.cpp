@@ -180,6 +180,7 @@ struct TermTrace {
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
   for (auto& kv : f32_cache_) (void)hipFree(kv.second);
+  for (auto& kv : bf16_cache_) (void)hipFree(kv.second);
 }
 
 Engine::Engine(hipStream_t s) : s_(s) {
@@ -313,7 +314,7 @@ __global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, i
 // workgroups finishes in ceil(tiles / 512) rounds; splitting K into ns chunks
 // trades rounds against chunk length plus the fold of ns partial products
 // (16 bytes per element and chunk at about 4 TB/s).
-constexpr double kF64UsPerK = 0.23, kF32UsPerK = 0.13;
+constexpr double kF64UsPerK = 0.23, kF32UsPerK = 0.13, kBF16UsPerK = 0.06;
 static int64_t big_split(int64_t tiles, int64_t K, int64_t MN, double us_per_k) {
   int64_t best = 1;
   double tbest = 1e300;
@@ -473,10 +474,10 @@ static ViewSpec pack_spec(const DView& src, const std::string& order, int64_t& c
   return vs;
 }
 
-const float* Engine::packed_f32(const DView& src, const std::string& order) {
+const float* Engine::packed_f32(const DView& src, const std::string& order, bool cache) {
   int64_t cnt = 0;
   const ViewSpec vs = pack_spec(src, order, cnt);
-  if (src.constant) {
+  if (src.constant && cache) {
     std::string key = std::to_string((uintptr_t)src.p);
     for (int k = 0; k < vs.nd; ++k)
       key += ":" + std::to_string(vs.dims[k]) + "/" + std::to_string(vs.istr[k]);
@@ -499,9 +500,51 @@ const float* Engine::packed_f32(const DView& src, const std::string& order) {
   return buf;
 }
 
+void Engine::packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K,
+                         int64_t Kp, const uint16_t** hi, const uint16_t** lo) {
+  std::string key;
+  if (src.constant) {
+    int64_t cnt = 0;
+    const ViewSpec vs = pack_spec(src, order, cnt);
+    key = std::to_string((uintptr_t)src.p) + ":" + std::to_string(Kp);
+    for (int k = 0; k < vs.nd; ++k)
+      key += ":" + std::to_string(vs.dims[k]) + "/" + std::to_string(vs.istr[k]);
+    auto it = bf16_cache_.find(key);
+    if (it != bf16_cache_.end()) {
+      *hi = it->second;
+      *lo = it->second + rows * Kp;
+      return;
+    }
+  }
+  const size_t n = (size_t)(rows * Kp);
+  uint16_t* buf = nullptr;
+  bool cached = false;
+  if (src.constant && bf16_cache_bytes_ + 2 * n * sizeof(uint16_t) <= ((size_t)8 << 30)) {
+    if (hipMalloc((void**)&buf, 2 * n * sizeof(uint16_t)) == hipSuccess) {
+      cached = true;
+    } else {
+      (void)hipGetLastError();
+      buf = nullptr;
+    }
+  }
+  if (!buf) buf = (uint16_t*)arena_.alloc((int64_t)((2 * n * sizeof(uint16_t) + 7) / 8));
+  // fp32 staging (arena; released at once when buf is a cache entry, else
+  // with the caller's arena scope)
+  const Arena::Mark pm = arena_.mark();
+  const float* f = packed_f32(src, order, false);
+  kcheck(split_bf16(s_, f, rows, (int)K, (int)Kp, buf, buf + n), "split bf16");
+  if (cached) arena_.rewind(pm);
+  if (cached) {
+    bf16_cache_[key] = buf;
+    bf16_cache_bytes_ += 2 * n * sizeof(uint16_t);
+  }
+  *hi = buf;
+  *lo = buf + n;
+}
+
 void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const DView& C,
                       bool overwrite) {
-  TermTrace trace(s_, lowp_ ? "mul32" : "mul", A_in, &B_in, C);
+  TermTrace trace(s_, lowp_ ? (bf16_ ? "mul16x3" : "mul32") : "mul", A_in, &B_in, C);
   // A pair-symmetric operand whose contracted labels sit in its leading half
   // is relabelled so that they sit in the trailing half (B: leading), which
   // turns a transposed GEMM operand into a plain one.
@@ -606,8 +649,19 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
       2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K >= lowp_min_flops_) {
     if (M0 > INT32_MAX || N0 > INT32_MAX || K > INT32_MAX || nb0 > INT32_MAX)
       throw Error(-1, "GEMM dimension overflow");
-    const float* a32 = packed_f32(A, sb + sm + sk);
-    const float* b32 = packed_f32(B, sb + sk + sn);
+    // bf16 pairs: A as [batch][rows][Kp], B transposed as [batch][cols][Kp]
+    const bool use_bf16 = bf16_ && K >= 32;
+    const int64_t Kp = (K + 31) / 32 * 32;
+    const float* a32 = nullptr;
+    const float* b32 = nullptr;
+    const uint16_t *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr;
+    if (use_bf16) {
+      packed_bf16(A, sb + sm + sk, nb0 * M0, K, Kp, &ah, &al);
+      packed_bf16(B, sb + sn + sk, nb0 * N0, K, Kp, &bh, &bl);
+    } else {
+      a32 = packed_f32(A, sb + sm + sk);
+      b32 = packed_f32(B, sb + sk + sn);
+    }
     int64_t ldc, sC;
     const bool direct = as_matrix(C, sb, sm, sn, ldc, sC);
     double* pc;
@@ -638,9 +692,32 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
       ns = std::min<int64_t>(std::max<int64_t>(1, 512 / tiles), K / 512);
       ns = std::max<int64_t>(1, std::min<int64_t>(ns, 256));
     } else if (nb0 == 1) {
-      ns = big_split(tiles, K, M0 * N0, kF32UsPerK);
+      ns = big_split(tiles, K, M0 * N0, use_bf16 ? kBF16UsPerK : kF32UsPerK);
     }
     auto launch = [&](int64_t nsplit, double* out, int64_t ldo, int64_t so, double aa, double bb) {
+      if (use_bf16) {
+        if (nsplit > 1) {
+          const int64_t kc = ((Kp + nsplit - 1) / nsplit + 31) / 32 * 32;
+          const int64_t nsr = (Kp + kc - 1) / kc;
+          const int64_t klast = Kp - (nsr - 1) * kc;
+          Arena::Mark pm = arena_.mark();
+          double* part = arena_.alloc(nsr * M0 * N0);
+          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)kc, (int)nsr, 1.0, ah, al, Kp, kc, bh, bl, Kp, kc,
+                             0.0, part, N0, M0 * N0, (int)klast),
+                 "gemm bf16x3 (split K)");
+          const int64_t tot = M0 * N0;
+          const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+          hipLaunchKernelGGL(splitk_fold_kernel, dim3(g), dim3(256), 0, s_, out, ldo, part, (int)M0,
+                             (int)N0, (int)nsr, aa, bb);
+          kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
+          arena_.rewind(pm);
+        } else {
+          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)Kp, (int)nb0, aa, ah, al, Kp, M0 * Kp, bh, bl, Kp,
+                             N0 * Kp, bb, out, ldo, so, 0),
+                 "gemm bf16x3");
+        }
+        return;
+      }
       if (nsplit > 1) {
         const int64_t kc = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
         const int64_t nsr = (K + kc - 1) / kc;
@@ -664,7 +741,7 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
     };
     if (nb0 == 1 && autotune_on() && 2.0 * (double)M0 * (double)N0 * (double)K >= kTuneMinFlops) {
       double* scratch = arena_.alloc(M0 * N0);
-      ns = tune_split(s_, tune_key('s', false, false, M0, N0, K), ns, 256,
+      ns = tune_split(s_, tune_key(use_bf16 ? 'h' : 's', false, false, M0, N0, K), ns, 256,
                       [&](int64_t c) { launch(c, scratch, N0, M0 * N0, 1.0, 0.0); });
     }
     launch(ns, pc, ldc, sC, a_, b_);

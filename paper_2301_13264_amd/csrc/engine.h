@@ -129,6 +129,11 @@ class Engine {
   void set_lowp_min_flops(double f) { lowp_min_flops_ = f; }
   bool lowp() const { return lowp_; }
   uint64_t lowp_flops() const { return lowp_flops_; }
+  // With set_bf16(true) as well, those contractions carry each fp32 operand
+  // as a bfloat16 pair (hi + lo) and run three bf16 matrix-core products
+  // (fp32 accumulation): about 2^-16 relative instead of fp32's 2^-24.
+  void set_bf16(bool on) { bf16_ = on; }
+  bool bf16() const { return bf16_; }
 
  private:
   hipStream_t s_;
@@ -142,7 +147,14 @@ class Engine {
   // fp32 packings of constant operands, keyed by source view and order
   std::map<std::string, float*> f32_cache_;
   size_t f32_cache_bytes_ = 0;
-  const float* packed_f32(const DView& src, const std::string& order);
+  const float* packed_f32(const DView& src, const std::string& order, bool cache = true);
+  // bfloat16 pair of src in `order` as [rows][Kp] (last K elements of each
+  // row from the trailing labels, zero-padded to Kp); constants cached
+  bool bf16_ = false;
+  std::map<std::string, uint16_t*> bf16_cache_;
+  size_t bf16_cache_bytes_ = 0;
+  void packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K, int64_t Kp,
+                   const uint16_t** hi, const uint16_t** lo);
 };
 
 class Graph {

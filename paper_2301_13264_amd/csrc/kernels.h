@@ -29,6 +29,15 @@ int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, do
 int view_gather(hipStream_t s, double* out, const double* in, const ViewSpec& v, double alpha,
                 double beta);
 int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec& v);
+// BF16 split-precision GEMM: C = alpha A B + beta C with A [M][K] and B^T [N][K]
+// given as bfloat16 pairs (hi, lo) in uint16 storage; K and Klast multiples
+// of 32, lda / ldb / batch strides multiples of 8, 16-byte aligned pointers.
+int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
+                const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
+                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast);
+// fp32 [rows][K] -> bfloat16 pairs [rows][Kp], zero-padded to Kp >= K
+int split_bf16(hipStream_t s, const float* src, int64_t rows, int K, int Kp, uint16_t* hi,
+               uint16_t* lo);
 int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
                 const float* A, int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB,
                 double beta, double* C, int64_t ldc, int64_t sC, int Klast = 0);

@@ -420,6 +420,163 @@ int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch,
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// ------------------------------------------------- BF16 split-precision GEMM
+// C[m][n] = alpha * sum_k A[m][k] B[k][n] + beta * C with each fp32 operand
+// carried as a bfloat16 pair x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+// so that x is held to about 2^-16 relative; every product is formed as
+// al*bh + ah*bl + ah*bh (the lo*lo term, ~2^-16 of the product, is dropped) on
+// the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with fp32 accumulation and
+// an fp64 epilogue.  Operands are K-contiguous: A [M][Kp] and B^T [N][Kp]
+// (uint16 storage of bf16, leading dimensions lda / ldb multiples of 8), K
+// zero-padded to a multiple of 32, so that every global load and LDS access is
+// a 16-byte vector and needs no K bound.  MFMA lane layout (checked on the
+// device): lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
+// for j < 8 and receives D rows 4 (l / 16) + v, column l % 16.
+// Tiles 128 x 128 x 32, 512 threads = 8 waves of 32 x 64 outputs, double-
+// buffered LDS rows of 40 bf16 (80 bytes: the 16 lanes of a quarter-wave read
+// 16 disjoint 4-bank groups), XCD-grouped tile order as the other kernels.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int HBK = 32, HKS = 40;
+
+__global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
+    int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
+    const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
+    const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int Klast) {
+  __shared__ __attribute__((aligned(16))) uint16_t S[2][4][128 * HKS];
+  const int64_t bz = blockIdx.z;
+  Ah += bz * sA;
+  Al += bz * sA;
+  Bh += bz * sB;
+  Bl += bz * sB;
+  C += bz * sC;
+  if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
+  const int gx = gridDim.x, gy = gridDim.y;
+  int bid = blockIdx.x + gx * blockIdx.y;
+  bid = xcd_tile(bid, gx * gy);
+  const int tm = bid % gy, tn = bid / gy;
+  const int m0 = tm * 128, n0 = tn * 128;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  // global loads: row tid / 4 of the tile, 8 consecutive k at 8 (tid % 4)
+  const int grow = tid >> 2, gch = (tid & 3) * 8;
+  const bool aok = m0 + grow < M, bok = n0 + grow < N;
+  const int64_t aoff = (int64_t)(aok ? m0 + grow : 0) * lda + gch;
+  const int64_t boff = (int64_t)(bok ? n0 + grow : 0) * ldb + gch;
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  uint4 r0, r1, r2, r3;
+  auto gload = [&](int t) {
+    const int64_t k0 = (int64_t)t * HBK;
+    r0 = aok ? *(const uint4*)(Ah + aoff + k0) : zero;
+    r1 = aok ? *(const uint4*)(Al + aoff + k0) : zero;
+    r2 = bok ? *(const uint4*)(Bh + boff + k0) : zero;
+    r3 = bok ? *(const uint4*)(Bl + boff + k0) : zero;
+  };
+  auto sstore = [&](int buf) {
+    const int o = grow * HKS + gch;
+    *(uint4*)&S[buf][0][o] = r0;
+    *(uint4*)&S[buf][1][o] = r1;
+    *(uint4*)&S[buf][2][o] = r2;
+    *(uint4*)&S[buf][3][o] = r3;
+  };
+  v4f acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int nk = K / HBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) gload(t + 1);
+    bf16x8 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int o = (wm * 32 + i * 16 + lr) * HKS + lk * 8;
+      ah[i] = *(const bf16x8*)&S[cur][0][o];
+      al[i] = *(const bf16x8*)&S[cur][1][o];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = (wn * 64 + j * 16 + lr) * HKS + lk * 8;
+      bh[j] = *(const bf16x8*)&S[cur][2][o];
+      bl[j] = *(const bf16x8*)&S[cur][3][o];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    if (t + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * 32 + i * 16 + 4 * lk + v;
+        const int gn = n0 + wn * 64 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          double* c = C + (int64_t)gm * ldc + gn;
+          const double r = alpha * (double)acc[i][j][v];
+          *c = (beta == 0.0) ? r : r + beta * (*c);
+        }
+      }
+}
+
+int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
+                const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
+                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast) {
+  if (M <= 0 || N <= 0 || batch <= 0) return 0;
+  if (K <= 0 || K % HBK || (Klast > 0 && Klast % HBK) || lda % 8 || ldb % 8 || sA % 8 || sB % 8 ||
+      ((uintptr_t)Ah | (uintptr_t)Al | (uintptr_t)Bh | (uintptr_t)Bl) % 16)
+    return -1;
+  if (batch > 32768) {
+    for (int b0 = 0; b0 < batch; b0 += 32768) {
+      const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
+      int rc = gemm_bf16x3(s, M, N, K, nb, alpha, Ah + (int64_t)b0 * sA, Al + (int64_t)b0 * sA, lda, sA,
+                           Bh + (int64_t)b0 * sB, Bl + (int64_t)b0 * sB, ldb, sB, beta,
+                           C + (int64_t)b0 * sC, ldc, sC, b0 + nb == batch ? Klast : 0);
+      if (rc) return rc;
+    }
+    return 0;
+  }
+  dim3 grid((N + 127) / 128, (M + 127) / 128, batch);
+  hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
+                     Bl, ldb, sB, beta, C, ldc, sC, Klast);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// fp32 [rows][K] -> bfloat16 pair [rows][Kp] (Kp >= K, zero padding):
+// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even.
+__device__ inline uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void split_bf16_kernel(const float* __restrict__ src, int64_t rows, int K, int Kp,
+                                  uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  const int64_t total = rows * Kp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / Kp;
+    const int k = (int)(e - r * Kp);
+    const float x = k < K ? src[r * K + k] : 0.f;
+    const uint16_t h = bf16_rne(x);
+    const float hf = __uint_as_float((uint32_t)h << 16);
+    hi[e] = h;
+    lo[e] = bf16_rne(x - hf);
+  }
+}
+
 // ------------------------------------------------------ tiled strided copy
 // A strided copy without summed labels runs as 64 x 64 tiles of two of its
 // dimensions: X, the input's fastest, and Y, the output's fastest; every
@@ -1111,4 +1268,15 @@ int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h,
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+}  // namespace nm
+
+namespace nm {
+int split_bf16(hipStream_t s, const float* src, int64_t rows, int K, int Kp, uint16_t* hi,
+               uint16_t* lo) {
+  if (rows <= 0) return 0;
+  if (K <= 0 || Kp < K) return -1;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3(grid_for(rows * Kp)), dim3(256), 0, s, src, rows, K, Kp,
+                     hi, lo);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 }  // namespace nm

@@ -244,22 +244,66 @@ def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
     ("ak,kx->ax", [(70, 4100), (4100, 3)], (70, 3)),                         # split K
     ("kicd,adkc->ia", [(5, 33, 20, 31), (127, 31, 5, 20)], (33, 127)),       # split K, packed
     ("zik,zkj->zij", [(3, 130, 41), (3, 41, 140)], (3, 130, 140)),           # batched
+    ("ik,kj->ij", [(257, 1000), (1000, 300)], (257, 300)),                   # several K tiles
 ])
-def test_contract_fp32_operands(nm, spec, shapes, oshape):
-    """Mixed-precision contraction (fp32 operands and accumulation): error at
-    the level of fp32 rounding of the products."""
-    say(f"[contract fp32] {spec}")
+@pytest.mark.parametrize("prec", [1, 2])
+def test_contract_low_precision_operands(nm, spec, shapes, oshape, prec):
+    """Mixed-precision contraction, fp32 operands (prec 1) or bfloat16 pairs
+    with three bf16 products (prec 2), fp32 accumulation: error at the level of
+    the operand rounding (2^-24 resp. about 3 * 2^-16 of each product), and
+    non-zero (the low-precision kernel really ran)."""
+    say(f"[contract prec={prec}] {spec}")
     rng = np.random.default_rng(3)
     A = T(rng.normal(size=shapes[0]))
     B = T(rng.normal(size=shapes[1]))
     C = torch.zeros(oshape, dtype=torch.float64, device="cuda")
-    nm.contract(spec, 1.0, A, B, 0.0, C, precision=1)
+    nm.contract(spec, 1.0, A, B, 0.0, C, precision=prec)
     torch.cuda.synchronize()
     ref = torch.einsum(spec, A.cpu(), B.cpu())
     k = np.prod(shapes[0]) * np.prod(shapes[1]) / np.prod(oshape) if oshape else 1
     err = (C.cpu() - ref).abs().max().item()
-    assert err < 1e-5 * np.sqrt(k) * ref.abs().max().item()
-    assert err > 0.0   # the fp32 path really ran
+    rel = 1e-5 * np.sqrt(k) if prec == 1 else 2e-4
+    assert err < rel * ref.abs().max().item()
+    assert err > 0.0
+    if prec == 2:
+        # far better than a single bf16 product (2^-8 per operand)
+        A16 = A.cpu().to(torch.bfloat16).double()
+        B16 = B.cpu().to(torch.bfloat16).double()
+        err1 = (torch.einsum(spec, A16, B16) - ref).abs().max().item()
+        assert err < 0.05 * err1
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320)])
+def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K):
+    """nm_gemm with bfloat16 pairs (the split-precision kernel alone): the
+    result equals the fp64 product of the pairs' values up to the dropped
+    lo x lo term and fp32 accumulation, and is far closer to the fp32
+    product than one bf16 product is."""
+    say(f"[nm_gemm bf16x3] {M}x{N}x{K}")
+    rng = np.random.default_rng(M + N + K)
+    A = torch.as_tensor(rng.normal(size=(M, K)), dtype=torch.float32, device="cuda")
+    Bt = torch.as_tensor(rng.normal(size=(N, K)), dtype=torch.float32, device="cuda")
+    def pair(x):
+        hi = x.to(torch.bfloat16)
+        lo = (x - hi.float()).to(torch.bfloat16)
+        return torch.stack([hi, lo]).contiguous(), hi, lo
+    Ap, ah, al = pair(A)
+    Bp, bh, bl = pair(Bt)
+    C0 = torch.as_tensor(rng.normal(size=(M, N)), device="cuda")
+    C = C0.clone()
+    nm.gemm(2, Ap, Bp, C, alpha=0.5, beta=-2.0)
+    torch.cuda.synchronize()
+    a64 = ah.double().cpu(), al.double().cpu()
+    b64 = bh.double().cpu(), bl.double().cpu()
+    three = a64[0] @ b64[0].T + a64[0] @ b64[1].T + a64[1] @ b64[0].T
+    ref = 0.5 * three - 2.0 * C0.cpu()
+    err = (C.cpu() - ref).abs().max().item()
+    assert err < 1e-6 * np.sqrt(K) * max(1.0, ref.abs().max().item())
+    exact = 0.5 * (A.double().cpu() @ Bt.double().cpu().T) - 2.0 * C0.cpu()
+    one = 0.5 * (a64[0] @ b64[0].T) - 2.0 * C0.cpu()
+    e3 = (C.cpu() - exact).abs().max().item()
+    e1 = (one - exact).abs().max().item()
+    assert e3 < 0.05 * e1
 
 
 @pytest.mark.gpu
@@ -284,18 +328,19 @@ def test_gemm_kernel_surface(nm, prec, M, N, K):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("o,v,naux,seed", [(2, 4, 18, None), (4, 12, 48, 2301)])
-def test_mixed_precision_pipeline_matches_oracle(nm, o, v, naux, seed):
-    """CC_FP32_REFINE with every unbatched contraction forced onto fp32
-    operands: the refined energies, states and couplings meet the fp64
-    tolerances against the oracle."""
-    say(f"[mixed pipeline] o={o} v={v}")
+def test_mixed_precision_pipeline_matches_oracle(nm, o, v, naux, seed, prec):
+    """CC_FP32_REFINE / CC_BF16X3_REFINE with every unbatched contraction
+    forced onto low-precision operands: the refined energies, states and
+    couplings meet the fp64 tolerances against the oracle."""
+    say(f"[mixed pipeline] prec={prec} o={o} v={v}")
     seed = synth.exact_check_seed(o, v) if seed is None else seed
     nroots = 2
     st = oracle_state(o, v, naux, seed, nroots)
     sysd = st["sys"]
     dirs = synth.make_directions(o + v, naux, seed + 17, 2)
-    opts = nm.default_opts(precision=1, mixed_min_flops=0.0)
+    opts = nm.default_opts(precision=prec, mixed_min_flops=0.0)
     ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]), opts)
     e, _, rc = ctx.ground()
     assert rc == 0
@@ -347,11 +392,12 @@ def test_block_transforms_match_single(nm, o, v):
             assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
             orc = fn(st["x"], torch.as_tensor(xs[z]), st["h"], st["g"], o, v).numpy()
             assert np.abs(to_packed(got, o, v) - orc).max() < 1e-9
-        Y32 = torch.zeros_like(X)
-        ctx.apply_jacobian_block(side, X, Y32, precision=1)
-        torch.cuda.synchronize()
         scale = Y.abs().max().item()
-        d32 = (Y32 - Y).abs().max().item()
-        assert d32 < 1e-5 * max(1.0, scale)
-        assert d32 > 0.0   # the fp32 contractions really ran
+        for prec, tol in [(1, 1e-5), (2, 1e-3)]:
+            Ylp = torch.zeros_like(X)
+            ctx.apply_jacobian_block(side, X, Ylp, precision=prec)
+            torch.cuda.synchronize()
+            d = (Ylp - Y).abs().max().item()
+            assert d < tol * max(1.0, scale)
+            assert d > 0.0   # the low-precision contractions really ran
     ctx.close()
