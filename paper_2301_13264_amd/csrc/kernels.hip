@@ -1067,8 +1067,27 @@ int reduce_scratch_doubles() { return kReduceBlocks; }
 // out[k] = sum_e V[k][e] x[e] for the m <= kMaxRows rows of V (row-major,
 // row stride n).  Every block covers a contiguous chunk of e, reads x once and
 // keeps m partial sums per thread; partials [block][k] are folded in a fixed
-// order by a second kernel (deterministic).
-constexpr int kRowBlocks = 512;
+// order by a second kernel (deterministic).  1024 blocks of 4 waves: 16 waves
+// per CU in flight, enough loads to cover HBM latency.
+constexpr int kRowBlocks = 1024;
+
+// out[r * m + k] = sum_b part[b * bstride + r * kMaxRows + k]: one workgroup
+// per output, fixed-order strided sums and a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void rows_fold_par_kernel(const double* __restrict__ part, int nb,
+                                                            int m, int64_t bstride,
+                                                            double* __restrict__ out) {
+  __shared__ double red[256];
+  const int o = blockIdx.x, r = o / m, k = o % m;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[(int64_t)b * bstride + r * kMaxRows + k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[o] = red[0];
+}
 
 constexpr int kRowGroup = 8;   // rows accumulated in registers at a time
 
@@ -1106,20 +1125,13 @@ __global__ __launch_bounds__(256) void rows_dot_partial_kernel(const double* __r
   }
 }
 
-__global__ void rows_fold_kernel(const double* part, int nb, int m, double* out) {
-  const int k = threadIdx.x;
-  if (k >= m) return;
-  double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * kMaxRows + k];
-  out[k] = acc;
-}
-
 int rows_dot(hipStream_t s, const double* V, int m, int64_t n, const double* x, double* part,
              double* out) {
   if (m <= 0) return 0;
   if (m > kMaxRows) return -1;
   hipLaunchKernelGGL(rows_dot_partial_kernel, dim3(kRowBlocks), dim3(256), 0, s, V, m, n, x, part);
-  hipLaunchKernelGGL(rows_fold_kernel, dim3(1), dim3(kMaxRows), 0, s, part, kRowBlocks, m, out);
+  hipLaunchKernelGGL(rows_fold_par_kernel, dim3(m), dim3(256), 0, s, part, kRowBlocks, m,
+                     (int64_t)kMaxRows, out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -1174,15 +1186,6 @@ __global__ __launch_bounds__(256) void rows_dot_multi_partial_kernel(
   }
 }
 
-// out[r][k] = sum_b part[b][r][k]
-__global__ void rows_fold_multi_kernel(const double* part, int nb, int m, int R, double* out) {
-  const int t = threadIdx.x, r = t / kMaxRows, k = t % kMaxRows;
-  if (r >= R || k >= m) return;
-  double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += part[((int64_t)b * kMaxRhs + r) * kMaxRows + k];
-  out[r * m + k] = acc;
-}
-
 int rows_dot_multi(hipStream_t s, const double* V, int m, int64_t n, const double* X, int64_t ldx,
                    int R, double* part, double* out) {
   if (m <= 0 || R <= 0) return 0;
@@ -1196,8 +1199,8 @@ int rows_dot_multi(hipStream_t s, const double* V, int m, int64_t n, const doubl
     default: NM_RD(4); break;
   }
 #undef NM_RD
-  hipLaunchKernelGGL(rows_fold_multi_kernel, dim3(1), dim3(kMaxRows * kMaxRhs), 0, s, part,
-                     kRowBlocks, m, R, out);
+  hipLaunchKernelGGL(rows_fold_par_kernel, dim3(R * m), dim3(256), 0, s, part, kRowBlocks, m,
+                     (int64_t)kMaxRhs * kMaxRows, out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
