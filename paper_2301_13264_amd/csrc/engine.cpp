@@ -533,8 +533,8 @@ void Engine::packed_bf16(const DView& src, const std::string& order, int64_t row
   const Arena::Mark pm = arena_.mark();
   const float* f = packed_f32(src, order, false);
   kcheck(split_bf16(s_, f, rows, (int)K, (int)Kp, buf, buf + n), "split bf16");
-  if (cached) arena_.rewind(pm);
   if (cached) {
+    arena_.rewind(pm);
     bf16_cache_[key] = buf;
     bf16_cache_bytes_ += 2 * n * sizeof(uint16_t);
   }

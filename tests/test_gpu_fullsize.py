@@ -72,6 +72,20 @@ def test_transforms_and_eom_full_size(nm, system):
     ctx.apply_jacobian(nm.CC_LEFT, T(to_full(r, O, V)), y)
     ref = rs.left_transform(x, torch.as_tensor(r), h, g, O, V).numpy()
     assert _rel(to_packed(y.cpu().numpy(), O, V), ref) < 1e-10
+    say("[full size] low-precision transforms")
+    # the solvers' fp32 and bfloat16-pair operators at this size (split-K,
+    # cached constant packs, padded K) against the fp64 ones: operand rounding
+    # only, and not identical (the low-precision kernels ran)
+    X = torch.stack([T(to_full(r, O, V)), T(to_full(rng.normal(scale=1e-2, size=x.numel()), O, V))])
+    for side in (nm.CC_RIGHT, nm.CC_LEFT):
+        Y64 = torch.zeros_like(X)
+        ctx.apply_jacobian_block(side, X, Y64, precision=0)
+        scale = Y64.abs().max().item()
+        for prec, tol in [(1, 1e-5), (2, 1e-3)]:
+            Ylp = torch.zeros_like(X)
+            ctx.apply_jacobian_block(side, X, Ylp, precision=prec)
+            d = (Ylp - Y64).abs().max().item()
+            assert 0.0 < d < tol * scale, (side, prec, d, scale)
     say("[full size] EOM properties")
     w, _, rc = ctx.eom(nm.CC_BOTH, 2)
     assert rc == 0
