@@ -155,6 +155,78 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
     return roof
 
 
+def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, steps=3000,
+                  batch=8192, lr=2e-3, tol=1e-8):
+    """The learned-guess workload: perturbed geometries of the thymine-shaped
+    system (orbital rotation exp(K), K_pq ~ N(0, 0.01^2), seeds 900 + k), a
+    network trained on the converged doubles of n_train of them by the
+    library's own kernels, and the amplitude solver on the n_eval others
+    started from MP2 (the default) and from the network, at tolerance tol.
+    Every answer is judged by the same residual tolerance."""
+    T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
+    base = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=SIGMA_B)
+    eps = T(base["eps"])
+    opts = nm.default_opts(precision=prec, tol_ground=tol)
+    n4 = (cfg["o"] * cfg["v"]) ** 2
+    F = torch.empty((n_train * n4, 8), dtype=torch.float32, device=dev)
+    Z = torch.empty((n_train * n4,), dtype=torch.float32, device=dev)
+    c0 = time.perf_counter()
+    for k in range(n_train):
+        ctx = nm.Context(cfg["o"], cfg["v"], cfg["naux"], eps, T(synth.perturbed_factor(base["B"], 900 + k)),
+                         opts)
+        _, _, rc = ctx.ground()
+        if rc != 0:
+            raise RuntimeError(f"training geometry {k}: ground state not converged")
+        ctx.t2_features(F[k * n4:(k + 1) * n4])
+        ctx.t2_target(Z[k * n4:(k + 1) * n4])
+        ctx.close()
+        log(f"[learned] training geometry {k + 1}/{n_train}")
+    torch.cuda.synchronize()
+    c1 = time.perf_counter()
+    mu = F.mean(dim=0)
+    sd = F.std(dim=0) + 1e-12
+    F.sub_(mu).div_(sd)
+    zs = float(Z.std())
+    Z.div_(zs)
+    net = nm.MLP(8, 256, 1, seed=4)
+    loss = net.train(F, Z[:, None], batch=batch, steps=steps, lr=lr, seed=5)
+    torch.cuda.synchronize()
+    c2 = time.perf_counter()
+    log(f"[learned] trained: loss {loss:.3e} in {c2 - c1:.1f} s")
+    del F, Z
+    mu_h, sd_h = mu.cpu().numpy(), sd.cpu().numpy()
+    rows = []
+    for k in range(n_eval):
+        Bk = T(synth.perturbed_factor(base["B"], 900 + n_train + k))
+        res = {}
+        for mode in ("mp2", "learned"):
+            ctx = nm.Context(cfg["o"], cfg["v"], cfg["naux"], eps, Bk, opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "learned":
+                ctx.guess_t2(net, mu_h, sd_h, zs)
+            e, it, rc = ctx.ground()
+            torch.cuda.synchronize()
+            res[mode] = (e, it, rc, time.perf_counter() - t0)
+            ctx.close()
+        rows.append(res)
+        log(f"[learned] held-out geometry {k + 1}/{n_eval}: iterations MP2 {res['mp2'][1]}, "
+            f"learned {res['learned'][1]}")
+    net.close()
+    it0 = [r["mp2"][1] for r in rows]
+    it1 = [r["learned"][1] for r in rows]
+    print(json.dumps(dict(
+        mode="learned-guess", workload="thymine_dz perturbed geometries (orbital rotations N(0, 0.01^2))",
+        n_train=n_train, n_eval=n_eval, tolerance=tol, training_s=c2 - c1, data_s=c1 - c0,
+        training_loss=loss, target_variance=1.0,
+        iterations_mp2=it0, iterations_learned=it1,
+        mean_iterations_mp2=float(np.mean(it0)), mean_iterations_learned=float(np.mean(it1)),
+        mean_time_mp2_s=float(np.mean([r["mp2"][3] for r in rows])),
+        mean_time_learned_s=float(np.mean([r["learned"][3] for r in rows])),
+        all_converged=all(r["mp2"][2] == 0 and r["learned"][2] == 0 for r in rows),
+        max_abs_d_energy=float(max(abs(r["mp2"][0] - r["learned"][0]) for r in rows)))), flush=True)
+
+
 def roofline_only(nm, torch, cfg, dev):
     """The ladder launches alone, plus a 1 GiB device copy that calibrates the
     HBM byte counters (for rocprofv3 --pmc runs)."""
@@ -181,6 +253,9 @@ def main():
                     help="skip the step in the other precision")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the ladder GEMM launches and a copy calibration (profiling)")
+    ap.add_argument("--learned-guess", action="store_true",
+                    help="only the learned-guess workload: 48 training and 16 held-out "
+                         "perturbed geometries, ground-state iterations from MP2 vs the network")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -197,6 +272,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.roofline_only:
         roofline_only(nm, torch, cfg, dev)
+        return
+    if args.learned_guess:
+        learned_guess(nm, torch, np, synth, cfg, dev, getattr(nm, PRECISIONS[args.precision][0]))
         return
     sysd = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=SIGMA_B)
     dirs = synth.make_directions(cfg["o"] + cfg["v"], cfg["naux"], cfg["seed"], cfg["ndir"],
