@@ -528,13 +528,16 @@ void Engine::packed_bf16(const DView& src, const std::string& order, int64_t row
     }
   }
   if (!buf) buf = (uint16_t*)arena_.alloc((int64_t)((2 * n * sizeof(uint16_t) + 7) / 8));
-  // fp32 staging (arena; released at once when buf is a cache entry, else
-  // with the caller's arena scope)
-  const Arena::Mark pm = arena_.mark();
-  const float* f = packed_f32(src, order, false);
-  kcheck(split_bf16(s_, f, rows, (int)K, (int)Kp, buf, buf + n), "split bf16");
+  // one pass from the fp64 view: output strides of the trailing K labels as
+  // packed, those of the leading (row) labels scaled from K to Kp
+  int64_t cnt = 0;
+  ViewSpec vs = pack_spec(src, order, cnt);
+  int nk = 0;
+  for (int64_t p = 1; nk < vs.nd && p < K; ++nk) p *= vs.dims[vs.nd - 1 - nk];
+  if (nk == 0 && K == 1) nk = 1;
+  for (int d = 0; d < vs.nd - nk; ++d) vs.ostr[d] = vs.ostr[d] / K * Kp;
+  kcheck(view_gather_bf16x2(s_, buf, (int64_t)n, src.p, vs, rows, (int)K, (int)Kp), "pack bf16 pairs");
   if (cached) {
-    arena_.rewind(pm);
     bf16_cache_[key] = buf;
     bf16_cache_bytes_ += 2 * n * sizeof(uint16_t);
   }

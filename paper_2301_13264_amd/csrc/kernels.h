@@ -35,9 +35,10 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
 int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
                 const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
                 int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast);
-// fp32 [rows][K] -> bfloat16 pairs [rows][Kp], zero-padded to Kp >= K
-int split_bf16(hipStream_t s, const float* src, int64_t rows, int K, int Kp, uint16_t* hi,
-               uint16_t* lo);
+// bfloat16 pair (hi at out, lo at out + lo_off) of a strided double view
+// whose output strides address a [rows][Kp] layout; padding [K, Kp) zeroed
+int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const double* in,
+                       const ViewSpec& v, int64_t rows, int K, int Kp);
 int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
                 const float* A, int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB,
                 double beta, double* C, int64_t ldc, int64_t sC, int Klast = 0);

@@ -555,26 +555,11 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-// fp32 [rows][K] -> bfloat16 pair [rows][Kp] (Kp >= K, zero padding):
-// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even.
+// fp32 -> bfloat16, rounded to nearest even (pairs: hi = bf16(x),
+// lo = bf16(x - hi))
 __device__ inline uint16_t bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
-__global__ void split_bf16_kernel(const float* __restrict__ src, int64_t rows, int K, int Kp,
-                                  uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
-  const int64_t total = rows * Kp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / Kp;
-    const int k = (int)(e - r * Kp);
-    const float x = k < K ? src[r * K + k] : 0.f;
-    const uint16_t h = bf16_rne(x);
-    const float hf = __uint_as_float((uint32_t)h << 16);
-    hi[e] = h;
-    lo[e] = bf16_rne(x - hf);
-  }
 }
 
 // ------------------------------------------------------ tiled strided copy
@@ -592,10 +577,13 @@ struct TileSpec {
   int64_t bdims[kMaxViewDims] = {0}, bistr[kMaxViewDims] = {0}, bostr[kMaxViewDims] = {0};
 };
 
-template <typename TO, bool TRANS>
+// PAIR: out is the hi array of a bfloat16 pair (uint16), lo at out + lo_off;
+// x = (float)(alpha in), hi = bf16(x), lo = bf16(x - hi)
+template <typename TO, bool TRANS, bool PAIR = false>
 __global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
                                                         const double* __restrict__ in,
-                                                        TileSpec t, double alpha, double beta) {
+                                                        TileSpec t, double alpha, double beta,
+                                                        int64_t lo_off = 0) {
   __shared__ double tile[TRANS ? 64 * 65 : 1];
   int64_t b = blockIdx.x;
   const int64_t txi = b % t.tx;
@@ -625,7 +613,14 @@ __global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
       if (x < t.nx && y < t.ny) {
         const double val = alpha * tile[lane * 65 + r];
         TO* o = out + ob + x * t.osx + y * t.osy;
-        *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+        if constexpr (PAIR) {
+          const float xf = (float)val;
+          const uint16_t h = bf16_rne(xf);
+          o[0] = h;
+          o[lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+        } else {
+          *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+        }
       }
     }
   } else {
@@ -635,7 +630,14 @@ __global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
       if (x < t.nx && y < t.ny) {
         const double val = alpha * in[ib + x * t.isx + y * t.isy];
         TO* o = out + ob + x * t.osx + y * t.osy;
-        *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+        if constexpr (PAIR) {
+          const float xf = (float)val;
+          const uint16_t h = bf16_rne(xf);
+          o[0] = h;
+          o[lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+        } else {
+          *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
+        }
       }
     }
   }
@@ -740,6 +742,74 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(view_gather_f32_kernel, dim3((int)g), dim3(256), 0, s, out, in, v, total);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// bfloat16 pair of in (double) through a strided view: hi at out, lo at
+// out + lo_off (generic path when the view does not tile)
+__global__ void view_gather_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off,
+                                          const double* __restrict__ in, ViewSpec v, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, oo = v.obase, io = v.ibase;
+    for (int d = v.nd - 1; d >= 0; --d) {
+      const int64_t q = rem / v.dims[d];
+      const int64_t i = rem - q * v.dims[d];
+      rem = q;
+      oo += i * v.ostr[d];
+      io += i * v.istr[d];
+    }
+    const float xf = (float)in[io];
+    const uint16_t h = bf16_rne(xf);
+    out[oo] = h;
+    out[oo + lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+  }
+}
+
+// zero the padding columns [K, Kp) of a [rows][Kp] pair
+__global__ void pad_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off, int64_t rows, int K,
+                                  int Kp) {
+  const int w = Kp - K;
+  const int64_t total = rows * w;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / w;
+    const int64_t o = r * Kp + K + (e - r * w);
+    out[o] = 0;
+    out[o + lo_off] = 0;
+  }
+}
+
+int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const double* in,
+                       const ViewSpec& v, int64_t rows, int K, int Kp) {
+  int64_t total = 1;
+  for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
+  if (total > 0) {
+    TileSpec t;
+    bool trans = false;
+    if (plan_tiles(v, t, trans)) {
+      int64_t blocks = t.tx * t.ty;
+      for (int d = 0; d < t.nb; ++d) blocks *= t.bdims[d];
+      if (trans)
+        hipLaunchKernelGGL((tile_copy_kernel<uint16_t, true, true>), dim3((unsigned)blocks), dim3(256), 0,
+                           s, out + v.obase, in + v.ibase, t, 1.0, 0.0, lo_off);
+      else
+        hipLaunchKernelGGL((tile_copy_kernel<uint16_t, false, true>), dim3((unsigned)blocks), dim3(256),
+                           0, s, out + v.obase, in + v.ibase, t, 1.0, 0.0, lo_off);
+    } else {
+      int64_t g = (total + 255) / 256;
+      if (g > 65536) g = 65536;
+      hipLaunchKernelGGL(view_gather_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, lo_off, in, v,
+                         total);
+    }
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  if (Kp > K && rows > 0) {
+    int64_t g = (rows * (Kp - K) + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(pad_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, lo_off, rows, K, Kp);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  return 0;
 }
 
 int gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
@@ -1273,13 +1343,4 @@ int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h,
 
 }  // namespace nm
 
-namespace nm {
-int split_bf16(hipStream_t s, const float* src, int64_t rows, int K, int Kp, uint16_t* hi,
-               uint16_t* lo) {
-  if (rows <= 0) return 0;
-  if (K <= 0 || Kp < K) return -1;
-  hipLaunchKernelGGL(split_bf16_kernel, dim3(grid_for(rows * Kp)), dim3(256), 0, s, src, rows, K, Kp,
-                     hi, lo);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-}  // namespace nm
+
