@@ -10,6 +10,8 @@
 // * elementwise   : orbital-energy denominators (Jacobi / Davidson
 //                   preconditioners), packed-metric weights.
 #include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 
 #include "kernels.h"
@@ -732,10 +734,29 @@ __global__ void view_gather_f32_kernel(float* __restrict__ out, const double* __
   }
 }
 
+__global__ void flat_f32_kernel(float* __restrict__ out, const double* __restrict__ in, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (float)in[e];
+}
+
 int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec& v) {
   int64_t total = 1;
   for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
   if (total == 0) return 0;
+  // a contiguous view in its own order: an elementwise conversion
+  bool flat = true;
+  int64_t st = 1;
+  for (int d = v.nd - 1; d >= 0; --d) {
+    if (v.dims[d] != 1 && (v.istr[d] != st || v.ostr[d] != st)) flat = false;
+    st *= v.dims[d];
+  }
+  if (flat) {
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(flat_f32_kernel, dim3((int)g), dim3(256), 0, s, out + v.obase, in + v.ibase, total);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
   const int rc = tile_copy<float>(s, out, in, v, 1.0, 0.0);
   if (rc <= 0) return rc;
   int64_t g = (total + 255) / 256;
@@ -765,6 +786,17 @@ __global__ void view_gather_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo
   }
 }
 
+__global__ void flat_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off,
+                                   const double* __restrict__ in, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float xf = (float)in[e];
+    const uint16_t h = bf16_rne(xf);
+    out[e] = h;
+    out[e + lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+  }
+}
+
 // zero the padding columns [K, Kp) of a [rows][Kp] pair
 __global__ void pad_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off, int64_t rows, int K,
                                   int Kp) {
@@ -783,7 +815,21 @@ int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const doubl
                        const ViewSpec& v, int64_t rows, int K, int Kp) {
   int64_t total = 1;
   for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
-  if (total > 0) {
+  // a contiguous view in its own order (no permutation, no padding): an
+  // elementwise pass
+  bool flat = true;
+  int64_t st = 1;
+  for (int d = v.nd - 1; d >= 0; --d) {
+    if (v.dims[d] != 1 && (v.istr[d] != st || v.ostr[d] != st)) flat = false;
+    st *= v.dims[d];
+  }
+  if (total > 0 && flat) {
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(flat_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out + v.obase, lo_off,
+                       in + v.ibase, total);
+    if (hipGetLastError() != hipSuccess) return -3;
+  } else if (total > 0) {
     TileSpec t;
     bool trans = false;
     if (plan_tiles(v, t, trans)) {
