@@ -603,13 +603,13 @@ __global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int64_t x0 = txi * 64, y0 = tyi * 64;
   if (TRANS) {
-#pragma unroll 4
+#pragma unroll
     for (int r = row; r < 64; r += 4) {
       const int64_t x = x0 + lane, y = y0 + r;
       if (x < t.nx && y < t.ny) tile[r * 65 + lane] = in[ib + x * t.isx + y * t.isy];
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll
     for (int r = row; r < 64; r += 4) {
       const int64_t y = y0 + lane, x = x0 + r;
       if (x < t.nx && y < t.ny) {
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(256) void tile_copy_kernel(TO* __restrict__ out,
       }
     }
   } else {
-#pragma unroll 4
+#pragma unroll
     for (int r = row; r < 64; r += 4) {
       const int64_t x = x0 + lane, y = y0 + r;
       if (x < t.nx && y < t.ny) {
