@@ -258,8 +258,8 @@ def main():
                          "perturbed geometries, ground-state iterations from MP2 vs the network")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for {args.gpus}); sharding a "
+              "step across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -139,9 +139,8 @@ struct ArenaScope {
   ~ArenaScope() { a.rewind(m); }
 };
 
-// Mixed precision: solvers run their operator applications with fp32
-// operands until the residual falls below kMixedSwitch, then finish with fp64
-// operators and fp64 residuals.
+// Ground state in the mixed modes: fp32-operand residuals until max|Omega|
+// falls below kMixedSwitch, then fp64 residuals to the tolerance.
 constexpr double kMixedSwitch = 1e-5;
 // Eigen- and linear solvers: fp32-operand images carry about 1e-7 relative
 // rounding (bf16 pairs about 1e-5), so the residual norms computed from them
