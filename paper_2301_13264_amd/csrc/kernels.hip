@@ -435,10 +435,13 @@ int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch,
 // device): lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
 // for j < 8 and receives D rows 4 (l / 16) + v, column l % 16.
 // Tiles 128 x 128 x 32, 512 threads = 8 waves of 32 x 64 outputs, double-
-// buffered LDS rows of 40 bf16 (80 bytes: the 16 lanes of a quarter-wave read
-// 16 disjoint 4-bank groups), XCD-grouped tile order as the other kernels.
+// buffered LDS rows of 32 bf16 with the 16-byte chunks XOR-swizzled (64 KB, two
+// workgroups per CU), XCD-grouped tile order as the other kernels.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int HBK = 32, HKS = 40;
+constexpr int HBK = 32, HKS = 32;
+// 16-byte chunk c of tile row r sits at chunk c ^ ((r >> 2) & 3): the 16 rows
+// x one chunk of a quarter-wave's operand read cover all 64 banks
+__device__ inline int swz(int r, int c) { return r * HKS + 8 * (c ^ ((r >> 2) & 3)); }
 
 __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
     int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
     r3 = bok ? *(const uint4*)(Bl + boff + k0) : zero;
   };
   auto sstore = [&](int buf) {
-    const int o = grow * HKS + gch;
+    const int o = swz(grow, gch >> 3);
     *(uint4*)&S[buf][0][o] = r0;
     *(uint4*)&S[buf][1][o] = r1;
     *(uint4*)&S[buf][2][o] = r2;
@@ -497,13 +500,13 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
     bf16x8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int o = (wm * 32 + i * 16 + lr) * HKS + lk * 8;
+      const int o = swz(wm * 32 + i * 16 + lr, lk);
       ah[i] = *(const bf16x8*)&S[cur][0][o];
       al[i] = *(const bf16x8*)&S[cur][1][o];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int o = (wn * 64 + j * 16 + lr) * HKS + lk * 8;
+      const int o = swz(wn * 64 + j * 16 + lr, lk);
       bh[j] = *(const bf16x8*)&S[cur][2][o];
       bl[j] = *(const bf16x8*)&S[cur][3][o];
     }
