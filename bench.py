@@ -83,7 +83,7 @@ def run_step(nm, torch, inp, cfg, opts):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.9597e+10, "fp32": 1.8890e+10, "bf16x3": None}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": 2.4182e+10}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
