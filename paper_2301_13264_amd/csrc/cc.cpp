@@ -1233,13 +1233,15 @@ static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(con
       axpby_(c, ax, r, -1.0, 1.0, n);      // D = (T64 x - b) - (W^T y - b)
       double yy = 0.0;
       for (int k = 0; k < m; ++k) yy += cvec[k] * cvec[k];
-      std::vector<double> z(m);
-      for (int k = 0; k < m; ++k) z[k] = cvec[k] / yy;
-      hip_check(hipMemcpyAsync(y, z.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-      kc(gemm_f64(c.s, false, false, m, (int)n, 1, 1, 1.0, y, 1, 0, ax, n, 0, 1.0, W, n, 0), "image update");
-      dots_rows(c, V, m, ax, n, packed, work, h);
-      for (int a = 0; a < m; ++a)
-        for (int bb = 0; bb < m; ++bb) G[(size_t)a * maxm + bb] += h[a] * z[bb];
+      if (yy > 0.0) {                      // (x = 0 has an exact image already)
+        std::vector<double> z(m);
+        for (int k = 0; k < m; ++k) z[k] = cvec[k] / yy;
+        hip_check(hipMemcpyAsync(y, z.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
+        kc(gemm_f64(c.s, false, false, m, (int)n, 1, 1, 1.0, y, 1, 0, ax, n, 0, 1.0, W, n, 0), "image update");
+        dots_rows(c, V, m, ax, n, packed, work, h);
+        for (int a = 0; a < m; ++a)
+          for (int bb = 0; bb < m; ++bb) G[(size_t)a * maxm + bb] += h[a] * z[bb];
+      }
       if (rt < goal) {
         axpby_(c, r, ax, 1.0, 1.0, n);     // r = true residual (x unchanged)
         status = CC_OK;
