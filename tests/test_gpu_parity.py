@@ -273,6 +273,29 @@ def test_contract_low_precision_operands(nm, spec, shapes, oshape, prec):
         assert err < 0.05 * err1
 
 
+@pytest.mark.parametrize("spec,ashape", [("ik,kj->ij", (300, 64)), ("ki,kj->ij", (64, 300)),
+                                         ("ik,kj->ij", (257, 100))])
+def test_bf16_pair_packing_is_exact(nm, spec, ashape):
+    """Through the bf16-pair path with B = identity every output is hi + lo
+    of its input (B's pair is (1, 0)): the packing (fp64 -> fp32 -> hi =
+    bf16 round-to-nearest-even, lo = bf16 of the remainder, in the contiguous,
+    transposing and padded layouts) equals torch's conversions bit for bit."""
+    say(f"[bf16 packing] {spec} {ashape}")
+    rng = np.random.default_rng(17)
+    A = T(rng.normal(size=ashape) * np.exp(rng.normal(size=ashape)))
+    K = 64 if spec.startswith("ki") else ashape[1]
+    M = ashape[1] if spec.startswith("ki") else ashape[0]
+    I = torch.eye(K, dtype=torch.float64, device="cuda")
+    C = torch.zeros((M, K), dtype=torch.float64, device="cuda")
+    nm.contract(spec, 1.0, A, I, 0.0, C, precision=2)
+    torch.cuda.synchronize()
+    a = (A.t() if spec.startswith("ki") else A).cpu().float()
+    hi = a.to(torch.bfloat16).float()
+    lo = (a - hi).to(torch.bfloat16).float()
+    ref = (hi + lo).double()
+    assert torch.equal(C.cpu(), ref)
+
+
 @pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320)])
 def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K):
     """nm_gemm with bfloat16 pairs (the split-precision kernel alone): the
