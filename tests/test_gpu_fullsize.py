@@ -100,3 +100,21 @@ def test_transforms_and_eom_full_size(nm, system):
         # right eigen-residual from an independent transform
         assert np.linalg.norm(AR - w[k] * R[k]) < 1e-8
     ctx.close()
+    say("[full size] EOM in the bf16-pair mode")
+    # the split-precision solver's refined states: same eigenvalues, and the
+    # fp64 operator's eigen-residual of its right states meets the same bound
+    ctx = nm.Context(O, V, NAUX, T(sysd["eps"]), T(sysd["B"]),
+                     nm.default_opts(precision=nm.CC_BF16X3_REFINE))
+    _, _, rc = ctx.ground()
+    assert rc == 0
+    w16, _, rc = ctx.eom(nm.CC_BOTH, 2)
+    assert rc == 0
+    assert np.abs(np.array(w16) - np.array(w)).max() < 1e-9
+    for k in range(2):
+        Rk = to_packed(ctx.export(nm._lib.CC_R, k + 1, 0, y).cpu().numpy(), O, V)
+        Lk = to_packed(ctx.export(nm._lib.CC_L, k + 1, 0, y).cpu().numpy(), O, V)
+        assert abs(float(Lk @ Rk) - 1.0) < 1e-8
+        ctx.apply_jacobian(nm.CC_RIGHT, T(to_full(Rk, O, V)), y)
+        AR = to_packed(y.cpu().numpy(), O, V)
+        assert np.linalg.norm(AR - w16[k] * Rk) < 1e-8
+    ctx.close()
