@@ -36,6 +36,10 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 WORKLOAD = dict(name="thymine_dz", o=33, v=127, naux=640, nroots=2, ndir=45, seed=4301)
+# the ordered pairs of excited states whose couplings one step produces
+PAIRS = [(1, 2), (2, 1)]
+# the metric's accuracy bound on every coupling component (au)
+F_TOL = 1e-6
 # DF factor scale: the recipe's N(0, 0.05) gives no convergent CCSD at this
 # size (ground-state iterations overflow from the MP2 start); the scale is
 # reduced so that naux * sigma^2 * v keeps its value at o = 4, v = 12, naux = 48.
@@ -58,23 +62,30 @@ def run_step(nm, torch, inp, cfg, opts):
         st[name] = st.get(name, 0.0) + (now - t)
         t = now
 
+    def need(rc, what):
+        # a coupling from unconverged solutions is not a valid measurement
+        if rc != nm.CC_OK:
+            raise RuntimeError(f"{what} returned {rc} (not converged); the step is invalid")
+
     ctx = nm.Context(cfg["o"], cfg["v"], cfg["naux"], inp["eps"], inp["B"], opts)
     lap("integrals")
-    e, it, rc0 = ctx.ground()
+    e, it, rc = ctx.ground()
+    need(rc, "cc_ground")
     lap("ground")
-    w, itw, rc1 = ctx.eom(nm.CC_BOTH, cfg["nroots"])
+    w, itw, rc = ctx.eom(nm.CC_BOTH, cfg["nroots"])
+    need(rc, "eom_solve")
     lap("eom")
     F = {}
-    for (i, j) in [(1, 2), (2, 1)]:
-        ctx.multipliers(i, j)
-        lap("multipliers")
+    _, rc = ctx.multipliers(PAIRS)
+    need(rc, "multipliers")
+    lap("multipliers")
+    for (i, j) in PAIRS:
         ctx.densities(i, j)
         lap("densities")
         F[(i, j)] = ctx.nacme(i, j, inp["dh"], inp["dB"])
         lap("nacme")
     torch.cuda.synchronize()
-    return ctx, dict(e_corr=e, omega=w, ground_iters=it, eom_iters=itw, F=F, rc=(rc0, rc1),
-                     stage_s=st)
+    return ctx, dict(e_corr=e, omega=w, ground_iters=it, eom_iters=itw, F=F, stage_s=st)
 
 
 # HBM traffic of one ladder GEMM launch for a block of LADDER_VECTORS trial
@@ -83,10 +94,12 @@ def run_step(nm, torch, inp, cfg, opts):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": 2.4182e+10}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": None}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
+# workgroup tiles of the bfloat16-pair kernel (nm_gemm_tiled)
+BF16_TILES = {0: "128x128", 1: "256x256", 2: "256x128", 3: "128x256"}
 
 # timed-step precision: library mode, dtype label, dominant ladder kernel
 PRECISIONS = {
@@ -131,21 +144,32 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
     A = torch.randn(2, rows, Kp, device=dev).to(torch.bfloat16)
     Bt = torch.randn(2, v * v, Kp, device=dev).to(torch.bfloat16)
     C = torch.zeros(rows, v * v, dtype=torch.float64, device=dev)
-    nm.gemm(2, A, Bt, C, stream=st)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(st)
-    for _ in range(nl):
-        nm.gemm(2, A, Bt, C, stream=st)
-    ev1.record(st)
-    ev1.synchronize()
-    lms = ev0.elapsed_time(ev1) / nl
-    tf = 3.0 * ladder_flop / (lms * 1e-3) / 1e12
+    # every workgroup tile shape of the kernel; the fastest is the one the
+    # contraction engine's autotuner keeps for this shape
+    tile_ms = {}
+    for tile in BF16_TILES:
+        nm.gemm(2, A, Bt, C, stream=st, tile=tile)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        for _ in range(nl):
+            nm.gemm(2, A, Bt, C, stream=st, tile=tile)
+        ev1.record(st)
+        ev1.synchronize()
+        tile_ms[BF16_TILES[tile]] = ev0.elapsed_time(ev1) / nl
+    best_tile = min(tile_ms, key=tile_ms.get)
+    lms = tile_ms[best_tile]
+    # achieved: the method's flops (2 o^2 v^4 per vector); the three bf16
+    # products each such flop issues are reported beside it
+    tf = ladder_flop / (lms * 1e-3) / 1e12
     roof["bf16x3"] = dict(bound="mfma", achieved=tf, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
                           frac=tf / PEAK_BF16_TFLOPS, traffic=LADDER_TRAFFIC_BYTES["bf16x3"],
-                          launch_ms=lms, flop_per_launch=3.0 * ladder_flop, products_per_flop=3,
+                          launch_ms=lms, flop_per_launch=ladder_flop, products_per_flop=3,
+                          issued_tflops=3.0 * tf, issued_frac=3.0 * tf / PEAK_BF16_TFLOPS,
+                          tile=best_tile, tile_launch_ms=tile_ms,
                           algorithmic_bytes=(A.numel() + Bt.numel()) * 2 + 8 * C.numel())
     del A, Bt, C
-    roof["bf16x3"]["kernel"] = (f"gemm_bf16x3_kernel (ladder X[z ij][cd] x W[cd][ab], "
+    roof["bf16x3"]["kernel"] = (f"{'gemm_bf16x3_kernel' if best_tile == '128x128' else 'gemm_bf16x3_big_kernel'} "
+                                f"{best_tile} (ladder X[z ij][cd] x W[cd][ab], "
                                 f"{LADDER_VECTORS} trial vectors, bfloat16 pairs, 3 bf16 products, "
                                 "fp32 accumulation)")
     roof["fp64"]["kernel"] = (f"gemm_f64_big_kernel (ladder X[z ij][cd] x W[cd][ab], "
@@ -240,6 +264,68 @@ def roofline_only(nm, torch, cfg, dev):
           flush=True)
 
 
+def cpu_info():
+    """Host CPU model, thread count and BLAS of the oracle (torch's CPU build)."""
+    import torch
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cfg = torch.__config__.show()
+    blas = "mkl" if "BLAS_INFO=mkl" in cfg else ("openblas" if "openblas" in cfg.lower() else "unknown")
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "MKL_NUM_THREADS",
+                                          "OPENBLAS_NUM_THREADS", "GOMP_CPU_AFFINITY")}
+    return dict(cpu_model=model, blas=f"torch {torch.__version__} CPU ({blas})",
+                thread_env={k: v for k, v in env.items() if v is not None})
+
+
+def cpu_baseline(sysd, cfg, counts):
+    """The oracle timed on the host cores at the same workload: one CCSD
+    residual, one right and one left Jacobian transform (at random amplitudes
+    and trial vectors of the ground-state size), each scaled by how many of
+    them one GPU step runs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import ccsd as occ
+    from oracle import response as ors
+
+    o, v = cfg["o"], cfg["v"]
+    threads = len(os.sched_getaffinity(0))
+    torch.set_num_threads(threads)
+    h, g = ors.system_hamiltonian(sysd["eps"], sysd["B"], o)
+    t1o, t2o = (torch.as_tensor(x) for x in synth.random_amplitudes(o, v, seed=1, scale=0.01))
+    x = occ.pack(t1o, t2o)
+    r = torch.as_tensor(np.random.default_rng(2).normal(scale=1e-2, size=x.numel()))
+    c0 = time.perf_counter()
+    occ.residual(t1o, t2o, h, g)
+    c1 = time.perf_counter()
+    ors.right_transform(x, r, h, g, o, v)
+    c2 = time.perf_counter()
+    ors.left_transform(x, r, h, g, o, v)
+    c3 = time.perf_counter()
+    del h, g
+    t_res, t_right, t_left = c1 - c0, c2 - c1, c3 - c2
+    step_s = (counts["residuals"] * t_res + counts["right"] * t_right
+              + counts["left"] * t_left)
+    out = dict(value=len(PAIRS) / step_s, unit="NACME vectors/s", cores=threads, kind="oracle",
+               sample=(f"oracle at o={o} v={v} naux={cfg['naux']}: one CCSD residual "
+                       f"{t_res:.2f} s, one right transform {t_right:.2f} s, one left "
+                       f"transform {t_left:.2f} s; scaled by the {int(counts['residuals'])} "
+                       f"residuals, {int(counts['right'])} right and {int(counts['left'])} left "
+                       "transforms of one GPU step (densities and contraction not counted)"),
+               residual_s=t_res, right_transform_s=t_right, left_transform_s=t_left,
+               step_s_estimate=step_s)
+    out.update(cpu_info())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +337,8 @@ def main():
                     help="precision of the timed steps")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the step in the other precision")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the warmup and timed steps (for kernel profiles of a step)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the ladder GEMM launches and a copy calibration (profiling)")
     ap.add_argument("--learned-guess", action="store_true",
@@ -281,6 +369,7 @@ def main():
                                  sigma_b=SIGMA_B)
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
     inp = dict(eps=T(sysd["eps"]), B=T(sysd["B"]), dh=T(dirs["dh"]), dB=T(dirs["dB"]))
+    del dirs
     torch.cuda.synchronize()
     prec = getattr(nm, PRECISIONS[args.precision][0])
     opts = nm.default_opts(precision=prec)
@@ -297,12 +386,20 @@ def main():
         if ctx is not None:
             ctx.close()
         ctx, out = run_step(nm, torch, inp, cfg, opts)
-        log(f"[bench] step {s + 1} done: omega={out['omega']} F12[0]={out['F'][(1, 2)][0]:.6e} "
+        log(f"[bench] step {s + 1} done: omega={out['omega']} F12[0]={out['F'][PAIRS[0]][0]:.6e} "
             f"stages={ {k: round(x, 2) for k, x in out['stage_s'].items()} }")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = 1000.0 * (t1 - t0) / args.steps
     stats = ctx.stats()
+    counts = dict(residuals=stats["residuals"], right=stats["right_transforms"],
+                  left=stats["left_transforms"])
+    value = len(PAIRS) * 1000.0 / ms   # NACME vectors (45 components each) per second
+    if args.step_only:
+        ctx.close()
+        print(json.dumps(dict(mode="step-only", ms_per_step=ms, value=value, stage_s=out["stage_s"],
+                              step_counts=counts, omega=out["omega"])), flush=True)
+        return
 
     # Jacobian transforms/s at the converged amplitudes (HIP events on the
     # library's stream): k vectors per batched call, fp64 and fp32 operands;
@@ -331,6 +428,7 @@ def main():
     ctx.close()
 
     other = None
+    valid = True
     if not args.no_compare:
         oname = "fp64" if args.precision != "fp64" else "mixed"
         oprec = nm.CC_FP64 if args.precision != "fp64" else nm.CC_FP32_REFINE
@@ -342,49 +440,34 @@ def main():
         dF = max(float(np.max(np.abs(np.asarray(out["F"][k]) - np.asarray(oout["F"][k]))))
                  for k in out["F"])
         dw = max(abs(a - b) for a, b in zip(out["omega"], oout["omega"]))
+        # the mixed path must meet the metric's bound against the fp64 path
+        valid = dF <= F_TOL
         other = dict(precision=oname, time_to_nacme_s=c1 - c0, stage_s=oout["stage_s"],
-                     max_abs_dF=dF, max_abs_domega=dw,
+                     max_abs_dF=dF, max_abs_domega=dw, within_bound=valid, bound=F_TOL,
                      d_e_corr=abs(out["e_corr"] - oout["e_corr"]),
                      ground_iters=oout["ground_iters"], eom_iters=oout["eom_iters"])
         log(f"[bench] {oname}: {c1 - c0:.2f} s, max|dF| = {dF:.3e} "
             f"stages={ {k: round(x, 2) for k, x in oout['stage_s'].items()} }")
 
-    o, v = cfg["o"], cfg["v"]
     roof = ladder_roofline(nm, torch, cfg, dev, st)
     main_roof = roof[PRECISIONS[args.precision][2]]
 
-    # CPU baseline: the oracle's residual at the same size on the host cores
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import ccsd as occ
-        from oracle import response as ors
-        threads = len(os.sched_getaffinity(0))
-        torch.set_num_threads(threads)
-        h, g = ors.system_hamiltonian(sysd["eps"], sysd["B"], o)
-        t1o, t2o = (torch.as_tensor(x) for x in synth.random_amplitudes(o, v, seed=1, scale=0.01))
-        c0 = time.perf_counter()
-        occ.residual(t1o, t2o, h, g)
-        c1 = time.perf_counter()
-        t_res = c1 - c0
-        # residual-equivalents of one GPU step (each transform counted as one
-        # residual: a lower bound on the oracle's cost, which differentiates
-        # by automatic differentiation)
-        work = stats["residuals"] + stats["right_transforms"] + stats["left_transforms"]
-        steps_per_s = 1.0 / (t_res * work)
-        cpu = dict(value=2.0 * steps_per_s, unit="NACME vectors/s", cores=threads, kind="oracle",
-                   sample=f"one oracle CCSD residual at o=33 v=127 naux=640 ({t_res:.2f} s); "
-                          f"scaled by the {int(work)} residual-equivalents of one GPU step",
-                   residual_s=t_res)
+        log("[bench] CPU baseline: oracle residual and transforms on the host")
+        cpu = cpu_baseline(sysd, cfg, counts)
 
-    value = 2.0 * 1000.0 / ms   # two NACME vectors (F_12, F_21; 45 components each) per step
     res = dict(
         metric="time-to-NACME vector & Jacobian transforms/s (TFLOP/s, % MFMA peak) at <=1e-6 au",
         value=value, unit="NACME vectors/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype=PRECISIONS[args.precision][1],
         data="synthetic",
-        config=dict(workload="thymine_dz: o=33 v=127 naux=640, 2 roots, 45 directions, "
-                             f"DF scale {SIGMA_B:.5f}", global_batch=1, parallelism="none"),
+        config=dict(workload=(f"thymine_dz: o=33 v=127 naux=640, {cfg['nroots']} roots "
+                              f"(pair gap {out['omega'][1] - out['omega'][0]:.4f} Ha), "
+                              f"{cfg['ndir']} directions, DF scale {SIGMA_B:.5f}"),
+                    global_batch=1, parallelism="none"),
+        valid=valid,
         precision=args.precision,
         time_to_nacme_s=ms / 1000.0,
         compare=other,
@@ -394,8 +477,7 @@ def main():
         omega=out["omega"], e_corr=out["e_corr"],
         jacobian_transforms_per_s={k: 1000.0 / x["ms_per_vector_k4"] for k, x in tr.items()},
         jacobian_transform_ms=tr,
-        step_counts=dict(residuals=stats["residuals"], right=stats["right_transforms"],
-                         left=stats["left_transforms"]),
+        step_counts=counts,
         step_gemm_tflops=stats["gemm_flops"] / (ms / 1000.0) / 1e12,
         device_work_area_gb=stats["peak_bytes"] / 1e9,
         roofline=main_roof,
@@ -404,6 +486,9 @@ def main():
         cpu_baseline=cpu,
     )
     print(json.dumps(res), flush=True)
+    if not valid:
+        log(f"[bench] INVALID: max |dF| = {other['max_abs_dF']:.3e} exceeds {F_TOL:g} au")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

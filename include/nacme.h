@@ -41,7 +41,7 @@
  *    biorthonormal norm with their largest-magnitude parameter positive; left
  *    states satisfy L_k . R_l = delta_kl.
  *  - Call order: cc_create -> cc_ground -> eom_solve(RIGHT) and
- *    eom_solve(LEFT) (or BOTH) -> multipliers(i,j) -> densities(i,j) ->
+ *    eom_solve(LEFT) (or BOTH) -> multipliers(pairs) -> densities(i,j) ->
  *    nacme(i,j).  Anything else returns -2.
  */
 #ifndef NACME_H
@@ -131,7 +131,8 @@ int cc_ground(cc_ctx* ctx, double* e_corr, int* iters);
  * -6 if a requested root is complex.                                        */
 int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
 
-/* Multipliers of the ordered pair (i, j), 0 <= i, j <= nroots:
+/* Multipliers of npairs ordered pairs (i, j), 0 <= i, j <= nroots, given as
+ * pairs[2 p] = i, pairs[2 p + 1] = j (host array [npairs][2], no pair twice):
  *  - 1 <= i != j: coupling F_ij; gamma = L_i/(omega_j - omega_i), xi = 0
  *    (Sec. II B); zeta-bar from A^T zeta = -eta_t (eq. amplituderelax) and,
  *    when relaxed, kappa-bar from (A^HF)^T kappa = -eta_kappa (eq.
@@ -144,9 +145,14 @@ int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
  *    place of eta_t and no overlap term; then densities(j, j) and
  *    nacme(j, j, ...) give dE_j/dlambda^q (branching-plane vectors:
  *    g^q = dE_2^q - dE_1^q, h^q = (E_2 - E_1) F_12^q).
+ * The zeta equations of all listed pairs are solved together: blocks of up
+ * to 8 right-hand sides share one Galerkin subspace and go through every
+ * left Jacobian transform as one batch.
  * Pair (0, 0) needs only cc_ground; every other pair needs both EOM sides.
- * iters: host [2] or NULL (zeta and kappa iterations).                       */
-int multipliers(cc_ctx* ctx, int i, int j, int* iters);
+ * iters: host [npairs][2] or NULL (zeta and kappa-bar iterations per pair).
+ * Returns 1 if any solve missed its tolerance (results are the last
+ * iterates); -1 for bad or repeated pairs, -2 before the states exist.     */
+int multipliers(cc_ctx* ctx, int npairs, const int* pairs, int* iters);
 
 /* Effective densities of the pair (i, j): D_eff (n x n) and the two-electron
  * density d_eff, such that F^q = sum D_eff dh^q + 1/2 sum d_eff dg^q
@@ -211,6 +217,15 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
 int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
             int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,
             void* stream);
+/* As nm_gemm, with the workgroup tile of the bfloat16-pair kernel chosen by
+ * `tile` (precision CC_BF16X3_REFINE only): 0 = 128 x 128 outputs per
+ * workgroup (two per CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one
+ * per CU), -1 = the library's model of the fastest shape (what nm_gemm and
+ * the contraction engine use before the autotuner has timed a shape).
+ * -1 (ARG) for a tile with another precision.                              */
+int nm_gemm_tiled(int precision, int tile, int ta, int tb, int M, int N, int K, double alpha,
+                  const void* A, int64_t lda, const void* B, int64_t ldb, double beta, double* C,
+                  int64_t ldc, void* stream);
 /* ---- learned initial guess --------------------------------------------- */
 /* A three-layer perceptron y = W3^T s(W2^T s(W1^T x + b1) + b2) + b3 with
  * SiLU s(u) = u / (1 + exp(-u)) and row-major W[in][out], trained on the

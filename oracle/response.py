@@ -26,7 +26,7 @@ import scipy.linalg
 import torch
 from torch.func import grad, jvp, vjp, vmap
 
-from . import ccsd
+from . import ccsd, iterative
 from .ccsd import DT, as_t
 
 
@@ -173,6 +173,41 @@ def hf_hessian(h, g, o, v):
 GROUND = -1   # index of the CC ground state when it is the right state of a pair
 
 
+def solve_zeta(st: dict, eta_t):
+    """zeta with A^T zeta = -eta_t (eq. amplituderelax): a dense solve with
+    the dense Jacobian, or GMRES on the left transform for a state solved
+    iteratively (``ground_and_eom_iterative``)."""
+    o, v, h, g, x = st["o"], st["v"], st["h"], st["g"], st["x"]
+    if st.get("iterative"):
+        return iterative.krylov_solve(lambda y: left_transform(x, y, h, g, o, v), -eta_t,
+                                      iterative.orbital_diagonal(h, g, o), tol=st["lin_tol"])
+    A = st.get("A")
+    if A is None:
+        A = dense_jacobian(x, h, g, o, v)
+        st["A"] = A
+    return torch.linalg.solve(A.T, -eta_t)
+
+
+def solve_kappa(st: dict, eta_k):
+    """kappa_bar with (A^HF)^T kappa_bar = -eta_kappa (eq. orbitalrelax): a
+    dense solve with the orbital Hessian, or, for a state solved iteratively,
+    GMRES on its transpose applied by a reverse derivative of F_ai through the
+    orbital rotation."""
+    o, v, h, g = st["o"], st["v"], st["h"], st["g"]
+    if st.get("iterative"):
+        f = lambda k: fock_ai(*rotate(h, g, k.reshape(o, v), o, v), o).reshape(-1)  # noqa: E731
+        _, pull = vjp(f, torch.zeros(o * v, dtype=DT))
+        f0 = ccsd.fock(h, g, o)
+        d = (torch.diag(f0)[o:][None, :] - torch.diag(f0)[:o][:, None]).reshape(-1)
+        x = iterative.krylov_solve(lambda y: pull(y)[0], -eta_k.reshape(-1), d, tol=st["lin_tol"])
+        return x.reshape(o, v)
+    AHF = st.get("AHF")
+    if AHF is None:
+        AHF = hf_hessian(h, g, o, v)
+        st["AHF"] = AHF
+    return torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
+
+
 def right_state(st: dict, j: int):
     """(omega_j, R0_j, R_j) of the right state j of a pair.  The ground state
     exp(T)|HF> (Sec. II C, j = 0) has R0 = 1, R = 0 and no EOM condition, so
@@ -210,11 +245,7 @@ def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
     eta_o = grad(lambda d: overlap(d, Li, R0j, Rj, o, v))(zero)
     eta_f = grad(lambda y: torch.dot(gamma, right_transform(y, Rj, h, g, o, v)))(x)
     eta_t = eta_o + eta_f
-    A = st.get("A")
-    if A is None:
-        A = dense_jacobian(x, h, g, o, v)
-        st["A"] = A
-    zeta = torch.linalg.solve(A.T, -eta_t)
+    zeta = solve_zeta(st, eta_t)
     out = dict(gamma=gamma, xi=xi, eta_t=eta_t, eta_t_overlap=eta_o, zeta=zeta)
     D = transition_density(x, Li, R0j, Rj, o, v, n)
     out["D"] = D
@@ -224,9 +255,8 @@ def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
         k23 = grad(lambda k: lagrangian_hamiltonian_part(
             x, gamma, zeta, Rj, *rotate(h, g, k, o, v), o, v))(k0)
         eta_k = k1 + k23
-        AHF = hf_hessian(h, g, o, v)
-        kbar = torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
-        out.update(eta_kappa=eta_k, eta_kappa_overlap=k1, AHF=AHF, kappa_bar=kbar)
+        kbar = solve_kappa(st, eta_k)
+        out.update(eta_kappa=eta_k, eta_kappa_overlap=k1, kappa_bar=kbar)
     else:
         out["kappa_bar"] = torch.zeros((o, v), dtype=DT)
     return out
@@ -298,18 +328,13 @@ def gradient_multipliers(st: dict, j: int, relaxed: bool = True) -> dict:
         Lj, Rj = st["L"][j], st["R"][j]
         eta_t = eta(x, h, g, o, v) + grad(
             lambda y: torch.dot(Lj, right_transform(y, Rj, h, g, o, v)))(x)
-    A = st.get("A")
-    if A is None:
-        A = dense_jacobian(x, h, g, o, v)
-        st["A"] = A
-    zeta = torch.linalg.solve(A.T, -eta_t)
+    zeta = solve_zeta(st, eta_t)
     out = dict(L=Lj, R=Rj, eta_t=eta_t, zeta=zeta)
     if relaxed:
         k0 = torch.zeros((o, v), dtype=DT)
         eta_k = grad(lambda k: energy_lagrangian_part(
             x, Lj, zeta, Rj, *rotate(h, g, k, o, v), o, v))(k0)
-        AHF = hf_hessian(h, g, o, v)
-        kbar = torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
+        kbar = solve_kappa(st, eta_k)
         out.update(eta_kappa=eta_k, kappa_bar=kbar)
     else:
         out["kappa_bar"] = torch.zeros((o, v), dtype=DT)
@@ -359,6 +384,34 @@ def ground_and_eom(h, g, o: int, nroots: int, tol: float = 1e-11, t_init=None):
     R0 = torch.stack([torch.dot(et, R[k]) / om[k] for k in range(nroots)])
     return dict(o=o, v=v, h=h, g=g, x=x, t1=t1, t2=t2, E0=E0, iters=it, A=A,
                 omega=torch.as_tensor(om), R=R, L=L, R0=R0, eta=et)
+
+
+def ground_and_eom_iterative(h, g, o: int, nroots: int, tol: float = 1e-11,
+                             eom_tol: float = 1e-10, lin_tol: float = 1e-12):
+    """As ``ground_and_eom`` without the dense Jacobian: the right and left
+    EOM states by Davidson on the right and left transforms (residual norms
+    below eom_tol), gauged and biorthonormalised the same way; the zeta
+    equations of the multipliers are then solved by GMRES (relative residual
+    lin_tol)."""
+    h, g = as_t(h), as_t(g)
+    n = h.shape[0]
+    v = n - o
+    t1, t2, E0, it = ccsd.solve_ground(h, g, o, tol=tol)
+    x = ccsd.pack(t1, t2)
+    diag = iterative.orbital_diagonal(h, g, o)
+    wr, Rr, _ = iterative.davidson(lambda y: right_transform(x, y, h, g, o, v), diag, nroots,
+                                   tol=eom_tol)
+    wl, Ll, _ = iterative.davidson(lambda y: left_transform(x, y, h, g, o, v), diag, nroots,
+                                   tol=eom_tol)
+    if np.abs(wr - wl).max() > 1e-8:
+        raise RuntimeError("left and right Davidson roots differ")
+    R = torch.stack([torch.as_tensor(gauge_right(Rr[k].numpy())) for k in range(nroots)])
+    L = torch.linalg.solve(Ll @ R.T, Ll)
+    et = eta(x, h, g, o, v)
+    R0 = torch.stack([torch.dot(et, R[k]) / wr[k] for k in range(nroots)])
+    return dict(o=o, v=v, h=h, g=g, x=x, t1=t1, t2=t2, E0=E0, iters=it, A=None,
+                omega=torch.as_tensor(wr), R=R, L=L, R0=R0, eta=et, iterative=True,
+                lin_tol=lin_tol)
 
 
 def system_hamiltonian(eps, B, o):

@@ -52,7 +52,7 @@ def lib():
         L.cc_create.argtypes = [ctypes.POINTER(P), I, I, I, P, P, ctypes.POINTER(Opts), P]
         L.cc_ground.argtypes = [P, PD, PI]
         L.eom_solve.argtypes = [P, I, I, PD, PI]
-        L.multipliers.argtypes = [P, I, I, PI]
+        L.multipliers.argtypes = [P, I, PI, PI]
         L.densities.argtypes = [P, I, I, P]
         L.nacme.argtypes = [P, I, I, I, P, P, PD]
         L.cc_apply_jacobian.argtypes = [P, I, P, P]
@@ -70,6 +70,9 @@ def lib():
         L.nm_gemm.argtypes = [I, I, I, I, I, I, D, P, ctypes.c_int64, P, ctypes.c_int64, D, P,
                               ctypes.c_int64, P]
         L.nm_gemm.restype = ctypes.c_int
+        L.nm_gemm_tiled.argtypes = [I, I, I, I, I, I, I, D, P, ctypes.c_int64, P, ctypes.c_int64, D, P,
+                                    ctypes.c_int64, P]
+        L.nm_gemm_tiled.restype = ctypes.c_int
         L.cc_stats.restype = ctypes.c_int
         L.cc_apply_jacobian_block.argtypes = [P, I, I, P, P, I]
         L.cc_apply_jacobian_block.restype = ctypes.c_int
@@ -108,7 +111,8 @@ def lib():
 EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multipliers",
             "densities", "nacme", "cc_apply_jacobian", "cc_residual", "cc_export",
             "cc_set_guess", "cc_last_error", "cc_destroy", "nm_contract", "nm_eig_host",
-            "nm_version", "cc_stats", "nm_gemm", "cc_apply_jacobian_block", "mlp_create",
+            "nm_version", "cc_stats", "nm_gemm", "nm_gemm_tiled", "cc_apply_jacobian_block",
+            "mlp_create",
             "mlp_num_params", "mlp_dims", "mlp_set_params", "mlp_get_params", "mlp_forward",
             "mlp_loss_grad", "mlp_adam_step", "mlp_train", "mlp_last_error", "mlp_destroy",
             "cc_t2_features", "cc_t2_target", "cc_guess_t2"]
@@ -182,10 +186,14 @@ class Context:
         rc = self._check(lib().eom_solve(self._h, side, nroots, w, ctypes.byref(it)))
         return list(w), it.value, rc
 
-    def multipliers(self, i, j):
-        it = (ctypes.c_int * 2)()
-        rc = self._check(lib().multipliers(self._h, i, j, it))
-        return list(it), rc
+    def multipliers(self, pairs):
+        """Multipliers of the ordered pairs [(i, j), ...], solved together;
+        returns ([[zeta iterations, kappa iterations] per pair], status)."""
+        pairs = [(int(i), int(j)) for i, j in pairs]
+        flat = (ctypes.c_int * (2 * len(pairs)))(*[x for p in pairs for x in p])
+        it = (ctypes.c_int * (2 * len(pairs)))()
+        rc = self._check(lib().multipliers(self._h, len(pairs), flat, it))
+        return [[it[2 * p], it[2 * p + 1]] for p in range(len(pairs))], rc
 
     def densities(self, i, j, D1=None):
         self._check(lib().densities(self._h, i, j, _ptr(D1) if D1 is not None else None))
@@ -252,11 +260,12 @@ def contract(spec: str, alpha, A, B, beta, C, stream=None, precision=0):
     return C
 
 
-def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None):
+def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None, tile=-1):
     """One matrix-core GEMM launch C = alpha A B + beta C (2-D row-major
     device tensors; A, B float64 for precision 0, float32 for precision 1).
     Precision 2: A [2][M][K] and Bt [2][N][K] bfloat16 pairs (hi, lo) with B
-    given transposed, K a multiple of 32."""
+    given transposed, K a multiple of 32; tile selects the kernel's workgroup
+    tile (nm_gemm_tiled, -1 = the library's choice)."""
     import torch
     if precision == 2:
         for t in (A, B):
@@ -266,8 +275,9 @@ def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None):
         _, N, K2 = B.shape
         if K2 != K or tuple(C.shape) != (M, N):
             raise ValueError("GEMM shape mismatch")
-        rc = lib().nm_gemm(2, 0, 1, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), K,
-                           ctypes.c_void_p(B.data_ptr()), K, beta, _ptr(C), N, _stream_ptr(stream))
+        rc = lib().nm_gemm_tiled(2, tile, 0, 1, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), K,
+                                 ctypes.c_void_p(B.data_ptr()), K, beta, _ptr(C), N,
+                                 _stream_ptr(stream))
         if rc != CC_OK:
             raise CCError(rc, "nm_gemm")
         return C

@@ -443,13 +443,19 @@ struct Tape {
   ResNodes r;
   explicit Tape(Ctx& cc) : c(cc), base(cc.eng->arena().mark()), G(*cc.eng) {
     // the recorded primal values are always fp64; only the derivative sweeps
-    // may run with fp32 operands
+    // may run with low-precision operands
     const bool lp = c.eng->lowp();
     c.eng->set_lowp(false);
     r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g, c.W, c.Wov);
     c.eng->set_lowp(lp);
+    // the recorded values stay as they are while the tape lives: every
+    // transform reuses their low-precision packings
+    G.freeze(G.size());
   }
-  ~Tape() { c.eng->arena().rewind(base); }
+  ~Tape() {
+    c.eng->clear_frozen();
+    c.eng->arena().rewind(base);
+  }
 
   // y = A x
   void right(const double* x, double* y) {
@@ -723,6 +729,8 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   int stall = 0;
   bool refreshed = false;
   Ritz res;
+  double* tmpx = nullptr;   // restart buffers, allocated on the first restart
+  double* tmpa = nullptr;
   auto refresh = [&](const std::vector<double>& Y, int nk) -> double {
     c.eng->set_lowp(false);
     T(X, AXd, nroots);
@@ -848,12 +856,15 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       res.converged = true;
       break;
     }
-    // restart when the subspace is full
+    // restart when the subspace is full: the Ritz vectors and images become
+    // the new basis (copied first, orth() works on its arguments in place)
     if (m + nk > maxm) {
       m = 0;
       std::fill(G.begin(), G.end(), 0.0);
-      double* tmpx = ar.alloc((int64_t)nk * N);
-      double* tmpa = ar.alloc((int64_t)nk * N);
+      if (!tmpx) {
+        tmpx = ar.alloc((int64_t)nb * N);
+        tmpa = ar.alloc((int64_t)nb * N);
+      }
       copy_d(c, tmpx, X, (int64_t)nk * N);
       copy_d(c, tmpa, AX, (int64_t)nk * N);
       for (int k = 0; k < nk; ++k) orth(tmpx + (int64_t)k * N, tmpa + (int64_t)k * N);
@@ -1135,131 +1146,279 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
 }
 
 // --------------------------------------------------------- linear solver
-// Solves T(x) = b (T: amplitude-shaped or small vectors of length n, metric
-// `packed`) by Galerkin projection on a growing preconditioned subspace.
-// Solves T(x) = b by a Galerkin projection on a growing subspace V with
-// images W = T(V): G y = V^T b with G = V^T W, x = V y, next basis vector
-// from the preconditioned residual.
+// Solves T(x_r) = b_r for k right-hand sides (T on amplitude-shaped vectors,
+// biorthonormal metric, or on plain vectors of length n) by a Galerkin
+// projection on one growing subspace V shared by all of them, with images
+// W = T(V): for each r, G y_r = V^T b_r with G = V^T W, x_r = V y_r.  Each
+// iteration extends V by the preconditioned residuals of the systems not yet
+// converged and images them in one block application of T, so that k systems
+// share every pass through the operator.  A system's solution is frozen once
+// its residual meets the tolerance.  When the subspace is full it restarts
+// from the current solutions.
 //
-// mixed: the images come from the fp32-operand operator.  When the residual
-// reaches the fp32 rounding floor (kEigSwitch relative, or a stall), and
-// before convergence is accepted, x gets an fp64 image and the true residual
-// is measured; the basis images then get the rank-1 correction
-// W <- W + z D with D = T64(x) - W^T y and z = y / (y . y), so that the
-// image of x becomes exact (G gets the same update) and the subspace is
-// kept.  Only a true residual below tol ends the solve.
-static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(const double*, double*)>& T,
-                    const std::function<void(double*, const double*)>& precond, const double* b,
-                    double* x, double tol, int maxit, int* iters, bool mixed_images = false) {
+// mixed: the images come from the low-precision operator.  When a residual
+// computed from them reaches its rounding floor (eig_switch relative, or a
+// stall), and whenever it meets the tolerance, the current solutions
+// X = Y V get fp64 images and their true residuals are measured; the basis
+// images then get the rank-k correction W <- W + Z^T D with D = T64(X) - Y W
+// and Z = (Y Y^T)^-1 Y (Z Y^T = I), so that the images of the solutions become
+// exact (G gets the same update) and the subspace is kept.  Only a true
+// residual below the tolerance ends a system's solve.
+constexpr int kMaxBlockRhs = 8;
+static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
+                          const std::function<void(const double*, double*, int)>& T,
+                          const std::function<void(double*, const double*)>& precond,
+                          const double* B, double* X, double tol, int maxit, int* iters,
+                          bool mixed_images) {
+  if (k < 1 || k > kMaxBlockRhs) throw Error(-1, "linear solver block size out of range");
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
-  const int maxm = std::min(maxit, 120);
+  const int maxm = std::min(kMaxRows - kMaxBlockRhs, 120);
   double* V = ar.alloc((int64_t)maxm * n);
   double* W = ar.alloc((int64_t)maxm * n);
-  double* r = ar.alloc(n);
-  double* y = ar.alloc(maxm);
-  double* ax = mixed_images ? ar.alloc(n) : nullptr;
+  double* Rr = ar.alloc((int64_t)k * n);      // residuals T x_r - b_r
+  double* Cb = ar.alloc((int64_t)k * n);      // new basis vectors / fp64 images
+  double* workm = ar.alloc((int64_t)k * n + (int64_t)k * maxm);
+  double* Db = ar.alloc((int64_t)k * n + (int64_t)k * maxm);   // second work block
+  double* hdm = ar.alloc((int64_t)k * maxm);
+  double* ydev = ar.alloc((int64_t)k * maxm);
+  double* zdev = ar.alloc((int64_t)k * maxm);
   auto dotf = [&](const double* p, const double* q) {
     return packed ? dot_bio(c, p, q) : dot_plain(c, p, q, n);
   };
-  std::vector<double> G((size_t)maxm * maxm), bv(maxm), h, cvec;
-  double* work = ar.alloc(n + 2 * maxm);
-  double* hd = work + n + maxm;
+  std::vector<double> G((size_t)maxm * maxm, 0.0), H, bvm((size_t)k * maxm, 0.0);
+  std::vector<double> bn(k), goal(k), best(k, 1e300), rn(k, 0.0);
+  std::vector<int> stall(k, 0), conv(k, 0), it_of(k, 0);
+  std::vector<char> refreshed(k, 0);
   int m = 0;
   c.eng->set_lowp(mixed_images);
   c.eng->set_bf16(mixed_images && solver_bf16(c));
-  precond(r, b);
+  for (int r = 0; r < k; ++r) {
+    const double* b = B + (int64_t)r * n;
+    bn[r] = std::sqrt(std::max(dotf(b, b), 0.0));
+    goal[r] = tol * std::max(1.0, bn[r]);
+    kc(fill(c.s, X + (int64_t)r * n, 0.0, n), "fill");
+    axpby_(c, Rr + (int64_t)r * n, b, -1.0, 0.0, n);   // residual of x = 0
+    if (bn[r] < goal[r]) conv[r] = 1;                  // x = 0 is exact
+  }
+  // images of rows [m0, m), then the new rows and columns of G and V^T b
+  auto extend = [&](int m0) {
+    const int r = m - m0;
+    if (r <= 0) return;
+    T(V + (int64_t)m0 * n, W + (int64_t)m0 * n, r);
+    dots_rows_multi(c, V, m, W + (int64_t)m0 * n, r, n, packed, workm, H);
+    for (int jj = 0; jj < r; ++jj)
+      for (int a = 0; a < m; ++a) G[(size_t)a * maxm + m0 + jj] = H[(size_t)jj * m + a];
+    dots_rows_multi(c, W, m, V + (int64_t)m0 * n, r, n, packed, workm, H);
+    for (int jj = 0; jj < r; ++jj)
+      for (int a = 0; a < m; ++a) G[(size_t)(m0 + jj) * maxm + a] = H[(size_t)jj * m + a];
+    dots_rows_multi(c, V + (int64_t)m0 * n, r, B, k, n, packed, workm, H);
+    for (int q = 0; q < k; ++q)
+      for (int jj = 0; jj < r; ++jj) bvm[(size_t)q * maxm + m0 + jj] = H[(size_t)q * r + jj];
+  };
+  // appends the nv vectors of Cb to the basis (block Gram-Schmidt against V,
+  // then one by one among themselves); returns how many were kept
+  auto append = [&](int nv) {
+    if (packed)
+      for (int a = 0; a < nv; ++a)
+        kc(apply_metric(c.s, Cb + (int64_t)a * n, Cb + (int64_t)a * n, c.o, c.v, 2), "symmetrise");
+    std::vector<double> n0(nv);
+    for (int a = 0; a < nv; ++a) n0[a] = std::sqrt(std::max(0.0, dotf(Cb + (int64_t)a * n, Cb + (int64_t)a * n)));
+    const int m0 = m;
+    for (int pass = 0; pass < 2 && m0 > 0; ++pass) {
+      dots_rows_multi(c, V, m0, Cb, nv, n, packed, workm, H);
+      sub_rows_multi(c, V, m0, H, Cb, nv, n, hdm);
+      bool again = false;
+      for (int a = 0; a < nv; ++a) {
+        double p2 = 0.0;
+        for (int q = 0; q < m0; ++q) p2 += H[(size_t)a * m0 + q] * H[(size_t)a * m0 + q];
+        if (p2 > 0.5 * n0[a] * n0[a]) again = true;
+      }
+      if (!again) break;
+    }
+    std::vector<double> h;
+    for (int a = 0; a < nv && m < maxm; ++a) {
+      double* x = Cb + (int64_t)a * n;
+      for (int pass = 0; pass < 2 && m > m0; ++pass) {
+        dots_rows(c, V + (int64_t)m0 * n, m - m0, x, n, packed, workm, h);
+        sub_rows(c, V + (int64_t)m0 * n, m - m0, h, x, n, hdm);
+      }
+      const double n1 = std::sqrt(std::max(0.0, dotf(x, x)));
+      if (!(n0[a] > 0) || n1 < 1e-12 * n0[a] || n1 < 1e-300) continue;
+      axpby_(c, V + (int64_t)m * n, x, 1.0 / n1, 0.0, n);
+      ++m;
+    }
+    return m - m0;
+  };
   int status = CC_NOT_CONVERGED;
   int it = 0;
-  const double bn = std::sqrt(std::max(dotf(b, b), 1e-300));
-  const double goal = tol * std::max(1.0, bn);
-  double best = 1e300;
-  int stall = 0;
-  bool refreshed = false;
-  for (it = 1; it <= maxit && m < maxm; ++it) {
-    if (packed) kc(apply_metric(c.s, r, r, c.o, c.v, 2), "symmetrise");
-    const double n0 = std::sqrt(std::max(0.0, dotf(r, r)));
-    // Gram-Schmidt against the orthonormal basis; a second pass only when the
-    // first removed more than half of the squared norm
-    for (int pass = 0; pass < 2 && m > 0; ++pass) {
-      dots_rows(c, V, m, r, n, packed, work, h);
-      sub_rows(c, V, m, h, r, n, hd);
-      double p2 = 0.0;
-      for (int k = 0; k < m; ++k) p2 += h[k] * h[k];
-      if (p2 <= 0.5 * n0 * n0) break;
+  for (it = 1; it <= maxit; ++it) {
+    std::vector<int> act;
+    for (int r = 0; r < k; ++r)
+      if (!conv[r]) act.push_back(r);
+    if (act.empty()) { status = CC_OK; break; }
+    const int na = (int)act.size();
+    // restart from the current solutions when the new vectors do not fit
+    if (m + na > maxm) {
+      m = 0;
+      std::fill(G.begin(), G.end(), 0.0);
+      for (int a = 0; a < na; ++a) copy_d(c, Cb + (int64_t)a * n, X + (int64_t)act[a] * n, n);
+      const int kept = append(na);
+      extend(0);
+      (void)kept;
     }
-    const double n1 = std::sqrt(std::max(0.0, dotf(r, r)));
-    if (!(n1 > 1e-14 * std::max(n0, 1e-300))) break;
-    axpby_(c, V + (int64_t)m * n, r, 1.0 / n1, 0.0, n);
-    T(V + (int64_t)m * n, W + (int64_t)m * n);
-    ++m;
-    dots_rows(c, V, m, W + (int64_t)(m - 1) * n, n, packed, work, h);
-    for (int k = 0; k < m; ++k) G[(size_t)k * maxm + m - 1] = h[k];
-    dots_rows(c, W, m, V + (int64_t)(m - 1) * n, n, packed, work, h);
-    for (int k = 0; k < m; ++k) G[(size_t)(m - 1) * maxm + k] = h[k];
-    bv[m - 1] = dotf(V + (int64_t)(m - 1) * n, b);
+    // next basis vectors: preconditioned residuals of the open systems
+    for (int a = 0; a < na; ++a) precond(Cb + (int64_t)a * n, Rr + (int64_t)act[a] * n);
+    const int m0 = m;
+    if (append(na) == 0) break;   // no new direction: stagnated
+    extend(m0);
     for (int pass = 0;; ++pass) {
-      std::vector<double> Gm((size_t)m * m);
-      cvec.assign(bv.begin(), bv.begin() + m);
+      // Galerkin solutions of the open systems
+      std::vector<double> Gm((size_t)m * m), Y((size_t)m * na);
       for (int a = 0; a < m; ++a)
-        for (int bb = 0; bb < m; ++bb) Gm[(size_t)a * m + bb] = G[(size_t)a * maxm + bb];
-      if (!lu_solve(Gm, cvec, m, 1)) throw Error(-5, "singular projected linear system");
-      hip_check(hipMemcpyAsync(y, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-      kc(rows_axpy_multi(c.s, V, m, n, y, 1.0, x, n, 1, true), "combine");
-      kc(rows_axpy_multi(c.s, W, m, n, y, 1.0, r, n, 1, true), "combine");
-      axpby_(c, r, b, -1.0, 1.0, n);    // r = T x - b
-      const double rn = std::sqrt(std::max(0.0, dotf(r, r)));
-      if (!std::isfinite(rn)) throw Error(-5, "non-finite linear-solver residual");
-      if (verbose()) std::fprintf(stderr, "[linsolve] it %d m %d |r| %.3e\n", it, m, rn);
-      if (mixed_images) {
-        if (rn < 0.7 * best) { best = rn; stall = 0; } else { ++stall; }
+        for (int b = 0; b < m; ++b) Gm[(size_t)a * m + b] = G[(size_t)a * maxm + b];
+      for (int q = 0; q < na; ++q)
+        for (int a = 0; a < m; ++a) Y[(size_t)a * na + q] = bvm[(size_t)act[q] * maxm + a];
+      if (!lu_solve(Gm, Y, m, na)) throw Error(-5, "singular projected linear system");
+      std::vector<double> Yr((size_t)na * m);   // row q = coefficients of system act[q]
+      for (int q = 0; q < na; ++q)
+        for (int a = 0; a < m; ++a) Yr[(size_t)q * m + a] = Y[(size_t)a * na + q];
+      hip_check(hipMemcpyAsync(ydev, Yr.data(), Yr.size() * sizeof(double), hipMemcpyHostToDevice, c.s),
+                "H2D");
+      double worst = 0.0;
+      for (int q = 0; q < na; ++q) {
+        const int r = act[q];
+        kc(rows_axpy_multi(c.s, V, m, n, ydev + (int64_t)q * m, 1.0, X + (int64_t)r * n, n, 1, true), "combine");
+        kc(rows_axpy_multi(c.s, W, m, n, ydev + (int64_t)q * m, 1.0, Rr + (int64_t)r * n, n, 1, true), "combine");
+        axpby_(c, Rr + (int64_t)r * n, B + (int64_t)r * n, -1.0, 1.0, n);
+        rn[r] = std::sqrt(std::max(0.0, dotf(Rr + (int64_t)r * n, Rr + (int64_t)r * n)));
+        if (!std::isfinite(rn[r])) throw Error(-5, "non-finite linear-solver residual");
+        worst = std::max(worst, rn[r] / goal[r]);
       }
-      if (!mixed_images || pass >= 2 ||
-          !(rn < goal || stall >= 3 || (!refreshed && rn < eig_switch(c) * bn))) {
-        if (rn < goal) status = CC_OK;
+      if (verbose()) {
+        std::fprintf(stderr, "[linsolve] it %d m %d", it, m);
+        for (int q = 0; q < na; ++q) std::fprintf(stderr, " |r%d| %.3e", act[q], rn[act[q]]);
+        std::fprintf(stderr, "\n");
+      }
+      if (!mixed_images) {
+        for (int q = 0; q < na; ++q)
+          if (rn[act[q]] < goal[act[q]]) { conv[act[q]] = 1; it_of[act[q]] = it; }
         break;
       }
-      // fp64 image of x: true residual, then the rank-1 image correction
+      // mixed: residuals from the low-precision images never end a solve by
+      // themselves; they decide when the solutions get fp64 images
+      bool want = false;
+      for (int q = 0; q < na; ++q) {
+        const int r = act[q];
+        if (rn[r] < 0.7 * best[r]) { best[r] = rn[r]; stall[r] = 0; } else { ++stall[r]; }
+        if (rn[r] < goal[r] || stall[r] >= 3 || (!refreshed[r] && rn[r] < eig_switch(c) * bn[r]))
+          want = true;
+      }
+      if (!want) break;
+      // fp64 images of the open solutions, true residuals, rank-na correction
+      for (int q = 0; q < na; ++q) copy_d(c, workm + (int64_t)q * n, X + (int64_t)act[q] * n, n);
       c.eng->set_lowp(false);
-      T(x, ax);
+      T(workm, Cb, na);
       c.eng->set_lowp(true);
-      refreshed = true;
-      best = 1e300;
-      stall = 0;
-      axpby_(c, ax, b, -1.0, 1.0, n);      // true residual T64 x - b
-      const double rt = std::sqrt(std::max(0.0, dotf(ax, ax)));
-      if (verbose()) std::fprintf(stderr, "[linsolve] it %d fp64 image, true |r| %.3e\n", it, rt);
-      if (!std::isfinite(rt)) throw Error(-5, "non-finite linear-solver residual");
-      axpby_(c, ax, r, -1.0, 1.0, n);      // D = (T64 x - b) - (W^T y - b)
-      double yy = 0.0;
-      for (int k = 0; k < m; ++k) yy += cvec[k] * cvec[k];
-      if (yy > 0.0) {                      // (x = 0 has an exact image already)
-        std::vector<double> z(m);
-        for (int k = 0; k < m; ++k) z[k] = cvec[k] / yy;
-        hip_check(hipMemcpyAsync(y, z.data(), m * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
-        kc(gemm_f64(c.s, false, false, m, (int)n, 1, 1, 1.0, y, 1, 0, ax, n, 0, 1.0, W, n, 0), "image update");
-        dots_rows(c, V, m, ax, n, packed, work, h);
-        for (int a = 0; a < m; ++a)
-          for (int bb = 0; bb < m; ++bb) G[(size_t)a * maxm + bb] += h[a] * z[bb];
+      std::vector<double> rt(na);
+      for (int q = 0; q < na; ++q) {
+        const int r = act[q];
+        double* d = Cb + (int64_t)q * n;
+        refreshed[r] = 1;
+        best[r] = 1e300;
+        stall[r] = 0;
+        axpby_(c, d, B + (int64_t)r * n, -1.0, 1.0, n);            // true residual
+        rt[q] = std::sqrt(std::max(0.0, dotf(d, d)));
+        if (!std::isfinite(rt[q])) throw Error(-5, "non-finite linear-solver residual");
+        axpby_(c, d, Rr + (int64_t)r * n, -1.0, 1.0, n);           // D = true - computed
+        if (verbose()) std::fprintf(stderr, "[linsolve] it %d fp64 image of %d, true |r| %.3e\n", it, r, rt[q]);
       }
-      if (rt < goal) {
-        axpby_(c, r, ax, 1.0, 1.0, n);     // r = true residual (x unchanged)
-        status = CC_OK;
+      // Z = (Y Y^T)^-1 Y over the open systems (solutions x = 0 have exact
+      // images already and are left out)
+      std::vector<int> nz;
+      for (int q = 0; q < na; ++q) {
+        double yy = 0.0;
+        for (int a = 0; a < m; ++a) yy += Yr[(size_t)q * m + a] * Yr[(size_t)q * m + a];
+        if (yy > 0.0) nz.push_back(q);
+      }
+      if (!nz.empty()) {
+        const int kz = (int)nz.size();
+        std::vector<double> S((size_t)kz * kz, 0.0), Z((size_t)kz * m);
+        for (int a = 0; a < kz; ++a)
+          for (int b = 0; b < kz; ++b)
+            for (int i = 0; i < m; ++i)
+              S[(size_t)a * kz + b] += Yr[(size_t)nz[a] * m + i] * Yr[(size_t)nz[b] * m + i];
+        for (int a = 0; a < kz; ++a)
+          for (int i = 0; i < m; ++i) Z[(size_t)a * m + i] = Yr[(size_t)nz[a] * m + i];
+        if (!lu_solve(S, Z, kz, m)) throw Error(-5, "dependent linear-solver solutions");
+        // D rows of the systems in nz, contiguous
+        const double* Dz = Cb;
+        if (kz != na) {
+          for (int a = 0; a < kz; ++a) copy_d(c, workm + (int64_t)a * n, Cb + (int64_t)nz[a] * n, n);
+          Dz = workm;
+        }
+        hip_check(hipMemcpyAsync(zdev, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice, c.s),
+                  "H2D");
+        kc(gemm_f64(c.s, true, false, m, (int)n, kz, 1, 1.0, zdev, m, 0, Dz, n, 0, 1.0, W, n, 0),
+           "image update");
+        dots_rows_multi(c, V, m, Dz, kz, n, packed, Db, H);
+        for (int a = 0; a < m; ++a)
+          for (int b = 0; b < m; ++b) {
+            double acc = 0.0;
+            for (int q = 0; q < kz; ++q) acc += H[(size_t)q * m + a] * Z[(size_t)q * m + b];
+            G[(size_t)a * maxm + b] += acc;
+          }
+      }
+      bool all = true;
+      for (int q = 0; q < na; ++q) {
+        const int r = act[q];
+        if (rt[q] < goal[r]) {
+          axpby_(c, Rr + (int64_t)r * n, Cb + (int64_t)q * n, 1.0, 1.0, n);   // true residual
+          conv[r] = 1;
+          it_of[r] = it;
+        } else {
+          all = false;
+        }
+      }
+      if (all) break;
+      if (pass >= 2) {
+        // after three corrected solves in a row the next basis vectors come
+        // from the true residuals
+        for (int q = 0; q < na; ++q)
+          if (!conv[act[q]]) axpby_(c, Rr + (int64_t)act[q] * n, Cb + (int64_t)q * n, 1.0, 1.0, n);
         break;
       }
-      // solve again with the corrected images (the true residual next)
+      // solve again with the corrected images: the converged systems drop out
+      std::vector<int> still;
+      for (int q = 0; q < na; ++q)
+        if (!conv[act[q]]) still.push_back(act[q]);
+      // (the remaining pass works on the systems still open)
+      if (still.size() != act.size()) break;
     }
-    if (status == CC_OK) break;
-    precond(r, r);
   }
+  bool all = true;
+  for (int r = 0; r < k; ++r) {
+    if (!conv[r]) all = false;
+    if (iters) iters[r] = conv[r] ? std::max(it_of[r], 1) : std::min(it, maxit);
+  }
+  if (all) status = CC_OK;
   c.eng->set_lowp(false);
   c.eng->set_bf16(false);
-  if (iters) *iters = it;
   return status;
 }
 
+// Single right-hand side.
+static int linsolve(Ctx& c, int64_t n, bool packed, const std::function<void(const double*, double*)>& T,
+                    const std::function<void(double*, const double*)>& precond, const double* b,
+                    double* x, double tol, int maxit, int* iters, bool mixed_images = false) {
+  auto Tb = [&](const double* X, double* Y, int kk) {
+    for (int z = 0; z < kk; ++z) T(X + (int64_t)z * n, Y + (int64_t)z * n);
+  };
+  return linsolve_block(c, n, packed, 1, Tb, precond, b, x, tol, maxit, iters, mixed_images);
+}
+
 // T(x) = b in the context's precision: plain fp64 linsolve, or with
-// fp32-operand images and fp64 image corrections (mixed precision).
+// low-precision images and fp64 image corrections (mixed precision).
 static int linsolve_refined(Ctx& c, int64_t n, bool packed,
                             const std::function<void(const double*, double*)>& T,
                             const std::function<void(double*, const double*)>& precond,
@@ -1354,7 +1513,7 @@ __global__ void ehf_terms_kernel(double* Fbar, double* Gbar, int64_t n, int o) {
   if (j == 0) Fbar[i * n + i] += 2.0;
 }
 
-// Multipliers of one Lagrangian, selected by the pair (i1, j1):
+// Multipliers of one Lagrangian per pair (i1, j1):
 //  * i1 != j1 >= 1: coupling F_ij, Phi = zeta.Omega + gamma.(A R_j), overlap
 //    of <L_i| with the right state j (Sec. II B);
 //  * j1 = 0 < i1: coupling F_i0 with the CC ground state exp(T)|HF> (R0 = 1,
@@ -1363,23 +1522,46 @@ __global__ void ehf_terms_kernel(double* Fbar, double* Gbar, int64_t n, int o) {
 //  * i1 = j1: gradient of the state energy E_j = E0 + L_j.(A R_j) (E0 alone
 //    for j1 = 0): Phi = E0 + zeta.Omega + L_j.(A R_j), no overlap term, so
 //    eta_t = dE0/dt + F(L_j) R_j and eta_kappa = d Phi / d kappa.
-static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
-  const bool grad_mode = (i1 == j1);
-  const bool has_right = (j1 > 0);
-  const int i = i1 - 1, j = j1 - 1;
+// All pairs share one recording of the residual graph and one forward
+// derivative along each right state R_j they use; their zeta equations
+// A^T zeta = -eta_t (eq. amplituderelax) are solved together, in blocks of up
+// to kMaxBlockRhs right-hand sides that go through each left transform as one
+// batch.  iters: [npairs][2] (zeta, kappa-bar iterations).
+struct PairJob {
+  int i1, j1;
+  bool grad_mode, has_right;
+  int i, j;
+  double wi, R0j;
+  PairData* P;
+  double* wg = nullptr;   // metric-weighted gamma (arena)
+};
+
+static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, int* iters) {
   const int64_t N = c.N, nov = (int64_t)c.o * c.v, nn = (int64_t)c.n * c.n;
-  PairData& P = pair_of(c, i1, j1);
-  const double wi = (i1 > 0) ? c.omega_r[i] : 0.0;
-  const double R0j = has_right ? c.R0[j] : 1.0;
-  if (grad_mode && has_right)
-    copy_d(c, P.gamma, c.L[j], N);
-  else if (!has_right)
-    kc(fill(c.s, P.gamma, 0.0, N), "fill");
-  else
-    axpby_(c, P.gamma, c.L[i], 1.0 / (c.omega_r[j] - wi), 0.0, N);
+  const int np = (int)pl.size();
+  std::vector<PairJob> jobs(np);
+  for (int p = 0; p < np; ++p) {
+    PairJob& J = jobs[p];
+    J.i1 = pl[p].first;
+    J.j1 = pl[p].second;
+    J.grad_mode = (J.i1 == J.j1);
+    J.has_right = (J.j1 > 0);
+    J.i = J.i1 - 1;
+    J.j = J.j1 - 1;
+    J.P = &pair_of(c, J.i1, J.j1);
+    J.wi = (J.i1 > 0) ? c.omega_r[J.i] : 0.0;
+    J.R0j = J.has_right ? c.R0[J.j] : 1.0;
+    PairData& P = *J.P;
+    if (J.grad_mode && J.has_right)
+      copy_d(c, P.gamma, c.L[J.j], N);
+    else if (!J.has_right)
+      kc(fill(c.s, P.gamma, 0.0, N), "fill");
+    else
+      axpby_(c, P.gamma, c.L[J.i], 1.0 / (c.omega_r[J.j] - J.wi), 0.0, N);
+  }
   Arena& ar = c.eng->arena();
   int status = CC_OK;
-  int it_z = 0, it_k = 0;
+  std::vector<int> it_z(np, 0), it_k(np, 0);
   // verbose: device time per phase
   double t_ph[6] = {0, 0, 0, 0, 0, 0};
   auto t_last = std::chrono::steady_clock::now();
@@ -1392,95 +1574,117 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
   };
   {
     Tape tp(c);
-    // JVP along R_j, kept on the tape
-    int ar1 = -1, ar2 = -1;
-    if (has_right) {
-      const int r1 = tp.G.leaf(T1of(c, c.R[j])), r2 = tp.G.leaf(T2of(c, c.R[j]));
+    // JVP along each right state used, kept on the tape
+    std::map<int, std::pair<int, int>> tanj;
+    for (const PairJob& J : jobs) {
+      if (!J.has_right || tanj.count(J.j)) continue;
+      const int r1 = tp.G.leaf(T1of(c, c.R[J.j])), r2 = tp.G.leaf(T2of(c, c.R[J.j]));
       auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
-      ar1 = tan.at(tp.r.om1);
-      ar2 = tan.at(tp.r.om2);
+      tanj[J.j] = {tan.at(tp.r.om1), tan.at(tp.r.om2)};
     }
     phase(0);
     ArenaScope sc(ar);
-    double* wg = ar.alloc(N);     // metric-weighted gamma
-    kc(apply_metric(c.s, wg, P.gamma, c.o, c.v, 0), "metric");
     double* tmp = ar.alloc(N);
-    // F-matrix term: d/dt [gamma . A(t) R_j]
-    if (has_right) {
-      ArenaScope s2(ar);
-      auto adj = tp.G.vjp({{ar1, wg}, {ar2, wg + nov}}, {tp.r.t1, tp.r.t2});
-      copy_d(c, tmp, adj[tp.r.t1].p, nov);
-      copy_d(c, tmp + nov, adj[tp.r.t2].p, N - nov);
-      kc(apply_metric(c.s, P.eta_t, tmp, c.o, c.v, 1), "metric");
-    } else {
-      kc(fill(c.s, P.eta_t, 0.0, N), "fill");
-    }
-    if (grad_mode) {
-      // dE0/dt (packed-gradient convention), added to eta_t
-      ArenaScope s2(ar);
-      Graph Ge(*c.eng);
-      EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
-      double* one = c.eng->scalar_slot(62);
-      kc(fill(c.s, one, 1.0, 1), "fill");
-      auto adj = Ge.vjp({{en.e, one}}, {en.t1, en.t2});
-      copy_d(c, tmp, adj[en.t1].p, nov);
-      copy_d(c, tmp + nov, adj[en.t2].p, N - nov);
-      double* et = ar.alloc(N);
-      kc(apply_metric(c.s, et, tmp, c.o, c.v, 1), "metric");
-      axpby_(c, P.eta_t, et, 1.0, 1.0, N);
-      kc(fill(c.s, P.dtrans, 0.0, nn), "fill");
-    } else {
-      // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
-      ArenaScope s2(ar);
-      Graph Gs(*c.eng);
-      const double* sv = nullptr;
-      if (has_right) {
-        const int l2 = Gs.leaf(T2of(c, c.L[i])), rr1 = Gs.leaf(T1of(c, c.R[j]));
-        const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
-                                            mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
-        sv = Gs.val(sn).p;
+    for (PairJob& J : jobs) {
+      PairData& P = *J.P;
+      J.wg = ar.alloc(N);
+      kc(apply_metric(c.s, J.wg, P.gamma, c.o, c.v, 0), "metric");
+      // F-matrix term: d/dt [gamma . A(t) R_j]
+      if (J.has_right) {
+        ArenaScope s2(ar);
+        const auto& tj = tanj.at(J.j);
+        auto adj = tp.G.vjp({{tj.first, J.wg}, {tj.second, J.wg + nov}}, {tp.r.t1, tp.r.t2});
+        copy_d(c, tmp, adj[tp.r.t1].p, nov);
+        copy_d(c, tmp + nov, adj[tp.r.t2].p, N - nov);
+        kc(apply_metric(c.s, P.eta_t, tmp, c.o, c.v, 1), "metric");
+      } else {
+        kc(fill(c.s, P.eta_t, 0.0, N), "fill");
       }
-      axpby_(c, P.eta_t, c.L[i], R0j, 1.0, N);
-      if (sv) axpby_(c, P.eta_t, sv, 1.0, 1.0, nov);
-      // transition density D_pq = <L_i| E_pq |R_j>: seeds L_i on A R_j,
-      // R0_j L_i + s on Omega (singles), wrt f
-      double* wl = ar.alloc(N);
-      kc(apply_metric(c.s, wl, c.L[i], c.o, c.v, 0), "metric");
-      double* sp = ar.alloc(N);
-      axpby_(c, sp, wl, R0j, 0.0, N);
-      if (sv) axpby_(c, sp, sv, 1.0, 1.0, nov);
-      std::map<int, const double*> seeds{{tp.r.om1, sp}, {tp.r.om2, sp + nov}};
-      if (has_right) {
-        seeds[ar1] = wl;
-        seeds[ar2] = wl + nov;
+      if (J.grad_mode) {
+        // dE0/dt (packed-gradient convention), added to eta_t
+        ArenaScope s2(ar);
+        Graph Ge(*c.eng);
+        EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
+        double* one = c.eng->scalar_slot(62);
+        kc(fill(c.s, one, 1.0, 1), "fill");
+        auto adj = Ge.vjp({{en.e, one}}, {en.t1, en.t2});
+        copy_d(c, tmp, adj[en.t1].p, nov);
+        copy_d(c, tmp + nov, adj[en.t2].p, N - nov);
+        double* et = ar.alloc(N);
+        kc(apply_metric(c.s, et, tmp, c.o, c.v, 1), "metric");
+        axpby_(c, P.eta_t, et, 1.0, 1.0, N);
+        kc(fill(c.s, P.dtrans, 0.0, nn), "fill");
+      } else {
+        // overlap term: R0_j L_i + singles s_ia = sum_jb L2_ijab R1_jb + L2_iiaa R1_ia
+        ArenaScope s2(ar);
+        Graph Gs(*c.eng);
+        const double* sv = nullptr;
+        if (J.has_right) {
+          const int l2 = Gs.leaf(T2of(c, c.L[J.i])), rr1 = Gs.leaf(T1of(c, c.R[J.j]));
+          const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
+                                              mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
+          sv = Gs.val(sn).p;
+        }
+        axpby_(c, P.eta_t, c.L[J.i], J.R0j, 1.0, N);
+        if (sv) axpby_(c, P.eta_t, sv, 1.0, 1.0, nov);
+        // transition density D_pq = <L_i| E_pq |R_j>: seeds L_i on A R_j,
+        // R0_j L_i + s on Omega (singles), wrt f
+        double* wl = ar.alloc(N);
+        kc(apply_metric(c.s, wl, c.L[J.i], c.o, c.v, 0), "metric");
+        double* sp = ar.alloc(N);
+        axpby_(c, sp, wl, J.R0j, 0.0, N);
+        if (sv) axpby_(c, sp, sv, 1.0, 1.0, nov);
+        std::map<int, const double*> seeds{{tp.r.om1, sp}, {tp.r.om2, sp + nov}};
+        if (J.has_right) {
+          const auto& tj = tanj.at(J.j);
+          seeds[tj.first] = wl;
+          seeds[tj.second] = wl + nov;
+        }
+        auto adj = tp.G.vjp(seeds, {tp.r.f});
+        copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
       }
-      auto adj = tp.G.vjp(seeds, {tp.r.f});
-      copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
     }
-    // zeta: A^T zeta = -eta_t
+    // zeta: A^T zeta = -eta_t, closed form for (i, 0), the rest in blocks
     phase(1);
-    if (!grad_mode && !has_right) {
-      axpby_(c, P.zeta, c.L[i], -1.0 / wi, 0.0, N);
-    } else {
-      double* b = ar.alloc(N);
-      axpby_(c, b, P.eta_t, -1.0, 0.0, N);
-      auto T = [&](const double* x, double* y) { tp.left(x, y); };
+    std::vector<int> solve;
+    for (int p = 0; p < np; ++p) {
+      const PairJob& J = jobs[p];
+      if (!J.grad_mode && !J.has_right)
+        axpby_(c, J.P->zeta, c.L[J.i], -1.0 / J.wi, 0.0, N);
+      else
+        solve.push_back(p);
+    }
+    for (size_t b0 = 0; b0 < solve.size(); b0 += kMaxBlockRhs) {
+      const int kb = (int)std::min<size_t>(kMaxBlockRhs, solve.size() - b0);
+      ArenaScope s2(ar);
+      double* Bm = ar.alloc((int64_t)kb * N);
+      double* Xm = ar.alloc((int64_t)kb * N);
+      for (int q = 0; q < kb; ++q) axpby_(c, Bm + (int64_t)q * N, jobs[solve[b0 + q]].P->eta_t, -1.0, 0.0, N);
+      auto T = [&](const double* x, double* y, int kk) { tp.left_block(x, y, kk); };
       auto pre = [&](double* y, const double* x) {
         kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
       };
-      const int st = linsolve_refined(c, N, true, T, pre, b, P.zeta, c.opts.tol_mult, c.opts.maxit, &it_z);
+      std::vector<int> its(kb, 0);
+      const int st = linsolve_block(c, N, true, kb, T, pre, Bm, Xm, c.opts.tol_mult, c.opts.maxit,
+                                    its.data(), mixed(c));
       if (st != CC_OK) status = st;
+      for (int q = 0; q < kb; ++q) {
+        copy_d(c, jobs[solve[b0 + q]].P->zeta, Xm + (int64_t)q * N, N);
+        it_z[solve[b0 + q]] = its[q];
+      }
     }
     // d Phi / d(f, g) with Phi = zeta.Omega + gamma.(A R_j) (+ E0)
     phase(2);
-    {
+    for (PairJob& J : jobs) {
+      PairData& P = *J.P;
+      ArenaScope s2(ar);
       double* wz = ar.alloc(N);
       kc(apply_metric(c.s, wz, P.zeta, c.o, c.v, 0), "metric");
-      ArenaScope s2(ar);
       std::map<int, const double*> seeds{{tp.r.om1, wz}, {tp.r.om2, wz + nov}};
-      if (has_right) {
-        seeds[ar1] = wg;
-        seeds[ar2] = wg + nov;
+      if (J.has_right) {
+        const auto& tj = tanj.at(J.j);
+        seeds[tj.first] = J.wg;
+        seeds[tj.second] = J.wg + nov;
       }
       auto adj = tp.G.vjp(seeds, {tp.r.f, tp.r.g, tp.r.w, tp.r.wov, tp.r.gc, tp.r.gvc});
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
@@ -1495,51 +1699,39 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       const Range Al{0, c.n};
       c.eng->linear(1.0, full_view(adj[tp.r.gc], "cprs"), Gd.view(op(gb, "pcrs", {Al, V, Al, Al})));
       c.eng->linear(1.0, full_view(adj[tp.r.gvc], "cpbr"), Gd.view(op(gb, "pbrc", {Al, V, Al, V})));
-    }
-    if (grad_mode) {
-      // + dE0/d(f, g): correlation energy by the energy graph, E_HF by hand
-      ArenaScope s2(ar);
-      Graph Ge(*c.eng);
-      EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
-      double* one = c.eng->scalar_slot(62);
-      kc(fill(c.s, one, 1.0, 1), "fill");
-      auto adj = Ge.vjp({{en.e, one}}, {en.f, en.g});
-      axpby_(c, P.Fbar, adj[en.f].p, 1.0, 1.0, nn);
-      axpby_(c, P.Gbar, adj[en.g].p, 1.0, 1.0, n4(c));
-      const int64_t oo = (int64_t)c.o * c.o;
-      hipLaunchKernelGGL(ehf_terms_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
-                         P.Fbar, P.Gbar, (int64_t)c.n, c.o);
-      hip_check(hipGetLastError(), "HF energy terms");
+      if (J.grad_mode) {
+        // + dE0/d(f, g): correlation energy by the energy graph, E_HF by hand
+        Graph Ge(*c.eng);
+        EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
+        double* one = c.eng->scalar_slot(62);
+        kc(fill(c.s, one, 1.0, 1), "fill");
+        auto adje = Ge.vjp({{en.e, one}}, {en.f, en.g});
+        axpby_(c, P.Fbar, adje[en.f].p, 1.0, 1.0, nn);
+        axpby_(c, P.Gbar, adje[en.g].p, 1.0, 1.0, n4(c));
+        const int64_t oo = (int64_t)c.o * c.o;
+        hipLaunchKernelGGL(ehf_terms_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
+                           P.Fbar, P.Gbar, (int64_t)c.n, c.o);
+        hip_check(hipGetLastError(), "HF energy terms");
+      }
     }
   }
   phase(3);
-  if (c.opts.relaxed) {
+  if (!c.opts.relaxed) {
+    for (PairJob& J : jobs) {
+      kc(fill(c.s, J.P->kbar, 0.0, nov), "fill");
+      kc(fill(c.s, J.P->eta_k, 0.0, nov), "fill");
+    }
+  } else {
     ArenaScope sc(ar);
-    Graph G(*c.eng);
     double* k0 = ar.alloc(nov);
     kc(fill(c.s, k0, 0.0, nov), "fill");
+    Graph G(*c.eng);
     RotNodes rn = rotation_graph(G, c, tview(k0, {c.o, c.v}));
-    // eta_kappa = -(D_ai - D_ia) + d/dkappa Phi
-    {
-      ArenaScope s2(ar);
-      auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.gr, P.Gbar}}, {rn.kap});
-      copy_d(c, P.eta_k, adj[rn.kap].p, nov);
-    }
-    if (!grad_mode) {
-      ArenaScope s2(ar);
-      Graph Gd(*c.eng);
-      const int d = Gd.leaf(tview(P.dtrans, {c.n, c.n}));
-      const Range O{0, c.o}, V{c.o, c.v};
-      const int e1 = Gd.node({c.o, c.v}, {lin(-1, op(d, "ai", {V, O}), "ia"), lin(1, op(d, "ia", {O, V}), "ia")});
-      axpby_(c, P.eta_k, Gd.val(e1).p, 1.0, 1.0, nov);
-    }
-    phase(4);
-    // (A^HF)^T kappa_bar = -eta_kappa, A^HF_(ai),(bj) = dF_ai/dkappa_bj
-    double* b = ar.alloc(nov);
-    axpby_(c, b, P.eta_k, -1.0, 0.0, nov);
-    double* seed = ar.alloc(nn);
     Graph Gf(*c.eng);
     RotNodes fn = fock_rotation_graph(Gf, c, tview(k0, {c.o, c.v}));
+    double* b = ar.alloc(nov);
+    double* seed = ar.alloc(nn);
+    // (A^HF)^T x, A^HF_(ai),(bj) = dF_ai/dkappa_bj
     auto T = [&](const double* x, double* y) {
       ArenaScope s2(ar);
       kc(fill(c.s, seed, 0.0, nn), "fill");
@@ -1562,23 +1754,45 @@ static int multipliers_impl(Ctx& c, int i1, int j1, int* iters) {
       kc(apply_denominator(c.s, big, big, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
       copy_d(c, y, big, nov);
     };
-    const int st = linsolve_refined(c, nov, false, T, pre1, b, P.kbar, c.opts.tol_mult, c.opts.maxit, &it_k);
-    if (st != CC_OK) status = st;
-  } else {
-    kc(fill(c.s, P.kbar, 0.0, nov), "fill");
-    kc(fill(c.s, P.eta_k, 0.0, nov), "fill");
+    for (int p = 0; p < np; ++p) {
+      const PairJob& J = jobs[p];
+      PairData& P = *J.P;
+      // eta_kappa = -(D_ai - D_ia) + d/dkappa Phi
+      {
+        ArenaScope s2(ar);
+        auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.gr, P.Gbar}}, {rn.kap});
+        copy_d(c, P.eta_k, adj[rn.kap].p, nov);
+      }
+      if (!J.grad_mode) {
+        ArenaScope s2(ar);
+        Graph Gd(*c.eng);
+        const int d = Gd.leaf(tview(P.dtrans, {c.n, c.n}));
+        const Range O{0, c.o}, V{c.o, c.v};
+        const int e1 = Gd.node({c.o, c.v}, {lin(-1, op(d, "ai", {V, O}), "ia"), lin(1, op(d, "ia", {O, V}), "ia")});
+        axpby_(c, P.eta_k, Gd.val(e1).p, 1.0, 1.0, nov);
+      }
+      phase(4);
+      // (A^HF)^T kappa_bar = -eta_kappa (eq. orbitalrelax)
+      axpby_(c, b, P.eta_k, -1.0, 0.0, nov);
+      const int st = linsolve_refined(c, nov, false, T, pre1, b, P.kbar, c.opts.tol_mult, c.opts.maxit,
+                                      &it_k[p]);
+      if (st != CC_OK) status = st;
+      phase(5);
+    }
   }
-  phase(5);
   if (verbose())
     std::fprintf(stderr,
-                 "[multipliers] (%d,%d) tape+jvp %.3f rhs %.3f zeta %.3f dens-adjoint %.3f eta-kappa %.3f "
-                 "kappa %.3f s\n", i1, j1, t_ph[0], t_ph[1], t_ph[2], t_ph[3], t_ph[4], t_ph[5]);
-  P.have_mult = true;
-  P.have_dens = false;
-  if (iters) {
-    iters[0] = it_z;
-    iters[1] = it_k;
+                 "[multipliers] %d pairs: tape+jvp %.3f rhs %.3f zeta %.3f dens-adjoint %.3f eta-kappa %.3f "
+                 "kappa %.3f s\n", np, t_ph[0], t_ph[1], t_ph[2], t_ph[3], t_ph[4], t_ph[5]);
+  for (PairJob& J : jobs) {
+    J.P->have_mult = true;
+    J.P->have_dens = false;
   }
+  if (iters)
+    for (int p = 0; p < np; ++p) {
+      iters[2 * p] = it_z[p];
+      iters[2 * p + 1] = it_k[p];
+    }
   sync(c);
   return status;
 }
@@ -1893,18 +2107,35 @@ int eom_solve(cc_ctx* c, int side, int nroots, double* omega, int* iters) {
   }
 }
 
-int multipliers(cc_ctx* c, int i, int j, int* iters) {
+int multipliers(cc_ctx* c, int npairs, const int* pairs, int* iters) {
   ABI_GUARD(c);
-  if (c->stage < 1 || (!c->gauged && !(i == 0 && j == 0))) {
-    c->err = "multipliers before the ground state (pair (0, 0)) or the right and left EOM states";
-    return CC_ERR_STATE;
-  }
-  if (i < 0 || j < 0 || i > c->nroots || j > c->nroots || (i == 0 && j != 0)) {
-    c->err = "pair indices must satisfy 0 <= i, j <= nroots with i >= 1 unless i = j = 0";
+  if (npairs < 1 || !pairs) {
+    c->err = "multipliers needs at least one pair";
     return CC_ERR_ARG;
   }
+  for (int p = 0; p < npairs; ++p) {
+    const int i = pairs[2 * p], j = pairs[2 * p + 1];
+    if (c->stage < 1 || (!c->gauged && !(i == 0 && j == 0))) {
+      c->err = "multipliers before the ground state (pair (0, 0)) or the right and left EOM states";
+      return CC_ERR_STATE;
+    }
+  }
+  std::vector<std::pair<int, int>> pl;
+  for (int p = 0; p < npairs; ++p) {
+    const int i = pairs[2 * p], j = pairs[2 * p + 1];
+    if (i < 0 || j < 0 || i > c->nroots || j > c->nroots || (i == 0 && j != 0)) {
+      c->err = "pair indices must satisfy 0 <= i, j <= nroots with i >= 1 unless i = j = 0";
+      return CC_ERR_ARG;
+    }
+    for (const auto& q : pl)
+      if (q.first == i && q.second == j) {
+        c->err = "a pair appears twice in one multipliers call";
+        return CC_ERR_ARG;
+      }
+    pl.push_back({i, j});
+  }
   try {
-    return nm::multipliers_impl(*c, i, j, iters);
+    return nm::multipliers_impl(*c, pl, iters);
   } catch (const Error& e) {
     return fail(c, e);
   }
@@ -2184,7 +2415,15 @@ int cc_stats(const cc_ctx* c, double* out, int n) {
 int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
             int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,
             void* stream) {
+  return nm_gemm_tiled(precision, -1, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+int nm_gemm_tiled(int precision, int tile, int ta, int tb, int M, int N, int K, double alpha,
+                  const void* A, int64_t lda, const void* B, int64_t ldb, double beta, double* C,
+                  int64_t ldc, void* stream) {
   if (!A || !B || !C || M < 0 || N < 0 || K < 1) return CC_ERR_ARG;
+  if (tile < -1 || tile >= nm::kBf16Tiles || (tile >= 0 && precision != CC_BF16X3_REFINE))
+    return CC_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   int rc;
   if (precision == CC_FP64)
@@ -2199,7 +2438,7 @@ int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, co
     const uint16_t* a = (const uint16_t*)A;
     const uint16_t* b = (const uint16_t*)B;
     rc = nm::gemm_bf16x3(st, M, N, K, 1, alpha, a, a + (int64_t)M * lda, lda, 0, b, b + (int64_t)N * ldb,
-                         ldb, 0, beta, C, ldc, 0, 0);
+                         ldb, 0, beta, C, ldc, 0, 0, tile);
     if (rc == -1) return CC_ERR_ARG;
   } else
     return CC_ERR_ARG;

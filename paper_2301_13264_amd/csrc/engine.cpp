@@ -112,6 +112,7 @@ DView full_view(const Tensor& t, const std::string& lab) {
   v.p = t.p;
   v.nd = t.nd;
   v.constant = t.constant;
+  v.frozen = t.frozen;
   strides_of(t, v.str);
   for (int k = 0; k < t.nd; ++k) {
     v.dims[k] = t.d[k];
@@ -181,6 +182,34 @@ struct TermTrace {
 Engine::~Engine() {
   for (auto& kv : f32_cache_) (void)hipFree(kv.second);
   for (auto& kv : bf16_cache_) (void)hipFree(kv.second);
+  clear_frozen();
+}
+
+// Packings of frozen views: up to 8 GB, each entry its own allocation so
+// that the arena's LIFO order is untouched; freed once the stream has drained.
+void Engine::clear_frozen() {
+  if (frozen_cache_.empty()) return;
+  (void)hipStreamSynchronize(s_);
+  for (auto& kv : frozen_cache_) (void)hipFree(kv.second);
+  frozen_cache_.clear();
+  frozen_cache_bytes_ = 0;
+}
+
+void* Engine::frozen_lookup(const std::string& key) const {
+  auto it = frozen_cache_.find(key);
+  return it == frozen_cache_.end() ? nullptr : it->second;
+}
+
+void* Engine::frozen_store(const std::string& key, size_t bytes) {
+  if (frozen_cache_bytes_ + bytes > ((size_t)8 << 30)) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  frozen_cache_[key] = p;
+  frozen_cache_bytes_ += bytes;
+  return p;
 }
 
 Engine::Engine(hipStream_t s) : s_(s) {
@@ -315,13 +344,13 @@ __global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, i
 // trades rounds against chunk length plus the fold of ns partial products
 // (16 bytes per element and chunk at about 4 TB/s).
 constexpr double kF64UsPerK = 0.23, kF32UsPerK = 0.13, kBF16UsPerK = 0.06;
-static int64_t big_split(int64_t tiles, int64_t K, int64_t MN, double us_per_k) {
+static int64_t big_split(int64_t tiles, int64_t K, int64_t MN, double us_per_k, int64_t conc = 512) {
   int64_t best = 1;
   double tbest = 1e300;
   for (int64_t ns = 1; ns <= 256; ++ns) {
     const int64_t kc = ((K + ns - 1) / ns + 15) / 16 * 16;
     if (ns > 1 && kc < 512) break;
-    const double rounds = (double)((tiles * ns + 511) / 512);
+    const double rounds = (double)((tiles * ns + conc - 1) / conc);
     const double t = rounds * (double)kc * us_per_k +
                      (ns > 1 ? (double)ns * (double)MN * 16.0 / 4e6 : 0.0);
     if (t < tbest * 0.98) { tbest = t; best = ns; }
@@ -345,18 +374,16 @@ static std::string tune_key(char prec, bool ta, bool tb, int64_t M, int64_t N, i
   return std::string(1, prec) + (ta ? "T" : "N") + (tb ? "T" : "N") + ":" + std::to_string(M) + "x" +
          std::to_string(N) + "x" + std::to_string(K);
 }
-// times launch(ns) for each candidate (outputs go to scratch) and returns the best
-static int64_t tune_split(hipStream_t s, const std::string& key, int64_t model, int64_t ns_max,
-                          const std::function<void(int64_t)>& launch) {
+// times launch(c) for each candidate configuration c (outputs go to scratch)
+// and returns the fastest; the first candidate is the model's choice
+static int64_t tune_config(hipStream_t s, const std::string& key, std::vector<int64_t> cand,
+                           const std::function<void(int64_t)>& launch) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return it->second;
   }
-  // no split at all only near a small model split: for the skinny long-K
-  // products (model splits in the hundreds) one chunk takes seconds
-  std::vector<int64_t> cand{model, std::max<int64_t>(1, model / 2), std::min<int64_t>(ns_max, model * 2)};
-  if (model <= 16) cand.push_back(1);
+  const int64_t model = cand.front();
   std::sort(cand.begin(), cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   hipEvent_t e0, e1;
@@ -376,11 +403,21 @@ static int64_t tune_split(hipStream_t s, const std::string& key, int64_t model, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (std::getenv("NACME_VERBOSE"))
-    std::fprintf(stderr, "[autotune] %s split %lld (model %lld) %.3f ms\n", key.c_str(),
+    std::fprintf(stderr, "[autotune] %s config %lld (model %lld) %.3f ms\n", key.c_str(),
                  (long long)best, (long long)model, tbest);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = best;
   return best;
+}
+
+// K split only: the model's split and its neighbours (no split at all only
+// near a small model split: for the skinny long-K products, model splits in
+// the hundreds, one chunk takes seconds)
+static int64_t tune_split(hipStream_t s, const std::string& key, int64_t model, int64_t ns_max,
+                          const std::function<void(int64_t)>& launch) {
+  std::vector<int64_t> cand{model, std::max<int64_t>(1, model / 2), std::min<int64_t>(ns_max, model * 2)};
+  if (model <= 16) cand.push_back(1);
+  return tune_config(s, key, cand, launch);
 }
 static constexpr double kTuneMinFlops = 2e10;
 
@@ -495,6 +532,16 @@ const float* Engine::packed_f32(const DView& src, const std::string& order, bool
       (void)hipGetLastError();
     }
   }
+  if (src.frozen && cache) {
+    std::string key = "f" + std::to_string((uintptr_t)src.p);
+    for (int k = 0; k < vs.nd; ++k)
+      key += ":" + std::to_string(vs.dims[k]) + "/" + std::to_string(vs.istr[k]);
+    if (void* hit = frozen_lookup(key)) return (const float*)hit;
+    if (float* buf = (float*)frozen_store(key, (size_t)cnt * sizeof(float))) {
+      kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
+      return buf;
+    }
+  }
   float* buf = (float*)arena_.alloc((cnt + 1) / 2);
   kcheck(view_gather_f32(s_, buf, src.p, vs), "pack fp32");
   return buf;
@@ -503,20 +550,28 @@ const float* Engine::packed_f32(const DView& src, const std::string& order, bool
 void Engine::packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K,
                          int64_t Kp, const uint16_t** hi, const uint16_t** lo) {
   std::string key;
-  if (src.constant) {
+  if (src.constant || src.frozen) {
     int64_t cnt = 0;
     const ViewSpec vs = pack_spec(src, order, cnt);
     key = std::to_string((uintptr_t)src.p) + ":" + std::to_string(Kp);
     for (int k = 0; k < vs.nd; ++k)
       key += ":" + std::to_string(vs.dims[k]) + "/" + std::to_string(vs.istr[k]);
+  }
+  const size_t n = (size_t)(rows * Kp);
+  if (src.constant) {
     auto it = bf16_cache_.find(key);
     if (it != bf16_cache_.end()) {
       *hi = it->second;
-      *lo = it->second + rows * Kp;
+      *lo = it->second + n;
+      return;
+    }
+  } else if (src.frozen) {
+    if (void* hit = frozen_lookup("h" + key)) {
+      *hi = (const uint16_t*)hit;
+      *lo = (const uint16_t*)hit + n;
       return;
     }
   }
-  const size_t n = (size_t)(rows * Kp);
   uint16_t* buf = nullptr;
   bool cached = false;
   if (src.constant && bf16_cache_bytes_ + 2 * n * sizeof(uint16_t) <= ((size_t)8 << 30)) {
@@ -526,6 +581,8 @@ void Engine::packed_bf16(const DView& src, const std::string& order, int64_t row
       (void)hipGetLastError();
       buf = nullptr;
     }
+  } else if (src.frozen) {
+    buf = (uint16_t*)frozen_store("h" + key, 2 * n * sizeof(uint16_t));
   }
   if (!buf) buf = (uint16_t*)arena_.alloc((int64_t)((2 * n * sizeof(uint16_t) + 7) / 8));
   // one pass from the fp64 view: output strides of the trailing K labels as
@@ -697,8 +754,13 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
     } else if (nb0 == 1) {
       ns = big_split(tiles, K, M0 * N0, use_bf16 ? kBF16UsPerK : kF32UsPerK);
     }
-    auto launch = [&](int64_t nsplit, double* out, int64_t ldo, int64_t so, double aa, double bb) {
+    // bf16 pairs: a configuration is tile shape * kCfgTile + K split
+    constexpr int64_t kCfgTile = 1024;
+    int bf16_tile = use_bf16 ? bf16x3_auto_tile((int)M0, (int)N0, (int)nb0) : 0;
+    auto launch = [&](int64_t cfg, double* out, int64_t ldo, int64_t so, double aa, double bb) {
       if (use_bf16) {
+        const int tile = (int)(cfg / kCfgTile);
+        const int64_t nsplit = cfg % kCfgTile;
         if (nsplit > 1) {
           const int64_t kc = ((Kp + nsplit - 1) / nsplit + 31) / 32 * 32;
           const int64_t nsr = (Kp + kc - 1) / kc;
@@ -706,7 +768,7 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
           Arena::Mark pm = arena_.mark();
           double* part = arena_.alloc(nsr * M0 * N0);
           kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)kc, (int)nsr, 1.0, ah, al, Kp, kc, bh, bl, Kp, kc,
-                             0.0, part, N0, M0 * N0, (int)klast),
+                             0.0, part, N0, M0 * N0, (int)klast, tile),
                  "gemm bf16x3 (split K)");
           const int64_t tot = M0 * N0;
           const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
@@ -716,11 +778,12 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
           arena_.rewind(pm);
         } else {
           kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)Kp, (int)nb0, aa, ah, al, Kp, M0 * Kp, bh, bl, Kp,
-                             N0 * Kp, bb, out, ldo, so, 0),
+                             N0 * Kp, bb, out, ldo, so, 0, tile),
                  "gemm bf16x3");
         }
         return;
       }
+      const int64_t nsplit = cfg;
       if (nsplit > 1) {
         const int64_t kc = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
         const int64_t nsr = (K + kc - 1) / kc;
@@ -742,12 +805,31 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
                "gemm fp32");
       }
     };
+    int64_t cfg = use_bf16 ? bf16_tile * kCfgTile + ns : ns;
     if (nb0 == 1 && autotune_on() && 2.0 * (double)M0 * (double)N0 * (double)K >= kTuneMinFlops) {
       double* scratch = arena_.alloc(M0 * N0);
-      ns = tune_split(s_, tune_key(use_bf16 ? 'h' : 's', false, false, M0, N0, K), ns, 256,
-                      [&](int64_t c) { launch(c, scratch, N0, M0 * N0, 1.0, 0.0); });
+      auto run = [&](int64_t c) { launch(c, scratch, N0, M0 * N0, 1.0, 0.0); };
+      if (use_bf16) {
+        // every tile shape with its own modelled split (one workgroup per CU
+        // for the large tiles), and the neighbours of the chosen split
+        std::vector<int64_t> cand{cfg, bf16_tile * kCfgTile + std::max<int64_t>(1, ns / 2),
+                                  bf16_tile * kCfgTile + std::min<int64_t>(256, ns * 2)};
+        for (int t = 0; t < kBf16Tiles; ++t) {
+          const int64_t bm = (t == 1 || t == 2) ? 256 : 128, bn = (t == 1 || t == 3) ? 256 : 128;
+          const int64_t tt = ((M0 + bm - 1) / bm) * ((N0 + bn - 1) / bn);
+          // a large-tile workgroup holds a whole CU and, by the model, moves
+          // 1.8x the outputs per cycle of two 128 x 128 workgroups
+          const double upk = t == 0 ? kBF16UsPerK
+                                    : kBF16UsPerK * (double)(bm * bn) / (2.0 * 16384.0) / 1.8;
+          const int64_t st = big_split(tt, K, M0 * N0, upk, t == 0 ? 512 : 256);
+          cand.push_back(t * kCfgTile + st);
+        }
+        cfg = tune_config(s_, tune_key('h', false, false, M0, N0, K), cand, run);
+      } else {
+        cfg = tune_split(s_, tune_key('s', false, false, M0, N0, K), ns, 256, run);
+      }
     }
-    launch(ns, pc, ldc, sC, a_, b_);
+    launch(cfg, pc, ldc, sC, a_, b_);
     if (!direct) gather_into(s_, alpha, cbuf, C, overwrite ? 0.0 : 1.0);
     lowp_flops_ += (uint64_t)(2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K);
     arena_.rewind(mk);
@@ -946,6 +1028,7 @@ DView Graph::view_of(const Op& o, const Tensor& t) const {
   v.p = t.p + base;
   v.pair_sym = t.pair_sym && o.box.empty() && v.nd == t.nd;
   v.constant = t.constant;
+  v.frozen = t.frozen;
   return v;
 }
 

@@ -66,6 +66,9 @@ struct Tensor {
   bool pair_sym = false;
   // never written after creation (integrals): fp32 packings may be cached
   bool constant = false;
+  // unchanged until Engine::clear_frozen() (the recorded values of a
+  // linearisation): its low-precision packings are cached until then
+  bool frozen = false;
   int64_t size() const {
     int64_t s = 1;
     for (int k = 0; k < nd; ++k) s *= d[k];
@@ -100,6 +103,7 @@ struct DView {
   int nd = 0;
   bool pair_sym = false;   // see Tensor::pair_sym (whole tensors only)
   bool constant = false;   // view of a Tensor::constant tensor
+  bool frozen = false;     // view of a Tensor::frozen tensor
   int64_t dims[kMaxViewDims] = {0};
   int64_t str[kMaxViewDims] = {0};
   char lab[kMaxViewDims] = {0};
@@ -134,6 +138,8 @@ class Engine {
   // (fp32 accumulation): about 2^-16 relative instead of fp32's 2^-24.
   void set_bf16(bool on) { bf16_ = on; }
   bool bf16() const { return bf16_; }
+  // Releases the packings of frozen tensors (their values may change next).
+  void clear_frozen();
 
  private:
   hipStream_t s_;
@@ -153,6 +159,11 @@ class Engine {
   bool bf16_ = false;
   std::map<std::string, uint16_t*> bf16_cache_;
   size_t bf16_cache_bytes_ = 0;
+  // packings of frozen views (fp32 or bf16 pairs), released by clear_frozen()
+  std::map<std::string, void*> frozen_cache_;
+  size_t frozen_cache_bytes_ = 0;
+  void* frozen_lookup(const std::string& key) const;
+  void* frozen_store(const std::string& key, size_t bytes);
   void packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K, int64_t Kp,
                    const uint16_t** hi, const uint16_t** lo);
 };
@@ -183,6 +194,10 @@ class Graph {
   // Truncate the tape to `n` nodes (values of removed nodes are released
   // when the arena is rewound by the caller).
   void truncate(int n) { nodes_.resize(n); }
+  // Marks the values of nodes [0, n) frozen (Tensor::frozen).
+  void freeze(int n) {
+    for (int k = 0; k < n && k < (int)nodes_.size(); ++k) nodes_[k].val.frozen = true;
+  }
   Engine& engine() { return e_; }
   // strided view of an operand (box + labels) of an existing node
   DView view(const Op& o) const { return view_of(o, nodes_.at(o.node).val); }

@@ -32,9 +32,14 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
 // BF16 split-precision GEMM: C = alpha A B + beta C with A [M][K] and B^T [N][K]
 // given as bfloat16 pairs (hi, lo) in uint16 storage; K and Klast multiples
 // of 32, lda / ldb / batch strides multiples of 8, 16-byte aligned pointers.
+// tile: 0 = 128 x 128 outputs per workgroup (two per CU), 1 = 256 x 256,
+// 2 = 256 x 128, 3 = 128 x 256 (one per CU); -1 = bf16x3_auto_tile's choice.
+constexpr int kBf16Tiles = 4;
+int bf16x3_auto_tile(int M, int N, int batch);
 int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
                 const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
-                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast);
+                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast,
+                int tile = -1);
 // bfloat16 pair (hi at out, lo at out + lo_off) of a strided double view
 // whose output strides address a [rows][Kp] layout; padding [K, Kp) zeroed
 int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const double* in,

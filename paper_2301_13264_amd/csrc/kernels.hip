@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstdint>
+#include <cmath>
 
 #include "kernels.h"
 
@@ -537,26 +538,187 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
       }
 }
 
+// Large-tile variant for one workgroup per CU: BM x BN x 32 tiles (256 x 256
+// or 256 x 128) over 8 waves of WM x WN, each wave a (BM / WM) x (BN / WN)
+// block of FI x FJ MFMA tiles, so that every fragment read from LDS feeds FJ
+// (A) or FI (B) products and a tile's operand panels are fetched once per
+// BM x BN outputs (a quarter of the 128 x 128 kernel's panel traffic).  LDS:
+// two stages of the four 32-wide bf16 row arrays (A hi, A lo, B hi, B lo),
+// 256 (BM + BN) bytes in all (128 KB at 256 x 256), with the same XOR-swizzled
+// 16-byte chunks as the 128 x 128 kernel.  Each thread moves
+// (BM + BN) / 64 16-byte chunks per K step, prefetched into registers while
+// the previous step's fragments are multiplied.  The three products of a
+// fragment pair are issued one per row block and then over the column blocks
+// (FJ independent accumulators between dependent MFMAs).
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
+    int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
+    const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
+    const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int Klast) {
+  static_assert(WM * WN == 8, "eight waves");
+  constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
+  constexpr int NCH = (BM + BN) * 8 / 512;   // 16-byte chunks per thread per K step
+  static_assert((4 * BM) % 512 == 0 && (4 * BN) % 512 == 0, "chunk rounds per array");
+  __shared__ __attribute__((aligned(16))) uint16_t SA[2][2][BM * HKS];
+  __shared__ __attribute__((aligned(16))) uint16_t SB[2][2][BN * HKS];
+  const int64_t bz = blockIdx.z;
+  Ah += bz * sA;
+  Al += bz * sA;
+  Bh += bz * sB;
+  Bl += bz * sB;
+  C += bz * sC;
+  if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
+  const int gx = gridDim.x, gy = gridDim.y;
+  int bid = blockIdx.x + gx * blockIdx.y;
+  bid = xcd_tile(bid, gx * gy);
+  const int tm = bid % gy, tn = bid / gy;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+  const int lr = lane & 15, lk = lane >> 4;
+  // chunk q = tid + 512 r runs over [A hi: 4 BM][A lo: 4 BM][B hi: 4 BN][B lo: 4 BN]
+  constexpr int RA = 4 * BM / 512, RB = 4 * BN / 512;
+  const uint16_t* src[NCH];
+  bool ok[NCH];
+  int sto[NCH];
+#pragma unroll
+  for (int r = 0; r < NCH; ++r) {
+    int q = tid + 512 * r;
+    const bool isA = r < 2 * RA;
+    const bool lo = isA ? (r >= RA) : (r >= 2 * RA + RB);
+    q -= isA ? (lo ? 4 * BM : 0) : (lo ? 8 * BM + 4 * BN : 8 * BM);
+    const int row = q >> 2, ch = q & 3;
+    if (isA) {
+      ok[r] = m0 + row < M;
+      src[r] = (lo ? Al : Ah) + (int64_t)(ok[r] ? m0 + row : 0) * lda + 8 * ch;
+    } else {
+      ok[r] = n0 + row < N;
+      src[r] = (lo ? Bl : Bh) + (int64_t)(ok[r] ? n0 + row : 0) * ldb + 8 * ch;
+    }
+    sto[r] = swz(row, ch);
+  }
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  uint4 reg[NCH];
+  auto gload = [&](int t) {
+    const int64_t k0 = (int64_t)t * HBK;
+#pragma unroll
+    for (int r = 0; r < NCH; ++r) reg[r] = ok[r] ? *(const uint4*)(src[r] + k0) : zero;
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < NCH; ++r) {
+      const bool isA = r < 2 * RA;
+      const bool lo = isA ? (r >= RA) : (r >= 2 * RA + RB);
+      uint16_t* base = isA ? SA[buf][lo] : SB[buf][lo];
+      *(uint4*)&base[sto[r]] = reg[r];
+    }
+  };
+  v4f acc[FI][FJ];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int nk = K / HBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) gload(t + 1);
+    bf16x8 bh[FJ], bl[FJ];
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+      const int o = swz(wn * TN + j * 16 + lr, lk);
+      bh[j] = *(const bf16x8*)&SB[cur][0][o];
+      bl[j] = *(const bf16x8*)&SB[cur][1][o];
+    }
+#pragma unroll
+    for (int i = 0; i < FI; ++i) {
+      const int o = swz(wm * TM + i * 16 + lr, lk);
+      const bf16x8 ah = *(const bf16x8*)&SA[cur][0][o];
+      const bf16x8 al = *(const bf16x8*)&SA[cur][1][o];
+#pragma unroll
+      for (int j = 0; j < FJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < FJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < FJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * TM + i * 16 + 4 * lk + v;
+        const int gn = n0 + wn * TN + j * 16 + lr;
+        if (gm < M && gn < N) {
+          double* c = C + (int64_t)gm * ldc + gn;
+          const double r = alpha * (double)acc[i][j][v];
+          *c = (beta == 0.0) ? r : r + beta * (*c);
+        }
+      }
+}
+
+// Tile shapes of the split-precision GEMM: 0 = 128 x 128 (two workgroups per
+// CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one workgroup per CU).
+static void bf16_tile_dims(int tile, int& bm, int& bn) {
+  bm = (tile == 1 || tile == 2) ? 256 : 128;
+  bn = (tile == 1 || tile == 3) ? 256 : 128;
+}
+
+// The shape used when none is given: the 128 x 128 kernel, measured faster
+// than the one-workgroup-per-CU tiles on every shape timed so far (two
+// workgroups per CU hide each other's load and barrier stalls); the large
+// tiles stay available to the autotuner and nm_gemm_tiled.
+int bf16x3_auto_tile(int M, int N, int batch) {
+  (void)M;
+  (void)N;
+  (void)batch;
+  return 0;
+}
+
 int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
                 const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
-                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast) {
+                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast,
+                int tile) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (K <= 0 || K % HBK || (Klast > 0 && Klast % HBK) || lda % 8 || ldb % 8 || sA % 8 || sB % 8 ||
-      ((uintptr_t)Ah | (uintptr_t)Al | (uintptr_t)Bh | (uintptr_t)Bl) % 16)
+      ((uintptr_t)Ah | (uintptr_t)Al | (uintptr_t)Bh | (uintptr_t)Bl) % 16 || tile >= kBf16Tiles)
     return -1;
   if (batch > 32768) {
     for (int b0 = 0; b0 < batch; b0 += 32768) {
       const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
       int rc = gemm_bf16x3(s, M, N, K, nb, alpha, Ah + (int64_t)b0 * sA, Al + (int64_t)b0 * sA, lda, sA,
                            Bh + (int64_t)b0 * sB, Bl + (int64_t)b0 * sB, ldb, sB, beta,
-                           C + (int64_t)b0 * sC, ldc, sC, b0 + nb == batch ? Klast : 0);
+                           C + (int64_t)b0 * sC, ldc, sC, b0 + nb == batch ? Klast : 0, tile);
       if (rc) return rc;
     }
     return 0;
   }
-  dim3 grid((N + 127) / 128, (M + 127) / 128, batch);
-  hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
-                     Bl, ldb, sB, beta, C, ldc, sC, Klast);
+  if (tile < 0) tile = bf16x3_auto_tile(M, N, batch);
+  int bm, bn;
+  bf16_tile_dims(tile, bm, bn);
+  dim3 grid((N + bn - 1) / bn, (M + bm - 1) / bm, batch);
+#define NM_BF16BIG(BM_, BN_, WM_, WN_)                                                              \
+  hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_>), grid, dim3(512), 0, s, M, N, K, \
+                     alpha, Ah, Al, lda, sA, Bh, Bl, ldb, sB, beta, C, ldc, sC, Klast)
+  switch (tile) {
+    case 1: NM_BF16BIG(256, 256, 2, 4); break;
+    case 2: NM_BF16BIG(256, 128, 4, 2); break;
+    case 3: NM_BF16BIG(128, 256, 2, 4); break;
+    default:
+      hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
+                         Bl, ldb, sB, beta, C, ldc, sC, Klast);
+  }
+#undef NM_BF16BIG
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -32,15 +32,15 @@ def test_call_order_is_enforced(nm):
         ctx.eom(nm.CC_BOTH, 2)
     assert e.value.code == -2
     with pytest.raises(nm.CCError) as e:
-        ctx.multipliers(1, 2)
+        ctx.multipliers([(1, 2)])
     assert e.value.code == -2
     ctx.ground()
     with pytest.raises(nm.CCError) as e:
-        ctx.multipliers(1, 2)           # needs both EOM sides
+        ctx.multipliers([(1, 2)])           # needs both EOM sides
     assert e.value.code == -2
     ctx.eom(nm.CC_RIGHT, 2)
     with pytest.raises(nm.CCError) as e:
-        ctx.multipliers(1, 2)           # left states still missing
+        ctx.multipliers([(1, 2)])           # left states still missing
     assert e.value.code == -2
     ctx.eom(nm.CC_LEFT, 2)
     with pytest.raises(nm.CCError) as e:
@@ -50,7 +50,7 @@ def test_call_order_is_enforced(nm):
         ctx.nacme(1, 2, T(np.zeros((1, 6, 6))), T(np.zeros((1, 18, 6, 6))))
     assert e.value.code == -2
     # the context is still usable: the full chain now succeeds
-    ctx.multipliers(1, 2)
+    ctx.multipliers([(1, 2)])
     ctx.densities(1, 2)
     F = ctx.nacme(1, 2, T(np.zeros((1, 6, 6))), T(np.zeros((1, 18, 6, 6))))
     assert F[0] == 0.0
@@ -77,9 +77,9 @@ def test_bad_arguments_are_rejected(nm):
         ctx.eom(4, 2)                   # no such side
     assert e.value.code == -1
     ctx.eom(nm.CC_BOTH, 2)
-    for (i, j) in [(3, 1), (0, 1), (1, -1)]:
+    for pl in [[(3, 1)], [(0, 1)], [(1, -1)], [(1, 2), (2, 1), (1, 2)], []]:
         with pytest.raises(nm.CCError) as e:
-            ctx.multipliers(i, j)
+            ctx.multipliers(pl)
         assert e.value.code == -1
     ctx.close()
 

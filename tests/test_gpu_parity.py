@@ -126,9 +126,11 @@ def test_pipeline_matches_oracle(nm, o, v, naux, seed):
         assert np.abs(R - st["R"][k].numpy()).max() < 1e-7
         assert np.abs(L - st["L"][k].numpy()).max() < 1e-7
         assert abs(ctx.export_r0(k + 1) - float(st["R0"][k])) < 1e-8
+    # both ordered pairs in one call: their zeta equations share the block solver
+    its, rc = ctx.multipliers([(1, 2), (2, 1)])
+    assert rc == 0 and all(z > 0 for z, _ in its)
     for (i, j) in [(0, 1), (1, 0)]:
         m = rs.multipliers(st, i, j, relaxed=True)
-        ctx.multipliers(i + 1, j + 1)
         eta = to_packed(ctx.export(nm._lib.CC_ETA_T, i + 1, j + 1, buf).cpu().numpy(), o, v)
         assert np.abs(eta - m["eta_t"].numpy()).max() < 1e-7
         zeta = to_packed(ctx.export(nm._lib.CC_ZETA, i + 1, j + 1, buf).cpu().numpy(), o, v)
@@ -167,7 +169,7 @@ def test_ground_pair_couplings_match_oracle(nm, o, v, naux, seed):
     buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
     for i in range(2):
         m = rs.multipliers(st, i, rs.GROUND, relaxed=True)
-        ctx.multipliers(i + 1, 0)
+        ctx.multipliers([(i + 1, 0)])
         zeta = to_packed(ctx.export(nm._lib.CC_ZETA, i + 1, 0, buf).cpu().numpy(), o, v)
         assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7
         kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
@@ -201,7 +203,7 @@ def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
     ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
     ctx.ground()
     # the ground-state gradient needs no EOM states
-    ctx.multipliers(0, 0)
+    ctx.multipliers([(0, 0)])
     w, _, _ = ctx.eom(nm.CC_BOTH, 2)
     Nf = o * v + (o * v) ** 2
     buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
@@ -209,7 +211,7 @@ def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
     for jj, jo in [(0, rs.GROUND), (1, 0), (2, 1)]:
         m = rs.gradient_multipliers(st, jo, relaxed=True)
         if jj > 0:
-            ctx.multipliers(jj, jj)
+            ctx.multipliers([(jj, jj)])
         zeta = to_packed(ctx.export(nm._lib.CC_ZETA, jj, jj, buf).cpu().numpy(), o, v)
         assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7
         kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
@@ -223,7 +225,7 @@ def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
             assert abs(G[q] - Go) < 1e-7 * max(1.0, abs(Go))
         grads[jj] = np.asarray(G)
     # branching plane: g = grad(E2 - E1), h = (E2 - E1) F_12
-    ctx.multipliers(1, 2)
+    ctx.multipliers([(1, 2)])
     ctx.densities(1, 2)
     F12 = np.asarray(ctx.nacme(1, 2, T(dirs["dh"]), T(dirs["dB"])))
     for q in range(2):
@@ -296,13 +298,15 @@ def test_bf16_pair_packing_is_exact(nm, spec, ashape):
     assert torch.equal(C.cpu(), ref)
 
 
-@pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320)])
-def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K):
-    """nm_gemm with bfloat16 pairs (the split-precision kernel alone): the
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320), (600, 700, 96)])
+def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K, tile):
+    """nm_gemm_tiled with bfloat16 pairs (the split-precision kernel alone, in
+    each workgroup tile shape; ragged edges in M and N, several tiles): the
     result equals the fp64 product of the pairs' values up to the dropped
     lo x lo term and fp32 accumulation, and is far closer to the fp32
     product than one bf16 product is."""
-    say(f"[nm_gemm bf16x3] {M}x{N}x{K}")
+    say(f"[nm_gemm bf16x3] tile={tile} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
     A = torch.as_tensor(rng.normal(size=(M, K)), dtype=torch.float32, device="cuda")
     Bt = torch.as_tensor(rng.normal(size=(N, K)), dtype=torch.float32, device="cuda")
@@ -314,7 +318,7 @@ def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K):
     Bp, bh, bl = pair(Bt)
     C0 = torch.as_tensor(rng.normal(size=(M, N)), device="cuda")
     C = C0.clone()
-    nm.gemm(2, Ap, Bp, C, alpha=0.5, beta=-2.0)
+    nm.gemm(2, Ap, Bp, C, alpha=0.5, beta=-2.0, tile=tile)
     torch.cuda.synchronize()
     a64 = ah.double().cpu(), al.double().cpu()
     b64 = bh.double().cpu(), bl.double().cpu()
@@ -373,10 +377,10 @@ def test_mixed_precision_pipeline_matches_oracle(nm, o, v, naux, seed, prec):
     w, _, rc = ctx.eom(nm.CC_BOTH, nroots)
     assert rc == 0
     assert np.abs(np.array(w) - st["omega"].numpy()).max() < 1e-9
+    _, rc = ctx.multipliers([(1, 2), (2, 1)])
+    assert rc == 0
     for (i, j) in [(0, 1), (1, 0)]:
         m = rs.multipliers(st, i, j, relaxed=True)
-        _, rc = ctx.multipliers(i + 1, j + 1)
-        assert rc == 0
         ctx.densities(i + 1, j + 1)
         F = ctx.nacme(i + 1, j + 1, T(dirs["dh"]), T(dirs["dB"]))
         for q in range(2):
