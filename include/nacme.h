@@ -249,6 +249,15 @@ int mlp_set_params(nm_mlp* net, const float* src);
 int mlp_get_params(nm_mlp* net, float* dst, int working);
 /* Y = net(X) for n rows.                                                     */
 int mlp_forward(nm_mlp* net, int64_t n, const float* X, float* Y);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): Y = net(X)
+ * for n rows, as mlp_forward, with every intermediate in a fixed 32 MiB
+ * device work area of the library instead of buffers it allocates; rows go
+ * through it in chunks.  No hipMalloc or hipFree is called.  The area is one
+ * per GPU, shared by every call on that GPU: calls that overlap on one GPU
+ * (other streams or host threads) race and must be serialised by the
+ * caller.  -1 for a network whose rows do not fit 64 at a time.             */
+int mlp_forward_noalloc(nm_mlp* net, int64_t n, const float* X, float* Y);
 /* Loss of (X, T) over n rows (host *loss) and its gradient with respect to
  * the parameters (kept for mlp_adam_step; copied to host grad if non-NULL). */
 int mlp_loss_grad(nm_mlp* net, int64_t n, const float* X, const float* T, double* loss,

@@ -86,6 +86,7 @@ def lib():
         L.mlp_set_params.argtypes = [P, PF]
         L.mlp_get_params.argtypes = [P, PF, I]
         L.mlp_forward.argtypes = [P, ctypes.c_int64, P, P]
+        L.mlp_forward_noalloc.argtypes = [P, ctypes.c_int64, P, P]
         L.mlp_loss_grad.argtypes = [P, ctypes.c_int64, P, P, PD, PF]
         L.mlp_adam_step.argtypes = [P, F]
         L.mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int64, I, F, U64, PD]
@@ -97,6 +98,7 @@ def lib():
         L.cc_t2_target.argtypes = [P, F, P]
         L.cc_guess_t2.argtypes = [P, P, PF, PF, F]
         for name in ("mlp_create", "mlp_dims", "mlp_set_params", "mlp_get_params", "mlp_forward",
+                     "mlp_forward_noalloc",
                      "mlp_loss_grad", "mlp_adam_step", "mlp_train", "cc_t2_features",
                      "cc_t2_target", "cc_guess_t2"):
             getattr(L, name).restype = ctypes.c_int
@@ -114,6 +116,7 @@ EXPORTED = ["cc_default_opts", "cc_create", "cc_ground", "eom_solve", "multiplie
             "nm_version", "cc_stats", "nm_gemm", "nm_gemm_tiled", "cc_apply_jacobian_block",
             "mlp_create",
             "mlp_num_params", "mlp_dims", "mlp_set_params", "mlp_get_params", "mlp_forward",
+            "mlp_forward_noalloc",
             "mlp_loss_grad", "mlp_adam_step", "mlp_train", "mlp_last_error", "mlp_destroy",
             "cc_t2_features", "cc_t2_target", "cc_guess_t2"]
 
@@ -335,6 +338,11 @@ class MLP:
 
     def forward(self, X, Y):
         self._check(lib().mlp_forward(self._h, X.shape[0], _fptr(X), _fptr(Y)))
+        return Y
+
+    def forward_noalloc(self, X, Y):
+        """As forward, through the library's fixed work area (no allocation)."""
+        self._check(lib().mlp_forward_noalloc(self._h, X.shape[0], _fptr(X), _fptr(Y)))
         return Y
 
     def loss_grad(self, X, T, want_grad=True):

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -263,25 +264,33 @@ void colsum(nm_mlp* m, const float* x, int64_t n, int w, float* out) {
                      (int)nch, (int64_t)w, out);
 }
 
-// forward of n rows of X (in the work buffers); output in m->y
-void forward(nm_mlp* m, int64_t n, const float* X) {
+// forward of n rows of X with the given work buffers: acc (fp64 GEMM output,
+// n x max(width, n_out)), pre-activations u1, u2 (kept for the backward pass;
+// may be null) and activations h1, h2 (n x width); output y (n x n_out)
+void forward_rows(nm_mlp* m, int64_t n, const float* X, double* acc, float* u1, float* h1,
+                  float* u2, float* h2, float* y) {
   const int w = m->width;
   const float* P = m->pw;
   kchk(nm::gemm_f32acc(m->s, false, false, (int)n, w, m->n_in, 1, 1.0, X, m->n_in, 0,
-                       P + m->off_W1(), w, 0, 0.0, m->acc, w, 0),
+                       P + m->off_W1(), w, 0, 0.0, acc, w, 0),
        "layer 1");
-  hipLaunchKernelGGL(nm::bias_act_kernel, dim3(nm::grid_of(n * w)), dim3(256), 0, m->s, m->acc,
-                     P + m->off_b1(), m->u1, m->h1, n, w, 1);
-  kchk(nm::gemm_f32acc(m->s, false, false, (int)n, w, w, 1, 1.0, m->h1, w, 0, P + m->off_W2(), w,
-                       0, 0.0, m->acc, w, 0),
+  hipLaunchKernelGGL(nm::bias_act_kernel, dim3(nm::grid_of(n * w)), dim3(256), 0, m->s, acc,
+                     P + m->off_b1(), u1, h1, n, w, 1);
+  kchk(nm::gemm_f32acc(m->s, false, false, (int)n, w, w, 1, 1.0, h1, w, 0, P + m->off_W2(), w,
+                       0, 0.0, acc, w, 0),
        "layer 2");
-  hipLaunchKernelGGL(nm::bias_act_kernel, dim3(nm::grid_of(n * w)), dim3(256), 0, m->s, m->acc,
-                     P + m->off_b2(), m->u2, m->h2, n, w, 1);
-  kchk(nm::gemm_f32acc(m->s, false, false, (int)n, m->n_out, w, 1, 1.0, m->h2, w, 0,
-                       P + m->off_W3(), m->n_out, 0, 0.0, m->acc, m->n_out, 0),
+  hipLaunchKernelGGL(nm::bias_act_kernel, dim3(nm::grid_of(n * w)), dim3(256), 0, m->s, acc,
+                     P + m->off_b2(), u2, h2, n, w, 1);
+  kchk(nm::gemm_f32acc(m->s, false, false, (int)n, m->n_out, w, 1, 1.0, h2, w, 0,
+                       P + m->off_W3(), m->n_out, 0, 0.0, acc, m->n_out, 0),
        "layer 3");
   hipLaunchKernelGGL(nm::bias_act_kernel, dim3(nm::grid_of(n * m->n_out)), dim3(256), 0, m->s,
-                     m->acc, P + m->off_b3(), (float*)nullptr, m->y, n, m->n_out, 0);
+                     acc, P + m->off_b3(), (float*)nullptr, y, n, m->n_out, 0);
+}
+
+// forward of n rows of X (in the work buffers); output in m->y
+void forward(nm_mlp* m, int64_t n, const float* X) {
+  forward_rows(m, n, X, m->acc, m->u1, m->h1, m->u2, m->h2, m->y);
 }
 
 // loss and gradient (into m->g) of n rows (X, T device)
@@ -326,6 +335,50 @@ int fail(nm_mlp* m, const std::string& e) {
   if (m) m->err = e;
   return CC_ERR_HIP;
 }
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free forward
+// Work area of mlp_forward_noalloc: a fixed device array, so that the call
+// needs no device allocation.  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code the array's name is only a
+// stand-in: its device address, per device, comes from hipGetSymbolAddress
+// (taken once per device, with that device current) and only that address
+// is handed to kernels.  All calls on one GPU share that GPU's copy, which
+// keeps the last call's contents; calls that overlap on one GPU (other
+// streams or host threads) race on it and must be serialised by the caller.
+constexpr size_t kScratchBytes = (size_t)32 << 20;   // 32 MiB
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;   // device address of scratch, by device
+
+// scratch's device address on the device that runs stream s
+void* scratch_on(hipStream_t s) {
+  int dev = 0;
+  if (s)
+    hcheck(hipStreamGetDevice(s, &dev), "stream device");
+  else
+    hcheck(hipGetDevice(&dev), "current device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    int cur = 0;
+    hcheck(hipGetDevice(&cur), "current device");
+    if (cur != dev) hcheck(hipSetDevice(dev), "set device");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    hcheck(e, "work area address");
+    if (!p) throw std::string("work area address is null");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -418,6 +471,36 @@ int mlp_forward(nm_mlp* m, int64_t n, const float* X, float* Y) {
       hcheck(hipMemcpyAsync(Y + r0 * m->n_out, m->y, k * m->n_out * sizeof(float),
                             hipMemcpyDeviceToDevice, m->s),
              "D2D");
+    }
+    hcheck(hipGetLastError(), "forward");
+    hcheck(hipStreamSynchronize(m->s), "sync");
+    return CC_OK;
+  } catch (const std::string& e) {
+    return fail(m, e);
+  }
+}
+
+int mlp_forward_noalloc(nm_mlp* m, int64_t n, const float* X, float* Y) {
+  if (!m || n < 0 || (n > 0 && (!X || !Y))) return CC_ERR_ARG;
+  // per row: one fp64 GEMM output row and the two hidden activations (fp32);
+  // rows go through the work area in chunks of a multiple of 64
+  const int w = m->width, wa = std::max(m->width, m->n_out);
+  const size_t per_row = (size_t)wa * sizeof(double) + 2 * (size_t)w * sizeof(float);
+  int64_t rows = (int64_t)((kScratchBytes - 3 * 256) / per_row) / 64 * 64;
+  if (rows < 64) {
+    m->err = "network too wide for the work area of mlp_forward_noalloc (" +
+             std::to_string(kScratchBytes) + " bytes, 64 rows at a time)";
+    return CC_ERR_ARG;
+  }
+  try {
+    if (n == 0) return CC_OK;
+    char* base = (char*)scratch_on(m->s);
+    double* acc = (double*)base;
+    float* h1 = (float*)(base + align256((size_t)rows * wa * sizeof(double)));
+    float* h2 = (float*)((char*)h1 + align256((size_t)rows * w * sizeof(float)));
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+      const int64_t k = std::min(rows, n - r0);
+      forward_rows(m, k, X + r0 * m->n_in, acc, nullptr, h1, nullptr, h2, Y + r0 * m->n_out);
     }
     hcheck(hipGetLastError(), "forward");
     hcheck(hipStreamSynchronize(m->s), "sync");
