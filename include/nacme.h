@@ -113,8 +113,10 @@ typedef struct {
 void cc_default_opts(cc_opts* opts);
 
 /* Creates a context.  eps[n]: canonical orbital energies (device); B[naux][n][n]
- * (device), symmetric in p, q.  Copies both; builds the two-electron
- * integrals.  opts may be NULL (defaults).  stream: hipStream_t or NULL.
+ * (device), symmetric in p, q.  Copies both; keeps the factor and builds from
+ * it only the bare blocks (ac|bd), (kc|bd) and (kc|ld) (v^4, o v^3, o^2 v^2
+ * doubles); every other integral block is formed from the factor where it is
+ * used.  opts may be NULL (defaults).  stream: hipStream_t or NULL.
  * Errors: -1 bad sizes/pointers, -4 out of device memory, -3 HIP failure.   */
 int cc_create(cc_ctx** ctx, int o, int v, int naux, const double* eps, const double* B,
               const cc_opts* opts, void* stream);
@@ -156,8 +158,10 @@ int multipliers(cc_ctx* ctx, int npairs, const int* pairs, int* iters);
 
 /* Effective densities of the pair (i, j): D_eff (n x n) and the two-electron
  * density d_eff, such that F^q = sum D_eff dh^q + 1/2 sum d_eff dg^q
- * (Sec. II C, eq. NAC_NC_densities).  Kept on the device for nacme();
- * D1 (device [n][n], may be NULL) receives D_eff.                            */
+ * (Sec. II C, eq. NAC_NC_densities).  d_eff is never formed as an n^4
+ * tensor: it is kept as occupied/virtual blocks against the density-fitted
+ * factor (the adjoints of the places where the integrals enter) on the
+ * device for nacme(); D1 (device [n][n], may be NULL) receives D_eff.       */
 int densities(cc_ctx* ctx, int i, int j, double* D1);
 
 /* Derivative coupling F_ij^q (or, for i = j, the energy gradient

@@ -41,6 +41,11 @@ static bool verbose() {
 }
 
 // ------------------------------------------------------------------ context
+// Two-electron density of a Lagrangian, kept as the adjoints of the places
+// where the integrals enter it (never as an n^4 tensor): the bare blocks W,
+// Wov, Gov and the T1-transformed blocks / Fock correction of the residual
+// graph (indexed by Use), plus the Hartree-Fock energy term of the energy
+// Lagrangian.
 struct PairData {
   double* zeta = nullptr;    // amplitude-shaped
   double* gamma = nullptr;   // amplitude-shaped
@@ -49,10 +54,17 @@ struct PairData {
   double* eta_k = nullptr;   // [o][v]
   double* dtrans = nullptr;  // [n][n] transition density
   double* Fbar = nullptr;    // [n][n]  d Phi / d f
-  double* Gbar = nullptr;    // [n]^4   d Phi / d g
   double* Deff = nullptr;    // [n][n]
-  double* Gam = nullptr;     // [n]^4   two-electron density (1/2 d_eff)
-  double* Gp = nullptr;      // [m][m]  Gam over unordered pairs p <= q, m = n(n+1)/2
+  double* gW = nullptr;      // [v][v][v][v]  d Phi / d W
+  double* gWov = nullptr;    // [v][v][o][v]  d Phi / d Wov
+  double* gGov = nullptr;    // [o][v][o][v]  d Phi / d Gov
+  double* guse[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // adjoints of the same uses in the forward derivative along R_j (the
+  // integrals' part of gamma . A R_j), when the pair has a right state
+  double* guse_t[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool has_tan = false;
+  double* Bbar = nullptr;    // [P][n][n]  d Phi / d B through every use (orbital rotation)
+  bool hf_term = false;      // energy Lagrangian: E_HF's two-electron part
   bool have_mult = false, have_dens = false;
 };
 
@@ -65,12 +77,11 @@ struct cc_ctx {
   hipStream_t s = nullptr;
   std::unique_ptr<nm::Engine> eng;
   std::vector<void*> owned;
-  nm::Tensor eps, f, g, I;
-  nm::Tensor W, Wov;   // W[c][d][a][b] = (ac|bd), Wov[c][d][k][b] = (kc|bd)
-  // virtual slices of g with the transformed index outermost, so that the
-  // annihilator transforms and their derivatives are plain GEMMs:
-  // Gc[c][p][r][s] = (p c|r s), Gvc[c][p][b][r] = (p b|r c)  (c, b virtual)
-  nm::Tensor Gc, Gvc;
+  nm::Tensor eps, f;
+  nm::Tensor B;        // density-fitting factor B[P][p][q], (pq|rs) = sum_P B[P][p][q] B[P][r][s]
+  // bare integral blocks: W[c][d][a][b] = (ac|bd), Wov[c][d][k][b] = (kc|bd),
+  // Gov[k][c][l][d] = (kc|ld)
+  nm::Tensor W, Wov, Gov;
   std::vector<double> eps_h;
   double* t = nullptr;
   bool have_guess = false;
@@ -180,25 +191,6 @@ static void axpby_(Ctx& c, double* y, const double* x, double a, double b, int64
   kc(axpby(c.s, y, x, a, b, n), "axpby");
 }
 
-static DView mat_view(const double* p, int64_t rows, int64_t cols, const char* lab) {
-  DView v;
-  v.p = const_cast<double*>(p);
-  v.nd = 2;
-  v.dims[0] = rows; v.dims[1] = cols;
-  v.str[0] = cols; v.str[1] = 1;
-  v.lab[0] = lab[0]; v.lab[1] = lab[1];
-  return v;
-}
-static DView vec_view(const double* p, int64_t n, char lab) {
-  DView v;
-  v.p = const_cast<double*>(p);
-  v.nd = 1;
-  v.dims[0] = n;
-  v.str[0] = 1;
-  v.lab[0] = lab;
-  return v;
-}
-
 // h[k] = <V_k, x> for the m rows of V ([m][n] contiguous), in one GEMV and one
 // copy to the host; `packed` selects the biorthonormal metric on
 // amplitude-shaped vectors.  work: n + m doubles.
@@ -261,76 +253,114 @@ static void sub_rows(Ctx& c, const double* V, int m, const std::vector<double>& 
 }
 
 // ------------------------------------------------------------ residual graph
+// Integral-use nodes of the residual graph: the T1-transformed two-electron
+// blocks, each sum_P Bhat_L[P](x) Bhat_R[P] of two blocks of the transformed
+// factor, and the Fock correction.  Each is bilinear in the two factor leaves,
+// so the adjoint of the node (a block of the transformed two-electron density)
+// contracted with the same node built from a direction's factor gives that
+// use's part of the coupling.
+enum Use { U_VOVO, U_OOOO, U_OOVV, U_VOOV, U_VVOV, U_VVOO, U_OOOV, U_FCORR, NUSE };
+
 struct ResNodes {
-  int t1, t2, f, g, w, wov, gc, gvc;
+  int t1, t2, f, bl, br, w, wov, gov;
   int om1, om2;
   int first;  // first non-leaf node of the residual
+  int use[NUSE];
 };
 
-// Omega(t; f, g) of closed-shell CCSD in the T1-transformed form.  The
-// transformed integrals are ghat = (X (x) Y (x) X (x) Y) g with X = 1 - t~ on
-// creator indices (1, 3) and Y = 1 + t~^T on annihilator indices (2, 4),
-// t~[a,i] = t_ai.  X is the identity on occupied creators and Y on virtual
-// annihilators, so each block of ghat only needs the transforms of its
-// virtual creators and occupied annihilators.  They are applied annihilators
-// first (shrinking an n-range to o) and only for the blocks the equations
-// use:
-//   Go  = Y_2 g            stored [i][p][r][s]  (index 2 outermost)
-//   Goo = Y_4 Go           [n][o][n][o]
-//   Gvo = Y_4 g[:,V,:,:]   stored [j][p][b][r]  (index 4 outermost)
-// then X_1 / X_3 on the virtual creators of each block.  The vvvv block only
-// enters the particle-particle ladder; that term is evaluated on the bare
-// integrals W[cd][ab] = (ac|bd) with the creator transforms written out:
+// Blocks of the T1-transformed factor Bhat[P] = X B[P] Y^T, with X = 1 - t~ on
+// creator indices and Y = 1 + t~^T on annihilator indices, t~[a,i] = t_ai (X is
+// the identity on occupied creators, Y on virtual annihilators):
+//   D[P][p][k]  = sum_c B[P][p][c] t_kc                 (p all, k occupied)
+//   Boo[P][k][l] = B[P][k][l] + D[P][k][l]
+//   Bvv[P][a][c] = B[P][a][c] - sum_l t_la B[P][l][c]
+//   Bvo[P][a][k] = B[P][a][k] + D[P][a][k] - sum_l t_la Boo[P][l][k]
+//   Bov[P][k][c] = B[P][k][c]
+struct FactorNodes { int d, oo, vv, vo; };
+static FactorNodes factor_graph(Graph& G, Ctx& c, int t1, int b) {
+  const int64_t o = c.o, v = c.v, n = c.n, P = c.naux;
+  const Range AP{0, P}, A{0, n}, O{0, o}, V{o, v}, Ol{0, o};
+  FactorNodes r;
+  r.d = G.node({P, n, o}, {mul(1, op(b, "Ppc", {AP, A, V}), op(t1, "kc"), "Ppk")});
+  r.oo = G.node({P, o, o}, {lin(1, op(b, "Pkl", {AP, O, O}), "Pkl"),
+                            lin(1, op(r.d, "Pkl", {AP, O, Ol}), "Pkl")});
+  r.vv = G.node({P, v, v}, {lin(1, op(b, "Pac", {AP, V, V}), "Pac"),
+                            mul(-1, op(t1, "la"), op(b, "Plc", {AP, O, V}), "Pac")});
+  r.vo = G.node({P, v, o}, {lin(1, op(b, "Pak", {AP, V, O}), "Pak"),
+                            lin(1, op(r.d, "Pak", {AP, V, Ol}), "Pak"),
+                            mul(-1, op(t1, "la"), op(r.oo, "Plk"), "Pak")});
+  return r;
+}
+
+// Operands of the T1-transformed two-electron use u (< U_FCORR): the block
+// sum_P a[P] (x) b[P] with output labels `out` (L, R: the transformed blocks
+// of the two factor leaves; br: the right factor leaf itself).
+struct UseSpec { Op a, b; std::string out; std::vector<int64_t> shape; };
+static UseSpec use_spec(Ctx& c, int u, const FactorNodes& L, const FactorNodes& R, int br) {
+  const int64_t o = c.o, v = c.v, P = c.naux;
+  const Range AP{0, P}, O{0, o}, V{o, v};
+  switch (u) {
+    case U_VOVO: return {op(L.vo, "Pai"), op(R.vo, "Pbj"), "aibj", {v, o, v, o}};
+    case U_OOOO: return {op(L.oo, "Pki"), op(R.oo, "Plj"), "kilj", {o, o, o, o}};
+    case U_OOVV: return {op(L.oo, "Pki"), op(R.vv, "Pac"), "kiac", {o, o, v, v}};
+    case U_VOOV: return {op(L.vo, "Pai"), op(br, "Pkc", {AP, O, V}), "aikc", {v, o, o, v}};
+    case U_VVOV: return {op(L.vv, "Pad"), op(br, "Pkc", {AP, O, V}), "adkc", {v, v, o, v}};
+    case U_VVOO: return {op(L.vv, "Pac"), op(R.oo, "Pki"), "acki", {v, v, o, o}};
+    default: return {op(L.oo, "Pki"), op(br, "Plc", {AP, O, V}), "kilc", {o, o, o, v}};
+  }
+}
+
+// Omega(t; f, g) of closed-shell CCSD in the T1-transformed form with
+// density-fitted integrals g_pqrs = sum_P B[P][p][q] B[P][r][s] (Mulliken).
+// The transformed integrals are ghat_pqrs = sum_P Bhat[P][p][q] Bhat[P][r][s];
+// the two factors of every product are separate leaves (bl, br) that hold the
+// same values, so that the graph is linear in each.  The transformed blocks
+// the equations use are built as GEMMs over P from the factor blocks above.
+// The vvvv block only enters the particle-particle ladder; that term is
+// evaluated on the bare integrals W[cd][ab] = (ac|bd) with the creator
+// transforms written out:
 //   sum_cd t_ij^cd ghat_acbd = sum_cd t_ij^cd g_acbd - sum_k t_ak Y1_ijkb
 //       - sum_l t_bl Y1_jila + sum_kl t_ak t_bl Z_ijkl,
 //   Y1_ijkb = sum_cd t_ij^cd g_kcbd,  Z_ijkl = sum_cd t_ij^cd g_kcld,
-// so that derivatives of the residual contain one ladder GEMM, not two.
-// The transformed Fock matrix is Fhat = X (f + 2 J(t1) - K(t1)) Y^T with
-// J(t1)_pq = sum_k Go[k,k,p,q] - J_pq and K(t1)_pq = sum_k Go[p,k,k,q] - K_pq.
-// The singles and doubles projections are those of the oracle's residual.
+// so that derivatives of the residual contain one ladder GEMM, not two
+// (W, Wov[c][d][k][b] = (kc|bd) and Gov[k][c][l][d] = (kc|ld) are bare leaves).
+// The transformed Fock matrix is Fhat = X (f + 2 J(t1) - K(t1)) Y^T, where
+// J(t1) - J = 2 sum_P (sum_k D[P][k][k]) B[P] and K(t1) - K =
+// sum_P D[P] B[P][occ rows]; the singles and doubles projections are those
+// of the oracle's residual.
 static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2,
-                               const Tensor& F, const Tensor& Gi, const Tensor& Wt,
-                               const Tensor& Wov) {
-  const int64_t o = c.o, v = c.v, n = c.n;
-  const Range O{0, o}, V{o, v}, A{0, n}, Vl{0, v};
+                               const Tensor& F, const Tensor& Bf, const Tensor& Wt,
+                               const Tensor& Wov, const Tensor& Gov) {
+  const int64_t o = c.o, v = c.v, n = c.n, P = c.naux;
+  const Range O{0, o}, V{o, v}, A{0, n}, AP{0, P}, Ol{0, o};
   ResNodes r;
   r.t1 = G.leaf(T1);
   r.t2 = G.leaf(T2);
   r.f = G.leaf(F);
-  r.g = G.leaf(Gi);
+  r.bl = G.leaf(Bf);
+  r.br = G.leaf(Bf);
   r.w = G.leaf(Wt);
   r.wov = G.leaf(Wov);
-  r.gc = G.leaf(c.Gc);
-  r.gvc = G.leaf(c.Gvc);
+  r.gov = G.leaf(Gov);
   r.first = G.size();
-  const int t1 = r.t1, t2 = r.t2, f = r.f, g = r.g;
-  // annihilator transforms
-  const int Go = G.node({o, n, n, n}, {lin(1, op(g, "pirs", {A, O, A, A}), "iprs"),
-                                       mul(1, op(t1, "ic"), op(r.gc, "cprs"), "iprs")});
-  const int Goo = G.node({n, o, n, o}, {lin(1, op(Go, "iprj", {O, A, A, O}), "pirj"),
-                                        mul(1, op(Go, "iprc", {O, A, A, V}), op(t1, "jc"), "pirj")});
-  const int Gvo = G.node({o, n, v, n}, {lin(1, op(g, "pbrj", {A, V, A, O}), "jpbr"),
-                                        mul(1, op(t1, "jc"), op(r.gvc, "cpbr"), "jpbr")});
-  // creator transforms of the blocks used below
-  const int Hv = G.node({v, o, n, o}, {lin(1, op(Goo, "airj", {V, O, A, O}), "airj"),
-                                       mul(-1, op(t1, "ka"), op(Goo, "kirj", {O, O, A, O}), "airj")});
-  const int gvovo = G.node({v, o, v, o}, {lin(1, op(Hv, "aibj", {Vl, O, V, O}), "aibj"),
-                                          mul(-1, op(Hv, "aikj", {Vl, O, O, O}), op(t1, "kb"), "aibj")});
-  const int goovv = G.node({o, o, v, v}, {lin(1, op(Go, "ikac", {O, O, V, V}), "kiac"),
-                                          mul(-1, op(Go, "iklc", {O, O, O, V}), op(t1, "la"), "kiac")});
-  const int gvoov = G.node({v, o, o, v}, {lin(1, op(Go, "iakc", {O, V, O, V}), "aikc"),
-                                          mul(-1, op(t1, "la"), op(Go, "ilkc", {O, O, O, V}), "aikc")});
-  const int gvvov = G.node({v, v, o, v}, {lin(1, op(g, "adkc", {V, V, O, V}), "adkc"),
-                                          mul(-1, op(t1, "la"), op(g, "ldkc", {O, V, O, V}), "adkc")});
-  const int gvvoo = G.node({v, v, o, o}, {lin(1, op(Gvo, "iack", {O, V, Vl, O}), "acki"),
-                                          mul(-1, op(t1, "la"), op(Gvo, "ilck", {O, O, Vl, O}), "acki")});
-  const Op g_ovov = op(g, "kcld", {O, V, O, V});
+  const int t1 = r.t1, t2 = r.t2, f = r.f;
+  const FactorNodes L = factor_graph(G, c, t1, r.bl), R = factor_graph(G, c, t1, r.br);
+  // transformed two-electron blocks (integral uses)
+  for (int u = 0; u < U_FCORR; ++u) {
+    const UseSpec us = use_spec(c, u, L, R, r.br);
+    r.use[u] = G.node(us.shape, {mul(1, us.a, us.b, us.out)});
+  }
+  const int gvovo = r.use[U_VOVO], goooo = r.use[U_OOOO], goovv = r.use[U_OOVV],
+            gvoov = r.use[U_VOOV], gvvov = r.use[U_VVOV], gvvoo = r.use[U_VVOO],
+            gooov = r.use[U_OOOV];
+  // Fock correction 2 (J(t1) - J) - (K(t1) - K)
+  const int trd = G.node({P}, {lin(1, op(L.d, "Pkk", {AP, O, Ol}), "P")});
+  const int fcorr = G.node({n, n}, {mul(2, op(trd, "P"), op(r.br, "Ppq"), "pq"),
+                                    mul(-1, op(L.d, "Ppk"), op(r.br, "Pkq", {AP, O, A}), "pq")});
+  r.use[U_FCORR] = fcorr;
+  const Op g_ovov = op(r.gov, "kcld");
   // transformed Fock matrix
-  const int fp = G.node({n, n}, {lin(1, op(f, "pq"), "pq"),
-                                 lin(2, op(Go, "kkpq", {O, O, A, A}), "pq"),
-                                 lin(-2, op(g, "kkpq", {O, O, A, A}), "pq"),
-                                 lin(-1, op(Go, "kpkq", {O, A, O, A}), "pq"),
-                                 lin(1, op(g, "pkkq", {A, O, O, A}), "pq")});
+  const int fp = G.node({n, n}, {lin(1, op(f, "pq"), "pq"), lin(1, op(fcorr, "pq"), "pq")});
   const int f1 = G.node({n, n}, {lin(1, op(fp, "pq"), "pq"),
                                  mul(-1, op(t1, "ka"), op(fp, "kq", {O, A}), "aq", {V, A})});
   const int Fh = G.node({n, n}, {lin(1, op(f1, "pq"), "pq"),
@@ -338,7 +368,7 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
   const int u = G.node({o, o, v, v}, {lin(2, op(t2, "ijab"), "ijab"), lin(-1, op(t2, "ijba"), "ijab")});
   // singles
   r.om1 = G.node({o, v}, {mul(1, op(u, "kicd"), op(gvvov, "adkc"), "ia"),
-                          mul(-1, op(u, "klac"), op(Go, "iklc", {O, O, O, V}), "ia"),
+                          mul(-1, op(u, "klac"), op(gooov, "kilc"), "ia"),
                           mul(1, op(u, "ikac"), op(Fh, "kc", {O, V}), "ia"),
                           lin(1, op(Fh, "ai", {V, O}), "ia")});
   // ladder pieces on bare integrals
@@ -346,54 +376,54 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
   const int Z = G.node({o, o, o, o}, {mul(1, op(t2, "ijcd"), g_ovov, "ijkl")});
   const int Zt = G.node({o, o, v, o}, {mul(1, op(t1, "ka"), op(Z, "ijkl"), "ijal")});
   // doubles
-  const int W = G.node({o, o, o, o}, {lin(1, op(Goo, "kilj", {O, O, O, O}), "kilj"),
+  const int W = G.node({o, o, o, o}, {lin(1, op(goooo, "kilj"), "kilj"),
                                       mul(1, op(t2, "ijcd"), g_ovov, "kilj")});
   const int Xc = G.node({o, o, v, v}, {lin(1, op(goovv, "kiac"), "kiac"),
-                                       mul(-0.5, op(t2, "liad"), op(g, "kdlc", {O, V, O, V}), "kiac")});
+                                       mul(-0.5, op(t2, "liad"), op(r.gov, "kdlc"), "kiac")});
   const int Lvoov = G.node({v, o, o, v}, {lin(2, op(gvoov, "aikc"), "aikc"),
                                           lin(-1, op(gvvoo, "acki"), "aikc")});
-  const int Lovov = G.node({o, v, o, v}, {lin(2, op(g, "ldkc", {O, V, O, V}), "ldkc"),
-                                          lin(-1, op(g, "lckd", {O, V, O, V}), "ldkc")});
+  const int Lovov = G.node({o, v, o, v}, {lin(2, op(r.gov, "ldkc"), "ldkc"),
+                                          lin(-1, op(r.gov, "lckd"), "ldkc")});
   const int Xd = G.node({v, o, o, v}, {lin(1, op(Lvoov, "aikc"), "aikc"),
                                        mul(0.5, op(u, "ilad"), op(Lovov, "ldkc"), "aikc")});
   const int Ev = G.node({v, v}, {lin(1, op(Fh, "bc", {V, V}), "bc"),
-                                 mul(-1, op(u, "klbd"), op(g, "ldkc", {O, V, O, V}), "bc")});
+                                 mul(-1, op(u, "klbd"), op(r.gov, "ldkc"), "bc")});
   const int Eo = G.node({o, o}, {lin(1, op(Fh, "kj", {O, O}), "kj"),
-                                 mul(1, op(u, "ljcd"), op(g, "kdlc", {O, V, O, V}), "kj")});
+                                 mul(1, op(u, "ljcd"), op(r.gov, "kdlc"), "kj")});
   // Q_ijab = sum_kc t_kjbc Xc_kiac; the exchange partner sum_kc t_kibc Xc_kjac
   // is Q with i and j swapped, added as a permutation instead of a second GEMM
   const int Q = G.node({o, o, v, v}, {mul(1, op(t2, "kjbc"), op(Xc, "kiac"), "ijab")});
-  const int P = G.node({o, o, v, v}, {lin(-0.5, op(Q, "ijab"), "ijab"),
-                                      lin(-1, op(Q, "jiab"), "ijab"),
-                                      mul(0.5, op(u, "jkbc"), op(Xd, "aikc"), "ijab"),
-                                      mul(1, op(t2, "ijac"), op(Ev, "bc"), "ijab"),
-                                      mul(-1, op(t2, "ikab"), op(Eo, "kj"), "ijab")});
+  const int Pn = G.node({o, o, v, v}, {lin(-0.5, op(Q, "ijab"), "ijab"),
+                                       lin(-1, op(Q, "jiab"), "ijab"),
+                                       mul(0.5, op(u, "jkbc"), op(Xd, "aikc"), "ijab"),
+                                       mul(1, op(t2, "ijac"), op(Ev, "bc"), "ijab"),
+                                       mul(-1, op(t2, "ikab"), op(Eo, "kj"), "ijab")});
   r.om2 = G.node({o, o, v, v}, {mul(1, op(t2, "ijcd"), op(r.w, "cdab"), "ijab"),
                                 lin(1, op(gvovo, "aibj"), "ijab"),
                                 mul(-1, op(t1, "ka"), op(Y1, "ijkb"), "ijab"),
                                 mul(-1, op(Y1, "jila"), op(t1, "lb"), "ijab"),
                                 mul(1, op(Zt, "ijal"), op(t1, "lb"), "ijab"),
                                 mul(1, op(t2, "klab"), op(W, "kilj"), "ijab"),
-                                lin(1, op(P, "ijab"), "ijab"),
-                                lin(1, op(P, "jiba"), "ijab")});
+                                lin(1, op(Pn, "ijab"), "ijab"),
+                                lin(1, op(Pn, "jiba"), "ijab")});
   return r;
 }
 
 // E_corr = 2 sum f_ia t_ai + sum (t_aibj + t_ai t_bj)(2 g_iajb - g_ibja).
-struct EnergyNodes { int t1, t2, f, g, e; };
+struct EnergyNodes { int t1, t2, f, gov, e; };
 static EnergyNodes energy_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor& T2) {
   const int64_t o = c.o, v = c.v;
   const Range O{0, o}, V{o, v};
   EnergyNodes r;
   r.t1 = G.leaf(T1);
   r.t2 = G.leaf(T2);
-  const int f = G.leaf(c.f), g = G.leaf(c.g);
+  const int f = G.leaf(c.f), g = G.leaf(c.Gov);
   r.f = f;
-  r.g = g;
+  r.gov = g;
   const int tau = G.node({o, o, v, v}, {lin(1, op(r.t2, "ijab"), "ijab"),
                                         mul(1, op(r.t1, "ia"), op(r.t1, "jb"), "ijab")});
-  const int Lb = G.node({o, v, o, v}, {lin(2, op(g, "iajb", {O, V, O, V}), "iajb"),
-                                       lin(-1, op(g, "ibja", {O, V, O, V}), "iajb")});
+  const int Lb = G.node({o, v, o, v}, {lin(2, op(g, "iajb"), "iajb"),
+                                       lin(-1, op(g, "ibja"), "iajb")});
   r.e = G.node({}, {mul(2, op(f, "ia", {O, V}), op(r.t1, "ia"), ""),
                     mul(1, op(tau, "ijab"), op(Lb, "iajb"), "")});
   return r;
@@ -409,7 +439,7 @@ static void residual(Ctx& c, double* x, double* out) {
   ++c.n_residual;
   ArenaScope sc(c.eng->arena());
   Graph G(*c.eng);
-  ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.g, c.W, c.Wov);
+  ResNodes r = residual_graph(G, c, T1of(c, x), T2of(c, x), c.f, c.B, c.W, c.Wov, c.Gov);
   const int64_t nov = (int64_t)c.o * c.v;
   copy_d(c, out, G.val(r.om1).p, nov);
   copy_d(c, out + nov, G.val(r.om2).p, c.N - nov);
@@ -446,7 +476,7 @@ struct Tape {
     // may run with low-precision operands
     const bool lp = c.eng->lowp();
     c.eng->set_lowp(false);
-    r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.g, c.W, c.Wov);
+    r = residual_graph(G, c, T1of(c, c.t), T2of(c, c.t), c.f, c.B, c.W, c.Wov, c.Gov);
     c.eng->set_lowp(lp);
     // the recorded values stay as they are while the tape lives: every
     // transform reuses their low-precision packings
@@ -982,11 +1012,12 @@ __global__ void signed_max_partial(const double* x, int o, int v, int64_t n, dou
 
 // ------------------------------------------------ learned doubles guess
 // Features of doubles index e = ((i o + j) v + a) v + b: e_i, e_j, e_a, e_b,
-// D, (ia|jb), (ib|ja), -(ia|jb)/D, standardised with mu and 1/sd.
+// D, (ia|jb), (ib|ja), -(ia|jb)/D, standardised with mu and 1/sd; g is the
+// bare block (ia|jb) stored [i][a][j][b].
 __global__ void t2_features_kernel(const double* __restrict__ g, const double* __restrict__ eps,
                                    int o, int v, const float* __restrict__ mu,
                                    const float* __restrict__ isd, float* __restrict__ F) {
-  const int64_t n = o + v, tot = (int64_t)o * o * v * v;
+  const int64_t tot = (int64_t)o * o * v * v;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
@@ -996,19 +1027,20 @@ __global__ void t2_features_kernel(const double* __restrict__ g, const double* _
     const int i = (int)(r / o);
     const double ei = eps[i], ej = eps[j], ea = eps[o + a], eb = eps[o + b];
     const double D = ea + eb - ei - ej;
-    const double giajb = g[((i * n + o + a) * n + j) * n + o + b];
-    const double gibja = g[((i * n + o + b) * n + j) * n + o + a];
+    const double giajb = g[(((int64_t)i * v + a) * o + j) * v + b];
+    const double gibja = g[(((int64_t)i * v + b) * o + j) * v + a];
     const double f[8] = {ei, ej, ea, eb, D, giajb, gibja, -giajb / D};
 #pragma unroll
     for (int k = 0; k < 8; ++k) F[e * 8 + k] = (float)((f[k] - (double)mu[k]) * (double)isd[k]);
   }
 }
 
-// z = (-D t - (ia|jb)) / scale (target) or t = -((ia|jb) + scale z) / D (guess)
+// z = (-D t - (ia|jb)) / scale (target) or t = -((ia|jb) + scale z) / D (guess);
+// g: (ia|jb) stored [i][a][j][b]
 __global__ void t2_map_kernel(const double* __restrict__ g, const double* __restrict__ eps, int o,
                               int v, double* __restrict__ t2, float* __restrict__ z, double scale,
                               int to_amplitudes) {
-  const int64_t n = o + v, tot = (int64_t)o * o * v * v;
+  const int64_t tot = (int64_t)o * o * v * v;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
@@ -1017,7 +1049,7 @@ __global__ void t2_map_kernel(const double* __restrict__ g, const double* __rest
     const int j = (int)(r % o);
     const int i = (int)(r / o);
     const double D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
-    const double giajb = g[((i * n + o + a) * n + j) * n + o + b];
+    const double giajb = g[(((int64_t)i * v + a) * o + j) * v + b];
     if (to_amplitudes)
       t2[e] = -(giajb + scale * (double)z[e]) / D;
     else
@@ -1427,60 +1459,37 @@ static int linsolve_refined(Ctx& c, int64_t n, bool packed,
 }
 
 // ------------------------------------------------------ orbital rotation
-// Integrals of exp(kappa) H exp(-kappa) to first order in kappa (exact for
-// derivatives at kappa = 0): h + K h + h K^T, g + sum of one-index K
-// insertions, and their Fock matrix; K_ai = kappa_ai, K_ia = -kappa_ai.
-struct RotNodes { int kap, fr, gr; };
+// The Hamiltonian exp(kappa) H exp(-kappa) to first order in kappa (exact
+// for derivatives at kappa = 0), K_ai = kappa_ai, K_ia = -kappa_ai: the factor
+// changes by db[P] = K B[P] + B[P] K^T, the one-electron integrals
+// h = f - 2 J[B] + X[B] (implied by the canonical Fock matrix f) by
+// K h + h K^T, and the Fock matrix of the rotated Hamiltonian, built over the
+// same occupied range, is
+//   fr = f + K h + h K^T + 2 (J(db, B) + J(B, db)) - (X(db, B) + X(B, db))
+// with J(Y, Z)_pq = sum_P (sum_k Y[P][k][k]) Z[P][p][q] and
+// X(Y, Z)_pq = sum_P sum_k Y[P][p][k] Z[P][k][q].  Derivatives of a function
+// of (f, B) along kappa are reverse sweeps of this graph seeded on fr and db.
+struct RotNodes { int kap, fr, db; };
 static RotNodes rotation_graph(Graph& G, Ctx& c, const Tensor& kappa) {
-  const int64_t o = c.o, v = c.v, n = c.n;
-  const Range O{0, o}, V{o, v}, A{0, n};
+  const int64_t o = c.o, v = c.v, n = c.n, P = c.naux;
+  const Range O{0, o}, V{o, v}, A{0, n}, AP{0, P};
   RotNodes r;
   r.kap = G.leaf(kappa);
-  const int fl = G.leaf(c.f), gl = G.leaf(c.g);
-  const int h = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"), lin(-2, op(gl, "pqkk", {A, A, O, O}), "pq"),
-                                lin(1, op(gl, "pkkq", {A, O, O, A}), "pq")});
+  const int fl = G.leaf(c.f), bl = G.leaf(c.B);
+  const int trb = G.node({P}, {lin(1, op(bl, "Pkk", {AP, O, O}), "P")});
+  const int h = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"),
+                                mul(-2, op(trb, "P"), op(bl, "Ppq"), "pq"),
+                                mul(1, op(bl, "Ppk", {AP, A, O}), op(bl, "Pkq", {AP, O, A}), "pq")});
   const int K = G.node({n, n}, {lin(1, op(r.kap, "ia"), "ai", {V, O}), lin(-1, op(r.kap, "ia"), "ia", {O, V})});
-  const int hr = G.node({n, n}, {lin(1, op(h, "pq"), "pq"), mul(1, op(K, "pt"), op(h, "tq"), "pq"),
-                                 mul(1, op(h, "pt"), op(K, "qt"), "pq")});
-  r.gr = G.node({n, n, n, n}, {lin(1, op(gl, "pqrs"), "pqrs"), mul(1, op(K, "pt"), op(gl, "tqrs"), "pqrs"),
-                               mul(1, op(K, "qt"), op(gl, "ptrs"), "pqrs"),
-                               mul(1, op(K, "rt"), op(gl, "pqts"), "pqrs"),
-                               mul(1, op(gl, "pqrt"), op(K, "st"), "pqrs")});
-  r.fr = G.node({n, n}, {lin(1, op(hr, "pq"), "pq"), lin(2, op(r.gr, "pqkk", {A, A, O, O}), "pq"),
-                         lin(-1, op(r.gr, "pkkq", {A, O, O, A}), "pq")});
-  return r;
-}
-
-// The Fock matrix of exp(kappa) H exp(-kappa) to first order in kappa from
-// the blocks of g it needs (one occupied index), for the A^HF transforms of
-// the kappa-bar equations: with J_pq = sum_k g_pqkk and X_pq = sum_k g_pkkq,
-//   J(kappa) = J + K J + J K^T + sum_kt K_kt (g_pqtk + g_pqkt),
-//   X(kappa) = X + K X + X K^T + sum_kt K_kt (g_ptkq + g_pktq),
-//   F(kappa) = h(kappa) + 2 J(kappa) - X(kappa),  h(kappa) = h + K h + h K^T,
-// the same first-order Fock matrix as rotation_graph's without its n^4 node.
-static RotNodes fock_rotation_graph(Graph& G, Ctx& c, const Tensor& kappa) {
-  const int64_t o = c.o, v = c.v, n = c.n;
-  const Range O{0, o}, V{o, v}, A{0, n};
-  RotNodes r;
-  r.kap = G.leaf(kappa);
-  const int fl = G.leaf(c.f), gl = G.leaf(c.g);
-  r.gr = -1;
-  const int J = G.node({n, n}, {lin(1, op(gl, "pqkk", {A, A, O, O}), "pq")});
-  const int X = G.node({n, n}, {lin(1, op(gl, "pkkq", {A, O, O, A}), "pq")});
-  const int h = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"), lin(-2, op(J, "pq"), "pq"),
-                                lin(1, op(X, "pq"), "pq")});
-  const int K = G.node({n, n}, {lin(1, op(r.kap, "ia"), "ai", {V, O}), lin(-1, op(r.kap, "ia"), "ia", {O, V})});
-  const int Ko = G.node({o, n}, {lin(1, op(K, "kt", {O, A}), "kt")});
-  r.fr = G.node({n, n}, {lin(1, op(h, "pq"), "pq"), mul(1, op(K, "pt"), op(h, "tq"), "pq"),
+  r.db = G.node({P, n, n}, {mul(1, op(K, "pt"), op(bl, "Ptq"), "Ppq"),
+                            mul(1, op(bl, "Ppt"), op(K, "qt"), "Ppq")});
+  const int trdb = G.node({P}, {lin(1, op(r.db, "Pkk", {AP, O, O}), "P")});
+  r.fr = G.node({n, n}, {lin(1, op(fl, "pq"), "pq"), mul(1, op(K, "pt"), op(h, "tq"), "pq"),
                          mul(1, op(h, "pt"), op(K, "qt"), "pq"),
-                         lin(2, op(J, "pq"), "pq"), mul(2, op(K, "pt"), op(J, "tq"), "pq"),
-                         mul(2, op(J, "pt"), op(K, "qt"), "pq"),
-                         mul(2, op(Ko, "kt"), op(gl, "pqtk", {A, A, A, O}), "pq"),
-                         mul(2, op(Ko, "kt"), op(gl, "pqkt", {A, A, O, A}), "pq"),
-                         lin(-1, op(X, "pq"), "pq"), mul(-1, op(K, "pt"), op(X, "tq"), "pq"),
-                         mul(-1, op(X, "pt"), op(K, "qt"), "pq"),
-                         mul(-1, op(Ko, "kt"), op(gl, "ptkq", {A, A, O, A}), "pq"),
-                         mul(-1, op(Ko, "kt"), op(gl, "pktq", {A, O, A, A}), "pq")});
+                         mul(2, op(trdb, "P"), op(bl, "Ppq"), "pq"),
+                         mul(2, op(trb, "P"), op(r.db, "Ppq"), "pq"),
+                         mul(-1, op(r.db, "Ppk", {AP, A, O}), op(bl, "Pkq", {AP, O, A}), "pq"),
+                         mul(-1, op(bl, "Ppk", {AP, A, O}), op(r.db, "Pkq", {AP, O, A}), "pq")});
   return r;
 }
 
@@ -1500,17 +1509,43 @@ static PairData& pair_of(Ctx& c, int i, int j) {
   return p;
 }
 
-static int64_t n4(Ctx& c) { return (int64_t)c.n * c.n * c.n * c.n; }
 
-// Hartree-Fock energy in terms of the Fock and Coulomb leaves,
-// E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji): its derivatives.
-__global__ void ehf_terms_kernel(double* Fbar, double* Gbar, int64_t n, int o) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)o * o) return;
-  const int64_t i = e / o, j = e - (e / o) * o;
-  Gbar[((i * n + i) * n + j) * n + j] -= 2.0;
-  Gbar[((i * n + j) * n + j) * n + i] += 1.0;
-  if (j == 0) Fbar[i * n + i] += 2.0;
+// Hartree-Fock energy E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji): its
+// derivative with respect to the Fock leaf
+__global__ void ehf_terms_kernel(double* Fbar, int64_t n, int o) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= o) return;
+  Fbar[i * n + i] += 2.0;
+}
+
+// d Phi / d B[P] from the bare blocks W[c][d][a][b] = sum_P B_ac B_bd,
+// Wov[c][d][k][b] = sum_P B_kc B_bd, Gov[k][c][l][d] = sum_P B_kc B_ld (each
+// product rule term), and, for the energy Lagrangian, from E_HF's
+// two-electron part -sum_P [2 (sum_i B_ii)^2 - sum_ij B_ij B_ji]; added to
+// the adjoint the factor leaves already hold.
+static void fold_bare_adjoints(Ctx& c, PairData& P) {
+  const int64_t o = c.o, v = c.v, n = c.n, Pn = c.naux;
+  const Range AP{0, Pn}, O{0, o}, V{o, v};
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  const int b = G.leaf(c.B);
+  const int bb = G.leaf(tview(P.Bbar, {Pn, n, n}));
+  const int gw = G.leaf(tview(P.gW, {v, v, v, v}));
+  const int gwov = G.leaf(tview(P.gWov, {v, v, o, v}));
+  const int ggov = G.leaf(tview(P.gGov, {o, v, o, v}));
+  Engine& e = *c.eng;
+  e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pbd", {AP, V, V})), G.view(op(bb, "Pac", {AP, V, V})));
+  e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pac", {AP, V, V})), G.view(op(bb, "Pbd", {AP, V, V})));
+  e.contract(1.0, G.view(op(gwov, "cdkb")), G.view(op(b, "Pbd", {AP, V, V})), G.view(op(bb, "Pkc", {AP, O, V})));
+  e.contract(1.0, G.view(op(gwov, "cdkb")), G.view(op(b, "Pkc", {AP, O, V})), G.view(op(bb, "Pbd", {AP, V, V})));
+  e.contract(1.0, G.view(op(ggov, "kcld")), G.view(op(b, "Pld", {AP, O, V})), G.view(op(bb, "Pkc", {AP, O, V})));
+  e.contract(1.0, G.view(op(ggov, "kcld")), G.view(op(b, "Pkc", {AP, O, V})), G.view(op(bb, "Pld", {AP, O, V})));
+  if (P.hf_term) {
+    // d/dB[P][p][q] = -4 s[P] delta_pq + 2 B[P][q][p]  (p, q occupied)
+    const int s = G.node({Pn}, {lin(1, op(b, "Pkk", {AP, O, O}), "P")});
+    e.linear(-4.0, G.view(op(s, "P")), G.view(op(bb, "Pkk", {AP, O, O})));
+    e.linear(2.0, G.view(op(b, "Pji", {AP, O, O})), G.view(op(bb, "Pij", {AP, O, O})));
+  }
 }
 
 // Multipliers of one Lagrangian per pair (i1, j1):
@@ -1576,11 +1611,13 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
     Tape tp(c);
     // JVP along each right state used, kept on the tape
     std::map<int, std::pair<int, int>> tanj;
+    std::map<int, std::map<int, int>> tanmap;   // right state -> node -> its tangent node
     for (const PairJob& J : jobs) {
       if (!J.has_right || tanj.count(J.j)) continue;
       const int r1 = tp.G.leaf(T1of(c, c.R[J.j])), r2 = tp.G.leaf(T2of(c, c.R[J.j]));
       auto tan = tp.G.jvp({{tp.r.t1, r1}, {tp.r.t2, r2}}, tp.r.first);
       tanj[J.j] = {tan.at(tp.r.om1), tan.at(tp.r.om2)};
+      tanmap[J.j] = tan;
     }
     phase(0);
     ArenaScope sc(ar);
@@ -1686,33 +1723,66 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
         seeds[tj.first] = J.wg;
         seeds[tj.second] = J.wg + nov;
       }
-      auto adj = tp.G.vjp(seeds, {tp.r.f, tp.r.g, tp.r.w, tp.r.wov, tp.r.gc, tp.r.gvc});
+      // adjoints of the leaves and of every integral use, primal and (along
+      // R_j) tangent
+      std::vector<int> wrt{tp.r.f, tp.r.bl, tp.r.br, tp.r.w, tp.r.wov, tp.r.gov};
+      std::vector<int> tuse(NUSE, -1);
+      for (int u = 0; u < NUSE; ++u) wrt.push_back(tp.r.use[u]);
+      if (J.has_right) {
+        const auto& tm = tanmap.at(J.j);
+        for (int u = 0; u < NUSE; ++u) {
+          auto it = tm.find(tp.r.use[u]);
+          if (it != tm.end()) {
+            tuse[u] = it->second;
+            wrt.push_back(tuse[u]);
+          }
+        }
+      }
+      auto adj = tp.G.vjp(seeds, wrt);
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
-      if (!P.Gbar) P.Gbar = palloc(c, n4(c));
-      copy_d(c, P.Gbar, adj[tp.r.g].p, n4(c));
-      // the ladder's integral copies are blocks of g: fold their adjoints back
-      Graph Gd(*c.eng);
-      const int gb = Gd.leaf(tview(P.Gbar, {c.n, c.n, c.n, c.n}));
-      const Range O{0, c.o}, V{c.o, c.v};
-      c.eng->linear(1.0, full_view(adj[tp.r.w], "cdab"), Gd.view(op(gb, "acbd", {V, V, V, V})));
-      c.eng->linear(1.0, full_view(adj[tp.r.wov], "cdkb"), Gd.view(op(gb, "kcbd", {O, V, V, V})));
-      const Range Al{0, c.n};
-      c.eng->linear(1.0, full_view(adj[tp.r.gc], "cprs"), Gd.view(op(gb, "pcrs", {Al, V, Al, Al})));
-      c.eng->linear(1.0, full_view(adj[tp.r.gvc], "cpbr"), Gd.view(op(gb, "pbrc", {Al, V, Al, V})));
+      const int64_t v4 = (int64_t)c.v * c.v * c.v * c.v, v3o = (int64_t)c.v * c.v * c.v * c.o,
+                    o2v2 = (int64_t)c.o * c.o * c.v * c.v, nB = (int64_t)c.naux * nn;
+      if (!P.gW) P.gW = palloc(c, v4);
+      if (!P.gWov) P.gWov = palloc(c, v3o);
+      if (!P.gGov) P.gGov = palloc(c, o2v2);
+      if (!P.Bbar) P.Bbar = palloc(c, nB);
+      copy_d(c, P.gW, adj[tp.r.w].p, v4);
+      copy_d(c, P.gWov, adj[tp.r.wov].p, v3o);
+      copy_d(c, P.gGov, adj[tp.r.gov].p, o2v2);
+      copy_d(c, P.Bbar, adj[tp.r.bl].p, nB);
+      axpby_(c, P.Bbar, adj[tp.r.br].p, 1.0, 1.0, nB);
+      for (int u = 0; u < NUSE; ++u) {
+        const Tensor& a = adj[tp.r.use[u]];
+        if (!P.guse[u]) P.guse[u] = palloc(c, a.size());
+        copy_d(c, P.guse[u], a.p, a.size());
+        if (tuse[u] >= 0) {
+          const Tensor& at = adj[tuse[u]];
+          if (!P.guse_t[u]) P.guse_t[u] = palloc(c, at.size());
+          copy_d(c, P.guse_t[u], at.p, at.size());
+        }
+      }
+      P.has_tan = J.has_right;
+      P.hf_term = false;
       if (J.grad_mode) {
-        // + dE0/d(f, g): correlation energy by the energy graph, E_HF by hand
+        // + dE0/d(f, g): correlation energy by the energy graph (f and the
+        // bare (ia|jb) block), E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji):
+        // its f part here, its two-electron part where the factor enters
         Graph Ge(*c.eng);
         EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
         double* one = c.eng->scalar_slot(62);
         kc(fill(c.s, one, 1.0, 1), "fill");
-        auto adje = Ge.vjp({{en.e, one}}, {en.f, en.g});
+        auto adje = Ge.vjp({{en.e, one}}, {en.f, en.gov});
         axpby_(c, P.Fbar, adje[en.f].p, 1.0, 1.0, nn);
-        axpby_(c, P.Gbar, adje[en.g].p, 1.0, 1.0, n4(c));
-        const int64_t oo = (int64_t)c.o * c.o;
+        axpby_(c, P.gGov, adje[en.gov].p, 1.0, 1.0, o2v2);
+        const int64_t oo = (int64_t)c.o;
         hipLaunchKernelGGL(ehf_terms_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
-                           P.Fbar, P.Gbar, (int64_t)c.n, c.o);
+                           P.Fbar, (int64_t)c.n, c.o);
         hip_check(hipGetLastError(), "HF energy terms");
+        P.hf_term = true;
       }
+      // the bare blocks are products of the factor: fold their adjoints into
+      // d Phi / d B (for the orbital-rotation derivative)
+      fold_bare_adjoints(c, P);
     }
   }
   phase(3);
@@ -1727,8 +1797,6 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
     kc(fill(c.s, k0, 0.0, nov), "fill");
     Graph G(*c.eng);
     RotNodes rn = rotation_graph(G, c, tview(k0, {c.o, c.v}));
-    Graph Gf(*c.eng);
-    RotNodes fn = fock_rotation_graph(Gf, c, tview(k0, {c.o, c.v}));
     double* b = ar.alloc(nov);
     double* seed = ar.alloc(nn);
     // (A^HF)^T x, A^HF_(ai),(bj) = dF_ai/dkappa_bj
@@ -1742,8 +1810,8 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       vs.obase = (int64_t)c.o * c.n;
       vs.istr[0] = c.v; vs.istr[1] = 1;
       kc(view_gather(c.s, seed, x, vs, 1.0, 0.0), "embed");
-      auto adj = Gf.vjp({{fn.fr, seed}}, {fn.kap});
-      copy_d(c, y, adj[fn.kap].p, nov);
+      auto adj = G.vjp({{rn.fr, seed}}, {rn.kap});
+      copy_d(c, y, adj[rn.kap].p, nov);
     };
     // preconditioner: orbital-energy differences on the singles block
     auto pre1 = [&](double* y, const double* x) {
@@ -1760,7 +1828,7 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       // eta_kappa = -(D_ai - D_ia) + d/dkappa Phi
       {
         ArenaScope s2(ar);
-        auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.gr, P.Gbar}}, {rn.kap});
+        auto adj = G.vjp({{rn.fr, P.Fbar}, {rn.db, P.Bbar}}, {rn.kap});
         copy_d(c, P.eta_k, adj[rn.kap].p, nov);
       }
       if (!J.grad_mode) {
@@ -1797,145 +1865,120 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
   return status;
 }
 
-// Index k of the unordered pair p <= q (row-major upper triangle of n x n)
-// and its multiplicity among the ordered pairs (2 off the diagonal).
-__device__ inline void pair_of_index(int64_t k, int64_t n, int64_t& p, int64_t& q) {
-  // rows p hold n - p entries; find p with start(p) <= k < start(p + 1)
-  int64_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) / 2;
-    if (mid * n - mid * (mid - 1) / 2 <= k) lo = mid; else hi = mid - 1;
-  }
-  p = lo;
-  q = p + (k - (p * n - p * (p - 1) / 2));
-}
-
-// Gp[k][l] = (Gam[p][q][r][s] + Gam[q][p][r][s] + Gam[p][q][s][r] + Gam[q][p][s][r]) / 4
-// for k = (p <= q), l = (r <= s): the part of Gam that meets integrals
-// symmetric in p <-> q and r <-> s.
-__global__ void pack_pairs_kernel(const double* __restrict__ Gam, int64_t n, int64_t m,
-                                  double* __restrict__ Gp) {
-  const int64_t tot = m * m;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = e / m, l = e - (e / m) * m;
-    int64_t p, q, r, s;
-    pair_of_index(k, n, p, q);
-    pair_of_index(l, n, r, s);
-    const int64_t pq = p * n + q, qp = q * n + p, rs = r * n + s, sr = s * n + r, nn = n * n;
-    Gp[e] = 0.25 * (Gam[pq * nn + rs] + Gam[qp * nn + rs] + Gam[pq * nn + sr] + Gam[qp * nn + sr]);
-  }
-}
-
-// U[row][k] = mult(k) * dB[row][p][q] for the rows of the direction factors
-// (row = (q, P)), k = (p <= q), mult = 2 off the diagonal
-__global__ void pack_factor_kernel(const double* __restrict__ dB, int64_t rows, int64_t n, int64_t m,
-                                   double* __restrict__ U) {
-  const int64_t tot = rows * m;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = e / m, k = e - (e / m) * m;
-    int64_t p, q;
-    pair_of_index(k, n, p, q);
-    U[e] = (p == q ? 1.0 : 2.0) * dB[row * n * n + p * n + q];
-  }
-}
-
-// D_eff = dPhi/df + kappa-bar embedded in the vo block; the two-electron
-// density Gamma = dPhi/dg + 2 D_eff(pq) delta_rs(occ) - D_eff(ps) delta_qr(occ)
-// so that F^q = sum D_eff dh^q + sum Gamma dg^q.
+// D_eff = dPhi/df + kappa-bar embedded in the vo block (Sec. II C); the
+// two-electron density stays as the adjoints of its uses (PairData).
 static void densities_impl(Ctx& c, int i1, int j1) {
   PairData& P = c.pairs.at({i1, j1});
   const int64_t nn = (int64_t)c.n * c.n;
   copy_d(c, P.Deff, P.Fbar, nn);
-  {
-    ViewSpec vs;  // Deff[o+a][i] += kbar[i][a]
-    vs.nd = 2;
-    vs.dims[0] = c.o; vs.dims[1] = c.v;
-    vs.ostr[0] = 1; vs.ostr[1] = c.n;
-    vs.obase = (int64_t)c.o * c.n;
-    vs.istr[0] = c.v; vs.istr[1] = 1;
-    kc(view_gather(c.s, P.Deff, P.kbar, vs, 1.0, 1.0), "kappa embed");
-  }
-  if (!P.Gam) P.Gam = palloc(c, n4(c));
-  copy_d(c, P.Gam, P.Gbar, n4(c));
-  ArenaScope sc(c.eng->arena());
-  Graph G(*c.eng);
-  const Range O{0, c.o}, A{0, c.n};
-  const int d = G.leaf(tview(P.Deff, {c.n, c.n}));
-  const int gm = G.leaf(tview(P.Gam, {c.n, c.n, c.n, c.n}));
-  (void)gm;
-  // broadcast adds into diagonal views of Gamma
-  DView src = full_view(G.val(d), "pq");
-  {
-    Op o1 = op(gm, "pqkk", {A, A, O, O});
-    DView dst;
-    {
-      // build the merged view by hand (p, q, k with k stride n + 1)
-      const int64_t n = c.n;
-      dst.p = P.Gam;
-      dst.nd = 3;
-      dst.lab[0] = 'p'; dst.lab[1] = 'q'; dst.lab[2] = 'k';
-      dst.dims[0] = n; dst.dims[1] = n; dst.dims[2] = c.o;
-      dst.str[0] = n * n * n; dst.str[1] = n * n; dst.str[2] = n + 1;
-    }
-    c.eng->linear(2.0, src, dst);
-    (void)o1;
-  }
-  {
-    const int64_t n = c.n;
-    DView dst;
-    dst.p = P.Gam;
-    dst.nd = 3;
-    dst.lab[0] = 'p'; dst.lab[1] = 'q'; dst.lab[2] = 'k';
-    dst.dims[0] = n; dst.dims[1] = n; dst.dims[2] = c.o;
-    dst.str[0] = n * n * n; dst.str[1] = 1; dst.str[2] = n * n + n;   // Gam[p][k][k][q]
-    c.eng->linear(-1.0, src, dst);
-  }
-  // the directions' integrals are symmetric in p <-> q and r <-> s: keep Gam
-  // over unordered index pairs for the coupling contraction
-  {
-    const int64_t n = c.n, m = n * (n + 1) / 2;
-    if (!P.Gp) P.Gp = palloc(c, m * m);
-    const int g = (int)std::min<int64_t>((m * m + 255) / 256, 65536);
-    hipLaunchKernelGGL(pack_pairs_kernel, dim3(g), dim3(256), 0, c.s, P.Gam, n, m, P.Gp);
-    hip_check(hipGetLastError(), "pair packing");
-  }
+  ViewSpec vs;  // Deff[o+a][i] += kbar[i][a]
+  vs.nd = 2;
+  vs.dims[0] = c.o; vs.dims[1] = c.v;
+  vs.ostr[0] = 1; vs.ostr[1] = c.n;
+  vs.obase = (int64_t)c.o * c.n;
+  vs.istr[0] = c.v; vs.istr[1] = 1;
+  kc(view_gather(c.s, P.Deff, P.kbar, vs, 1.0, 1.0), "kappa embed");
   P.have_dens = true;
 }
 
-// F^q = sum_pq D_eff dh^q + sum_P sum_(pq),(rs) dB^P_pq Gam_pqrs dB^P_rs.  With
-// u^P[k] = mult(k) dB^P[p][q] over unordered pairs k = (p <= q) the second
-// term is sum_P u^P . (Gp u^P): one GEMM [rows = directions x naux] x [m] x [m]
-// per chunk of directions (m = n(n+1)/2, a quarter of the n^2 x n^2 flops),
-// then one dot product per direction.
+// F^q = sum D_eff dh^q + sum Gamma dg^q with dg^q = sum_P dB^q[P] (x) dB^q[P]
+// (Sec. II C, eq. NAC_NC), the second term summed over the places where the
+// integrals enter the Lagrangian: every use is bilinear in the factor, so its
+// share is the use's adjoint contracted with the same use built from dB^q
+// (T1-transformed with the ground amplitudes, and along R_j for the uses in
+// gamma . A R_j); the bare blocks W, Wov, Gov directly; the Fock matrix's own
+// dependence on g (f = h + 2 J - K) through D_eff; and, for the energy
+// Lagrangian, E_HF's two-electron part.  Each such share is one GEMM over the
+// direction's factor and a dot product.
+static double coupling_direction(Ctx& c, PairData& P, int j1, const double* dhq, const double* dBq) {
+  const int64_t o = c.o, v = c.v, n = c.n, Pn = c.naux, nn = n * n;
+  const Range AP{0, Pn}, O{0, o}, V{o, v}, A{0, n}, Ol{0, o};
+  ArenaScope sc(c.eng->arena());
+  Graph G(*c.eng);
+  const int t1 = G.leaf(T1of(c, c.t));
+  const int db = G.leaf(tview(const_cast<double*>(dBq), {Pn, n, n}));
+  const int first = G.size();
+  const FactorNodes Fd = factor_graph(G, c, t1, db);
+  std::map<int, int> tan;
+  const bool has_tan = P.has_tan && j1 > 0;
+  if (has_tan) {
+    const int r1 = G.leaf(T1of(c, c.R[j1 - 1]));
+    tan = G.jvp({{t1, r1}}, first);
+  }
+  std::vector<int> terms;
+  auto dot_of = [&](double alpha, const Op& x, const Op& y) {
+    terms.push_back(G.node({}, {mul(alpha, x, y, "")}));
+  };
+  auto tangent = [&](const Op& x) -> Op {
+    auto it = tan.find(x.node);
+    Op t = x;
+    t.node = (it == tan.end()) ? -1 : it->second;
+    return t;
+  };
+  // T1-transformed two-electron uses
+  for (int u = 0; u < U_FCORR; ++u) {
+    const UseSpec us = use_spec(c, u, Fd, Fd, db);
+    const int gu = G.leaf(tview(P.guse[u], us.shape));
+    const std::vector<int64_t> zs = G.val(us.a.node).shape();
+    auto share = [&](int gnode, const Op& a, const Op& b) {
+      if (a.node < 0 || b.node < 0) return;
+      const int z = G.node(zs, {mul(1, op(gnode, us.out), b, us.a.lab)});
+      dot_of(1, a, op(z, us.a.lab));
+    };
+    share(gu, us.a, us.b);
+    if (has_tan && P.guse_t[u]) {
+      const int gt = G.leaf(tview(P.guse_t[u], us.shape));
+      share(gt, tangent(us.a), us.b);
+      share(gt, us.a, tangent(us.b));
+    }
+  }
+  // Fock correction 2 sum_P tr(D[P]) B[P] - sum_P D[P] B[P][occ rows]
+  auto fcorr_share = [&](const double* gbar, int dnode) {
+    const int fc = G.leaf(tview(const_cast<double*>(gbar), {n, n}));
+    const int y = G.node({Pn}, {mul(1, op(fc, "pq"), op(db, "Ppq"), "P")});
+    const int trd = G.node({Pn}, {lin(1, op(dnode, "Pkk", {AP, O, Ol}), "P")});
+    dot_of(2, op(trd, "P"), op(y, "P"));
+    const int zk = G.node({Pn, n, o}, {mul(1, op(fc, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
+    dot_of(-1, op(dnode, "Ppk"), op(zk, "Ppk"));
+  };
+  fcorr_share(P.guse[U_FCORR], Fd.d);
+  if (has_tan && P.guse_t[U_FCORR] && tan.count(Fd.d)) fcorr_share(P.guse_t[U_FCORR], tan.at(Fd.d));
+  // bare blocks
+  const int gw = G.leaf(tview(P.gW, {v, v, v, v}));
+  const int zw = G.node({Pn, v, v}, {mul(1, op(gw, "cdab"), op(db, "Pbd", {AP, V, V}), "Pac")});
+  dot_of(1, op(db, "Pac", {AP, V, V}), op(zw, "Pac"));
+  const int gwov = G.leaf(tview(P.gWov, {v, v, o, v}));
+  const int zov = G.node({Pn, o, v}, {mul(1, op(gwov, "cdkb"), op(db, "Pbd", {AP, V, V}), "Pkc")});
+  dot_of(1, op(db, "Pkc", {AP, O, V}), op(zov, "Pkc"));
+  const int ggov = G.leaf(tview(P.gGov, {o, v, o, v}));
+  const int zg = G.node({Pn, o, v}, {mul(1, op(ggov, "kcld"), op(db, "Pld", {AP, O, V}), "Pkc")});
+  dot_of(1, op(db, "Pkc", {AP, O, V}), op(zg, "Pkc"));
+  // the Fock matrix's dependence on g: 2 D_eff.J(dg) - D_eff.K(dg)
+  const int de = G.leaf(tview(P.Deff, {n, n}));
+  const int s = G.node({Pn}, {lin(1, op(db, "Pkk", {AP, O, O}), "P")});
+  const int yd = G.node({Pn}, {mul(1, op(de, "pq"), op(db, "Ppq"), "P")});
+  dot_of(2, op(s, "P"), op(yd, "P"));
+  const int zd = G.node({Pn, n, o}, {mul(1, op(de, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
+  dot_of(-1, op(db, "Ppk", {AP, A, O}), op(zd, "Ppk"));
+  // E_HF two-electron part: -sum_ij (2 dg_iijj - dg_ijji)
+  if (P.hf_term) {
+    dot_of(-2, op(s, "P"), op(s, "P"));
+    dot_of(1, op(db, "Pij", {AP, O, O}), op(db, "Pji", {AP, O, O}));
+  }
+  std::vector<Term> sum;
+  for (int t : terms) sum.push_back(lin(1, op(t, ""), ""));
+  const int tot = G.node({}, sum);
+  const double f2 = d2h(c, G.val(tot).p);
+  const double f1 = dot_plain(c, P.Deff, dhq, nn);
+  return f1 + f2;
+}
+
 static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const double* dB,
                        double* F) {
   PairData& P = c.pairs.at({i1, j1});
-  const int64_t n = c.n, nn = n * n, naux = c.naux, m = n * (n + 1) / 2;
-  Arena& ar = c.eng->arena();
-  ArenaScope sc(ar);
-  // directions per chunk: U and Z of about 3 GB each at most
-  const int64_t per_dir = naux * m;
-  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(3.0e9 / 8.0) / per_dir));
-  double* U = ar.alloc((int64_t)chunk * per_dir);
-  double* Z = ar.alloc((int64_t)chunk * per_dir);
-  for (int q0 = 0; q0 < nq; q0 += chunk) {
-    const int kq = std::min(chunk, nq - q0);
-    const int64_t rows = (int64_t)kq * naux;
-    const int g = (int)std::min<int64_t>((rows * m + 255) / 256, 65536);
-    hipLaunchKernelGGL(pack_factor_kernel, dim3(g), dim3(256), 0, c.s, dB + (int64_t)q0 * naux * nn,
-                       rows, n, m, U);
-    hip_check(hipGetLastError(), "factor packing");
-    kc(gemm_f64(c.s, false, false, (int)rows, (int)m, (int)m, 1, 1.0, U, m, 0, P.Gp, m, 0, 0.0, Z,
-                m, 0),
-       "nacme gemm");
-    for (int q = 0; q < kq; ++q) {
-      const double f1 = dot_plain(c, P.Deff, dh + (int64_t)(q0 + q) * nn, nn);
-      const double f2 = dot_plain(c, Z + (int64_t)q * per_dir, U + (int64_t)q * per_dir, per_dir);
-      F[q0 + q] = f1 + f2;
-    }
-  }
+  const int64_t nn = (int64_t)c.n * c.n;
+  for (int q = 0; q < nq; ++q)
+    F[q] = coupling_direction(c, P, j1, dh + (int64_t)q * nn, dB + (int64_t)q * c.naux * nn);
 }
 
 }  // namespace nm
@@ -2018,36 +2061,29 @@ int cc_create(cc_ctx** out, int o, int v, int naux, const double* eps, const dou
       vs.istr[0] = 1;
       nm::kc(nm::view_gather(c->s, c->f.p, c->eps.p, vs, 1.0, 0.0), "diag");
     }
-    // g_pqrs = sum_P B[P][pq] B[P][rs]
-    c->g = nm::tview(nm::palloc(*c, nn * nn), {n, n, n, n});
-    nm::kc(nm::gemm_f64(c->s, true, false, (int)nn, (int)nn, naux, 1, 1.0, B, nn, 0, B, nn, 0, 0.0, c->g.p,
-                        nn, 0),
-           "eri build");
+    // the factor (kept) and the bare blocks the residual uses directly:
+    // W[c][d][a][b] = (ac|bd), Wov[c][d][k][b] = (kc|bd), Gov[k][c][l][d] = (kc|ld),
+    // each one GEMM over P
+    c->B = nm::tview(nm::palloc(*c, (int64_t)naux * nn), {naux, n, n});
+    nm::copy_d(*c, c->B.p, B, (int64_t)naux * nn);
     {
-      // GEMM-ready copies of the all-virtual and one-occupied blocks
       const int64_t vv = (int64_t)v * v;
       c->W = nm::tview(nm::palloc(*c, vv * vv), {v, v, v, v});
       c->Wov = nm::tview(nm::palloc(*c, vv * v * o), {v, v, o, v});
+      c->Gov = nm::tview(nm::palloc(*c, (int64_t)o * v * o * v), {o, v, o, v});
       nm::Graph G(*c->eng);
-      const int gl = G.leaf(c->g);
-      const nm::Range Oo{0, o}, Vv{o, v};
-      nm::DView src = nm::full_view(c->g, "acbd");
-      (void)src;
-      nm::Term tw = nm::lin(1, nm::op(gl, "acbd", {Vv, Vv, Vv, Vv}), "cdab");
-      nm::Term to = nm::lin(1, nm::op(gl, "kcbd", {Oo, Vv, Vv, Vv}), "cdkb");
-      const int iw = G.leaf(c->W), io = G.leaf(c->Wov);
-      c->eng->linear(1.0, G.view(tw.a), nm::full_view(G.val(iw), "cdab"), true);
-      c->eng->linear(1.0, G.view(to.a), nm::full_view(G.val(io), "cdkb"), true);
-      const nm::Range Aa{0, n};
-      c->Gc = nm::tview(nm::palloc(*c, (int64_t)v * n * n * n), {v, n, n, n});
-      c->Gvc = nm::tview(nm::palloc(*c, (int64_t)v * n * v * n), {v, n, v, n});
-      c->eng->linear(1.0, G.view(nm::op(gl, "pcrs", {Aa, Vv, Aa, Aa})), nm::full_view(c->Gc, "cprs"), true);
-      c->eng->linear(1.0, G.view(nm::op(gl, "pbrc", {Aa, Vv, Aa, Vv})), nm::full_view(c->Gvc, "cpbr"), true);
+      const int bl = G.leaf(c->B);
+      const nm::Range Oo{0, o}, Vv{o, v}, AP{0, naux};
+      c->eng->contract(1.0, G.view(nm::op(bl, "Pac", {AP, Vv, Vv})), G.view(nm::op(bl, "Pbd", {AP, Vv, Vv})),
+                       nm::full_view(c->W, "cdab"), true);
+      c->eng->contract(1.0, G.view(nm::op(bl, "Pkc", {AP, Oo, Vv})), G.view(nm::op(bl, "Pbd", {AP, Vv, Vv})),
+                       nm::full_view(c->Wov, "cdkb"), true);
+      c->eng->contract(1.0, G.view(nm::op(bl, "Pkc", {AP, Oo, Vv})), G.view(nm::op(bl, "Pld", {AP, Oo, Vv})),
+                       nm::full_view(c->Gov, "kcld"), true);
       // W[cd][ab] = (ac|bd) = (ca|db) = W[ab][cd] for real orbitals and a
       // factor symmetric in p, q
       c->W.pair_sym = true;
-      c->W.constant = c->Wov.constant = c->g.constant = true;
-      c->Gc.constant = c->Gvc.constant = true;
+      c->W.constant = c->Wov.constant = c->Gov.constant = c->B.constant = true;
     }
     c->t = nm::palloc(*c, c->N);
     nm::kc(nm::fill(c->s, c->t, 0.0, c->N), "fill");
@@ -2300,7 +2336,7 @@ int cc_t2_features(cc_ctx* c, const float* mu, const float* sd, float* F) {
     const float* nrm = nm::feature_norm(*c, mu, sd);
     const int64_t tot = (int64_t)c->o * c->o * c->v * c->v;
     const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    hipLaunchKernelGGL(nm::t2_features_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o,
+    hipLaunchKernelGGL(nm::t2_features_kernel, dim3(g), dim3(256), 0, c->s, c->Gov.p, c->eps.p, c->o,
                        c->v, nrm, nrm + 8, F);
     nm::hip_check(hipGetLastError(), "t2 features");
     nm::sync(*c);
@@ -2317,7 +2353,7 @@ int cc_t2_target(cc_ctx* c, float scale, float* Z) {
   try {
     const int64_t tot = (int64_t)c->o * c->o * c->v * c->v, nov = (int64_t)c->o * c->v;
     const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o, c->v,
+    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->Gov.p, c->eps.p, c->o, c->v,
                        c->t + nov, Z, (double)scale, 0);
     nm::hip_check(hipGetLastError(), "t2 target");
     nm::sync(*c);
@@ -2345,7 +2381,7 @@ int cc_guess_t2(cc_ctx* c, nm_mlp* net, const float* mu, const float* sd, float 
     }
     nm::kc(nm::fill(c->s, c->t, 0.0, nov), "fill");
     const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->g.p, c->eps.p, c->o, c->v,
+    hipLaunchKernelGGL(nm::t2_map_kernel, dim3(g), dim3(256), 0, c->s, c->Gov.p, c->eps.p, c->o, c->v,
                        c->t + nov, Z, (double)scale, 1);
     nm::hip_check(hipGetLastError(), "t2 guess");
     // the network sees (i, a) and (j, b) in order: restore t_ij^ab = t_ji^ba

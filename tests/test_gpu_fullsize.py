@@ -201,8 +201,9 @@ def test_full_size_multipliers_satisfy_oracle_equations(nm, system, coupling_run
     eta_o = torch.func.grad(lambda d: rs.overlap(d, Li, R0j, Rj, O, V))(zero)
     gt = torch.func.grad(lambda y: rs.lagrangian_hamiltonian_part(
         y, m["gamma"], m["zeta"], Rj, h, g, O, V))(x)
-    # the solver's tolerance is 1e-9 relative to the right-hand side's norm
-    scale_t = max(1.0, float(torch.linalg.norm(eta_o)), float(torch.linalg.norm(gt)))
+    # the solver's tolerance is 1e-9 relative to the norm of the right-hand
+    # side eta_t = -A^T zeta (the oracle's left transform of zeta gives it)
+    scale_t = max(1.0, float(torch.linalg.norm(rs.left_transform(x, m["zeta"], h, g, O, V))))
     res_t = float(torch.linalg.norm(gt + eta_o))
     say(f"[full size] |dL/dt| = {res_t:.2e} (scale {scale_t:.2e})")
     assert res_t < 1e-8 * scale_t
@@ -217,7 +218,10 @@ def test_full_size_multipliers_satisfy_oracle_equations(nm, system, coupling_run
                 + torch.sum(m["kappa_bar"] * rs.fock_ai(hr, gr, O)))
 
     gk = torch.func.grad(lag_k)(k0)
-    scale_k = max(1.0, float(torch.linalg.norm(k1)), float(torch.linalg.norm(gk)))
+    # relative to the right-hand side's norm, eta_kappa = -(A^HF)^T kappa_bar
+    f_ai = lambda k: rs.fock_ai(*rs.rotate(h, g, k, O, V), O)  # noqa: E731
+    _, pull = torch.func.vjp(f_ai, k0)
+    scale_k = max(1.0, float(torch.linalg.norm(pull(m["kappa_bar"])[0])))
     res_k = float(torch.linalg.norm(gk + k1))
     say(f"[full size] |dL/dkappa| = {res_k:.2e} (scale {scale_k:.2e})")
     assert res_k < 1e-8 * scale_k
