@@ -439,6 +439,9 @@ int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch,
 // buffered LDS rows of 32 bf16 with the 16-byte chunks XOR-swizzled (64 KB, two
 // workgroups per CU), XCD-grouped tile order as the other kernels.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16-byte register chunk (a native vector: a HIP uint4 is a struct that is
+// copied by memcpy and can be left in private or shared memory)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int HBK = 32, HKS = 32;
 // 16-byte chunk c of tile row r sits at chunk c ^ ((r >> 2) & 3): the 16 rows
 // x one chunk of a quarter-wave's operand read cover all 64 banks
@@ -558,8 +561,8 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
     int64_t ldc, int64_t sC, int Klast) {
   static_assert(WM * WN == 8, "eight waves");
   constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
-  constexpr int NCH = (BM + BN) * 8 / 512;   // 16-byte chunks per thread per K step
-  static_assert((4 * BM) % 512 == 0 && (4 * BN) % 512 == 0, "chunk rounds per array");
+  // 16-byte chunks per thread and operand half per K step: rows / 128
+  constexpr int RA = BM / 128, RB = BN / 128;
   __shared__ __attribute__((aligned(16))) uint16_t SA[2][2][BM * HKS];
   __shared__ __attribute__((aligned(16))) uint16_t SB[2][2][BN * HKS];
   const int64_t bz = blockIdx.z;
@@ -577,55 +580,74 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int lr = lane & 15, lk = lane >> 4;
-  // chunk q = tid + 512 r runs over [A hi: 4 BM][A lo: 4 BM][B hi: 4 BN][B lo: 4 BN]
-  constexpr int RA = 4 * BM / 512, RB = 4 * BN / 512;
-  const uint16_t* src[NCH];
-  bool ok[NCH];
-  int sto[NCH];
+  // this thread's rows: (tid >> 2) + 128 r, 16-byte chunk tid & 3 of the
+  // 32-wide K step, in each of A hi, A lo (r < RA) and B hi, B lo (r < RB)
+  const int row0 = tid >> 2, ch = tid & 3;
+  int64_t aoff[RA], boff[RB];
+  bool aok[RA], bok[RB];
 #pragma unroll
-  for (int r = 0; r < NCH; ++r) {
-    int q = tid + 512 * r;
-    const bool isA = r < 2 * RA;
-    const bool lo = isA ? (r >= RA) : (r >= 2 * RA + RB);
-    q -= isA ? (lo ? 4 * BM : 0) : (lo ? 8 * BM + 4 * BN : 8 * BM);
-    const int row = q >> 2, ch = q & 3;
-    if (isA) {
-      ok[r] = m0 + row < M;
-      src[r] = (lo ? Al : Ah) + (int64_t)(ok[r] ? m0 + row : 0) * lda + 8 * ch;
-    } else {
-      ok[r] = n0 + row < N;
-      src[r] = (lo ? Bl : Bh) + (int64_t)(ok[r] ? n0 + row : 0) * ldb + 8 * ch;
-    }
-    sto[r] = swz(row, ch);
+  for (int r = 0; r < RA; ++r) {
+    aok[r] = m0 + row0 + 128 * r < M;
+    aoff[r] = (int64_t)(aok[r] ? m0 + row0 + 128 * r : 0) * lda + 8 * ch;
   }
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  uint4 reg[NCH];
-  auto gload = [&](int t) {
-    const int64_t k0 = (int64_t)t * HBK;
 #pragma unroll
-    for (int r = 0; r < NCH; ++r) reg[r] = ok[r] ? *(const uint4*)(src[r] + k0) : zero;
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < NCH; ++r) {
-      const bool isA = r < 2 * RA;
-      const bool lo = isA ? (r >= RA) : (r >= 2 * RA + RB);
-      uint16_t* base = isA ? SA[buf][lo] : SB[buf][lo];
-      *(uint4*)&base[sto[r]] = reg[r];
-    }
-  };
+  for (int r = 0; r < RB; ++r) {
+    bok[r] = n0 + row0 + 128 * r < N;
+    boff[r] = (int64_t)(bok[r] ? n0 + row0 + 128 * r : 0) * ldb + 8 * ch;
+  }
+  // rows outside the matrix read row 0 of the panel instead (always valid):
+  // they only reach accumulators of output rows or columns that are never
+  // stored, so they need no zeroing
+  u32x4 rah[RA], ral[RA], rbh[RB], rbl[RB];
   v4f acc[FI][FJ];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
     for (int j = 0; j < FJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nk = K / HBK;
-  gload(0);
-  sstore(0);
+  // prologue: K step 0 into stage 0
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    rah[r] = *(const u32x4*)(Ah + aoff[r]);
+    ral[r] = *(const u32x4*)(Al + aoff[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    rbh[r] = *(const u32x4*)(Bh + boff[r]);
+    rbl[r] = *(const u32x4*)(Bl + boff[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    *(u32x4*)&SA[0][0][swz(row0 + 128 * r, ch)] = rah[r];
+    *(u32x4*)&SA[0][1][swz(row0 + 128 * r, ch)] = ral[r];
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    *(u32x4*)&SB[0][0][swz(row0 + 128 * r, ch)] = rbh[r];
+    *(u32x4*)&SB[0][1][swz(row0 + 128 * r, ch)] = rbl[r];
+  }
   __syncthreads();
+  // loop-carried K offset of the loads (uniform; the streams keep their
+  // global base pointers, so the loads stay global rather than flat)
+  int64_t kof = 0;
   for (int t = 0; t < nk; ++t) {
     const int cur = t & 1;
-    if (t + 1 < nk) gload(t + 1);
+    // next K step (the last step reloads itself: every load is unconditional,
+    // so its wait falls after this step's products, at the LDS store)
+    kof += t + 1 < nk ? HBK : 0;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      rah[r] = *(const u32x4*)(Ah + aoff[r] + kof);
+      ral[r] = *(const u32x4*)(Al + aoff[r] + kof);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      rbh[r] = *(const u32x4*)(Bh + boff[r] + kof);
+      rbl[r] = *(const u32x4*)(Bl + boff[r] + kof);
+    }
+    // keep the loads ahead of this step's products (the scheduler would
+    // otherwise sink them next to their LDS stores and expose their latency)
+    __builtin_amdgcn_sched_barrier(0);
     bf16x8 bh[FJ], bl[FJ];
 #pragma unroll
     for (int j = 0; j < FJ; ++j) {
@@ -648,7 +670,21 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
       for (int j = 0; j < FJ; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
     }
-    if (t + 1 < nk) sstore(cur ^ 1);
+    // the other stage (unread since the last barrier); on the last step
+    // nothing reads it again.  The stores wait for this step's loads, so they
+    // stay behind the products.
+    __builtin_amdgcn_sched_barrier(0);
+    const int nx = cur ^ 1;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      *(u32x4*)&SA[nx][0][swz(row0 + 128 * r, ch)] = rah[r];
+      *(u32x4*)&SA[nx][1][swz(row0 + 128 * r, ch)] = ral[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      *(u32x4*)&SB[nx][0][swz(row0 + 128 * r, ch)] = rbh[r];
+      *(u32x4*)&SB[nx][1][swz(row0 + 128 * r, ch)] = rbl[r];
+    }
     __syncthreads();
   }
 #pragma unroll
