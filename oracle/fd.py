@@ -49,14 +49,20 @@ def richardson(fn, delta):
 
 
 def fd_unrelaxed(st, i, j, dh, dg, delta=1e-4):
+    """i = GROUND: the bra <HF| (1 + Lambda) exp(-T0), whose reference part
+    projects (R0 + R) exp(T) |HF> on R0."""
     o, v = st["o"], st["v"]
     dh, dg = as_t(dh), as_t(dg)
+    Li = response.ground_left(st) if i == response.GROUND else st["L"][i]
     vals = []
     for lam in (delta, -delta):
         h = st["h"] + lam * dh
         g = st["g"] + lam * dg
         _, _, x, R0, R = _right_state_at(st, j, h, g, (st["t1"], st["t2"]))
-        vals.append(float(response.overlap(x - st["x"], st["L"][i], R0, R, o, v)))
+        val = float(response.overlap(x - st["x"], Li, R0, R, o, v))
+        if i == response.GROUND:
+            val += float(R0)
+        vals.append(val)
     return (vals[0] - vals[1]) / (2.0 * delta)
 
 
@@ -93,8 +99,12 @@ class CIStates:
         return c
 
     def bra(self, i):
+        """<HF| L_i exp(-T0) as a CI vector; i = GROUND: <HF| (1 + Lambda) exp(-T0)."""
         st, ds = self.st, self.ds
-        ell = ds.dual_vector(st["L"][i].numpy(), self.M, self.S)
+        if i == response.GROUND:
+            ell = ds.hf() + ds.dual_vector(response.ground_left(st).numpy(), self.M, self.S)
+        else:
+            ell = ds.dual_vector(st["L"][i].numpy(), self.M, self.S)
         return ds.exp_excite(st["t1"].numpy(), st["t2"].numpy(), ell, sign=-1.0,
                              transpose=True)
 
@@ -139,7 +149,8 @@ def hellmann_feynman_two_electron(st, i, j, dh, dg, ci: CIStates | None = None):
     b, c = ci.bra(i), ci.ket0(j)
     Hc = ci.ds.H(np.asarray(dh), np.asarray(dg), c)
     wj = response.right_state(st, j)[0]
-    return float(np.sum(b * Hc)) / float(wj - st["omega"][i])
+    wi = 0.0 if i == response.GROUND else float(st["omega"][i])
+    return float(np.sum(b * Hc)) / float(wj - wi)
 
 
 def _state_energy_at(st, j, h, g):

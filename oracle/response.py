@@ -112,6 +112,18 @@ def overlap(dT, L, R0, R, o, v):
     return torch.dot(L, ccsd.pack(s1, s2))
 
 
+def reference_transition_density(x, R0, R, o, v, n):
+    """D_pq = <HF| exp(-T) E_pq (R0 + R) exp(T) |HF> (the reference row of a
+    bra, L0 = 1): R0 E(h1) + eta(h1).R for the one-electron operator h1,
+    differentiated with respect to h1."""
+    g0 = torch.zeros((n, n, n, n), dtype=DT)
+
+    def functional(h1):
+        return R0 * energy_vec(x, h1, g0, o, v) + torch.dot(eta(x, h1, g0, o, v), R)
+
+    return grad(functional)(torch.zeros((n, n), dtype=DT))
+
+
 def transition_density(x, L, R0, R, o, v, n):
     """D_pq = <HF| L exp(-T) E_pq (R0 + R) exp(T) |HF> (L0 = 0).
 
@@ -208,6 +220,16 @@ def solve_kappa(st: dict, eta_k):
     return torch.linalg.solve(AHF.T, -eta_k.reshape(-1)).reshape(o, v)
 
 
+def ground_left(st: dict):
+    """Lambda of the ground-state left state <psi_0^L| = <HF| (1 + Lambda)
+    exp(-T): the left eigenvector of the Jacobian bordered by the reference
+    row [[0, eta], [0, A]] with eigenvalue 0, (1, Lambda), so that
+    A^T Lambda = -eta (Sec. II C, eq. nac with i = 0).  Cached in st."""
+    if "Lambda" not in st:
+        st["Lambda"] = solve_zeta(st, eta(st["x"], st["h"], st["g"], st["o"], st["v"]))
+    return st["Lambda"]
+
+
 def right_state(st: dict, j: int):
     """(omega_j, R0_j, R_j) of the right state j of a pair.  The ground state
     exp(T)|HF> (Sec. II C, j = 0) has R0 = 1, R = 0 and no EOM condition, so
@@ -217,14 +239,19 @@ def right_state(st: dict, j: int):
     return st["omega"][j], st["R0"][j], st["R"][j]
 
 
-def lagrangian_hamiltonian_part(x, gamma, zeta, Rj, h, g, o, v):
-    """gamma . A(t; h, g) R_j + zeta . Omega(t; h, g)."""
-    return (torch.dot(gamma, right_transform(x, Rj, h, g, o, v))
-            + torch.dot(zeta, omega_vec(x, h, g, o, v)))
+def lagrangian_hamiltonian_part(x, gamma, zeta, Rj, h, g, o, v, gamma0=0.0):
+    """gamma . A(t; h, g) R_j + zeta . Omega(t; h, g) (+ gamma0 eta(t; h, g).R_j,
+    the reference row of the excited-state condition, for a ground-state bra)."""
+    val = (torch.dot(gamma, right_transform(x, Rj, h, g, o, v))
+           + torch.dot(zeta, omega_vec(x, h, g, o, v)))
+    if gamma0:
+        val = val + gamma0 * torch.dot(eta(x, h, g, o, v), Rj)
+    return val
 
 
 def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
-    """Multipliers of the ordered pair (i, j), i != j excited, or j = GROUND.
+    """Multipliers of the ordered pair (i, j): i != j excited, j = GROUND
+    (i excited), or i = GROUND (j excited).
 
     gamma = L_i/(omega_j - omega_i) and xi = -omega_j gamma.R_j (Sec. II B);
     t-stationarity A^T zeta = -eta_t with
@@ -232,28 +259,43 @@ def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
     kappa-stationarity (A^HF)^T kappa_bar = -eta_kappa with
     eta_kappa = d/dkappa [O + zeta.Omega + gamma.(A R_j)] under
     H -> exp(kappa) H exp(-kappa) and |psi_j^R> -> exp(-kappa) |psi_j^R>.
+
+    i = GROUND: the bra is <HF| (1 + Lambda) exp(-T) (``ground_left``,
+    omega_0 = 0).  Its reference weight makes R0_j enter the overlap, so the
+    excited-state condition keeps its reference row eta.R_j - omega_j R0_j,
+    whose multiplier is gamma0 = 1/omega_j (stationarity in R0_j); gamma =
+    Lambda/omega_j then satisfies the R_j condition because Lambda A = -eta,
+    and xi = -(R0_j + Lambda.R_j) = -<psi_0^L|psi_j^R> = 0.
     """
     o, v, h, g, x = st["o"], st["v"], st["h"], st["g"], st["x"]
     n = o + v
     om, L = st["omega"], st["L"]
-    Li = L[i]
     wj, R0j, Rj = right_state(st, j)
-    gamma = torch.zeros_like(Li) if j == GROUND else Li / (wj - om[i])
-    xi = -wj * torch.dot(gamma, Rj)
+    if i == GROUND:
+        Li, wi = ground_left(st), 0.0
+        gamma0 = 1.0 / wj
+    else:
+        Li, wi = L[i], om[i]
+        gamma0 = 0.0
+    gamma = torch.zeros_like(Li) if j == GROUND else Li / (wj - wi)
+    xi = -wj * (torch.dot(gamma, Rj) + gamma0 * R0j)
     # eta_t
     zero = torch.zeros_like(x)
     eta_o = grad(lambda d: overlap(d, Li, R0j, Rj, o, v))(zero)
-    eta_f = grad(lambda y: torch.dot(gamma, right_transform(y, Rj, h, g, o, v)))(x)
+    eta_f = grad(lambda y: lagrangian_hamiltonian_part(
+        y, gamma, torch.zeros_like(y), Rj, h, g, o, v, gamma0))(x)
     eta_t = eta_o + eta_f
     zeta = solve_zeta(st, eta_t)
-    out = dict(gamma=gamma, xi=xi, eta_t=eta_t, eta_t_overlap=eta_o, zeta=zeta)
+    out = dict(gamma=gamma, gamma0=gamma0, xi=xi, eta_t=eta_t, eta_t_overlap=eta_o, zeta=zeta)
     D = transition_density(x, Li, R0j, Rj, o, v, n)
+    if i == GROUND:
+        D = D + reference_transition_density(x, R0j, Rj, o, v, n)
     out["D"] = D
     if relaxed:
         k1 = -(D[o:, :o].T - D[:o, o:])
         k0 = torch.zeros((o, v), dtype=DT)
         k23 = grad(lambda k: lagrangian_hamiltonian_part(
-            x, gamma, zeta, Rj, *rotate(h, g, k, o, v), o, v))(k0)
+            x, gamma, zeta, Rj, *rotate(h, g, k, o, v), o, v, gamma0))(k0)
         eta_k = k1 + k23
         kbar = solve_kappa(st, eta_k)
         out.update(eta_kappa=eta_k, eta_kappa_overlap=k1, kappa_bar=kbar)
@@ -264,11 +306,12 @@ def multipliers(st: dict, i: int, j: int, relaxed: bool = True) -> dict:
 
 # ----------------------------------------------------------- coupling
 def coupling_direct(st: dict, mult: dict, j: int, dh, dg) -> float:
-    """F^q = gamma.(A(t; H^q) R_j) + zeta.Omega(t; H^q) + kappa_bar.F^q_ai (Sec. II C)."""
+    """F^q = gamma.(A(t; H^q) R_j) + zeta.Omega(t; H^q) + kappa_bar.F^q_ai (Sec. II C),
+    plus gamma0 eta(t; H^q).R_j for a ground-state bra."""
     o, v, x = st["o"], st["v"], st["x"]
     dh, dg = as_t(dh), as_t(dg)
     val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"], right_state(st, j)[2],
-                                      dh, dg, o, v)
+                                      dh, dg, o, v, mult.get("gamma0", 0.0))
     val = val + torch.sum(mult["kappa_bar"] * fock_ai(dh, dg, o))
     return float(val)
 
@@ -286,7 +329,8 @@ def effective_densities(st: dict, mult: dict, j: int):
 
     def functional(h, g):
         val = lagrangian_hamiltonian_part(x, mult["gamma"], mult["zeta"],
-                                          right_state(st, j)[2], h, g, o, v)
+                                          right_state(st, j)[2], h, g, o, v,
+                                          mult.get("gamma0", 0.0))
         return val + torch.sum(mult["kappa_bar"] * fock_ai(h, g, o))
 
     h0 = torch.zeros((n, n), dtype=DT)

@@ -264,6 +264,61 @@ def test_ground_pair_relaxed_matches_finite_difference(o, v):
     assert abs(rs.coupling_from_densities(D, d, dh, dg) - F) < 1e-12 * max(1.0, abs(F))
 
 
+# ------------------------------------------------ ground-state left state
+@pytest.mark.parametrize("o,v", [(1, 6), (2, 3), (3, 9)])
+def test_ground_bra_is_left_eigenvector_and_biorthogonal(o, v):
+    """(1, Lambda) is the left eigenvector with eigenvalue 0 of the Jacobian
+    bordered by the reference row, and the CI bra <HF| (1 + Lambda) exp(-T)
+    is biorthonormal to the ground and excited CI kets (brute force in
+    determinant space)."""
+    st = solved(o, v)
+    lam = rs.ground_left(st)
+    et = rs.eta(st["x"], st["h"], st["g"], o, v)
+    assert torch.abs(st["A"].T @ lam + et).max() < 1e-10 * max(1.0, float(et.abs().max()))
+    ci = fd.CIStates(st)
+    b = ci.bra(GROUND)
+    assert abs(float(np.sum(b * ci.ket0(GROUND))) - 1.0) < 1e-10
+    for j in range(st["omega"].numel()):
+        assert abs(float(np.sum(b * ci.ket0(j)))) < 1e-9
+
+
+def test_ground_bra_two_electron_closed_form():
+    """Exact states: F_0j = <psi_0^L|H^q|psi_j^R>/(E_j - E0)."""
+    st = solved(1, 6)
+    ci = fd.CIStates(st)
+    for j in range(3):
+        m = rs.multipliers(st, GROUND, j, relaxed=True)
+        assert torch.abs(m["kappa_bar"]).max() < 1e-10
+        assert abs(m["xi"]) < 1e-10
+        for dh, dg in directions(st, 2):
+            F = rs.coupling_direct(st, m, j, dh, dg)
+            assert abs(F - fd.hellmann_feynman_two_electron(st, GROUND, j, dh, dg, ci)) < 1e-9
+
+
+@pytest.mark.parametrize("o,v", [(1, 10), (3, 9)])
+def test_ground_bra_unrelaxed_matches_finite_difference(o, v):
+    st = solved(o, v)
+    (dh, dg), = directions(st, 1)
+    for j in range(2):
+        m = rs.multipliers(st, GROUND, j, relaxed=False)
+        F = rs.coupling_direct(st, m, j, dh, dg)
+        Fr = fd.richardson(lambda d: fd.fd_unrelaxed(st, GROUND, j, dh, dg, delta=d), 1e-4)
+        assert abs(F - Fr) < 1e-7 * max(1.0, abs(F))
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 9)])
+def test_ground_bra_relaxed_matches_finite_difference(o, v):
+    st = solved(o, v)
+    ci = fd.CIStates(st)
+    (dh, dg), = directions(st, 1)
+    m = rs.multipliers(st, GROUND, 0, relaxed=True)
+    F = rs.coupling_direct(st, m, 0, dh, dg)
+    Fr = fd.richardson(lambda d: fd.fd_relaxed(st, GROUND, 0, dh, dg, delta=d, ci=ci), 1e-4)
+    assert abs(F - Fr) < 1e-7 * max(1.0, abs(F))
+    D, d = rs.effective_densities(st, m, 0)
+    assert abs(rs.coupling_from_densities(D, d, dh, dg) - F) < 1e-12 * max(1.0, abs(F))
+
+
 # ------------------------------------------------ state-energy gradients
 @pytest.mark.parametrize("o,v,relaxed", [(1, 6, True), (2, 3, True), (3, 9, True), (3, 9, False)])
 def test_energy_gradient_matches_finite_difference(o, v, relaxed):
