@@ -102,7 +102,8 @@ typedef struct {
   int maxit;           /* iteration cap of every solver                        */
   int diis_dim;        /* DIIS history of the ground-state solver              */
   int davidson_block;  /* extra trial vectors beyond nroots                    */
-  int davidson_max;    /* subspace size before a restart                       */
+  int davidson_max;    /* subspace size before a restart (Davidson; the      */
+                       /* linear solvers use min(120, max(it, 4 k + 4)))     */
   double mixed_min_flops; /* CC_FP32_REFINE: contractions with fewer flops     */
                           /* stay fp64 (default 1e9)                           */
 } cc_opts;
@@ -142,6 +143,12 @@ int eom_solve(cc_ctx* ctx, int side, int nroots, double* omega, int* iters);
  *  - j = 0 < i: coupling F_i0 of the excited left state i with the CC ground
  *    state exp(T)|HF> (R0 = 1, R = 0): gamma = 0 and zeta = -L_i/omega_i in
  *    closed form (Sec. II C); only kappa-bar is solved;
+ *  - i = 0 < j: coupling F_0j of the ground-state left state
+ *    <HF| (1 + Lambda) exp(-T) (eq. nac with i = 0), Lambda from
+ *    A^T Lambda = -eta (solved on first use, kept until the next cc_ground);
+ *    gamma = Lambda/omega_j, and the reference row of the excited-state
+ *    condition (multiplier 1/omega_j) adds d/dt (eta . R_j) / omega_j to
+ *    eta_t and its f-derivative to the transition density;
  *  - i = j: gradient of the state energy E_j = E0 + omega_j (E0 for j = 0)
  *    from the same stationarity conditions, with dE0/dt + F(L_j) R_j in
  *    place of eta_t and no overlap term; then densities(j, j) and
@@ -224,7 +231,8 @@ int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, co
 /* As nm_gemm, with the workgroup tile of the bfloat16-pair kernel chosen by
  * `tile` (precision CC_BF16X3_REFINE only): 0 = 128 x 128 outputs per
  * workgroup (two per CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one
- * per CU), -1 = the library's model of the fastest shape (what nm_gemm and
+ * per CU), 4 = 256 x 128 and 5 = 128 x 256 with the global loads issued two
+ * K steps ahead, -1 = the library's model of the fastest shape (what nm_gemm and
  * the contraction engine use before the autotuner has timed a shape).
  * -1 (ARG) for a tile with another precision.                              */
 int nm_gemm_tiled(int precision, int tile, int ta, int tb, int M, int N, int K, double alpha,

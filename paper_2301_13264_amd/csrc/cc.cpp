@@ -41,11 +41,18 @@ static bool verbose() {
 }
 
 // ------------------------------------------------------------------ context
+// Operand groups of the one-sided two-electron density blocks, by what a
+// perturbation direction supplies for the unlifted half of each integral use:
+// vo(dB) and oo(dB) (T1-transformed blocks of its factor), their forward
+// derivatives along R1_j, and the bare dB_ov block.
+enum { G_VO, G_VOT, G_OO, G_OOT, G_OV, NGRP };
+
 // Two-electron density of a Lagrangian, kept as the adjoints of the places
 // where the integrals enter it (never as an n^4 tensor): the bare blocks W,
 // Wov, Gov and the T1-transformed blocks / Fock correction of the residual
 // graph (indexed by Use), plus the Hartree-Fock energy term of the energy
-// Lagrangian.
+// Lagrangian.  densities() lifts one half of every use onto the packed pairs
+// of the factor (gam); the vvvv block stays factorised.
 struct PairData {
   double* zeta = nullptr;    // amplitude-shaped
   double* gamma = nullptr;   // amplitude-shaped
@@ -55,7 +62,11 @@ struct PairData {
   double* dtrans = nullptr;  // [n][n] transition density
   double* Fbar = nullptr;    // [n][n]  d Phi / d f
   double* Deff = nullptr;    // [n][n]
-  double* gW = nullptr;      // [v][v][v][v]  d Phi / d W
+  // vvvv block d Phi / d W[c][d][a][b] = sum_ij t_ij^cd Y0_ij^ab
+  // (+ R_ij^cd Y1_ij^ab, R = R_jr): Y0 (and Y1), the adjoints of the ladder's
+  // output in the residual (and in its derivative along R_jr)
+  double* ylad = nullptr;    // [nlad][o][o][v][v]
+  int nlad = 0, jr = -1;
   double* gWov = nullptr;    // [v][v][o][v]  d Phi / d Wov
   double* gGov = nullptr;    // [o][v][o][v]  d Phi / d Gov
   double* guse[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -65,6 +76,12 @@ struct PairData {
   bool has_tan = false;
   double* Bbar = nullptr;    // [P][n][n]  d Phi / d B through every use (orbital rotation)
   bool hf_term = false;      // energy Lagrangian: E_HF's two-electron part
+  // one-sided blocks [gcols][m]: column group g (offset goff[g], glen[g]
+  // operand entries) holds, for each operand entry, the lifted half of the
+  // uses as a linear form on the packed symmetric pairs of the factor
+  // (m = n (n + 1) / 2, order [oo | ov | vv])
+  double* gam = nullptr;
+  int64_t goff[NGRP] = {0, 0, 0, 0, 0}, glen[NGRP] = {0, 0, 0, 0, 0}, gcols = 0;
   bool have_mult = false, have_dens = false;
 };
 
@@ -99,6 +116,10 @@ struct cc_ctx {
   bool sticky = false;
   int64_t n_right = 0, n_left = 0, n_residual = 0;
   double* rows_part = nullptr;   // partial sums of multi-row dot products
+  // Lambda of the ground-state left state <HF| (1 + Lambda) exp(-T)
+  // (A^T Lambda = -eta), solved on first use by a pair (0, j)
+  double* Lam = nullptr;
+  bool have_lam = false;
 };
 
 namespace nm {
@@ -277,15 +298,18 @@ struct ResNodes {
 //   Bvo[P][a][k] = B[P][a][k] + D[P][a][k] - sum_l t_la Boo[P][l][k]
 //   Bov[P][k][c] = B[P][k][c]
 struct FactorNodes { int d, oo, vv, vo; };
-static FactorNodes factor_graph(Graph& G, Ctx& c, int t1, int b) {
-  const int64_t o = c.o, v = c.v, n = c.n, P = c.naux;
+static FactorNodes factor_graph(Graph& G, Ctx& c, int t1, int b, bool with_vv = true) {
+  // P: the leaf's leading extent (the auxiliary index, or any batch of
+  // factor-shaped matrices)
+  const int64_t o = c.o, v = c.v, n = c.n, P = G.val(b).d[0];
   const Range AP{0, P}, A{0, n}, O{0, o}, V{o, v}, Ol{0, o};
   FactorNodes r;
   r.d = G.node({P, n, o}, {mul(1, op(b, "Ppc", {AP, A, V}), op(t1, "kc"), "Ppk")});
   r.oo = G.node({P, o, o}, {lin(1, op(b, "Pkl", {AP, O, O}), "Pkl"),
                             lin(1, op(r.d, "Pkl", {AP, O, Ol}), "Pkl")});
-  r.vv = G.node({P, v, v}, {lin(1, op(b, "Pac", {AP, V, V}), "Pac"),
-                            mul(-1, op(t1, "la"), op(b, "Plc", {AP, O, V}), "Pac")});
+  r.vv = !with_vv ? -1
+                   : G.node({P, v, v}, {lin(1, op(b, "Pac", {AP, V, V}), "Pac"),
+                                        mul(-1, op(t1, "la"), op(b, "Plc", {AP, O, V}), "Pac")});
   r.vo = G.node({P, v, o}, {lin(1, op(b, "Pak", {AP, V, O}), "Pak"),
                             lin(1, op(r.d, "Pak", {AP, V, Ol}), "Pak"),
                             mul(-1, op(t1, "la"), op(r.oo, "Plk"), "Pak")});
@@ -1205,7 +1229,9 @@ static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
   if (k < 1 || k > kMaxBlockRhs) throw Error(-1, "linear solver block size out of range");
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
-  const int maxm = std::min(kMaxRows - kMaxBlockRhs, 120);
+  // subspace size: as the Davidson solver's (davidson_max), at least room
+  // for four blocks of k vectors
+  const int maxm = std::min({kMaxRows - kMaxBlockRhs, 120, std::max(c.opts.davidson_max, 4 * k + 4)});
   double* V = ar.alloc((int64_t)maxm * n);
   double* W = ar.alloc((int64_t)maxm * n);
   double* Rr = ar.alloc((int64_t)k * n);      // residuals T x_r - b_r
@@ -1510,12 +1536,29 @@ static PairData& pair_of(Ctx& c, int i, int j) {
 }
 
 
-// Hartree-Fock energy E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji): its
-// derivative with respect to the Fock leaf
-__global__ void ehf_terms_kernel(double* Fbar, int64_t n, int o) {
+// M[i][i] += a for the occupied i (e.g. the derivative of the Hartree-Fock
+// energy E_HF = 2 sum_i f_ii - sum_ij (2 g_iijj - g_ijji) by the Fock leaf)
+__global__ void diag_occ_add_kernel(double* M, int64_t n, int o, double a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= o) return;
-  Fbar[i * n + i] += 2.0;
+  M[i * n + i] += a;
+}
+
+// The vvvv block d Phi / d W[c][d][a][b] from its factors, as a node of G:
+// the ladder sum_cd t_ij^cd W[c][d][a][b] is the only place W enters the
+// residual, so its adjoint is t2 (and R2 along R_jr) times the ladder
+// output's adjoint.
+static int vvvv_density(Graph& G, Ctx& c, const PairData& P) {
+  const int64_t o = c.o, v = c.v, o2v2 = o * o * v * v;
+  const int t2 = G.leaf(T2of(c, c.t));
+  const int y0 = G.leaf(tview(P.ylad, {o, o, v, v}));
+  std::vector<Term> terms{mul(1, op(t2, "ijcd"), op(y0, "ijab"), "cdab")};
+  if (P.nlad > 1) {
+    const int r2 = G.leaf(T2of(c, c.R[P.jr]));
+    const int y1 = G.leaf(tview(P.ylad + o2v2, {o, o, v, v}));
+    terms.push_back(mul(1, op(r2, "ijcd"), op(y1, "ijab"), "cdab"));
+  }
+  return G.node({v, v, v, v}, terms);
 }
 
 // d Phi / d B[P] from the bare blocks W[c][d][a][b] = sum_P B_ac B_bd,
@@ -1530,7 +1573,7 @@ static void fold_bare_adjoints(Ctx& c, PairData& P) {
   Graph G(*c.eng);
   const int b = G.leaf(c.B);
   const int bb = G.leaf(tview(P.Bbar, {Pn, n, n}));
-  const int gw = G.leaf(tview(P.gW, {v, v, v, v}));
+  const int gw = vvvv_density(G, c, P);
   const int gwov = G.leaf(tview(P.gWov, {v, v, o, v}));
   const int ggov = G.leaf(tview(P.gGov, {o, v, o, v}));
   Engine& e = *c.eng;
@@ -1556,15 +1599,40 @@ static void fold_bare_adjoints(Ctx& c, PairData& P) {
 //    solution zeta = -L_i / omega_i (L_i is a left eigenvector) (Sec. II C);
 //  * i1 = j1: gradient of the state energy E_j = E0 + L_j.(A R_j) (E0 alone
 //    for j1 = 0): Phi = E0 + zeta.Omega + L_j.(A R_j), no overlap term, so
-//    eta_t = dE0/dt + F(L_j) R_j and eta_kappa = d Phi / d kappa.
+//    eta_t = dE0/dt + F(L_j) R_j and eta_kappa = d Phi / d kappa;
+//  * i1 = 0 < j1: coupling F_0j of the ground-state left state
+//    <HF| (1 + Lambda) exp(-T), the left eigenvector (1, Lambda) of the
+//    Jacobian bordered by the reference row (eq. nac with i = 0), Lambda from
+//    A^T Lambda = -eta (solved first, kept in the context).  Its reference
+//    weight brings R0_j into the overlap, so the excited-state condition keeps
+//    its reference row eta.R_j - omega_j R0_j, with multiplier 1/omega_j:
+//    Phi gains eta(t; f, g).R_j / omega_j (the energy's derivative along
+//    R_j), gamma = Lambda/omega_j, and the transition density gains the
+//    reference row R0_j dE/df + d(eta.R_j)/df (its first term cancels the
+//    E(f) (Lambda . R_j) = -R0_j E(f) of the Lambda part).
 // All pairs share one recording of the residual graph and one forward
 // derivative along each right state R_j they use; their zeta equations
 // A^T zeta = -eta_t (eq. amplituderelax) are solved together, in blocks of up
 // to kMaxBlockRhs right-hand sides that go through each left transform as one
 // batch.  iters: [npairs][2] (zeta, kappa-bar iterations).
+// The energy graph at the current amplitudes with its forward derivative
+// along the right state j: te is dE/dt . R_j = eta(t; f, g) . R_j.
+struct EnergyTangent {
+  Graph G;
+  EnergyNodes en;
+  int te = -1;
+  EnergyTangent(Ctx& c, int j) : G(*c.eng) {
+    en = energy_graph(G, c, T1of(c, c.t), T2of(c, c.t));
+    const int r1 = G.leaf(T1of(c, c.R[j])), r2 = G.leaf(T2of(c, c.R[j]));
+    te = G.jvp({{en.t1, r1}, {en.t2, r2}}).at(en.e);
+  }
+};
+
 struct PairJob {
   int i1, j1;
   bool grad_mode, has_right;
+  bool ground_bra = false;   // i1 = 0 < j1: the bra <HF| (1 + Lambda) exp(-T)
+  const double* Lleft = nullptr;   // left amplitudes of the bra (L_i or Lambda)
   int i, j;
   double wi, R0j;
   PairData* P;
@@ -1581,17 +1649,19 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
     J.j1 = pl[p].second;
     J.grad_mode = (J.i1 == J.j1);
     J.has_right = (J.j1 > 0);
+    J.ground_bra = (J.i1 == 0 && J.j1 > 0);
     J.i = J.i1 - 1;
     J.j = J.j1 - 1;
     J.P = &pair_of(c, J.i1, J.j1);
     J.wi = (J.i1 > 0) ? c.omega_r[J.i] : 0.0;
     J.R0j = J.has_right ? c.R0[J.j] : 1.0;
     PairData& P = *J.P;
+    J.Lleft = J.ground_bra ? nullptr : (J.i1 > 0 ? c.L[J.i] : nullptr);
     if (J.grad_mode && J.has_right)
       copy_d(c, P.gamma, c.L[J.j], N);
     else if (!J.has_right)
       kc(fill(c.s, P.gamma, 0.0, N), "fill");
-    else
+    else if (!J.ground_bra)
       axpby_(c, P.gamma, c.L[J.i], 1.0 / (c.omega_r[J.j] - J.wi), 0.0, N);
   }
   Arena& ar = c.eng->arena();
@@ -1622,6 +1692,39 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
     phase(0);
     ArenaScope sc(ar);
     double* tmp = ar.alloc(N);
+    // Lambda of the ground-state bra: A^T Lambda = -eta, eta = dE0/dt
+    bool need_lam = false;
+    for (const PairJob& J : jobs) need_lam = need_lam || J.ground_bra;
+    if (need_lam && !c.have_lam) {
+      if (!c.Lam) c.Lam = palloc(c, N);
+      ArenaScope s2(ar);
+      double* b = ar.alloc(N);
+      {
+        Graph Ge(*c.eng);
+        EnergyNodes en = energy_graph(Ge, c, T1of(c, c.t), T2of(c, c.t));
+        double* one = c.eng->scalar_slot(62);
+        kc(fill(c.s, one, 1.0, 1), "fill");
+        auto adj = Ge.vjp({{en.e, one}}, {en.t1, en.t2});
+        copy_d(c, tmp, adj[en.t1].p, nov);
+        copy_d(c, tmp + nov, adj[en.t2].p, N - nov);
+      }
+      kc(apply_metric(c.s, b, tmp, c.o, c.v, 1), "metric");
+      axpby_(c, b, b, -1.0, 0.0, N);
+      auto T = [&](const double* x, double* y, int kk) { tp.left_block(x, y, kk); };
+      auto pre = [&](double* y, const double* x) {
+        kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
+      };
+      int itl = 0;
+      const int st = linsolve_block(c, N, true, 1, T, pre, b, c.Lam, c.opts.tol_mult, c.opts.maxit, &itl,
+                                    mixed(c));
+      if (st != CC_OK) status = st;
+      c.have_lam = (st == CC_OK);
+    }
+    for (PairJob& J : jobs)
+      if (J.ground_bra) {
+        J.Lleft = c.Lam;
+        axpby_(c, J.P->gamma, c.Lam, 1.0 / c.omega_r[J.j], 0.0, N);
+      }
     for (PairJob& J : jobs) {
       PairData& P = *J.P;
       J.wg = ar.alloc(N);
@@ -1636,6 +1739,19 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
         kc(apply_metric(c.s, P.eta_t, tmp, c.o, c.v, 1), "metric");
       } else {
         kc(fill(c.s, P.eta_t, 0.0, N), "fill");
+      }
+      if (J.ground_bra) {
+        // reference row: (1/omega_j) d/dt [eta(t) . R_j]
+        ArenaScope s2(ar);
+        EnergyTangent et(c, J.j);
+        double* g0 = c.eng->scalar_slot(61);
+        kc(fill(c.s, g0, 1.0 / c.omega_r[J.j], 1), "fill");
+        auto adj = et.G.vjp({{et.te, g0}}, {et.en.t1, et.en.t2});
+        copy_d(c, tmp, adj[et.en.t1].p, nov);
+        copy_d(c, tmp + nov, adj[et.en.t2].p, N - nov);
+        double* e2 = ar.alloc(N);
+        kc(apply_metric(c.s, e2, tmp, c.o, c.v, 1), "metric");
+        axpby_(c, P.eta_t, e2, 1.0, 1.0, N);
       }
       if (J.grad_mode) {
         // dE0/dt (packed-gradient convention), added to eta_t
@@ -1657,17 +1773,17 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
         Graph Gs(*c.eng);
         const double* sv = nullptr;
         if (J.has_right) {
-          const int l2 = Gs.leaf(T2of(c, c.L[J.i])), rr1 = Gs.leaf(T1of(c, c.R[J.j]));
+          const int l2 = Gs.leaf(T2of(c, const_cast<double*>(J.Lleft))), rr1 = Gs.leaf(T1of(c, c.R[J.j]));
           const int sn = Gs.node({c.o, c.v}, {mul(1, op(l2, "ijab"), op(rr1, "jb"), "ia"),
                                               mul(1, op(l2, "iiaa"), op(rr1, "ia"), "ia")});
           sv = Gs.val(sn).p;
         }
-        axpby_(c, P.eta_t, c.L[J.i], J.R0j, 1.0, N);
+        axpby_(c, P.eta_t, J.Lleft, J.R0j, 1.0, N);
         if (sv) axpby_(c, P.eta_t, sv, 1.0, 1.0, nov);
         // transition density D_pq = <L_i| E_pq |R_j>: seeds L_i on A R_j,
         // R0_j L_i + s on Omega (singles), wrt f
         double* wl = ar.alloc(N);
-        kc(apply_metric(c.s, wl, c.L[J.i], c.o, c.v, 0), "metric");
+        kc(apply_metric(c.s, wl, J.Lleft, c.o, c.v, 0), "metric");
         double* sp = ar.alloc(N);
         axpby_(c, sp, wl, J.R0j, 0.0, N);
         if (sv) axpby_(c, sp, sv, 1.0, 1.0, nov);
@@ -1679,6 +1795,18 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
         }
         auto adj = tp.G.vjp(seeds, {tp.r.f});
         copy_d(c, P.dtrans, adj[tp.r.f].p, nn);
+        if (J.ground_bra) {
+          // reference row of the bra: R0_j dE/df + d(eta . R_j)/df.  The
+          // sweep above leaves out E(f) (L . R_j), which vanishes for an
+          // excited bra but is -R0_j E(f) here (Lambda . R_j = -R0_j), so the
+          // two energy terms cancel and only d(eta . R_j)/df remains.
+          ArenaScope s3(ar);
+          EnergyTangent et(c, J.j);
+          double* a1 = c.eng->scalar_slot(59);
+          kc(fill(c.s, a1, 1.0, 1), "fill");
+          auto adje = et.G.vjp({{et.te, a1}}, {et.en.f});
+          axpby_(c, P.dtrans, adje[et.en.f].p, 1.0, 1.0, nn);
+        }
       }
     }
     // zeta: A^T zeta = -eta_t, closed form for (i, 0), the rest in blocks
@@ -1725,7 +1853,7 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       }
       // adjoints of the leaves and of every integral use, primal and (along
       // R_j) tangent
-      std::vector<int> wrt{tp.r.f, tp.r.bl, tp.r.br, tp.r.w, tp.r.wov, tp.r.gov};
+      std::vector<int> wrt{tp.r.f, tp.r.bl, tp.r.br, tp.r.wov, tp.r.gov};
       std::vector<int> tuse(NUSE, -1);
       for (int u = 0; u < NUSE; ++u) wrt.push_back(tp.r.use[u]);
       if (J.has_right) {
@@ -1740,13 +1868,21 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       }
       auto adj = tp.G.vjp(seeds, wrt);
       copy_d(c, P.Fbar, adj[tp.r.f].p, nn);
-      const int64_t v4 = (int64_t)c.v * c.v * c.v * c.v, v3o = (int64_t)c.v * c.v * c.v * c.o,
-                    o2v2 = (int64_t)c.o * c.o * c.v * c.v, nB = (int64_t)c.naux * nn;
-      if (!P.gW) P.gW = palloc(c, v4);
+      const int64_t v3o = (int64_t)c.v * c.v * c.v * c.o, o2v2 = (int64_t)c.o * c.o * c.v * c.v,
+                    nB = (int64_t)c.naux * nn;
+      // vvvv factors: the seeds of the doubles residual and of its tangent
+      if (!P.ylad) P.ylad = palloc(c, 2 * o2v2);
+      copy_d(c, P.ylad, wz + nov, o2v2);
+      P.nlad = 1;
+      P.jr = -1;
+      if (J.has_right) {
+        copy_d(c, P.ylad + o2v2, J.wg + nov, o2v2);
+        P.nlad = 2;
+        P.jr = J.j;
+      }
       if (!P.gWov) P.gWov = palloc(c, v3o);
       if (!P.gGov) P.gGov = palloc(c, o2v2);
       if (!P.Bbar) P.Bbar = palloc(c, nB);
-      copy_d(c, P.gW, adj[tp.r.w].p, v4);
       copy_d(c, P.gWov, adj[tp.r.wov].p, v3o);
       copy_d(c, P.gGov, adj[tp.r.gov].p, o2v2);
       copy_d(c, P.Bbar, adj[tp.r.bl].p, nB);
@@ -1775,10 +1911,19 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
         axpby_(c, P.Fbar, adje[en.f].p, 1.0, 1.0, nn);
         axpby_(c, P.gGov, adje[en.gov].p, 1.0, 1.0, o2v2);
         const int64_t oo = (int64_t)c.o;
-        hipLaunchKernelGGL(ehf_terms_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
-                           P.Fbar, (int64_t)c.n, c.o);
+        hipLaunchKernelGGL(diag_occ_add_kernel, dim3((unsigned)((oo + 255) / 256)), dim3(256), 0, c.s,
+                           P.Fbar, (int64_t)c.n, c.o, 2.0);
         hip_check(hipGetLastError(), "HF energy terms");
         P.hf_term = true;
+      }
+      if (J.ground_bra) {
+        // reference row: (1/omega_j) eta(t; f, g) . R_j through f and (kc|ld)
+        EnergyTangent et(c, J.j);
+        double* g0 = c.eng->scalar_slot(61);
+        kc(fill(c.s, g0, 1.0 / c.omega_r[J.j], 1), "fill");
+        auto adje = et.G.vjp({{et.te, g0}}, {et.en.f, et.en.gov});
+        axpby_(c, P.Fbar, adje[et.en.f].p, 1.0, 1.0, nn);
+        axpby_(c, P.gGov, adje[et.en.gov].p, 1.0, 1.0, o2v2);
       }
       // the bare blocks are products of the factor: fold their adjoints into
       // d Phi / d B (for the orbital-rotation derivative)
@@ -1865,8 +2010,143 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
   return status;
 }
 
+// One-sided blocks of the two-electron density (Sec. II C, eq.
+// NAC_NC_densities).  A use sum_P a(B)[P] (x) b(B)[P] enters the coupling of
+// a direction as sum_P <Gbar, a(dB)[P] (x) b(dB)[P]> with a, b linear in the
+// factor (T1-transformed blocks, their forward derivatives along R1_j, or
+// bare blocks).  Its adjoint Gbar is lifted through the transform of one
+// half (a reverse sweep over the factor graph with the other half's entries
+// as the batch), which turns it into one linear form on the symmetric pairs
+// of the bare factor per entry of the other half; the other half stays the
+// direction's own transformed block.  The bare (kc|bd) and (kc|ld) blocks
+// enter with the identity as their lifted half.
+static void lift_uses(Ctx& c, PairData& P) {
+  const int64_t o = c.o, v = c.v, n = c.n, nn = n * n, m = n * (n + 1) / 2;
+  const bool tn = P.has_tan;
+  const int64_t len[NGRP] = {v * o, tn ? v * o : 0, o * o, tn ? o * o : 0, o * v};
+  int64_t cols = 0;
+  for (int g = 0; g < NGRP; ++g) {
+    P.goff[g] = cols;
+    P.glen[g] = len[g];
+    cols += len[g];
+  }
+  if (!P.gam || P.gcols != cols) P.gam = palloc(c, cols * m);
+  P.gcols = cols;
+  Arena& ar = c.eng->arena();
+  const int64_t shape_of[NUSE][4] = {{v, o, v, o}, {o, o, o, o}, {o, o, v, v}, {v, o, o, v},
+                                     {v, v, o, v}, {v, v, o, o}, {o, o, o, v}, {n, n, 1, 1}};
+  for (int g = 0; g < NGRP; ++g) {
+    if (!len[g]) continue;
+    // the operand entry is a pair (lead, inner); batches of whole leads
+    const int64_t lead = (g == G_VO || g == G_VOT) ? v : o, inner = len[g] / lead;
+    const int64_t budget = (int64_t)1 << 27;   // doubles of lifted rows per batch
+    const int64_t cl = std::max<int64_t>(1, std::min<int64_t>(lead, budget / (inner * nn)));
+    for (int64_t l0 = 0; l0 < lead; l0 += cl) {
+      const int64_t lc = std::min(cl, lead - l0), rows = lc * inner;
+      ArenaScope sc(ar);
+      Graph G(*c.eng);
+      double* zb = ar.alloc(rows * nn);
+      kc(fill(c.s, zb, 0.0, rows * nn), "fill");
+      const int t1 = G.leaf(T1of(c, c.t));
+      const int b = G.leaf(tview(zb, {rows, n, n}));
+      const int first = G.size();
+      const FactorNodes F = factor_graph(G, c, t1, b);
+      std::map<int, int> tm;
+      if (tn) {
+        const int r1 = G.leaf(T1of(c, c.R[P.jr]));
+        tm = G.jvp({{t1, r1}}, first);
+      }
+      // seed terms per lifted node: the use adjoint with the operand's pair
+      // first (its lead index restricted to this batch)
+      std::map<int, std::vector<Term>> terms;
+      std::map<int, std::vector<int64_t>> shapes;
+      auto add = [&](int target, int u, bool tangent, const char* lin_, char leadlab, const char* lout) {
+        double* src = tangent ? P.guse_t[u] : P.guse[u];
+        if (!src) return;
+        const std::vector<int64_t> sh(shape_of[u], shape_of[u] + 4);
+        const int gl = G.leaf(tview(src, sh));
+        std::vector<Range> box;
+        for (int k = 0; k < 4; ++k) box.push_back(lin_[k] == leadlab ? Range{l0, lc} : Range{0, sh[k]});
+        std::vector<int64_t> osh;
+        for (int k = 0; k < 4; ++k) {
+          const int pos = (int)(std::string(lin_).find(lout[k]));
+          osh.push_back(lout[k] == leadlab ? lc : sh[pos]);
+        }
+        terms[target].push_back(lin(1, op(gl, lin_, box), lout));
+        shapes[target] = osh;
+      };
+      auto T = [&](int node) { return tm.count(node) ? tm.at(node) : -1; };
+      switch (g) {
+        case G_VO:
+          add(F.vo, U_VOVO, false, "aibj", 'b', "bjai");
+          if (tn) add(T(F.vo), U_VOVO, true, "aibj", 'b', "bjai");
+          break;
+        case G_VOT:
+          add(F.vo, U_VOVO, true, "aibj", 'b', "bjai");
+          break;
+        case G_OO:
+          add(F.oo, U_OOOO, false, "kilj", 'l', "ljki");
+          add(F.vv, U_OOVV, false, "kiac", 'k', "kiac");
+          add(F.vv, U_VVOO, false, "acki", 'k', "kiac");
+          if (tn) {
+            add(T(F.oo), U_OOOO, true, "kilj", 'l', "ljki");
+            add(T(F.vv), U_OOVV, true, "kiac", 'k', "kiac");
+            add(T(F.vv), U_VVOO, true, "acki", 'k', "kiac");
+          }
+          break;
+        case G_OOT:
+          add(F.oo, U_OOOO, true, "kilj", 'l', "ljki");
+          add(F.vv, U_OOVV, true, "kiac", 'k', "kiac");
+          add(F.vv, U_VVOO, true, "acki", 'k', "kiac");
+          break;
+        default:  // G_OV
+          add(F.vo, U_VOOV, false, "aikc", 'k', "kcai");
+          add(F.vv, U_VVOV, false, "adkc", 'k', "kcad");
+          add(F.oo, U_OOOV, false, "kilc", 'l', "lcki");
+          if (tn) {
+            add(T(F.vo), U_VOOV, true, "aikc", 'k', "kcai");
+            add(T(F.vv), U_VVOV, true, "adkc", 'k', "kcad");
+            add(T(F.oo), U_OOOV, true, "kilc", 'l', "lcki");
+          }
+          break;
+      }
+      std::map<int, const double*> seeds;
+      for (auto& kv : terms) {
+        if (kv.first < 0) throw Error(-3, "density lift: missing tangent node");
+        seeds[kv.first] = G.val(G.node(shapes.at(kv.first), kv.second)).p;
+      }
+      auto adj = G.vjp(seeds, {b});
+      double* bb = adj.at(b).p;
+      if (g == G_OV) {
+        // (kc|bd): bb[(k, c)][o + b][o + d] += dPhi/dWov[c][d][k][b]
+        const int gw = G.leaf(tview(P.gWov, {v, v, o, v}));
+        const int pw = G.node({lc, v, v, v}, {lin(1, op(gw, "cdkb", {{0, v}, {0, v}, {l0, lc}, {0, v}}), "kcbd")});
+        ViewSpec vs;
+        vs.nd = 3;
+        vs.dims[0] = rows; vs.dims[1] = v; vs.dims[2] = v;
+        vs.ostr[0] = nn; vs.ostr[1] = n; vs.ostr[2] = 1;
+        vs.obase = o * n + o;
+        vs.istr[0] = v * v; vs.istr[1] = v; vs.istr[2] = 1;
+        kc(view_gather(c.s, bb, G.val(pw).p, vs, 1.0, 1.0), "bare vvov");
+        // (kc|ld): bb[(k, c)][l][o + d] += dPhi/dGov[k][c][l][d]
+        ViewSpec vg;
+        vg.nd = 3;
+        vg.dims[0] = rows; vg.dims[1] = o; vg.dims[2] = v;
+        vg.ostr[0] = nn; vg.ostr[1] = n; vg.ostr[2] = 1;
+        vg.obase = o;
+        vg.istr[0] = o * v; vg.istr[1] = v; vg.istr[2] = 1;
+        vg.ibase = l0 * v * o * v;
+        kc(view_gather(c.s, bb, P.gGov, vg, 1.0, 1.0), "bare ovov");
+      }
+      kc(pack_pairs(c.s, P.gam + (P.goff[g] + l0 * inner) * m, m, bb, nn, rows, c.o, c.v, true),
+         "pair packing");
+    }
+  }
+}
+
 // D_eff = dPhi/df + kappa-bar embedded in the vo block (Sec. II C); the
-// two-electron density stays as the adjoints of its uses (PairData).
+// two-electron density as one-sided blocks (lift_uses) and the factorised
+// vvvv block.
 static void densities_impl(Ctx& c, int i1, int j1) {
   PairData& P = c.pairs.at({i1, j1});
   const int64_t nn = (int64_t)c.n * c.n;
@@ -1878,107 +2158,127 @@ static void densities_impl(Ctx& c, int i1, int j1) {
   vs.obase = (int64_t)c.o * c.n;
   vs.istr[0] = c.v; vs.istr[1] = 1;
   kc(view_gather(c.s, P.Deff, P.kbar, vs, 1.0, 1.0), "kappa embed");
+  lift_uses(c, P);
   P.have_dens = true;
 }
 
 // F^q = sum D_eff dh^q + sum Gamma dg^q with dg^q = sum_P dB^q[P] (x) dB^q[P]
-// (Sec. II C, eq. NAC_NC), the second term summed over the places where the
-// integrals enter the Lagrangian: every use is bilinear in the factor, so its
-// share is the use's adjoint contracted with the same use built from dB^q
-// (T1-transformed with the ground amplitudes, and along R_j for the uses in
-// gamma . A R_j); the bare blocks W, Wov, Gov directly; the Fock matrix's own
-// dependence on g (f = h + 2 J - K) through D_eff; and, for the energy
-// Lagrangian, E_HF's two-electron part.  Each such share is one GEMM over the
-// direction's factor and a dot product.
-static double coupling_direction(Ctx& c, PairData& P, int j1, const double* dhq, const double* dBq) {
-  const int64_t o = c.o, v = c.v, n = c.n, Pn = c.naux, nn = n * n;
-  const Range AP{0, Pn}, O{0, o}, V{o, v}, A{0, n}, Ol{0, o};
-  ArenaScope sc(c.eng->arena());
-  Graph G(*c.eng);
-  const int t1 = G.leaf(T1of(c, c.t));
-  const int db = G.leaf(tview(const_cast<double*>(dBq), {Pn, n, n}));
-  const int first = G.size();
-  const FactorNodes Fd = factor_graph(G, c, t1, db);
-  std::map<int, int> tan;
-  const bool has_tan = P.has_tan && j1 > 0;
-  if (has_tan) {
-    const int r1 = G.leaf(T1of(c, c.R[j1 - 1]));
-    tan = G.jvp({{t1, r1}}, first);
-  }
-  std::vector<int> terms;
-  auto dot_of = [&](double alpha, const Op& x, const Op& y) {
-    terms.push_back(G.node({}, {mul(alpha, x, y, "")}));
-  };
-  auto tangent = [&](const Op& x) -> Op {
-    auto it = tan.find(x.node);
-    Op t = x;
-    t.node = (it == tan.end()) ? -1 : it->second;
-    return t;
-  };
-  // T1-transformed two-electron uses
-  for (int u = 0; u < U_FCORR; ++u) {
-    const UseSpec us = use_spec(c, u, Fd, Fd, db);
-    const int gu = G.leaf(tview(P.guse[u], us.shape));
-    const std::vector<int64_t> zs = G.val(us.a.node).shape();
-    auto share = [&](int gnode, const Op& a, const Op& b) {
-      if (a.node < 0 || b.node < 0) return;
-      const int z = G.node(zs, {mul(1, op(gnode, us.out), b, us.a.lab)});
-      dot_of(1, a, op(z, us.a.lab));
-    };
-    share(gu, us.a, us.b);
-    if (has_tan && P.guse_t[u]) {
-      const int gt = G.leaf(tview(P.guse_t[u], us.shape));
-      share(gt, tangent(us.a), us.b);
-      share(gt, us.a, tangent(us.b));
-    }
-  }
-  // Fock correction 2 sum_P tr(D[P]) B[P] - sum_P D[P] B[P][occ rows]
-  auto fcorr_share = [&](const double* gbar, int dnode) {
-    const int fc = G.leaf(tview(const_cast<double*>(gbar), {n, n}));
-    const int y = G.node({Pn}, {mul(1, op(fc, "pq"), op(db, "Ppq"), "P")});
-    const int trd = G.node({Pn}, {lin(1, op(dnode, "Pkk", {AP, O, Ol}), "P")});
-    dot_of(2, op(trd, "P"), op(y, "P"));
-    const int zk = G.node({Pn, n, o}, {mul(1, op(fc, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
-    dot_of(-1, op(dnode, "Ppk"), op(zk, "Ppk"));
-  };
-  fcorr_share(P.guse[U_FCORR], Fd.d);
-  if (has_tan && P.guse_t[U_FCORR] && tan.count(Fd.d)) fcorr_share(P.guse_t[U_FCORR], tan.at(Fd.d));
-  // bare blocks
-  const int gw = G.leaf(tview(P.gW, {v, v, v, v}));
-  const int zw = G.node({Pn, v, v}, {mul(1, op(gw, "cdab"), op(db, "Pbd", {AP, V, V}), "Pac")});
-  dot_of(1, op(db, "Pac", {AP, V, V}), op(zw, "Pac"));
-  const int gwov = G.leaf(tview(P.gWov, {v, v, o, v}));
-  const int zov = G.node({Pn, o, v}, {mul(1, op(gwov, "cdkb"), op(db, "Pbd", {AP, V, V}), "Pkc")});
-  dot_of(1, op(db, "Pkc", {AP, O, V}), op(zov, "Pkc"));
-  const int ggov = G.leaf(tview(P.gGov, {o, v, o, v}));
-  const int zg = G.node({Pn, o, v}, {mul(1, op(ggov, "kcld"), op(db, "Pld", {AP, O, V}), "Pkc")});
-  dot_of(1, op(db, "Pkc", {AP, O, V}), op(zg, "Pkc"));
-  // the Fock matrix's dependence on g: 2 D_eff.J(dg) - D_eff.K(dg)
-  const int de = G.leaf(tview(P.Deff, {n, n}));
-  const int s = G.node({Pn}, {lin(1, op(db, "Pkk", {AP, O, O}), "P")});
-  const int yd = G.node({Pn}, {mul(1, op(de, "pq"), op(db, "Ppq"), "P")});
-  dot_of(2, op(s, "P"), op(yd, "P"));
-  const int zd = G.node({Pn, n, o}, {mul(1, op(de, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
-  dot_of(-1, op(db, "Ppk", {AP, A, O}), op(zd, "Ppk"));
-  // E_HF two-electron part: -sum_ij (2 dg_iijj - dg_ijji)
-  if (P.hf_term) {
-    dot_of(-2, op(s, "P"), op(s, "P"));
-    dot_of(1, op(db, "Pij", {AP, O, O}), op(db, "Pji", {AP, O, O}));
-  }
-  std::vector<Term> sum;
-  for (int t : terms) sum.push_back(lin(1, op(t, ""), ""));
-  const int tot = G.node({}, sum);
-  const double f2 = d2h(c, G.val(tot).p);
-  const double f1 = dot_plain(c, P.Deff, dhq, nn);
-  return f1 + f2;
-}
-
+// (Sec. II C, eq. NAC_NC): every place the integrals enter the Lagrangian is
+// bilinear in the factor, so the second term is a sum over P of quadratic
+// forms in the direction's factor dB^q[P].  All directions of a batch go
+// through each step together, with the rows (q, P) as one index:
+//  * one-sided blocks: x = packed pairs of dB^q[P], Z = x gam^T (one GEMM),
+//    contracted row by row with the direction's transformed operands;
+//  * vvvv: the factorised block formed once per call, packed over symmetric
+//    pairs, then x_vv Gw^T x_vv;
+//  * the Fock matrix's dependence on g through D_eff (2 J - K of dg), the
+//    Fock correction of the T1 transform and, for the energy Lagrangian,
+//    E_HF's two-electron part, as small contractions per row.
 static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const double* dB,
                        double* F) {
   PairData& P = c.pairs.at({i1, j1});
-  const int64_t nn = (int64_t)c.n * c.n;
-  for (int q = 0; q < nq; ++q)
-    F[q] = coupling_direction(c, P, j1, dh + (int64_t)q * nn, dB + (int64_t)q * c.naux * nn);
+  const int64_t o = c.o, v = c.v, n = c.n, nn = n * n, Pn = c.naux, m = n * (n + 1) / 2;
+  const int64_t mv = v * (v + 1) / 2, xvv = o * (o + 1) / 2 + o * v, gc = P.gcols;
+  const bool tn = P.has_tan;
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  double* Gw = ar.alloc(mv * mv);
+  {
+    ArenaScope s2(ar);
+    Graph G(*c.eng);
+    const int gw = vvvv_density(G, c, P);
+    kc(pack_vvvv(c.s, Gw, G.val(gw).p, c.v), "vvvv packing");
+  }
+  // directions per batch from the arena use of one direction's rows
+  const int64_t per_dir = Pn * (m + 2 * gc + mv + 3 * (n * o + o * o + v * o) + n * v + 4 * n * o + 2 * o * o);
+  const int64_t budget = (int64_t)2 << 30;   // doubles
+  const int kq = (int)std::max<int64_t>(1, std::min<int64_t>(nq, budget / per_dir));
+  double* f1 = ar.alloc(kq);
+  std::vector<double> sh, fh(kq);
+  for (int q0 = 0; q0 < nq; q0 += kq) {
+    const int nb = std::min(kq, nq - q0);
+    const int64_t R = nb * Pn;
+    ArenaScope s2(ar);
+    double* db_p = const_cast<double*>(dB) + (int64_t)q0 * Pn * nn;
+    double* x = ar.alloc(R * m);
+    kc(pack_pairs(c.s, x, m, db_p, nn, R, c.o, c.v, false), "pair packing");
+    double* s = ar.alloc(R);
+    // one-sided blocks
+    double* Z = ar.alloc(R * gc);
+    kc(gemm_f64(c.s, false, true, (int)R, (int)gc, (int)m, 1, 1.0, x, m, 0, P.gam, m, 0, 0.0, Z, gc, 0),
+       "density gemm");
+    double* Bop = ar.alloc(R * gc);
+    Graph G(*c.eng);
+    const Range AP{0, R}, O{0, o}, A{0, n}, Ol{0, o};
+    const int t1 = G.leaf(T1of(c, c.t));
+    const int db = G.leaf(tview(db_p, {R, n, n}));
+    const int first = G.size();
+    const FactorNodes Fd = factor_graph(G, c, t1, db, false);
+    std::map<int, int> tm;
+    if (tn) {
+      const int r1 = G.leaf(T1of(c, c.R[P.jr]));
+      tm = G.jvp({{t1, r1}}, first);
+    }
+    copy_rows(c, Bop + P.goff[G_VO], gc, G.val(Fd.vo).p, v * o, v * o, R);
+    copy_rows(c, Bop + P.goff[G_OO], gc, G.val(Fd.oo).p, o * o, o * o, R);
+    if (tn) {
+      copy_rows(c, Bop + P.goff[G_VOT], gc, G.val(tm.at(Fd.vo)).p, v * o, v * o, R);
+      copy_rows(c, Bop + P.goff[G_OOT], gc, G.val(tm.at(Fd.oo)).p, o * o, o * o, R);
+    }
+    {
+      ViewSpec vs;  // Bop[r][ov + k v + c] = dB[r][k][o + c]
+      vs.nd = 3;
+      vs.dims[0] = R; vs.dims[1] = o; vs.dims[2] = v;
+      vs.ostr[0] = gc; vs.ostr[1] = v; vs.ostr[2] = 1;
+      vs.obase = P.goff[G_OV];
+      vs.istr[0] = nn; vs.istr[1] = n; vs.istr[2] = 1;
+      vs.ibase = o;
+      kc(view_gather(c.s, Bop, db_p, vs, 1.0, 0.0), "ov block");
+    }
+    kc(rowdot(c.s, s, Z, gc, Bop, gc, R, gc, 1.0, 0.0), "row dots");
+    // vvvv
+    double* Zw = ar.alloc(R * mv);
+    kc(gemm_f64(c.s, false, true, (int)R, (int)mv, (int)mv, 1, 1.0, x + xvv, m, 0, Gw, mv, 0, 0.0, Zw, mv,
+                0),
+       "vvvv gemm");
+    kc(rowdot(c.s, s, Zw, mv, x + xvv, m, R, mv, 1.0, 1.0), "row dots");
+    // Fock correction 2 sum_P tr(D[P]) B[P] - sum_P D[P] B[P][occ rows]
+    auto fcorr_rows = [&](const double* gbar, int dnode) {
+      const int fc = G.leaf(tview(const_cast<double*>(gbar), {n, n}));
+      const int y = G.node({R}, {mul(1, op(fc, "pq"), op(db, "Ppq"), "P")});
+      const int trd = G.node({R}, {lin(1, op(dnode, "Pkk", {AP, O, Ol}), "P")});
+      kc(rowdot(c.s, s, G.val(trd).p, 1, G.val(y).p, 1, R, 1, 2.0, 1.0), "row dots");
+      const int zk = G.node({R, n, o}, {mul(1, op(fc, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
+      kc(rowdot(c.s, s, G.val(dnode).p, n * o, G.val(zk).p, n * o, R, n * o, -1.0, 1.0), "row dots");
+    };
+    fcorr_rows(P.guse[U_FCORR], Fd.d);
+    if (tn && P.guse_t[U_FCORR] && tm.count(Fd.d)) fcorr_rows(P.guse_t[U_FCORR], tm.at(Fd.d));
+    // the Fock matrix's dependence on g: 2 D_eff.J(dg) - D_eff.K(dg)
+    const int de = G.leaf(tview(P.Deff, {n, n}));
+    const int sn = G.node({R}, {lin(1, op(db, "Pkk", {AP, O, O}), "P")});
+    const int yd = G.node({R}, {mul(1, op(de, "pq"), op(db, "Ppq"), "P")});
+    kc(rowdot(c.s, s, G.val(sn).p, 1, G.val(yd).p, 1, R, 1, 2.0, 1.0), "row dots");
+    const int zd = G.node({R, n, o}, {mul(1, op(de, "pq"), op(db, "Pkq", {AP, O, A}), "Ppk")});
+    const int dpk = G.node({R, n, o}, {lin(1, op(db, "Ppk", {AP, A, O}), "Ppk")});
+    kc(rowdot(c.s, s, G.val(dpk).p, n * o, G.val(zd).p, n * o, R, n * o, -1.0, 1.0), "row dots");
+    // E_HF two-electron part: -sum_ij (2 dg_iijj - dg_ijji)
+    if (P.hf_term) {
+      kc(rowdot(c.s, s, G.val(sn).p, 1, G.val(sn).p, 1, R, 1, -2.0, 1.0), "row dots");
+      const int d1 = G.node({R, o, o}, {lin(1, op(db, "Pij", {AP, O, O}), "Pij")});
+      const int d2 = G.node({R, o, o}, {lin(1, op(db, "Pji", {AP, O, O}), "Pij")});
+      kc(rowdot(c.s, s, G.val(d1).p, o * o, G.val(d2).p, o * o, R, o * o, 1.0, 1.0), "row dots");
+    }
+    kc(rowdot(c.s, f1, dh + (int64_t)q0 * nn, nn, P.Deff, 0, nb, nn, 1.0, 0.0), "row dots");
+    sh.resize(R);
+    hip_check(hipMemcpyAsync(sh.data(), s, R * sizeof(double), hipMemcpyDeviceToHost, c.s), "copy D2H");
+    hip_check(hipMemcpyAsync(fh.data(), f1, nb * sizeof(double), hipMemcpyDeviceToHost, c.s), "copy D2H");
+    sync(c);
+    for (int q = 0; q < nb; ++q) {
+      double f2 = 0.0;
+      for (int64_t p = 0; p < Pn; ++p) f2 += sh[q * Pn + p];
+      F[q0 + q] = fh[q] + f2;
+    }
+  }
 }
 
 }  // namespace nm
@@ -2119,6 +2419,7 @@ int cc_ground(cc_ctx* c, double* e_corr, int* iters) {
     c->have_guess = false;
     c->have_right = c->have_left = c->gauged = false;
     c->pairs.clear();
+    c->have_lam = false;
     if (st == CC_NOT_CONVERGED) c->err = "CCSD amplitudes not converged";
     return st;
   } catch (const Error& e) {
@@ -2159,8 +2460,8 @@ int multipliers(cc_ctx* c, int npairs, const int* pairs, int* iters) {
   std::vector<std::pair<int, int>> pl;
   for (int p = 0; p < npairs; ++p) {
     const int i = pairs[2 * p], j = pairs[2 * p + 1];
-    if (i < 0 || j < 0 || i > c->nroots || j > c->nroots || (i == 0 && j != 0)) {
-      c->err = "pair indices must satisfy 0 <= i, j <= nroots with i >= 1 unless i = j = 0";
+    if (i < 0 || j < 0 || i > c->nroots || j > c->nroots) {
+      c->err = "pair indices must satisfy 0 <= i, j <= nroots";
       return CC_ERR_ARG;
     }
     for (const auto& q : pl)

@@ -33,8 +33,9 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
 // given as bfloat16 pairs (hi, lo) in uint16 storage; K and Klast multiples
 // of 32, lda / ldb / batch strides multiples of 8, 16-byte aligned pointers.
 // tile: 0 = 128 x 128 outputs per workgroup (two per CU), 1 = 256 x 256,
-// 2 = 256 x 128, 3 = 128 x 256 (one per CU); -1 = bf16x3_auto_tile's choice.
-constexpr int kBf16Tiles = 4;
+// 2 = 256 x 128, 3 = 128 x 256 (one per CU), 4 = 256 x 128 and 5 = 128 x 256
+// with loads two K steps ahead; -1 = bf16x3_auto_tile's choice.
+constexpr int kBf16Tiles = 6;
 int bf16x3_auto_tile(int M, int N, int batch);
 int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
                 const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
@@ -68,5 +69,20 @@ int rows_axpy_multi(hipStream_t s, const double* V, int m, int64_t n, const doub
                     double* X, int64_t ldx, int R, bool overwrite = false);
 int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h, double alpha,
               double* x);
+
+// Blocked two-electron density (density.hip).
+// Symmetric index pairs of an n x n matrix (n = o + v) in the order
+// [oo (p >= q) | ov (k, c) | vv (a >= c)], m = n (n + 1) / 2 of them:
+// out[r][j] = in[r][p][q] + in[r][q][p] (sum, p != q) or in[r][p][q] (p >= q).
+int pack_pairs(hipStream_t s, double* out, int64_t ldo, const double* in, int64_t ldi, int64_t rows,
+               int o, int v, bool sum);
+// out[(a >= c)][(b >= d)] (pairs packed as x (x + 1) / 2 + y, v (v + 1) / 2 <=
+// 65535 of them) = sum over the distinct images (a, c) <-> (c, a),
+// (b, d) <-> (d, b) of G[c][d][a][b] (G: [v][v][v][v]).
+int pack_vvvv(hipStream_t s, double* out, const double* G, int v);
+// out[r] = alpha sum_j A[r lda + j] B[r ldb + j] + beta out[r]  (j < len; ldb 0
+// broadcasts one row of B)
+int rowdot(hipStream_t s, double* out, const double* A, int64_t lda, const double* B, int64_t ldb,
+           int64_t rows, int64_t len, double alpha, double beta);
 
 }  // namespace nm

@@ -77,7 +77,7 @@ def test_bad_arguments_are_rejected(nm):
         ctx.eom(4, 2)                   # no such side
     assert e.value.code == -1
     ctx.eom(nm.CC_BOTH, 2)
-    for pl in [[(3, 1)], [(0, 1)], [(1, -1)], [(1, 2), (2, 1), (1, 2)], []]:
+    for pl in [[(3, 1)], [(0, 3)], [(1, -1)], [(1, 2), (2, 1), (1, 2)], []]:
         with pytest.raises(nm.CCError) as e:
             ctx.multipliers(pl)
         assert e.value.code == -1

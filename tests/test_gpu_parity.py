@@ -191,6 +191,48 @@ def test_ground_pair_couplings_match_oracle(nm, o, v, naux, seed):
 
 
 @pytest.mark.parametrize("o,v,naux,seed", [(1, 5, 18, None), (2, 4, 18, None), (4, 12, 48, 2301)])
+def test_ground_bra_couplings_match_oracle(nm, o, v, naux, seed):
+    """F_0j: the ground-state left state <HF|(1 + Lambda) exp(-T) on the left,
+    excited right state j; both pairs (0, 1), (0, 2) in one multipliers call
+    (Lambda solved once), with an excited pair beside them."""
+    say(f"[ground bra] o={o} v={v}")
+    seed = synth.exact_check_seed(o, v) if seed is None else seed
+    st = oracle_state(o, v, naux, seed, 2)
+    sysd = st["sys"]
+    n = o + v
+    dirs = synth.make_directions(n, naux, seed + 17, 2)
+    ctx = nm.Context(o, v, naux, T(sysd["eps"]), T(sysd["B"]))
+    ctx.ground()
+    ctx.eom(nm.CC_BOTH, 2)
+    Nf = o * v + (o * v) ** 2
+    buf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+    its, rc = ctx.multipliers([(0, 1), (1, 2), (0, 2)])
+    assert rc == 0
+    for j in range(2):
+        m = rs.multipliers(st, rs.GROUND, j, relaxed=True)
+        eta = to_packed(ctx.export(nm._lib.CC_ETA_T, 0, j + 1, buf).cpu().numpy(), o, v)
+        assert np.abs(eta - m["eta_t"].numpy()).max() < 1e-7 * max(1.0, float(m["eta_t"].abs().max()))
+        zeta = to_packed(ctx.export(nm._lib.CC_ZETA, 0, j + 1, buf).cpu().numpy(), o, v)
+        assert np.abs(zeta - m["zeta"].numpy()).max() < 1e-7 * max(1.0, float(m["zeta"].abs().max()))
+        kb = torch.zeros(o * v, dtype=torch.float64, device="cuda")
+        ek = ctx.export(nm._lib.CC_ETA_K, 0, j + 1, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(ek - m["eta_kappa"].numpy()).max() < 1e-7
+        kb = ctx.export(nm._lib.CC_KAPPA, 0, j + 1, kb).cpu().numpy().reshape(o, v)
+        assert np.abs(kb - m["kappa_bar"].numpy()).max() < 1e-7
+        D1 = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+        ctx.densities(0, j + 1, D1)
+        Dref, _ = rs.effective_densities(st, m, j)
+        Dg = D1.cpu().numpy()
+        assert np.abs(0.5 * (Dg + Dg.T) - Dref.numpy()).max() < 1e-7
+        F = ctx.nacme(0, j + 1, T(dirs["dh"]), T(dirs["dB"]))
+        for q in range(2):
+            dg = np.einsum("Ppq,Prs->pqrs", dirs["dB"][q], dirs["dB"][q])
+            Fo = rs.coupling_direct(st, m, j, dirs["dh"][q], dg)
+            assert abs(F[q] - Fo) < 1e-7 * max(1.0, abs(Fo))
+    ctx.close()
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 5, 18, None), (2, 4, 18, None), (4, 12, 48, 2301)])
 def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
     """dE_j/dlambda (pairs (j, j)) of the ground and two excited states, and the
     branching-plane vectors built from them, against the oracle."""
@@ -298,7 +340,7 @@ def test_bf16_pair_packing_is_exact(nm, spec, ashape):
     assert torch.equal(C.cpu(), ref)
 
 
-@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320), (600, 700, 96)])
 def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K, tile):
     """nm_gemm_tiled with bfloat16 pairs (the split-precision kernel alone, in
