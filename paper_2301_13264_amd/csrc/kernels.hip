@@ -549,17 +549,22 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
 // two stages of the four 32-wide bf16 row arrays (A hi, A lo, B hi, B lo),
 // 256 (BM + BN) bytes in all (128 KB at 256 x 256), with the same XOR-swizzled
 // 16-byte chunks as the 128 x 128 kernel.  Each thread moves
-// (BM + BN) / 64 16-byte chunks per K step, prefetched into registers while
-// the previous step's fragments are multiplied.  The three products of a
-// fragment pair are issued one per row block and then over the column blocks
-// (FJ independent accumulators between dependent MFMAs).
-template <int BM, int BN, int WM, int WN>
+// (BM + BN) / 64 16-byte chunks per K step through registers.  PD = 1: the
+// next K step is loaded while this one is multiplied; PD = 2 (two register
+// sets, the loop unrolled by two so that each set has fixed registers): the
+// K step after next, so a global load has two steps of products to arrive.
+// Every load is unconditional (past the last step the last one is read
+// again), which keeps the waits at the LDS stores fixed.  The three products
+// of a fragment pair are issued one per row block and then over the column
+// blocks (FJ independent accumulators between dependent MFMAs).
+template <int BM, int BN, int WM, int WN, int PD>
 __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
     int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
     const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int Klast) {
   static_assert(WM * WN == 8, "eight waves");
+  static_assert(PD == 1 || PD == 2, "prefetch depth");
   constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
   // 16-byte chunks per thread and operand half per K step: rows / 128
   constexpr int RA = BM / 128, RB = BN / 128;
@@ -584,109 +589,114 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
   // 32-wide K step, in each of A hi, A lo (r < RA) and B hi, B lo (r < RB)
   const int row0 = tid >> 2, ch = tid & 3;
   int64_t aoff[RA], boff[RB];
-  bool aok[RA], bok[RB];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
-    aok[r] = m0 + row0 + 128 * r < M;
-    aoff[r] = (int64_t)(aok[r] ? m0 + row0 + 128 * r : 0) * lda + 8 * ch;
+    const bool ok = m0 + row0 + 128 * r < M;
+    aoff[r] = (int64_t)(ok ? m0 + row0 + 128 * r : 0) * lda + 8 * ch;
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    bok[r] = n0 + row0 + 128 * r < N;
-    boff[r] = (int64_t)(bok[r] ? n0 + row0 + 128 * r : 0) * ldb + 8 * ch;
+    const bool ok = n0 + row0 + 128 * r < N;
+    boff[r] = (int64_t)(ok ? n0 + row0 + 128 * r : 0) * ldb + 8 * ch;
   }
   // rows outside the matrix read row 0 of the panel instead (always valid):
   // they only reach accumulators of output rows or columns that are never
   // stored, so they need no zeroing
-  u32x4 rah[RA], ral[RA], rbh[RB], rbl[RB];
+  u32x4 ah0[RA], al0[RA], bh0[RB], bl0[RB];
+  u32x4 ah1[RA], al1[RA], bh1[RB], bl1[RB];
   v4f acc[FI][FJ];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
     for (int j = 0; j < FJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nk = K / HBK;
-  // prologue: K step 0 into stage 0
-#pragma unroll
-  for (int r = 0; r < RA; ++r) {
-    rah[r] = *(const u32x4*)(Ah + aoff[r]);
-    ral[r] = *(const u32x4*)(Al + aoff[r]);
+  // K offset of step t (clamped to the last step)
+#define NM_KOFF(t) ((int64_t)((t) < nk ? (t) : nk - 1) * HBK)
+#define NM_LOAD(S, KO)                                     \
+  _Pragma("unroll") for (int r = 0; r < RA; ++r) {         \
+    ah##S[r] = *(const u32x4*)(Ah + aoff[r] + (KO));       \
+    al##S[r] = *(const u32x4*)(Al + aoff[r] + (KO));       \
+  }                                                        \
+  _Pragma("unroll") for (int r = 0; r < RB; ++r) {         \
+    bh##S[r] = *(const u32x4*)(Bh + boff[r] + (KO));       \
+    bl##S[r] = *(const u32x4*)(Bl + boff[r] + (KO));       \
   }
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    rbh[r] = *(const u32x4*)(Bh + boff[r]);
-    rbl[r] = *(const u32x4*)(Bl + boff[r]);
+#define NM_STORE(S, G)                                                     \
+  _Pragma("unroll") for (int r = 0; r < RA; ++r) {                         \
+    *(u32x4*)&SA[G][0][swz(row0 + 128 * r, ch)] = ah##S[r];                \
+    *(u32x4*)&SA[G][1][swz(row0 + 128 * r, ch)] = al##S[r];                \
+  }                                                                        \
+  _Pragma("unroll") for (int r = 0; r < RB; ++r) {                         \
+    *(u32x4*)&SB[G][0][swz(row0 + 128 * r, ch)] = bh##S[r];                \
+    *(u32x4*)&SB[G][1][swz(row0 + 128 * r, ch)] = bl##S[r];                \
   }
-#pragma unroll
-  for (int r = 0; r < RA; ++r) {
-    *(u32x4*)&SA[0][0][swz(row0 + 128 * r, ch)] = rah[r];
-    *(u32x4*)&SA[0][1][swz(row0 + 128 * r, ch)] = ral[r];
+#define NM_COMPUTE(G)                                                                             \
+  {                                                                                               \
+    bf16x8 fbh[FJ], fbl[FJ];                                                                      \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                              \
+      const int o = swz(wn * TN + j * 16 + lr, lk);                                               \
+      fbh[j] = *(const bf16x8*)&SB[G][0][o];                                                      \
+      fbl[j] = *(const bf16x8*)&SB[G][1][o];                                                      \
+    }                                                                                             \
+    _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                              \
+      const int o = swz(wm * TM + i * 16 + lr, lk);                                               \
+      const bf16x8 fah = *(const bf16x8*)&SA[G][0][o];                                            \
+      const bf16x8 fal = *(const bf16x8*)&SA[G][1][o];                                            \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                  \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal, fbh[j], acc[i][j], 0, 0, 0);               \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                  \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah, fbl[j], acc[i][j], 0, 0, 0);               \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                  \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah, fbh[j], acc[i][j], 0, 0, 0);               \
+    }                                                                                             \
   }
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    *(u32x4*)&SB[0][0][swz(row0 + 128 * r, ch)] = rbh[r];
-    *(u32x4*)&SB[0][1][swz(row0 + 128 * r, ch)] = rbl[r];
-  }
-  __syncthreads();
-  // loop-carried K offset of the loads (uniform; the streams keep their
-  // global base pointers, so the loads stay global rather than flat)
-  int64_t kof = 0;
-  for (int t = 0; t < nk; ++t) {
-    const int cur = t & 1;
-    // next K step (the last step reloads itself: every load is unconditional,
-    // so its wait falls after this step's products, at the LDS store)
-    kof += t + 1 < nk ? HBK : 0;
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      rah[r] = *(const u32x4*)(Ah + aoff[r] + kof);
-      ral[r] = *(const u32x4*)(Al + aoff[r] + kof);
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      rbh[r] = *(const u32x4*)(Bh + boff[r] + kof);
-      rbl[r] = *(const u32x4*)(Bl + boff[r] + kof);
-    }
-    // keep the loads ahead of this step's products (the scheduler would
-    // otherwise sink them next to their LDS stores and expose their latency)
-    __builtin_amdgcn_sched_barrier(0);
-    bf16x8 bh[FJ], bl[FJ];
-#pragma unroll
-    for (int j = 0; j < FJ; ++j) {
-      const int o = swz(wn * TN + j * 16 + lr, lk);
-      bh[j] = *(const bf16x8*)&SB[cur][0][o];
-      bl[j] = *(const bf16x8*)&SB[cur][1][o];
-    }
-#pragma unroll
-    for (int i = 0; i < FI; ++i) {
-      const int o = swz(wm * TM + i * 16 + lr, lk);
-      const bf16x8 ah = *(const bf16x8*)&SA[cur][0][o];
-      const bf16x8 al = *(const bf16x8*)&SA[cur][1][o];
-#pragma unroll
-      for (int j = 0; j < FJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < FJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < FJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-    }
-    // the other stage (unread since the last barrier); on the last step
-    // nothing reads it again.  The stores wait for this step's loads, so they
-    // stay behind the products.
-    __builtin_amdgcn_sched_barrier(0);
-    const int nx = cur ^ 1;
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      *(u32x4*)&SA[nx][0][swz(row0 + 128 * r, ch)] = rah[r];
-      *(u32x4*)&SA[nx][1][swz(row0 + 128 * r, ch)] = ral[r];
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      *(u32x4*)&SB[nx][0][swz(row0 + 128 * r, ch)] = rbh[r];
-      *(u32x4*)&SB[nx][1][swz(row0 + 128 * r, ch)] = rbl[r];
-    }
+  // (the scheduling barriers keep each step's loads ahead of its products and
+  // its LDS stores, which wait for older loads, behind them)
+  NM_LOAD(0, 0)
+  NM_STORE(0, 0)
+  if constexpr (PD == 1) {
     __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+      const int cur = t & 1;
+      NM_LOAD(0, NM_KOFF(t + 1))
+      __builtin_amdgcn_sched_barrier(0);
+      NM_COMPUTE(cur)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_STORE(0, cur ^ 1)
+      __syncthreads();
+    }
+  } else {
+    // (the empty asm statements with a memory clobber keep the compiler's
+    // loop transformations from moving loads between the two halves)
+    NM_LOAD(1, NM_KOFF(1))
+    __syncthreads();
+    int t = 0;
+    for (; t + 1 < nk; t += 2) {
+      // stage 0 holds step t, set 1 step t + 1 (in flight)
+      asm volatile("" ::: "memory");
+      NM_LOAD(0, NM_KOFF(t + 2))
+      __builtin_amdgcn_sched_barrier(0);
+      NM_COMPUTE(0)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_STORE(1, 1)
+      __syncthreads();
+      asm volatile("" ::: "memory");
+      // stage 1 holds step t + 1, set 0 step t + 2 (in flight)
+      NM_LOAD(1, NM_KOFF(t + 3))
+      __builtin_amdgcn_sched_barrier(0);
+      NM_COMPUTE(1)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_STORE(0, 0)
+      __syncthreads();
+    }
+    if (t < nk) {   // odd step count: the last step is in stage 0
+      NM_COMPUTE(0)
+    }
   }
+#undef NM_KOFF
+#undef NM_LOAD
+#undef NM_STORE
+#undef NM_COMPUTE
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
@@ -706,8 +716,8 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
 // Tile shapes of the split-precision GEMM: 0 = 128 x 128 (two workgroups per
 // CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one workgroup per CU).
 static void bf16_tile_dims(int tile, int& bm, int& bn) {
-  bm = (tile == 1 || tile == 2) ? 256 : 128;
-  bn = (tile == 1 || tile == 3) ? 256 : 128;
+  bm = (tile == 1 || tile == 2 || tile == 4) ? 256 : 128;
+  bn = (tile == 1 || tile == 3 || tile == 5) ? 256 : 128;
 }
 
 // The shape used when none is given: the 128 x 128 kernel, measured faster
@@ -743,13 +753,15 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
   int bm, bn;
   bf16_tile_dims(tile, bm, bn);
   dim3 grid((N + bn - 1) / bn, (M + bm - 1) / bm, batch);
-#define NM_BF16BIG(BM_, BN_, WM_, WN_)                                                              \
-  hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_>), grid, dim3(512), 0, s, M, N, K, \
+#define NM_BF16BIG(BM_, BN_, WM_, WN_, PD_)                                                              \
+  hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_, PD_>), grid, dim3(512), 0, s, M, N, K, \
                      alpha, Ah, Al, lda, sA, Bh, Bl, ldb, sB, beta, C, ldc, sC, Klast)
   switch (tile) {
-    case 1: NM_BF16BIG(256, 256, 2, 4); break;
-    case 2: NM_BF16BIG(256, 128, 4, 2); break;
-    case 3: NM_BF16BIG(128, 256, 2, 4); break;
+    case 1: NM_BF16BIG(256, 256, 2, 4, 1); break;
+    case 2: NM_BF16BIG(256, 128, 4, 2, 1); break;
+    case 3: NM_BF16BIG(128, 256, 2, 4, 1); break;
+    case 4: NM_BF16BIG(256, 128, 4, 2, 2); break;
+    case 5: NM_BF16BIG(128, 256, 2, 4, 2); break;
     default:
       hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
                          Bl, ldb, sB, beta, C, ldc, sC, Klast);
