@@ -35,7 +35,15 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
-WORKLOAD = dict(name="thymine_dz", o=33, v=127, naux=640, nroots=2, ndir=45, seed=4301)
+# the benchmark's workload (thymine/cc-pVDZ-shaped) and the aug-cc-pVDZ-shaped
+# one (o = 33, v = 250, naux = 1100, four roots in one block Davidson; its
+# subspaces are capped at 48 vectors of 0.55 GB)
+WORKLOADS = {
+    "thymine_dz": dict(name="thymine_dz", o=33, v=127, naux=640, nroots=2, ndir=45, seed=4301),
+    "thymine_adz": dict(name="thymine_adz", o=33, v=250, naux=1100, nroots=4, ndir=45, seed=6301,
+                        davidson_max=48),
+}
+WORKLOAD = WORKLOADS["thymine_dz"]
 # the ordered pairs of excited states whose couplings one step produces
 PAIRS = [(1, 2), (2, 1)]
 # the metric's accuracy bound on every coupling component (au)
@@ -43,7 +51,11 @@ F_TOL = 1e-6
 # DF factor scale: the recipe's N(0, 0.05) gives no convergent CCSD at this
 # size (ground-state iterations overflow from the MP2 start); the scale is
 # reduced so that naux * sigma^2 * v keeps its value at o = 4, v = 12, naux = 48.
-SIGMA_B = 0.05 * (48 * 12 / (640 * 127)) ** 0.5
+def sigma_b(cfg):
+    return 0.05 * (48 * 12 / (cfg["naux"] * cfg["v"])) ** 0.5
+
+
+SIGMA_B = sigma_b(WORKLOAD)
 
 
 def log(msg):
@@ -99,7 +111,7 @@ LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": None}
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
 # workgroup tiles of the bfloat16-pair kernel (nm_gemm_tiled)
-BF16_TILES = {0: "128x128", 1: "256x256", 2: "256x128", 3: "128x256"}
+BF16_TILES = {0: "128x128", 1: "256x256", 2: "256x128", 3: "128x256", 4: "256x128 (loads 2 steps ahead)", 5: "128x256 (loads 2 steps ahead)"}
 
 # timed-step precision: library mode, dtype label, dominant ladder kernel
 PRECISIONS = {
@@ -188,7 +200,7 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
     started from MP2 (the default) and from the network, at tolerance tol.
     Every answer is judged by the same residual tolerance."""
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
-    base = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=SIGMA_B)
+    base = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=sigma_b(cfg))
     eps = T(base["eps"])
     opts = nm.default_opts(precision=prec, tol_ground=tol)
     n4 = (cfg["o"] * cfg["v"]) ** 2
@@ -341,6 +353,8 @@ def main():
                     help="only the warmup and timed steps (for kernel profiles of a step)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the ladder GEMM launches and a copy calibration (profiling)")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="thymine_dz",
+                    help="thymine_dz (default, the benchmark) or thymine_adz (v = 250, 4 roots)")
     ap.add_argument("--learned-guess", action="store_true",
                     help="only the learned-guess workload: 48 training and 16 held-out "
                          "perturbed geometries, ground-state iterations from MP2 vs the network")
@@ -356,7 +370,8 @@ def main():
     import synth
     import paper_2301_13264_amd as nm
 
-    cfg = WORKLOAD
+    cfg = WORKLOADS[args.workload]
+    sb = sigma_b(cfg)
     dev = torch.device("cuda:0")
     if args.roofline_only:
         roofline_only(nm, torch, cfg, dev)
@@ -364,15 +379,22 @@ def main():
     if args.learned_guess:
         learned_guess(nm, torch, np, synth, cfg, dev, getattr(nm, PRECISIONS[args.precision][0]))
         return
-    sysd = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=SIGMA_B)
-    dirs = synth.make_directions(cfg["o"] + cfg["v"], cfg["naux"], cfg["seed"], cfg["ndir"],
-                                 sigma_b=SIGMA_B)
+    sysd = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=sb)
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
-    inp = dict(eps=T(sysd["eps"]), B=T(sysd["B"]), dh=T(dirs["dh"]), dB=T(dirs["dB"]))
-    del dirs
+    inp = dict(eps=T(sysd["eps"]), B=T(sysd["B"]))
+    # directions one at a time (the same values as synth.make_directions),
+    # straight into device memory
+    n = cfg["o"] + cfg["v"]
+    inp["dh"] = torch.empty((cfg["ndir"], n, n), dtype=torch.float64, device=dev)
+    inp["dB"] = torch.empty((cfg["ndir"], cfg["naux"], n, n), dtype=torch.float64, device=dev)
+    for q in range(cfg["ndir"]):
+        d = synth.make_direction(n, cfg["naux"], cfg["seed"], q, sigma_b=sb)
+        inp["dh"][q].copy_(T(d["dh"]))
+        inp["dB"][q].copy_(T(d["dB"]))
     torch.cuda.synchronize()
     prec = getattr(nm, PRECISIONS[args.precision][0])
-    opts = nm.default_opts(precision=prec)
+    extra = {"davidson_max": cfg["davidson_max"]} if "davidson_max" in cfg else {}
+    opts = nm.default_opts(precision=prec, **extra)
 
     for w in range(args.warmup):
         log(f"[bench] warmup step {w + 1}/{args.warmup} ({args.precision})")
@@ -407,8 +429,9 @@ def main():
     N = cfg["o"] * cfg["v"] + (cfg["o"] * cfg["v"]) ** 2
     st = torch.cuda.current_stream()
     tr = {}
-    for pname, pcode in [("fp64", nm.CC_FP64), ("fp32", nm.CC_FP32_REFINE),
-                         ("bf16x3", nm.CC_BF16X3_REFINE)]:
+    for pname, pcode in ([] if args.transforms <= 0 else
+                         [("fp64", nm.CC_FP64), ("fp32", nm.CC_FP32_REFINE),
+                          ("bf16x3", nm.CC_BF16X3_REFINE)]):
         for side, sname in [(nm.CC_RIGHT, "right"), (nm.CC_LEFT, "left")]:
             per_call = {}
             for k in (1, 4):
@@ -434,7 +457,7 @@ def main():
         oprec = nm.CC_FP64 if args.precision != "fp64" else nm.CC_FP32_REFINE
         log(f"[bench] one step in {oname} for comparison")
         c0 = time.perf_counter()
-        octx, oout = run_step(nm, torch, inp, cfg, nm.default_opts(precision=oprec))
+        octx, oout = run_step(nm, torch, inp, cfg, nm.default_opts(precision=oprec, **extra))
         c1 = time.perf_counter()
         octx.close()
         dF = max(float(np.max(np.abs(np.asarray(out["F"][k]) - np.asarray(oout["F"][k]))))
@@ -463,9 +486,10 @@ def main():
         ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype=PRECISIONS[args.precision][1],
         data="synthetic",
-        config=dict(workload=(f"thymine_dz: o=33 v=127 naux=640, {cfg['nroots']} roots "
+        config=dict(workload=(f"{cfg['name']}: o={cfg['o']} v={cfg['v']} naux={cfg['naux']}, "
+                              f"{cfg['nroots']} roots "
                               f"(pair gap {out['omega'][1] - out['omega'][0]:.4f} Ha), "
-                              f"{cfg['ndir']} directions, DF scale {SIGMA_B:.5f}"),
+                              f"{cfg['ndir']} directions, DF scale {sb:.5f}"),
                     global_batch=1, parallelism="none"),
         valid=valid,
         precision=args.precision,
@@ -475,7 +499,8 @@ def main():
                          if other and args.precision != "fp64" else None),
         stage_s=out["stage_s"],
         omega=out["omega"], e_corr=out["e_corr"],
-        jacobian_transforms_per_s={k: 1000.0 / x["ms_per_vector_k4"] for k, x in tr.items()},
+        jacobian_transforms_per_s=({k: 1000.0 / x["ms_per_vector_k4"] for k, x in tr.items()}
+                                   if tr else None),
         jacobian_transform_ms=tr,
         step_counts=counts,
         step_gemm_tflops=stats["gemm_flops"] / (ms / 1000.0) / 1e12,

@@ -80,15 +80,23 @@ def make_system(o: int, v: int, naux: int, seed: int,
     return dict(o=o, v=v, naux=naux, eps=eps, B=np.ascontiguousarray(B))
 
 
+def make_direction(n: int, naux: int, seed: int, q: int, sigma_b: float = SIGMA_B) -> dict:
+    """Perturbation direction q (dh^q, dB^q) of the set drawn from seed."""
+    rng = np.random.default_rng(direction_seed(seed, q))
+    dh = direction_one_electron(n, rng)
+    dB = symmetric_factor(naux, n, sigma_b, rng)
+    return dict(dh=dh, dB=dB)
+
+
 def make_directions(n: int, naux: int, seed: int, ndir: int,
                     sigma_b: float = SIGMA_B) -> dict:
     """ndir independent perturbation directions (dh^q, dB^q)."""
     dh = np.zeros((ndir, n, n))
     dB = np.zeros((ndir, naux, n, n))
     for q in range(ndir):
-        rng = np.random.default_rng(direction_seed(seed, q))
-        dh[q] = direction_one_electron(n, rng)
-        dB[q] = symmetric_factor(naux, n, sigma_b, rng)
+        d = make_direction(n, naux, seed, q, sigma_b)
+        dh[q] = d["dh"]
+        dB[q] = d["dB"]
     return dict(dh=dh, dB=dB)
 
 
