@@ -111,7 +111,9 @@ LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": None}
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
 # workgroup tiles of the bfloat16-pair kernel (nm_gemm_tiled)
-BF16_TILES = {0: "128x128", 1: "256x256", 2: "256x128", 3: "128x256", 4: "256x128 (loads 2 steps ahead)", 5: "128x256 (loads 2 steps ahead)"}
+BF16_TILES = {0: "128x128", 1: "256x256", 2: "256x128", 3: "128x256",
+              4: "256x128 (loads 2 steps ahead)", 5: "128x256 (loads 2 steps ahead)",
+              6: "256x128 (fragments 1 step ahead)", 7: "128x256 (fragments 1 step ahead)"}
 
 # timed-step precision: library mode, dtype label, dominant ladder kernel
 PRECISIONS = {

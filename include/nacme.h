@@ -232,7 +232,9 @@ int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, co
  * `tile` (precision CC_BF16X3_REFINE only): 0 = 128 x 128 outputs per
  * workgroup (two per CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one
  * per CU), 4 = 256 x 128 and 5 = 128 x 256 with the global loads issued two
- * K steps ahead, -1 = the library's model of the fastest shape (what nm_gemm and
+ * K steps ahead, 6 = 256 x 128 and 7 = 128 x 256 with the next K step's
+ * fragments read from LDS during this step's products, -1 = the library's
+ * model of the fastest shape (what nm_gemm and
  * the contraction engine use before the autotuner has timed a shape).
  * -1 (ARG) for a tile with another precision.                              */
 int nm_gemm_tiled(int precision, int tile, int ta, int tb, int M, int N, int K, double alpha,

@@ -553,6 +553,9 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
 // next K step is loaded while this one is multiplied; PD = 2 (two register
 // sets, the loop unrolled by two so that each set has fixed registers): the
 // K step after next, so a global load has two steps of products to arrive.
+// PD = 3: the fragments of the next K step are read from LDS into a second
+// register set while this step's products run (and the next-but-one step's
+// chunks are stored), so no product waits for an LDS read after the barrier.
 // Every load is unconditional (past the last step the last one is read
 // again), which keeps the waits at the LDS stores fixed.  The three products
 // of a fragment pair are issued one per row block and then over the column
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
     const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int Klast) {
   static_assert(WM * WN == 8, "eight waves");
-  static_assert(PD == 1 || PD == 2, "prefetch depth");
+  static_assert(PD == 1 || PD == 2 || PD == 3, "pipeline variant");
   constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
   // 16-byte chunks per thread and operand half per K step: rows / 128
   constexpr int RA = BM / 128, RB = BN / 128;
@@ -650,11 +653,65 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
           __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah, fbh[j], acc[i][j], 0, 0, 0);               \
     }                                                                                             \
   }
+#define NM_FRAGS(S, G)                                                                            \
+  _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                                \
+    const int o = swz(wn * TN + j * 16 + lr, lk);                                                 \
+    qbh##S[j] = *(const bf16x8*)&SB[G][0][o];                                                     \
+    qbl##S[j] = *(const bf16x8*)&SB[G][1][o];                                                     \
+  }                                                                                               \
+  _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                                \
+    const int o = swz(wm * TM + i * 16 + lr, lk);                                                 \
+    qah##S[i] = *(const bf16x8*)&SA[G][0][o];                                                     \
+    qal##S[i] = *(const bf16x8*)&SA[G][1][o];                                                     \
+  }
+#define NM_MMA(S)                                                                                 \
+  _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                                \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                    \
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(qal##S[i], qbh##S[j], acc[i][j], 0, 0, 0);        \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                    \
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(qah##S[i], qbl##S[j], acc[i][j], 0, 0, 0);        \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) acc[i][j] =                                    \
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(qah##S[i], qbh##S[j], acc[i][j], 0, 0, 0);        \
+  }
   // (the scheduling barriers keep each step's loads ahead of its products and
   // its LDS stores, which wait for older loads, behind them)
   NM_LOAD(0, 0)
   NM_STORE(0, 0)
-  if constexpr (PD == 1) {
+  if constexpr (PD == 3) {
+    // fragment register sets; stage s of LDS holds step s mod 2 ahead
+    bf16x8 qah0[FI], qal0[FI], qbh0[FJ], qbl0[FJ];
+    bf16x8 qah1[FI], qal1[FI], qbh1[FJ], qbl1[FJ];
+    NM_LOAD(0, NM_KOFF(1))
+    __syncthreads();
+    NM_FRAGS(0, 0)
+    NM_STORE(0, 1)
+    NM_LOAD(0, NM_KOFF(2))
+    __syncthreads();
+    int t = 0;
+    for (; t + 1 < nk; t += 2) {
+      // set 0: fragments of step t; stage 1: step t + 1; registers: step t + 2
+      asm volatile("" ::: "memory");
+      NM_FRAGS(1, 1)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_MMA(0)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_STORE(0, 0)
+      NM_LOAD(0, NM_KOFF(t + 3))
+      __syncthreads();
+      asm volatile("" ::: "memory");
+      // set 1: step t + 1; stage 0: step t + 2; registers: step t + 3
+      NM_FRAGS(0, 0)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_MMA(1)
+      __builtin_amdgcn_sched_barrier(0);
+      NM_STORE(0, 1)
+      NM_LOAD(0, NM_KOFF(t + 4))
+      __syncthreads();
+    }
+    if (t < nk) {   // odd step count: the last step's fragments are in set 0
+      NM_MMA(0)
+    }
+  } else if constexpr (PD == 1) {
     __syncthreads();
     for (int t = 0; t < nk; ++t) {
       const int cur = t & 1;
@@ -697,6 +754,8 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
 #undef NM_LOAD
 #undef NM_STORE
 #undef NM_COMPUTE
+#undef NM_FRAGS
+#undef NM_MMA
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
@@ -716,8 +775,8 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
 // Tile shapes of the split-precision GEMM: 0 = 128 x 128 (two workgroups per
 // CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one workgroup per CU).
 static void bf16_tile_dims(int tile, int& bm, int& bn) {
-  bm = (tile == 1 || tile == 2 || tile == 4) ? 256 : 128;
-  bn = (tile == 1 || tile == 3 || tile == 5) ? 256 : 128;
+  bm = (tile == 1 || tile == 2 || tile == 4 || tile == 6) ? 256 : 128;
+  bn = (tile == 1 || tile == 3 || tile == 5 || tile == 7) ? 256 : 128;
 }
 
 // The shape used when none is given: the 128 x 128 kernel, measured faster
@@ -762,6 +821,8 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
     case 3: NM_BF16BIG(128, 256, 2, 4, 1); break;
     case 4: NM_BF16BIG(256, 128, 4, 2, 2); break;
     case 5: NM_BF16BIG(128, 256, 2, 4, 2); break;
+    case 6: NM_BF16BIG(256, 128, 4, 2, 3); break;
+    case 7: NM_BF16BIG(128, 256, 2, 4, 3); break;
     default:
       hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
                          Bl, ldb, sB, beta, C, ldc, sC, Klast);

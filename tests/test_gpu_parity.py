@@ -340,7 +340,7 @@ def test_bf16_pair_packing_is_exact(nm, spec, ashape):
     assert torch.equal(C.cpu(), ref)
 
 
-@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 32), (130, 257, 64), (1089, 640, 320), (600, 700, 96)])
 def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K, tile):
     """nm_gemm_tiled with bfloat16 pairs (the split-precision kernel alone, in
