@@ -200,6 +200,12 @@ static double dot_bio(Ctx& c, const double* x, const double* y) {
   kc(dot(c.s, x, y, c.N, c.o, c.v, 1, c.eng->scratch_reduce(), c.eng->scalar_slot(0)), "dot");
   return d2h(c, c.eng->scalar_slot(0));
 }
+// length of the half layout (singles, doubles (ia) <= (jb)) of an
+// amplitude-shaped vector
+static int64_t half_len(const Ctx& c) {
+  const int64_t nov = (int64_t)c.o * c.v;
+  return nov + nov * (nov + 1) / 2;
+}
 static double dot_plain(Ctx& c, const double* x, const double* y, int64_t n) {
   kc(dot(c.s, x, y, n, 1, 1, 0, c.eng->scratch_reduce(), c.eng->scalar_slot(0)), "dot");
   return d2h(c, c.eng->scalar_slot(0));
@@ -675,11 +681,30 @@ struct Ritz {
 // T(X, Y, k) applies the operator to k vectors stored [k][N] at once.
 static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*, int)>& T,
                      std::vector<double*>& out, const std::vector<double*>* guess = nullptr) {
-  const int64_t N = c.N, nov = (int64_t)c.o * c.v;
+  // Every subspace vector (basis, images, Ritz vectors, corrections) is kept
+  // in the half layout (singles and the doubles (ia) <= (jb)), where the
+  // biorthonormal product is the plain dot product: half the bytes of every
+  // pass over the subspace.  Vectors go to the full symmetric layout only
+  // for the transform (and for the caller).
+  const int64_t N = half_len(c), nov = (int64_t)c.o * c.v;
   const int nb = nroots + std::max(0, c.opts.davidson_block);
   const int maxm = std::min(kMaxRows, std::max(c.opts.davidson_max, 2 * nb + 2));
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
+  double* Fin = ar.alloc((int64_t)nb * c.N);   // full-layout transform inputs / outputs
+  double* Fout = ar.alloc((int64_t)nb * c.N);
+  // T on r half-layout rows: unpack, transform, pack
+  auto Th = [&](const double* Xh, double* Yh, int r) {
+    for (int z0 = 0; z0 < r; z0 += nb) {
+      const int rr = std::min(nb, r - z0);
+      for (int z = 0; z < rr; ++z)
+        kc(half_unpack(c.s, Fin + (int64_t)z * c.N, Xh + (int64_t)(z0 + z) * N, c.o, c.v), "unpack");
+      T(Fin, Fout, rr);
+      for (int z = 0; z < rr; ++z)
+        kc(half_pack(c.s, Yh + (int64_t)(z0 + z) * N, Fout + (int64_t)z * c.N, c.o, c.v), "pack");
+    }
+  };
+  auto dotb = [&](const double* x, const double* y) { return dot_plain(c, x, y, N); };
   double* V = ar.alloc((int64_t)maxm * N);
   double* W = ar.alloc((int64_t)maxm * N);
   double* X = ar.alloc((int64_t)nb * N);
@@ -707,15 +732,14 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   // false if x is in the span.  Rows without an image get one from flush().
   auto orth = [&](double* x, double* ax) -> bool {
     if (m >= maxm) return false;
-    if (!ax) kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
-    double n0 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+    double n0 = std::sqrt(std::max(0.0, dotb(x, x)));
     if (!(n0 > 0)) return false;
     for (int pass = 0; pass < 2 && m > 0; ++pass) {
-      dots_rows(c, V, m, x, N, true, work, h);
+      dots_rows(c, V, m, x, N, false, work, h);
       sub_rows(c, V, m, h, x, N, hd);
       if (ax) sub_rows(c, W, m, h, ax, N, hd);
     }
-    const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+    const double n1 = std::sqrt(std::max(0.0, dotb(x, x)));
     if (n1 < 1e-4 * n0 || n1 < 1e-14) return false;
     axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
     if (ax) axpby_(c, W + (int64_t)m * N, ax, 1.0 / n1, 0.0, N);
@@ -728,7 +752,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   auto flush = [&](int m0, int mimg) {
     if (mimg < m) {
       const auto t0 = std::chrono::steady_clock::now();
-      T(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
+      Th(V + (int64_t)mimg * N, W + (int64_t)mimg * N, m - mimg);
       if (verbose()) {
         sync(c);
         t_apply += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -737,10 +761,10 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     const int r = m - m0;
     if (r <= 0) return;
     // columns G[k][j] = <V_k, W_j> and rows G[j][k] = <W_k, V_j>, j >= m0
-    dots_rows_multi(c, V, m, W + (int64_t)m0 * N, r, N, true, workm, H);
+    dots_rows_multi(c, V, m, W + (int64_t)m0 * N, r, N, false, workm, H);
     for (int jj = 0; jj < r; ++jj)
       for (int k = 0; k < m; ++k) G[(size_t)k * maxm + m0 + jj] = H[(size_t)jj * m + k];
-    dots_rows_multi(c, W, m, V + (int64_t)m0 * N, r, N, true, workm, H);
+    dots_rows_multi(c, W, m, V + (int64_t)m0 * N, r, N, false, workm, H);
     for (int jj = 0; jj < r; ++jj)
       for (int k = 0; k < m; ++k) G[(size_t)(m0 + jj) * maxm + k] = H[(size_t)jj * m + k];
   };
@@ -750,7 +774,10 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   if (guess)
     for (double* gv : *guess) {
       if (m >= nb) break;
-      copy_d(c, Rs, gv, N);
+      // symmetric part of the given vector, in the half layout
+      copy_d(c, Fin, gv, c.N);
+      kc(apply_metric(c.s, Fin, Fin, c.o, c.v, 2), "symmetrise");
+      kc(half_pack(c.s, Rs, Fin, c.o, c.v), "pack");
       orth(Rs, nullptr);
     }
   if (m < nb) {
@@ -760,7 +787,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     std::sort(d.begin(), d.end());
     const double one = 1.0;
     for (int k = 0; k < (int)d.size() && m < nb; ++k) {
-      kc(fill(c.s, Rs, 0.0, N), "fill");
+      kc(fill(c.s, Rs, 0.0, N), "fill");   // a singles unit vector (same offset in both layouts)
       hip_check(hipMemcpyAsync(Rs + d[k].second, &one, sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
       sync(c);
       orth(Rs, nullptr);
@@ -787,7 +814,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   double* tmpa = nullptr;
   auto refresh = [&](const std::vector<double>& Y, int nk) -> double {
     c.eng->set_lowp(false);
-    T(X, AXd, nroots);
+    Th(X, AXd, nroots);
     c.eng->set_lowp(true);
     double wt = 0.0;
     for (int k = 0; k < nroots; ++k) {
@@ -795,8 +822,8 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       double* dk = AXd + (int64_t)k * N;
       copy_d(c, Rs, dk, N);
       axpby_(c, Rs, xk, -res.w[k], 1.0, N);
-      const double xn = std::sqrt(dot_bio(c, xk, xk));
-      wt = std::max(wt, std::sqrt(std::max(0.0, dot_bio(c, Rs, Rs))) / xn);
+      const double xn = std::sqrt(dotb(xk, xk));
+      wt = std::max(wt, std::sqrt(std::max(0.0, dotb(Rs, Rs))) / xn);
       axpby_(c, dk, AX + (int64_t)k * N, -1.0, 1.0, N);   // D_k
     }
     (void)nk;
@@ -808,7 +835,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     hip_check(hipMemcpyAsync(zdev, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice, c.s), "H2D");
     kc(gemm_f64(c.s, true, false, m, (int)N, nroots, 1, 1.0, zdev, m, 0, AXd, N, 0, 1.0, W, N, 0),
        "image update");
-    dots_rows_multi(c, V, m, AXd, nroots, N, true, workm, H);
+    dots_rows_multi(c, V, m, AXd, nroots, N, false, workm, H);
     for (int a = 0; a < m; ++a)
       for (int b = 0; b < m; ++b) {
         double acc = 0.0;
@@ -873,8 +900,8 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       double* axk = AX + (int64_t)k * N;
       copy_d(c, Rs, axk, N);
       axpby_(c, Rs, xk, -res.w[k], 1.0, N);
-      const double xn = std::sqrt(dot_bio(c, xk, xk));
-      rn[k] = std::sqrt(std::max(0.0, dot_bio(c, Rs, Rs))) / xn;
+      const double xn = std::sqrt(dotb(xk, xk));
+      rn[k] = std::sqrt(std::max(0.0, dotb(Rs, Rs))) / xn;
       if (k < nroots) worst = std::max(worst, rn[k]);
     }
     if (!std::isfinite(worst)) throw Error(-5, "non-finite Davidson residual");
@@ -935,15 +962,14 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       double* x = Cblk + (int64_t)r * N;
       copy_d(c, x, AX + (int64_t)k * N, N);
       axpby_(c, x, X + (int64_t)k * N, -res.w[k], 1.0, N);
-      kc(apply_denominator(c.s, x, x, c.eps.p, c.o, c.v, res.w[k], 1), "precondition");
-      kc(apply_metric(c.s, x, x, c.o, c.v, 2), "symmetrise");
-      n0.push_back(std::sqrt(std::max(0.0, dot_bio(c, x, x))));
+      kc(half_denominator(c.s, x, x, c.eps.p, c.o, c.v, res.w[k]), "precondition");
+      n0.push_back(std::sqrt(std::max(0.0, dotb(x, x))));
       ++r;
     }
     // block Gram-Schmidt against the (orthonormal) basis; a second pass only
     // when the first removed more than half of some vector's squared norm
     for (int pass = 0; pass < 2 && m0 > 0 && r > 0; ++pass) {
-      dots_rows_multi(c, V, m0, Cblk, r, N, true, workm, H);
+      dots_rows_multi(c, V, m0, Cblk, r, N, false, workm, H);
       sub_rows_multi(c, V, m0, H, Cblk, r, N, hdm);
       bool again = false;
       for (int a = 0; a < r; ++a) {
@@ -956,10 +982,10 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
     for (int a = 0; a < r && m < maxm; ++a) {
       double* x = Cblk + (int64_t)a * N;
       for (int pass = 0; pass < 2 && m > m0; ++pass) {
-        dots_rows(c, V + (int64_t)m0 * N, m - m0, x, N, true, work, h);
+        dots_rows(c, V + (int64_t)m0 * N, m - m0, x, N, false, work, h);
         sub_rows(c, V + (int64_t)m0 * N, m - m0, h, x, N, hd);
       }
-      const double n1 = std::sqrt(std::max(0.0, dot_bio(c, x, x)));
+      const double n1 = std::sqrt(std::max(0.0, dotb(x, x)));
       if (!(n0[a] > 0) || n1 < 1e-4 * n0[a] || n1 < 1e-14) continue;
       axpby_(c, V + (int64_t)m * N, x, 1.0 / n1, 0.0, N);
       ++m;
@@ -976,8 +1002,9 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
                  res.iters, t_apply, t_ph[0], t_ph[1], t_ph[2], t_ph[3], t_ph[4] - t_apply);
   // normalise and hand out the nroots lowest Ritz vectors
   for (int k = 0; k < nroots; ++k) {
-    const double xn = std::sqrt(dot_bio(c, X + (int64_t)k * N, X + (int64_t)k * N));
-    axpby_(c, out[k], X + (int64_t)k * N, 1.0 / xn, 0.0, N);
+    const double xn = std::sqrt(dotb(X + (int64_t)k * N, X + (int64_t)k * N));
+    kc(half_unpack(c.s, out[k], X + (int64_t)k * N, c.o, c.v), "unpack");
+    axpby_(c, out[k], out[k], 1.0 / xn, 0.0, c.N);
   }
   res.w.resize(nroots);
   (void)nov;
@@ -1221,11 +1248,11 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
 // exact (G gets the same update) and the subspace is kept.  Only a true
 // residual below the tolerance ends a system's solve.
 constexpr int kMaxBlockRhs = 8;
-static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
-                          const std::function<void(const double*, double*, int)>& T,
-                          const std::function<void(double*, const double*)>& precond,
-                          const double* B, double* X, double tol, int maxit, int* iters,
-                          bool mixed_images) {
+static int linsolve_core(Ctx& c, int64_t n, bool packed, int k,
+                         const std::function<void(const double*, double*, int)>& T,
+                         const std::function<void(double*, const double*)>& precond,
+                         const double* B, double* X, double tol, int maxit, int* iters,
+                         bool mixed_images) {
   if (k < 1 || k > kMaxBlockRhs) throw Error(-1, "linear solver block size out of range");
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
@@ -1463,6 +1490,47 @@ static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
   c.eng->set_lowp(false);
   c.eng->set_bf16(false);
   return status;
+}
+
+// T X = B for k right-hand sides.  Amplitude-shaped systems (packed) run in
+// the half layout (singles and doubles (ia) <= (jb), where the biorthonormal
+// product is the plain dot product), so every pass over the subspace moves
+// half the bytes; vectors are unpacked to the full symmetric layout for T and
+// the preconditioner.
+static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
+                          const std::function<void(const double*, double*, int)>& T,
+                          const std::function<void(double*, const double*)>& precond,
+                          const double* B, double* X, double tol, int maxit, int* iters,
+                          bool mixed_images) {
+  if (!packed) return linsolve_core(c, n, false, k, T, precond, B, X, tol, maxit, iters, mixed_images);
+  if (k < 1 || k > kMaxBlockRhs) throw Error(-1, "linear solver block size out of range");
+  const int64_t nh = half_len(c);
+  Arena& ar = c.eng->arena();
+  ArenaScope sc(ar);
+  double* Fin = ar.alloc((int64_t)k * n);
+  double* Fout = ar.alloc((int64_t)k * n);
+  double* Bh = ar.alloc((int64_t)k * nh);
+  double* Xh = ar.alloc((int64_t)k * nh);
+  for (int r = 0; r < k; ++r) {
+    copy_d(c, Fin, B + (int64_t)r * n, n);
+    kc(apply_metric(c.s, Fin, Fin, c.o, c.v, 2), "symmetrise");
+    kc(half_pack(c.s, Bh + (int64_t)r * nh, Fin, c.o, c.v), "pack");
+  }
+  auto Th = [&](const double* xh, double* yh, int r) {
+    for (int z = 0; z < r; ++z)
+      kc(half_unpack(c.s, Fin + (int64_t)z * n, xh + (int64_t)z * nh, c.o, c.v), "unpack");
+    T(Fin, Fout, r);
+    for (int z = 0; z < r; ++z)
+      kc(half_pack(c.s, yh + (int64_t)z * nh, Fout + (int64_t)z * n, c.o, c.v), "pack");
+  };
+  auto preh = [&](double* yh, const double* xh) {
+    kc(half_unpack(c.s, Fin, xh, c.o, c.v), "unpack");
+    precond(Fout, Fin);
+    kc(half_pack(c.s, yh, Fout, c.o, c.v), "pack");
+  };
+  const int st = linsolve_core(c, nh, false, k, Th, preh, Bh, Xh, tol, maxit, iters, mixed_images);
+  for (int r = 0; r < k; ++r) kc(half_unpack(c.s, X + (int64_t)r * n, Xh + (int64_t)r * nh, c.o, c.v), "unpack");
+  return st;
 }
 
 // Single right-hand side.

@@ -56,6 +56,14 @@ int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t
 int apply_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o, int v,
                       double shift, int mode);
 int apply_metric(hipStream_t s, double* y, const double* x, int o, int v, int mode);
+// Half layout of amplitude-shaped vectors: singles, then the doubles of the
+// unordered pairs (ia) <= (jb) (o v + o v (o v + 1) / 2 doubles), in which the
+// biorthonormal product of symmetric vectors is the plain dot product.
+int half_pack(hipStream_t s, double* h, const double* x, int o, int v);
+int half_unpack(hipStream_t s, double* x, const double* h, int o, int v);
+// y = x / (shift - D) on the half layout (the Davidson preconditioner)
+int half_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o, int v,
+                     double shift);
 int dot(hipStream_t s, const double* x, const double* y, int64_t n, int o, int v, int packed,
         double* scratch, double* out_dev);
 int absmax(hipStream_t s, const double* x, int64_t n, double* scratch, double* out_dev);

@@ -1319,6 +1319,104 @@ int apply_denominator(hipStream_t s, double* y, const double* x, const double* e
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// Half layout of an amplitude-shaped vector: the singles, then the doubles
+// x2[i][j][a][b] of the unordered pairs P = i v + a <= Q = j v + b, row by
+// row of the upper triangle (offset P nov - P (P - 1) / 2 + Q - P).  For
+// vectors with x2[i][j][a][b] = x2[j][i][b][a] the biorthonormal product is
+// the plain dot product of their half layouts.
+__device__ inline int64_t half_index(int64_t P, int64_t Q, int64_t nov) {
+  return nov + P * nov - P * (P - 1) / 2 + (Q - P);
+}
+
+// full (symmetric doubles) -> half; one thread per full element, the P <= Q
+// ones write (contiguously in Q for a fixed P)
+__global__ void half_pack_kernel(double* __restrict__ h, const double* __restrict__ x, int o, int v) {
+  const int64_t nov = (int64_t)o * v, n2 = nov * nov;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nov + n2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nov) {
+      h[e] = x[e];
+      continue;
+    }
+    int64_t r = e - nov;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    const int64_t P = (int64_t)i * v + a, Q = (int64_t)j * v + b;
+    if (P <= Q) h[half_index(P, Q, nov)] = x[e];
+  }
+}
+
+// half -> full symmetric doubles
+__global__ void half_unpack_kernel(double* __restrict__ x, const double* __restrict__ h, int o, int v) {
+  const int64_t nov = (int64_t)o * v, n2 = nov * nov;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nov + n2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nov) {
+      x[e] = h[e];
+      continue;
+    }
+    int64_t r = e - nov;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    const int64_t P = (int64_t)i * v + a, Q = (int64_t)j * v + b;
+    x[e] = P <= Q ? h[half_index(P, Q, nov)] : h[half_index(Q, P, nov)];
+  }
+}
+
+// y = x / (shift - D) on the half layout (D the orbital-energy difference of
+// the element; |shift - D| kept >= floor_abs), as denom_kernel's mode 1
+__global__ void half_denom_kernel(double* y, const double* x, const double* eps, int o, int v,
+                                  double shift, double floor_abs) {
+  const int64_t nov = (int64_t)o * v, nh = nov + nov * (nov + 1) / 2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nh;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double D;
+    if (e < nov) {
+      const int i = (int)(e / v), a = (int)(e % v);
+      D = eps[o + a] - eps[i];
+    } else {
+      // row P of the upper triangle: the largest P with its offset <= e - nov
+      const int64_t t = e - nov;
+      const double nn = (double)nov;
+      int64_t P = (int64_t)(((2.0 * nn + 1.0) - sqrt((2.0 * nn + 1.0) * (2.0 * nn + 1.0) - 8.0 * (double)t)) * 0.5);
+      if (P < 0) P = 0;
+      if (P > nov - 1) P = nov - 1;
+      while (P > 0 && P * nov - P * (P - 1) / 2 > t) --P;
+      while (P + 1 < nov && (P + 1) * nov - (P + 1) * P / 2 <= t) ++P;
+      const int64_t Q = P + (t - (P * nov - P * (P - 1) / 2));
+      const int i = (int)(P / v), a = (int)(P % v), j = (int)(Q / v), b = (int)(Q % v);
+      D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
+    }
+    double d = shift - D;
+    if (fabs(d) < floor_abs) d = (d < 0.0) ? -floor_abs : floor_abs;
+    y[e] = x[e] / d;
+  }
+}
+
+int half_pack(hipStream_t s, double* h, const double* x, int o, int v) {
+  const int64_t n = (int64_t)o * v * (1 + (int64_t)o * v);
+  hipLaunchKernelGGL(half_pack_kernel, dim3(grid_for(n)), dim3(256), 0, s, h, x, o, v);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int half_unpack(hipStream_t s, double* x, const double* h, int o, int v) {
+  const int64_t n = (int64_t)o * v * (1 + (int64_t)o * v);
+  hipLaunchKernelGGL(half_unpack_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, h, o, v);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int half_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o, int v,
+                     double shift) {
+  const int64_t nov = (int64_t)o * v, n = nov + nov * (nov + 1) / 2;
+  hipLaunchKernelGGL(half_denom_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, eps, o, v, shift,
+                     1e-3);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 // Packed-metric weights on the doubles block: w = 1/2 (1 + delta_(ia),(jb)).
 // mode 0: y = w x (seed of a packed functional on the full tensor);
 // mode 1: y[ijab] = x[ijab] + x[jiba] - delta x (full-tensor gradient -> packed gradient);
