@@ -200,6 +200,16 @@ static double dot_bio(Ctx& c, const double* x, const double* y) {
   kc(dot(c.s, x, y, c.N, c.o, c.v, 1, c.eng->scratch_reduce(), c.eng->scalar_slot(0)), "dot");
   return d2h(c, c.eng->scalar_slot(0));
 }
+// Vectors per batched transform: the largest intermediates of a transform
+// grow with the batch as a few o v^3 tensors per vector (the tangent and the
+// adjoint of the vvov integral use, and their low-precision packings); the
+// batch is kept to about 40 GB of them (8 vectors at o = 33, v = 127; 2 at
+// v = 250).
+static int transform_batch(const Ctx& c) {
+  const double per_vec = 4.0 * (double)c.o * c.v * c.v * c.v * 8.0;
+  return (int)std::max(1.0, std::min(8.0, std::floor(40e9 / per_vec)));
+}
+
 // length of the half layout (singles, doubles (ia) <= (jb)) of an
 // amplitude-shaped vector
 static int64_t half_len(const Ctx& c) {
@@ -694,9 +704,10 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
   double* Fin = ar.alloc((int64_t)nb * c.N);   // full-layout transform inputs / outputs
   double* Fout = ar.alloc((int64_t)nb * c.N);
   // T on r half-layout rows: unpack, transform, pack
+  const int kt = std::min(nb, transform_batch(c));
   auto Th = [&](const double* Xh, double* Yh, int r) {
-    for (int z0 = 0; z0 < r; z0 += nb) {
-      const int rr = std::min(nb, r - z0);
+    for (int z0 = 0; z0 < r; z0 += kt) {
+      const int rr = std::min(kt, r - z0);
       for (int z = 0; z < rr; ++z)
         kc(half_unpack(c.s, Fin + (int64_t)z * c.N, Xh + (int64_t)(z0 + z) * N, c.o, c.v), "unpack");
       T(Fin, Fout, rr);
@@ -1516,12 +1527,16 @@ static int linsolve_block(Ctx& c, int64_t n, bool packed, int k,
     kc(apply_metric(c.s, Fin, Fin, c.o, c.v, 2), "symmetrise");
     kc(half_pack(c.s, Bh + (int64_t)r * nh, Fin, c.o, c.v), "pack");
   }
+  const int kt = transform_batch(c);
   auto Th = [&](const double* xh, double* yh, int r) {
-    for (int z = 0; z < r; ++z)
-      kc(half_unpack(c.s, Fin + (int64_t)z * n, xh + (int64_t)z * nh, c.o, c.v), "unpack");
-    T(Fin, Fout, r);
-    for (int z = 0; z < r; ++z)
-      kc(half_pack(c.s, yh + (int64_t)z * nh, Fout + (int64_t)z * n, c.o, c.v), "pack");
+    for (int z0 = 0; z0 < r; z0 += kt) {
+      const int rr = std::min(kt, r - z0);
+      for (int z = 0; z < rr; ++z)
+        kc(half_unpack(c.s, Fin + (int64_t)z * n, xh + (int64_t)(z0 + z) * nh, c.o, c.v), "unpack");
+      T(Fin, Fout, rr);
+      for (int z = 0; z < rr; ++z)
+        kc(half_pack(c.s, yh + (int64_t)(z0 + z) * nh, Fout + (int64_t)z * n, c.o, c.v), "pack");
+    }
   };
   auto preh = [&](double* yh, const double* xh) {
     kc(half_unpack(c.s, Fin, xh, c.o, c.v), "unpack");
@@ -1616,17 +1631,27 @@ __global__ void diag_occ_add_kernel(double* M, int64_t n, int o, double a) {
 // the ladder sum_cd t_ij^cd W[c][d][a][b] is the only place W enters the
 // residual, so its adjoint is t2 (and R2 along R_jr) times the ladder
 // output's adjoint.
-static int vvvv_density(Graph& G, Ctx& c, const PairData& P) {
+// Only the rows c in [c0, c0 + cc) of its first index are formed (cc = v
+// for the whole block).
+static int vvvv_density(Graph& G, Ctx& c, const PairData& P, int64_t c0 = 0, int64_t cc = -1) {
   const int64_t o = c.o, v = c.v, o2v2 = o * o * v * v;
+  if (cc < 0) cc = v;
+  const Range O{0, o}, V{0, v}, Cc{c0, cc};
   const int t2 = G.leaf(T2of(c, c.t));
   const int y0 = G.leaf(tview(P.ylad, {o, o, v, v}));
-  std::vector<Term> terms{mul(1, op(t2, "ijcd"), op(y0, "ijab"), "cdab")};
+  std::vector<Term> terms{mul(1, op(t2, "ijcd", {O, O, Cc, V}), op(y0, "ijab"), "cdab")};
   if (P.nlad > 1) {
     const int r2 = G.leaf(T2of(c, c.R[P.jr]));
     const int y1 = G.leaf(tview(P.ylad + o2v2, {o, o, v, v}));
-    terms.push_back(mul(1, op(r2, "ijcd"), op(y1, "ijab"), "cdab"));
+    terms.push_back(mul(1, op(r2, "ijcd", {O, O, Cc, V}), op(y1, "ijab"), "cdab"));
   }
-  return G.node({v, v, v, v}, terms);
+  return G.node({cc, v, v, v}, terms);
+}
+
+// rows of the vvvv block formed at a time: about 4 GB of them
+static int64_t vvvv_chunk(const Ctx& c) {
+  const double row = (double)c.v * c.v * c.v * 8.0;
+  return std::max<int64_t>(1, std::min<int64_t>(c.v, (int64_t)(4e9 / row)));
 }
 
 // d Phi / d B[P] from the bare blocks W[c][d][a][b] = sum_P B_ac B_bd,
@@ -1641,12 +1666,23 @@ static void fold_bare_adjoints(Ctx& c, PairData& P) {
   Graph G(*c.eng);
   const int b = G.leaf(c.B);
   const int bb = G.leaf(tview(P.Bbar, {Pn, n, n}));
-  const int gw = vvvv_density(G, c, P);
   const int gwov = G.leaf(tview(P.gWov, {v, v, o, v}));
   const int ggov = G.leaf(tview(P.gGov, {o, v, o, v}));
   Engine& e = *c.eng;
-  e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pbd", {AP, V, V})), G.view(op(bb, "Pac", {AP, V, V})));
-  e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pac", {AP, V, V})), G.view(op(bb, "Pbd", {AP, V, V})));
+  // vvvv, formed a block of rows c at a time
+  const int64_t cch = vvvv_chunk(c);
+  for (int64_t c0 = 0; c0 < v; c0 += cch) {
+    const int64_t cc = std::min(cch, v - c0);
+    ArenaScope s2(c.eng->arena());
+    const int n0 = G.size();
+    const int gw = vvvv_density(G, c, P, c0, cc);
+    const Range Vc{o + c0, cc};
+    e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pbd", {AP, V, V})),
+               G.view(op(bb, "Pac", {AP, V, Vc})));
+    e.contract(1.0, G.view(op(gw, "cdab")), G.view(op(b, "Pac", {AP, V, Vc})),
+               G.view(op(bb, "Pbd", {AP, V, V})));
+    G.truncate(n0);
+  }
   e.contract(1.0, G.view(op(gwov, "cdkb")), G.view(op(b, "Pbd", {AP, V, V})), G.view(op(bb, "Pkc", {AP, O, V})));
   e.contract(1.0, G.view(op(gwov, "cdkb")), G.view(op(b, "Pkc", {AP, O, V})), G.view(op(bb, "Pbd", {AP, V, V})));
   e.contract(1.0, G.view(op(ggov, "kcld")), G.view(op(b, "Pld", {AP, O, V})), G.view(op(bb, "Pkc", {AP, O, V})));
@@ -2250,12 +2286,28 @@ static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const d
   const bool tn = P.has_tan;
   Arena& ar = c.eng->arena();
   ArenaScope sc(ar);
+  // packed vvvv block from its factors, a chunk of rows c at a time: the
+  // chunk's rows of d Phi/dW (M1) and its columns c (M2, the image with the
+  // first and third indices swapped), two GEMMs over the o^2 pairs each
   double* Gw = ar.alloc(mv * mv);
   {
+    const int64_t cch = vvvv_chunk(c), v2 = v * v, o2v2 = o * o * v2;
     ArenaScope s2(ar);
-    Graph G(*c.eng);
-    const int gw = vvvv_density(G, c, P);
-    kc(pack_vvvv(c.s, Gw, G.val(gw).p, c.v), "vvvv packing");
+    double* M1 = ar.alloc(cch * v * v2);
+    double* M2 = ar.alloc(cch * v * v2);
+    const double* Xf[2] = {c.t + o * v, P.nlad > 1 ? c.R[P.jr] + o * v : nullptr};
+    const double* Yf[2] = {P.ylad, P.ylad + o2v2};
+    for (int64_t c0 = 0; c0 < v; c0 += cch) {
+      const int cc = (int)std::min(cch, v - c0);
+      for (int f = 0; f < P.nlad; ++f) {
+        const double beta = f == 0 ? 0.0 : 1.0;
+        kc(gemm_f64(c.s, true, false, (int)(cc * v), (int)v2, (int)(o * o), 1, 1.0, Xf[f] + c0 * v, v2, 0,
+                    Yf[f], v2, 0, beta, M1, v2, 0), "vvvv rows");
+        kc(gemm_f64(c.s, true, false, (int)v2, (int)(cc * v), (int)(o * o), 1, 1.0, Xf[f], v2, 0,
+                    Yf[f] + c0 * v, v2, 0, beta, M2, cc * v, 0), "vvvv columns");
+      }
+      kc(pack_vvvv_rows(c.s, Gw, M1, M2, c.v, (int)c0, cc), "vvvv packing");
+    }
   }
   // directions per batch from the arena use of one direction's rows
   const int64_t per_dir = Pn * (m + 2 * gc + mv + 3 * (n * o + o * o + v * o) + n * v + 4 * n * o + 2 * o * o);
@@ -2503,6 +2555,9 @@ int eom_solve(cc_ctx* c, int side, int nroots, double* omega, int* iters) {
     return CC_ERR_ARG;
   }
   try {
+    // stages differ in their large work buffers: release the arena chunks
+    // the previous stage left unused before this one allocates its own
+    c->eng->arena().trim();
     int st = nm::eom(*c, side, nroots, omega, iters);
     if (st == CC_ERR_COMPLEX_ROOT) c->err = "complex EOM root among the requested states";
     if (st == CC_NOT_CONVERGED) c->err = "EOM states not converged";
@@ -2540,6 +2595,9 @@ int multipliers(cc_ctx* c, int npairs, const int* pairs, int* iters) {
     pl.push_back({i, j});
   }
   try {
+    // stages differ in their large work buffers: release the arena chunks
+    // the previous stage left unused before this one allocates its own
+    c->eng->arena().trim();
     return nm::multipliers_impl(*c, pl, iters);
   } catch (const Error& e) {
     return fail(c, e);
@@ -2554,6 +2612,9 @@ int densities(cc_ctx* c, int i, int j, double* D1) {
     return CC_ERR_STATE;
   }
   try {
+    // stages differ in their large work buffers: release the arena chunks
+    // the previous stage left unused before this one allocates its own
+    c->eng->arena().trim();
     nm::densities_impl(*c, i, j);
     if (D1) nm::copy_d(*c, D1, it->second.Deff, (int64_t)c->n * c->n);
     nm::sync(*c);
@@ -2575,6 +2636,9 @@ int nacme(cc_ctx* c, int i, int j, int nq, const double* dh, const double* dB, d
     return CC_ERR_ARG;
   }
   try {
+    // stages differ in their large work buffers: release the arena chunks
+    // the previous stage left unused before this one allocates its own
+    c->eng->arena().trim();
     nm::nacme_impl(*c, i, j, nq, dh, dB, F);
     return CC_OK;
   } catch (const Error& e) {

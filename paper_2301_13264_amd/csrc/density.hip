@@ -47,32 +47,35 @@ __global__ __launch_bounds__(256) void pack_pairs_kernel(const double* __restric
   out[r * ldo + j] = val;
 }
 
-// One workgroup per packed row pair (a >= c) and 32 x 32 tile of column
-// pairs (b, d): the four index images of G[c][d][a][b] are read as rows of
-// M1[x][y] = G[c][x][a][y] and M2[x][y] = G[a][x][c][y] (y contiguous) and
-// transposed through LDS so that the packed output (d fastest) is written in
-// order.
-__global__ __launch_bounds__(256) void pack_vvvv_kernel(const double* __restrict__ G, int v,
-                                                        int64_t mv, double* __restrict__ out) {
+// One workgroup per packed row pair (a >= c), c in the chunk [c0, c0 + cc),
+// and 32 x 32 tile of column pairs (b, d): the four index images of
+// G[c][d][a][b] are read as rows of M1[x][y] = G[c][x][a][y] (from the chunk
+// M1c[c - c0][x][a][y]) and M2[x][y] = G[a][x][c][y] (from
+// M2c[a][x][c - c0][y]), y contiguous, and transposed through LDS so that the
+// packed output (d fastest) is written in order.
+__global__ __launch_bounds__(256) void pack_vvvv_rows_kernel(const double* __restrict__ M1c,
+                                                             const double* __restrict__ M2c, int v,
+                                                             int c0, int cc, int64_t mv,
+                                                             double* __restrict__ out) {
   __shared__ double T[4][32][33];
-  const int64_t r = blockIdx.y;
-  int a, c;
-  tri_decode(r, a, c);
+  const int cl = blockIdx.y, c = c0 + cl, a = blockIdx.z;
+  if (a < c) return;
+  const int64_t r = (int64_t)a * (a + 1) / 2 + c;
   int tb, td;
   tri_decode(blockIdx.x, tb, td);
   const int b0 = tb * 32, d0 = td * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
-  const double* M1 = G + (int64_t)c * v3 + (int64_t)a * v;
-  const double* M2 = G + (int64_t)a * v3 + (int64_t)c * v;
+  const int64_t v2 = (int64_t)v * v, s2 = (int64_t)cc * v;
+  const double* M1 = M1c + (int64_t)cl * v * v2 + (int64_t)a * v;   // M1[x][y] = M1[x v2 + y]
+  const double* M2 = M2c + (int64_t)a * v * s2 + (int64_t)cl * v;   // M2[x][y] = M2[x s2 + y]
   const bool two = (a != c);
   for (int i = ty; i < 32; i += 8) {
     const int d = d0 + i, b = b0 + i, bj = b0 + tx, dj = d0 + tx;
     const bool in0 = d < v && bj < v, in1 = b < v && dj < v;
     T[0][i][tx] = in0 ? M1[(int64_t)d * v2 + bj] : 0.0;
     T[1][i][tx] = in1 ? M1[(int64_t)b * v2 + dj] : 0.0;
-    T[2][i][tx] = (two && in0) ? M2[(int64_t)d * v2 + bj] : 0.0;
-    T[3][i][tx] = (two && in1) ? M2[(int64_t)b * v2 + dj] : 0.0;
+    T[2][i][tx] = (two && in0) ? M2[(int64_t)d * s2 + bj] : 0.0;
+    T[3][i][tx] = (two && in1) ? M2[(int64_t)b * s2 + dj] : 0.0;
   }
   __syncthreads();
   for (int i = ty; i < 32; i += 8) {
@@ -118,12 +121,13 @@ int pack_pairs(hipStream_t s, double* out, int64_t ldo, const double* in, int64_
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int pack_vvvv(hipStream_t s, double* out, const double* G, int v) {
+int pack_vvvv_rows(hipStream_t s, double* out, const double* M1c, const double* M2c, int v, int c0,
+                   int cc) {
   const int64_t mv = (int64_t)v * (v + 1) / 2;
   const int nt = (v + 31) / 32;
-  if (mv > 65535) return -1;
-  hipLaunchKernelGGL(pack_vvvv_kernel, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)mv), dim3(256), 0,
-                     s, G, v, mv, out);
+  if (cc <= 0 || c0 < 0 || c0 + cc > v || cc > 65535) return -1;
+  hipLaunchKernelGGL(pack_vvvv_rows_kernel, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)cc, (unsigned)v),
+                     dim3(256), 0, s, M1c, M2c, v, c0, cc, mv, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -70,6 +70,13 @@ double* Arena::alloc(int64_t ndouble) {
   }
 }
 
+void Arena::trim() {
+  if (cur_ + 1 >= chunks_.size()) return;
+  (void)hipDeviceSynchronize();
+  for (size_t k = cur_ + 1; k < chunks_.size(); ++k) (void)hipFree(chunks_[k].base);
+  chunks_.resize(cur_ + 1);
+}
+
 void Arena::rewind(Mark m) {
   if (chunks_.empty()) return;
   // recompute live bytes: chunks before m.chunk full up to their top

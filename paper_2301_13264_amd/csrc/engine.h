@@ -46,6 +46,8 @@ class Arena {
   Mark mark() const { return {cur_, chunks_.empty() ? 0 : chunks_[cur_].top}; }
   void rewind(Mark m);
   size_t peak_bytes() const { return peak_; }
+  // frees the chunks after the current one (unused since the last rewind)
+  void trim();
   size_t reserved_bytes() const;
 
  private:

@@ -86,10 +86,13 @@ int rows_axpy(hipStream_t s, const double* V, int m, int64_t n, const double* h,
 // out[r][j] = in[r][p][q] + in[r][q][p] (sum, p != q) or in[r][p][q] (p >= q).
 int pack_pairs(hipStream_t s, double* out, int64_t ldo, const double* in, int64_t ldi, int64_t rows,
                int o, int v, bool sum);
-// out[(a >= c)][(b >= d)] (pairs packed as x (x + 1) / 2 + y, v (v + 1) / 2 <=
-// 65535 of them) = sum over the distinct images (a, c) <-> (c, a),
-// (b, d) <-> (d, b) of G[c][d][a][b] (G: [v][v][v][v]).
-int pack_vvvv(hipStream_t s, double* out, const double* G, int v);
+// Rows (a >= c) with c in [c0, c0 + cc) of out[(a >= c)][(b >= d)] (pairs
+// packed as x (x + 1) / 2 + y) = the sum over the distinct images
+// (a, c) <-> (c, a), (b, d) <-> (d, b) of G[c][d][a][b], from the chunk's two
+// images M1c[c - c0][d][a][b] = G[c][d][a][b] ([cc][v][v][v]) and
+// M2c[a][d][c - c0][b] = G[a][d][c][b] ([v][v][cc][v]).
+int pack_vvvv_rows(hipStream_t s, double* out, const double* M1c, const double* M2c, int v, int c0,
+                   int cc);
 // out[r] = alpha sum_j A[r lda + j] B[r ldb + j] + beta out[r]  (j < len; ldb 0
 // broadcasts one row of B)
 int rowdot(hipStream_t s, double* out, const double* A, int64_t lda, const double* B, int64_t ldb,
