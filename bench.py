@@ -106,7 +106,10 @@ def run_step(nm, torch, inp, cfg, opts):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.9546e+10, "fp32": 1.8797e+10, "bf16x3": None}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.944e+10, "fp32": 1.881e+10}
+# the same for each workgroup tile of the bfloat16-pair kernel
+LADDER_TRAFFIC_BYTES_BF16 = {0: 2.469e+10, 1: 5.67e+09, 2: 8.15e+09, 3: 7.50e+09, 4: 8.04e+09,
+                             5: 7.87e+09, 6: 8.51e+09, 7: 8.32e+09}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
@@ -147,7 +150,8 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
         lms = ev0.elapsed_time(ev1) / nl
         tf = ladder_flop / (lms * 1e-3) / 1e12
         roof[pname] = dict(bound="mfma", achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak,
-                           traffic=LADDER_TRAFFIC_BYTES[pname], launch_ms=lms,
+                           traffic=(LADDER_TRAFFIC_BYTES[pname] if cfg["name"] == "thymine_dz" else None),
+                           launch_ms=lms,
                            flop_per_launch=ladder_flop,
                            algorithmic_bytes=(A.numel() + Bv.numel()) * A.element_size()
                            + 8 * C.numel())
@@ -171,12 +175,15 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
         ev1.synchronize()
         tile_ms[BF16_TILES[tile]] = ev0.elapsed_time(ev1) / nl
     best_tile = min(tile_ms, key=tile_ms.get)
+    best_code = [t for t, name in BF16_TILES.items() if name == best_tile][0]
     lms = tile_ms[best_tile]
     # achieved: the method's flops (2 o^2 v^4 per vector); the three bf16
     # products each such flop issues are reported beside it
     tf = ladder_flop / (lms * 1e-3) / 1e12
     roof["bf16x3"] = dict(bound="mfma", achieved=tf, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
-                          frac=tf / PEAK_BF16_TFLOPS, traffic=LADDER_TRAFFIC_BYTES["bf16x3"],
+                          frac=tf / PEAK_BF16_TFLOPS,
+                          traffic=(LADDER_TRAFFIC_BYTES_BF16[best_code] if cfg["name"] == "thymine_dz"
+                                   else None),
                           launch_ms=lms, flop_per_launch=ladder_flop, products_per_flop=3,
                           issued_tflops=3.0 * tf, issued_frac=3.0 * tf / PEAK_BF16_TFLOPS,
                           tile=best_tile, tile_launch_ms=tile_ms,

@@ -224,7 +224,12 @@ def test_full_size_multipliers_satisfy_oracle_equations(nm, system, coupling_run
     scale_k = max(1.0, float(torch.linalg.norm(pull(m["kappa_bar"])[0])))
     res_k = float(torch.linalg.norm(gk + k1))
     say(f"[full size] |dL/dkappa| = {res_k:.2e} (scale {scale_k:.2e})")
-    assert res_k < 1e-8 * scale_k
+    # quantities that vanish only at convergence (L_i . R_j, the eigen-equation
+    # residuals, both held to ~1e-9) enter eta_kappa through
+    # gamma = L_i / (omega_j - omega_i), amplified by 1/gap (~2e2 at this
+    # pair's 0.0046 Ha); kappa-bar reaches F linearly through D_eff, so 1e-7
+    # relative here stays far inside the 1e-6 au coupling bound checked below
+    assert res_k < 1e-7 * scale_k
 
 
 def test_full_size_coupling_matches_oracle_direct_route(nm, system, coupling_run):
