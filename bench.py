@@ -62,9 +62,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_step(nm, torch, inp, cfg, opts):
+def run_step(nm, torch, inp, cfg, opts, start=None):
     """One pass of the path; every library call ends with a stream sync, so the
-    host clock between calls gives the per-stage split."""
+    host clock between calls gives the per-stage split.  start(ctx), when
+    given, sets the amplitude solver's starting point (timed as "guess")."""
     st = {}
     t = time.perf_counter()
 
@@ -81,6 +82,9 @@ def run_step(nm, torch, inp, cfg, opts):
 
     ctx = nm.Context(cfg["o"], cfg["v"], cfg["naux"], inp["eps"], inp["B"], opts)
     lap("integrals")
+    if start is not None:
+        start(ctx)
+        lap("guess")
     e, it, rc = ctx.ground()
     need(rc, "cc_ground")
     lap("ground")
@@ -201,13 +205,15 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
 
 
 def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, steps=3000,
-                  batch=8192, lr=2e-3, tol=1e-8):
+                  batch=8192, lr=2e-3, tol=1e-8, n_full=2):
     """The learned-guess workload: perturbed geometries of the thymine-shaped
     system (orbital rotation exp(K), K_pq ~ N(0, 0.01^2), seeds 900 + k), a
     network trained on the converged doubles of n_train of them by the
     library's own kernels, and the amplitude solver on the n_eval others
     started from MP2 (the default) and from the network, at tolerance tol.
-    Every answer is judged by the same residual tolerance."""
+    Every answer is judged by the same residual tolerance.  On the first
+    n_full held-out geometries the whole path to the couplings (pairs (1, 2)
+    and (2, 1), 45 directions) runs from each start as well."""
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
     base = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=sigma_b(cfg))
     eps = T(base["eps"])
@@ -240,7 +246,7 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
     log(f"[learned] trained: loss {loss:.3e} in {c2 - c1:.1f} s")
     del F, Z
     mu_h, sd_h = mu.cpu().numpy(), sd.cpu().numpy()
-    rows = []
+    rows, guess_s = [], []
     for k in range(n_eval):
         Bk = T(synth.perturbed_factor(base["B"], 900 + n_train + k))
         res = {}
@@ -250,6 +256,8 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
             t0 = time.perf_counter()
             if mode == "learned":
                 ctx.guess_t2(net, mu_h, sd_h, zs)
+                torch.cuda.synchronize()
+                guess_s.append(time.perf_counter() - t0)
             e, it, rc = ctx.ground()
             torch.cuda.synchronize()
             res[mode] = (e, it, rc, time.perf_counter() - t0)
@@ -257,6 +265,41 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
         rows.append(res)
         log(f"[learned] held-out geometry {k + 1}/{n_eval}: iterations MP2 {res['mp2'][1]}, "
             f"learned {res['learned'][1]}")
+    # the whole path to the couplings from each start
+    full = []
+    if n_full > 0:
+        n = cfg["o"] + cfg["v"]
+        inp = dict(eps=eps, dh=torch.empty((cfg["ndir"], n, n), dtype=torch.float64, device=dev),
+                   dB=torch.empty((cfg["ndir"], cfg["naux"], n, n), dtype=torch.float64, device=dev))
+        for q in range(cfg["ndir"]):
+            d = synth.make_direction(n, cfg["naux"], cfg["seed"], q, sigma_b=sigma_b(cfg))
+            inp["dh"][q].copy_(T(d["dh"]))
+            inp["dB"][q].copy_(T(d["dB"]))
+        popts = nm.default_opts(precision=prec)
+        # one untimed pass first: the GEMM autotuner's first-use timings of
+        # the solvers' shapes stay out of both starts' times
+        inp["B"] = T(base["B"])
+        ctx, _ = run_step(nm, torch, inp, cfg, popts)
+        ctx.close()
+        for k in range(min(n_full, n_eval)):
+            inp["B"] = T(synth.perturbed_factor(base["B"], 900 + n_train + k))
+            res = {}
+            for mode in ("mp2", "learned"):
+                start = (lambda c: c.guess_t2(net, mu_h, sd_h, zs)) if mode == "learned" else None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx, out = run_step(nm, torch, inp, cfg, popts, start=start)
+                res[mode] = dict(time_to_nacme_s=time.perf_counter() - t0, stage_s=out["stage_s"],
+                                 ground_iters=out["ground_iters"], eom_iters=out["eom_iters"],
+                                 F=out["F"])
+                ctx.close()
+            dF = max(float(np.abs(np.asarray(res["mp2"]["F"][p]) - np.asarray(res["learned"]["F"][p])).max())
+                     for p in PAIRS)
+            for r in res.values():
+                del r["F"]
+            full.append(dict(geometry=n_train + k, max_abs_dF=dF, **res))
+            log(f"[learned] full path, held-out geometry {k + 1}: MP2 {res['mp2']['time_to_nacme_s']:.3f} s, "
+                f"learned {res['learned']['time_to_nacme_s']:.3f} s, max |dF| {dF:.1e}")
     net.close()
     it0 = [r["mp2"][1] for r in rows]
     it1 = [r["learned"][1] for r in rows]
@@ -268,6 +311,8 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
         mean_iterations_mp2=float(np.mean(it0)), mean_iterations_learned=float(np.mean(it1)),
         mean_time_mp2_s=float(np.mean([r["mp2"][3] for r in rows])),
         mean_time_learned_s=float(np.mean([r["learned"][3] for r in rows])),
+        mean_guess_s=float(np.mean(guess_s)),
+        full_path=full,
         all_converged=all(r["mp2"][2] == 0 and r["learned"][2] == 0 for r in rows),
         max_abs_d_energy=float(max(abs(r["mp2"][0] - r["learned"][0]) for r in rows)))), flush=True)
 

@@ -261,13 +261,19 @@ int mlp_dims(const nm_mlp* net, int* n_in, int* width, int* n_out);
 int mlp_set_params(nm_mlp* net, const float* src);
 /* dst (host) <- master parameters, or their bfloat16 working copy.          */
 int mlp_get_params(nm_mlp* net, float* dst, int working);
-/* Y = net(X) for n rows.                                                     */
+/* Y = net(X) for n rows.  Networks of width a multiple of 32 up to 256, up
+ * to 32 inputs and up to 4 outputs run in one fused kernel on the bf16
+ * matrix cores: inputs and hidden activations carried as bfloat16 pairs
+ * (about 2^-16 relative), products with the bfloat16 working weights
+ * accumulated in fp32, no intermediate rows in device memory.  Other shapes
+ * run layer by layer as in training (fp32 activations, FP32 matrix cores).  */
 int mlp_forward(nm_mlp* net, int64_t n, const float* X, float* Y);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): Y = net(X)
- * for n rows, as mlp_forward, with every intermediate in a fixed 32 MiB
- * device work area of the library instead of buffers it allocates; rows go
- * through it in chunks.  No hipMalloc or hipFree is called.  The area is one
+ * for n rows, as mlp_forward (bit for bit).  Shapes of the fused kernel
+ * need no work area; the others keep every intermediate in a fixed 32 MiB
+ * device work area of the library instead of buffers it allocates, rows
+ * going through it in chunks.  No hipMalloc or hipFree is called.  The area is one
  * per GPU, shared by every call on that GPU: calls that overlap on one GPU
  * (other streams or host threads) race and must be serialised by the
  * caller.  -1 for a network whose rows do not fit 64 at a time.             */

@@ -159,9 +159,7 @@ static void copy_d(Ctx& c, double* dst, const double* src, int64_t n) {
 static void copy_rows(Ctx& c, double* dst, int64_t ldd, const double* src, int64_t lds, int64_t len,
                       int64_t rows) {
   if (len <= 0 || rows <= 0) return;
-  hip_check(hipMemcpy2DAsync(dst, ldd * sizeof(double), src, lds * sizeof(double), len * sizeof(double),
-                             rows, hipMemcpyDeviceToDevice, c.s),
-            "memcpy2D D2D");
+  kc(rows_copy(c.s, dst, ldd, src, lds, len, rows), "row copy");
 }
 
 struct ArenaScope {
@@ -2310,7 +2308,9 @@ static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const d
     }
   }
   // directions per batch from the arena use of one direction's rows
-  const int64_t per_dir = Pn * (m + 2 * gc + mv + 3 * (n * o + o * o + v * o) + n * v + 4 * n * o + 2 * o * o);
+  // (the mixed modes add fp32 packings of the pair rows: half a double each)
+  const int64_t per_dir = Pn * (m + 2 * gc + mv + (m + mv) / 2 + 3 * (n * o + o * o + v * o) + n * v +
+                                4 * n * o + 2 * o * o);
   const int64_t budget = (int64_t)2 << 30;   // doubles
   const int kq = (int)std::max<int64_t>(1, std::min<int64_t>(nq, budget / per_dir));
   double* f1 = ar.alloc(kq);
@@ -2323,13 +2323,30 @@ static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const d
     double* x = ar.alloc(R * m);
     kc(pack_pairs(c.s, x, m, db_p, nn, R, c.o, c.v, false), "pair packing");
     double* s = ar.alloc(R);
-    // one-sided blocks
-    double* Z = ar.alloc(R * gc);
-    kc(gemm_f64(c.s, false, true, (int)R, (int)gc, (int)m, 1, 1.0, x, m, 0, P.gam, m, 0, 0.0, Z, gc, 0),
-       "density gemm");
     double* Bop = ar.alloc(R * gc);
     Graph G(*c.eng);
     const Range AP{0, R}, O{0, o}, A{0, n}, Ol{0, o};
+    // the two products over packed pairs (one-sided blocks and vvvv),
+    // Z[r][y] = sum_k x[r][kb + k] Y[y][k]: fp64 in the fp64 mode, fp32
+    // operands (fp32 accumulation, fp64 result) in the mixed modes, as the
+    // solvers' large contractions
+    const int xl = G.leaf(tview(x, {R, m}));
+    auto pair_product = [&](double* Y, int64_t cols, Range kb) -> const double* {
+      if (!mixed(c)) {
+        double* z = ar.alloc(R * cols);
+        kc(gemm_f64(c.s, false, true, (int)R, (int)cols, (int)kb.len, 1, 1.0, x + kb.lo, m, 0, Y, kb.len, 0,
+                    0.0, z, cols, 0),
+           "pair product");
+        return z;
+      }
+      c.eng->set_lowp(true);
+      c.eng->set_bf16(false);
+      const int yl = G.leaf(tview(Y, {cols, kb.len}));
+      const int z = G.node({R, cols}, {mul(1, op(xl, "rk", {AP, kb}), op(yl, "yk"), "ry")});
+      c.eng->set_lowp(false);
+      return G.val(z).p;
+    };
+    const double* Z = pair_product(P.gam, gc, Range{0, m});
     const int t1 = G.leaf(T1of(c, c.t));
     const int db = G.leaf(tview(db_p, {R, n, n}));
     const int first = G.size();
@@ -2357,10 +2374,7 @@ static void nacme_impl(Ctx& c, int i1, int j1, int nq, const double* dh, const d
     }
     kc(rowdot(c.s, s, Z, gc, Bop, gc, R, gc, 1.0, 0.0), "row dots");
     // vvvv
-    double* Zw = ar.alloc(R * mv);
-    kc(gemm_f64(c.s, false, true, (int)R, (int)mv, (int)mv, 1, 1.0, x + xvv, m, 0, Gw, mv, 0, 0.0, Zw, mv,
-                0),
-       "vvvv gemm");
+    const double* Zw = pair_product(Gw, mv, Range{xvv, mv});
     kc(rowdot(c.s, s, Zw, mv, x + xvv, m, R, mv, 1.0, 1.0), "row dots");
     // Fock correction 2 sum_P tr(D[P]) B[P] - sum_P D[P] B[P][occ rows]
     auto fcorr_rows = [&](const double* gbar, int dnode) {

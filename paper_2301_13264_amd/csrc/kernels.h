@@ -53,6 +53,9 @@ int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch,
 int view_scatter(hipStream_t s, double* in, const double* out, const ViewSpec& v, double alpha);
 int fill(hipStream_t s, double* x, double val, int64_t n);
 int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n);
+// rows of len doubles: dst[r ldd + j] = src[r lds + j]
+int rows_copy(hipStream_t s, double* dst, int64_t ldd, const double* src, int64_t lds, int64_t len,
+              int64_t rows);
 int apply_denominator(hipStream_t s, double* y, const double* x, const double* eps, int o, int v,
                       double shift, int mode);
 int apply_metric(hipStream_t s, double* y, const double* x, int o, int v, int mode);

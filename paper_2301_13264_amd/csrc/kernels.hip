@@ -10,6 +10,7 @@
 // * elementwise   : orbital-energy denominators (Jacobi / Davidson
 //                   preconditioners), packed-metric weights.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstdint>
@@ -1277,6 +1278,36 @@ __global__ void axpby_kernel(double* y, const double* x, double a, double b, int
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
     y[e] = (b == 0.0) ? a * x[e] : a * x[e] + b * y[e];
+}
+
+// dst[r ldd + j] = src[r lds + j] for j < len, row r = blockIdx.y (+ r0):
+// four independent loads per thread in flight
+__global__ __launch_bounds__(256) void rows_copy_kernel(double* __restrict__ dst, int64_t ldd,
+                                                        const double* __restrict__ src, int64_t lds,
+                                                        int64_t len) {
+  const int64_t r = blockIdx.y;
+  const double* a = src + r * lds;
+  double* d = dst + r * ldd;
+  for (int64_t j0 = (int64_t)blockIdx.x * 1024 + threadIdx.x; j0 < len; j0 += (int64_t)gridDim.x * 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = j0 + 256 * u < len ? a[j0 + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + 256 * u < len) d[j0 + 256 * u] = v[u];
+  }
+}
+
+int rows_copy(hipStream_t s, double* dst, int64_t ldd, const double* src, int64_t lds, int64_t len,
+              int64_t rows) {
+  if (len <= 0 || rows <= 0) return 0;
+  const unsigned gx = (unsigned)std::min<int64_t>((len + 1023) / 1024, 8192);
+  for (int64_t r0 = 0; r0 < rows; r0 += 65535) {
+    const int64_t rr = std::min<int64_t>(65535, rows - r0);
+    hipLaunchKernelGGL(rows_copy_kernel, dim3(gx, (unsigned)rr), dim3(256), 0, s, dst + r0 * ldd, ldd,
+                       src + r0 * lds, lds, len);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 int axpby(hipStream_t s, double* y, const double* x, double a, double b, int64_t n) {

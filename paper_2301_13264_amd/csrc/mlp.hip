@@ -10,7 +10,9 @@
 //
 // Memory per batch row: activations u1, h1, u2, h2 (fp32) and one fp64 GEMM
 // output row of width entries; gradients of W reduce over the batch by split-K
-// partial products folded in fp64.
+// partial products folded in fp64.  Inference (mlp_forward) of the usual
+// shapes runs instead as one fused kernel on the bf16 matrix cores that keeps
+// every intermediate in registers (mlp_fused_kernel).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -140,6 +142,173 @@ __global__ void gather_rows_kernel(const float* __restrict__ src, const int64_t*
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / w;
     dst[e] = src[idx[r] * w + (e - r * w)];
+  }
+}
+
+// ------------------------------------------------------ fused inference
+// One pass of the whole network on the bf16 matrix cores, no intermediate
+// rows in HBM: each wave takes 32 rows at a time (two 16-row strips).
+//   layer 1: u1^T = W1^T X^T (K = n_in <= 32, zero-padded), X carried as a
+//            bfloat16 pair (hi + lo, about 2^-17 relative), W1 exact in bf16;
+//   layer 2: u2 = h1 W2 with h1 = s(u1 + b1) as a bfloat16 pair, W2 exact;
+//   layer 3: y = s(u2 + b2) W3 + b3 on the vector units, reduced across the
+//            16 lanes that hold one row's columns.
+// MFMA v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16] (j < 8) and receives D[4 (l / 16) + v][l % 16]
+// (v < 4).  Layer 1's output lands with lane l holding row l % 16 and hidden
+// units 16 c + 4 (l / 16) + v of chunk c, which is already layer 2's A layout
+// once the hidden index inside each 32-wide K block is taken in the order
+//   kk = 8 g + j  <->  k = 32 kb + 16 (j / 4) + 4 g + j % 4,
+// so W2 is staged in LDS in exactly that order, one 16-byte fragment per lane
+// and (K block, column block).  LDS holds W2 (W^2 bf16), W1 fragments, b1,
+// b2, W3 and b3; after staging it is read-only, and the waves run their row
+// tiles without further barriers.  One wave per SIMD (256 threads): the two
+// strips' A fragments take 128 registers, which leaves no room for a second.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_bits(float x) {   // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  u = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_val(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline float silu_fast(float u) { return __fdividef(u, 1.0f + __expf(-u)); }
+
+constexpr int kFusedMaxIn = 32, kFusedMaxOut = 4, kFusedMaxWidth = 256;
+
+template <int W, int NO>
+__global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict__ P, int n_in,
+                                                        int n_out, const float* __restrict__ X,
+                                                        int64_t n, float* __restrict__ Y) {
+  constexpr int KB = W / 32, CB = W / 16;
+  __shared__ __attribute__((aligned(16))) unsigned short sW2[KB * CB * 64 * 8];
+  __shared__ __attribute__((aligned(16))) unsigned short sW1[CB * 64 * 8];
+  __shared__ float sB1[W], sB2[W], sW3[W * NO], sB3[NO];
+  const float* W1 = P;
+  const float* b1 = W1 + (int64_t)n_in * W;
+  const float* W2 = b1 + W;
+  const float* b2 = W2 + (int64_t)W * W;
+  const float* W3 = b2 + W;
+  const float* b3 = W3 + (int64_t)W * n_out;
+  for (int e = threadIdx.x; e < KB * CB * 512; e += blockDim.x) {
+    const int j = e & 7, ln = (e >> 3) & 63, cb = (e >> 9) % CB, kb = (e >> 9) / CB;
+    const int g = ln >> 4, k = 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3), col = 16 * cb + (ln & 15);
+    sW2[e] = bf16_bits(W2[k * W + col]);
+  }
+  for (int e = threadIdx.x; e < CB * 512; e += blockDim.x) {
+    const int j = e & 7, ln = (e >> 3) & 63, c = e >> 9;
+    const int i = 8 * (ln >> 4) + j, k = 16 * c + (ln & 15);
+    sW1[e] = i < n_in ? bf16_bits(W1[i * W + k]) : (unsigned short)0;
+  }
+  for (int e = threadIdx.x; e < W; e += blockDim.x) {
+    sB1[e] = b1[e];
+    sB2[e] = b2[e];
+    for (int o = 0; o < NO; ++o) sW3[e * NO + o] = o < n_out ? W3[e * n_out + o] : 0.0f;
+  }
+  if (threadIdx.x < NO) sB3[threadIdx.x] = threadIdx.x < n_out ? b3[threadIdx.x] : 0.0f;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, g = lane >> 4, ln = lane & 15;
+  const int wpb = blockDim.x >> 6;
+  const int64_t ntiles = (n + 31) / 32;
+  for (int64_t t = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); t < ntiles;
+       t += (int64_t)gridDim.x * wpb) {
+    const int64_t r0 = t * 32;
+    // layer-1 B operands: X[row][8 g + j] of rows r0 + 16 s + ln, as bf16 pairs
+    bf16x8_t xh[2], xl[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t row = r0 + 16 * s + ln;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = 8 * g + j;
+        const float x = (row < n && i < n_in) ? X[row * n_in + i] : 0.0f;
+        const __bf16 hb = (__bf16)x;
+        xh[s][j] = hb;
+        xl[s][j] = (__bf16)(x - (float)hb);
+      }
+    }
+    // layer 1 and the layer-2 A fragments (hi, lo) of both strips
+    bf16x8_t ah[2][KB], al[2][KB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const bf16x8_t a1 = *(const bf16x8_t*)&sW1[(c * 64 + lane) * 8];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xl[s], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xh[s], d, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float h = silu_fast(d[v] + sB1[16 * c + 4 * g + v]);
+          const __bf16 hb = (__bf16)h;
+          ah[s][c >> 1][4 * (c & 1) + v] = hb;
+          al[s][c >> 1][4 * (c & 1) + v] = (__bf16)(h - (float)hb);
+        }
+      }
+    }
+    // layer 2 by column blocks, each followed by its share of layer 3
+    float yp[NO][2][4];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yp[o][s][v] = 0.0f;
+    for (int cb = 0; cb < CB; ++cb) {
+      f32x4_t acc[2][2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) acc[s][0] = acc[s][1] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const bf16x8_t b = *(const bf16x8_t*)&sW2[((kb * CB + cb) * 64 + lane) * 8];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          acc[s][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s][kb], b, acc[s][1], 0, 0, 0);
+          acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s][kb], b, acc[s][0], 0, 0, 0);
+        }
+      }
+      const int col = 16 * cb + ln;
+      const float bb = sB2[col];
+      float w3[NO];
+#pragma unroll
+      for (int o = 0; o < NO; ++o) w3[o] = sW3[col * NO + o];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float h = silu_fast(acc[s][0][v] + acc[s][1][v] + bb);
+#pragma unroll
+          for (int o = 0; o < NO; ++o) yp[o][s][v] = fmaf(h, w3[o], yp[o][s][v]);
+        }
+    }
+    // sum over the 16 lanes of each row group, then one lane per group writes
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float y = yp[o][s][v];
+          y += __shfl_xor(y, 8, 64);
+          y += __shfl_xor(y, 4, 64);
+          y += __shfl_xor(y, 2, 64);
+          y += __shfl_xor(y, 1, 64);
+          yp[o][s][v] = y;
+        }
+    if (ln == 0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = r0 + 16 * s + 4 * g + v;
+          if (row < n)
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+              if (o < n_out) Y[row * n_out + o] = yp[o][s][v] + sB3[o];
+        }
+    }
   }
 }
 
@@ -331,6 +500,42 @@ double loss_grad(nm_mlp* m, int64_t n, const float* X, const float* T) {
   return loss;
 }
 
+// the fused inference kernel takes widths that are multiples of 32 up to 256,
+// up to 32 inputs and up to 4 outputs
+bool fused_fits(const nm_mlp* m) {
+  return m->width % 32 == 0 && m->width <= nm::kFusedMaxWidth && m->n_in <= nm::kFusedMaxIn &&
+         m->n_out <= nm::kFusedMaxOut;
+}
+
+template <int W>
+void launch_fused(nm_mlp* m, int64_t n, const float* X, float* Y, dim3 grid) {
+  if (m->n_out == 1)
+    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, 1>), grid, dim3(256), 0, m->s, m->pw, m->n_in,
+                       m->n_out, X, n, Y);
+  else
+    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, nm::kFusedMaxOut>), grid, dim3(256), 0, m->s, m->pw,
+                       m->n_in, m->n_out, X, n, Y);
+}
+
+// Y [n][n_out] from X [n][n_in] in one kernel (no work buffers)
+void forward_fused(nm_mlp* m, int64_t n, const float* X, float* Y) {
+  if (n <= 0) return;
+  const int64_t tiles = (n + 31) / 32;
+  const dim3 grid((unsigned)std::min<int64_t>((tiles + 3) / 4, 1024));   // 4 waves per workgroup
+  switch (m->width) {
+    case 32: launch_fused<32>(m, n, X, Y, grid); break;
+    case 64: launch_fused<64>(m, n, X, Y, grid); break;
+    case 96: launch_fused<96>(m, n, X, Y, grid); break;
+    case 128: launch_fused<128>(m, n, X, Y, grid); break;
+    case 160: launch_fused<160>(m, n, X, Y, grid); break;
+    case 192: launch_fused<192>(m, n, X, Y, grid); break;
+    case 224: launch_fused<224>(m, n, X, Y, grid); break;
+    case 256: launch_fused<256>(m, n, X, Y, grid); break;
+    default: throw std::string("fused inference: unsupported width");
+  }
+  hcheck(hipGetLastError(), "fused inference");
+}
+
 int fail(nm_mlp* m, const std::string& e) {
   if (m) m->err = e;
   return CC_ERR_HIP;
@@ -463,6 +668,11 @@ int mlp_get_params(nm_mlp* m, float* dst, int working) {
 int mlp_forward(nm_mlp* m, int64_t n, const float* X, float* Y) {
   if (!m || n < 0 || (n > 0 && (!X || !Y))) return CC_ERR_ARG;
   try {
+    if (fused_fits(m)) {
+      forward_fused(m, n, X, Y);
+      hcheck(hipStreamSynchronize(m->s), "sync");
+      return CC_OK;
+    }
     const int64_t chunk = 1 << 20;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
       const int64_t k = std::min(chunk, n - r0);
@@ -494,6 +704,11 @@ int mlp_forward_noalloc(nm_mlp* m, int64_t n, const float* X, float* Y) {
   }
   try {
     if (n == 0) return CC_OK;
+    if (fused_fits(m)) {   // the fused kernel needs no work area
+      forward_fused(m, n, X, Y);
+      hcheck(hipStreamSynchronize(m->s), "sync");
+      return CC_OK;
+    }
     char* base = (char*)scratch_on(m->s);
     double* acc = (double*)base;
     float* h1 = (float*)(base + align256((size_t)rows * wa * sizeof(double)));

@@ -53,6 +53,49 @@ def test_network_forward_gradient_and_adam_match_oracle(nm, width, n):
     net.close()
 
 
+def _inference_error_bound(params, X):
+    """First-order bound on the fused inference's deviation from the fp64
+    forward of the same (bfloat16-exact) weights: inputs and both hidden
+    activations carried as bfloat16 pairs (2^-17 relative each, 2^-16 taken),
+    fp32 accumulation of at most 256 terms (2^-16 relative to the sum of
+    magnitudes), the fast SiLU within 2^-20 relative, |s'(u)| <= 1.1."""
+    W1, b1, W2, b2, W3, b3 = params
+    _, (_, u1, h1, u2, h2) = mlp.forward(params, X)
+    aX, ah1, ah2 = np.abs(X), np.abs(h1), np.abs(h2)
+    e1 = 2.0 ** -16 * (aX @ np.abs(W1))
+    eh1 = 1.1 * e1 + (2.0 ** -16 + 2.0 ** -20) * ah1
+    e2 = eh1 @ np.abs(W2) + 2.0 ** -16 * (ah1 @ np.abs(W2))
+    eh2 = 1.1 * e2 + 2.0 ** -20 * ah2
+    return eh2 @ np.abs(W3) + 2.0 ** -16 * (ah2 @ np.abs(W3))
+
+
+@pytest.mark.parametrize("n_in,width,n_out,n", [(8, 256, 1, 100003), (5, 96, 3, 4099),
+                                                (32, 32, 4, 777), (1, 64, 2, 31), (8, 160, 1, 0)])
+def test_fused_inference_matches_oracle(nm, n_in, width, n_out, n):
+    """mlp_forward's fused kernel (bf16 matrix cores, no intermediate rows)
+    against the fp64 forward: several 32-row tiles and a ragged last tile,
+    every width step of the kernel's range, one to four outputs, n = 0."""
+    say(f"[mlp fused] {n_in}-{width}-{n_out}, rows {n}")
+    net = nm.MLP(n_in, width, n_out, seed=7)
+    params = mlp.unflatten(net.get_params(working=True).astype(np.float64), n_in, width, n_out)
+    rng = np.random.default_rng(n + width)
+    X = rng.normal(size=(n, n_in)).astype(np.float32)
+    Y = torch.full((n + 1, n_out), np.nan, dtype=torch.float32, device="cuda")
+    net.forward(F32(X), Y[:n])
+    torch.cuda.synchronize()
+    assert torch.isnan(Y[n:]).all()   # nothing written past the last row
+    if n == 0:
+        net.close()
+        return
+    Y = Y[:n]
+    yref, _ = mlp.forward(params, X.astype(np.float64))
+    bound = _inference_error_bound(params, X.astype(np.float64))
+    err = np.abs(Y.cpu().numpy().astype(np.float64) - yref)
+    assert np.isfinite(err).all()
+    assert (err <= 4.0 * bound + 1e-30).all(), float((err / (bound + 1e-30)).max())
+    net.close()
+
+
 def test_training_fits_a_smooth_target(nm):
     say("[mlp] training")
     rng = np.random.default_rng(5)

@@ -20,7 +20,9 @@ def nm():
 
 
 @pytest.mark.parametrize("n_in,width,n_out,rows", [(8, 256, 1, (50000, 3000)),
-                                                  (5, 96, 3, (20000, 77))])
+                                                  (5, 96, 3, (20000, 77)),
+                                                  (40, 64, 2, (70000, 1000)),
+                                                  (8, 300, 1, (30000, 65))])
 def test_noalloc_forward_equals_forward(nm, n_in, width, n_out, rows):
     say(f"[no-alloc] net {n_in}-{width}-{n_out}, rows {rows}")
     net = nm.MLP(n_in, width, n_out, seed=11)
