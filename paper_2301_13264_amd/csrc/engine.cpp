@@ -344,6 +344,199 @@ __global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, i
   }
 }
 
+// ---------------------------------------------- short contracted range
+// C[x, f] = alpha sum_k X[x, k] F[f, k] (+ beta C): x the labels X shares
+// with C, f the labels F shares with C, k the contracted labels (K < 64), F
+// small; every label any stride.  Such products (a large tensor times a
+// small matrix over an occupied index) are bound by memory: X is read once,
+// each output written once, F sits in LDS.  Two layouts of the work:
+//   x-fast: one x index per thread (C's unit-stride label is an x label),
+//           X[x, :] in registers, a loop over f;
+//   f-fast: one f index per lane (C's unit-stride label is an f label), a
+//           loop over x indices whose X[x, :] every lane reads alike.
+constexpr int kSmallKMax = 64, kSmallKF = 4096;   // K, NF * K limits (LDS: 8 (NF K + NF + K) bytes)
+struct SmallK {
+  int nx = 0, nk = 0, nf = 0;
+  int64_t xd[kMaxViewDims], xsX[kMaxViewDims], xsC[kMaxViewDims];
+  int64_t kd[kMaxViewDims], ksX[kMaxViewDims], ksF[kMaxViewDims];
+  int64_t fd[kMaxViewDims], fsF[kMaxViewDims], fsC[kMaxViewDims];
+  int64_t NX = 0;
+  int K = 0, NF = 0;
+};
+
+__device__ inline void smallk_decode(int64_t e, int n, const int64_t* d, const int64_t* s1,
+                                     const int64_t* s2, int64_t& o1, int64_t& o2) {
+  o1 = 0;
+  o2 = 0;
+  for (int q = n - 1; q >= 0; --q) {
+    const int64_t i = e % d[q];
+    e /= d[q];
+    o1 += i * s1[q];
+    o2 += i * s2[q];
+  }
+}
+
+// F into LDS ([f][k] or [k][f]) and the per-k offsets of X, per-f offsets of C
+__device__ inline void smallk_stage(const double* __restrict__ F, const SmallK& sp, bool fk,
+                                    double* sF, int64_t* sxk, int64_t* scf) {
+  for (int e = threadIdx.x; e < sp.NF * sp.K; e += blockDim.x) {
+    const int f = e / sp.K, k = e - f * sp.K;
+    int64_t of, dummy, ok, okx;
+    smallk_decode(f, sp.nf, sp.fd, sp.fsF, sp.fsC, of, dummy);
+    smallk_decode(k, sp.nk, sp.kd, sp.ksF, sp.ksX, ok, okx);
+    sF[fk ? e : k * sp.NF + f] = F[of + ok];
+  }
+  for (int k = threadIdx.x; k < sp.K; k += blockDim.x) {
+    int64_t ok, okx;
+    smallk_decode(k, sp.nk, sp.kd, sp.ksF, sp.ksX, ok, okx);
+    sxk[k] = okx;
+  }
+  for (int f = threadIdx.x; f < sp.NF; f += blockDim.x) {
+    int64_t of, oc;
+    smallk_decode(f, sp.nf, sp.fd, sp.fsF, sp.fsC, of, oc);
+    scf[f] = oc;
+  }
+  __syncthreads();
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void smallk_xfast_kernel(double* __restrict__ C,
+                                                           const double* __restrict__ X,
+                                                           const double* __restrict__ F, SmallK sp,
+                                                           double alpha, double beta) {
+  extern __shared__ double smallk_lds[];   // sF [NF][K], sxk [K], scf [NF]
+  double* sF = smallk_lds;
+  int64_t* sxk = (int64_t*)(sF + sp.NF * sp.K);
+  int64_t* scf = sxk + sp.K;
+  smallk_stage(F, sp, true, sF, sxk, scf);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < sp.NX;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t ox, oc;
+    smallk_decode(e, sp.nx, sp.xd, sp.xsX, sp.xsC, ox, oc);
+    double xv[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) xv[k] = k < sp.K ? X[ox + sxk[k]] : 0.0;
+    for (int f = 0; f < sp.NF; ++f) {
+      const double* fr = sF + f * sp.K;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        if (k < sp.K) acc = fma(xv[k], fr[k], acc);
+      double* c = C + oc + scf[f];
+      *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * (*c));
+    }
+  }
+}
+
+// blockIdx.y: chunk of 64 f indices; blockIdx.x strides over x indices, one
+// wave per x index at a time (4 waves per workgroup)
+template <int KM>
+__global__ __launch_bounds__(256) void smallk_ffast_kernel(double* __restrict__ C,
+                                                           const double* __restrict__ X,
+                                                           const double* __restrict__ F, SmallK sp,
+                                                           double alpha, double beta) {
+  extern __shared__ double smallk_lds[];   // sF [K][NF], sxk [K], scf [NF]
+  double* sF = smallk_lds;
+  int64_t* sxk = (int64_t*)(sF + sp.NF * sp.K);
+  int64_t* scf = sxk + sp.K;
+  smallk_stage(F, sp, false, sF, sxk, scf);
+  const int f = blockIdx.y * 64 + (threadIdx.x & 63);
+  const bool fin = f < sp.NF;
+  const int64_t cf = fin ? scf[f] : 0;
+  for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < sp.NX; e += (int64_t)gridDim.x * 4) {
+    int64_t ox, oc;
+    smallk_decode(e, sp.nx, sp.xd, sp.xsX, sp.xsC, ox, oc);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < sp.K) acc = fma(X[ox + sxk[k]], fin ? sF[k * sp.NF + f] : 0.0, acc);
+    if (fin) {
+      double* c = C + oc + cf;
+      *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * (*c));
+    }
+  }
+}
+
+// C (+)= alpha sum_k X F over the labels of X not in C (K < 64); false when
+// the sizes do not fit the short-K kernels (the caller then takes a GEMM path)
+static bool smallk_contract(hipStream_t s, double alpha, const DView& X, const DView& F, const DView& C,
+                            bool overwrite) {
+  SmallK sp;
+  int64_t K = 1, NX = 1, NF = 1;
+  struct Lab { int64_t d, s1, s2, s3; };
+  std::vector<Lab> xl, fl;
+  for (int q = 0; q < X.nd; ++q) {
+    const int jc = find_lab(C, X.lab[q]);
+    if (jc < 0) {
+      const int jf = find_lab(F, X.lab[q]);
+      if (jf < 0 || sp.nk >= kMaxViewDims) return false;
+      sp.kd[sp.nk] = X.dims[q];
+      sp.ksX[sp.nk] = X.str[q];
+      sp.ksF[sp.nk] = F.str[jf];
+      ++sp.nk;
+      K *= X.dims[q];
+    } else {
+      if (find_lab(F, X.lab[q]) >= 0) return false;   // batch label
+      xl.push_back({X.dims[q], X.str[q], C.str[jc], 0});
+      NX *= X.dims[q];
+    }
+  }
+  for (int q = 0; q < F.nd; ++q) {
+    const int jc = find_lab(C, F.lab[q]);
+    if (jc >= 0) {
+      fl.push_back({F.dims[q], F.str[q], C.str[jc], 0});
+      NF *= F.dims[q];
+    } else if (find_lab(X, F.lab[q]) < 0) {
+      return false;
+    }
+  }
+  if (K < 1 || K > kSmallKMax || NF * K > kSmallKF || NF > 2048 || NX < 1 ||
+      (int)xl.size() > kMaxViewDims || (int)fl.size() > kMaxViewDims)
+    return false;
+  // outermost first: decreasing stride in C
+  auto by_c = [](const Lab& a, const Lab& b) { return a.s2 > b.s2; };
+  std::sort(xl.begin(), xl.end(), by_c);
+  std::sort(fl.begin(), fl.end(), by_c);
+  sp.nx = (int)xl.size();
+  for (int q = 0; q < sp.nx; ++q) {
+    sp.xd[q] = xl[q].d;
+    sp.xsX[q] = xl[q].s1;
+    sp.xsC[q] = xl[q].s2;
+  }
+  sp.nf = (int)fl.size();
+  for (int q = 0; q < sp.nf; ++q) {
+    sp.fd[q] = fl[q].d;
+    sp.fsF[q] = fl[q].s1;
+    sp.fsC[q] = fl[q].s2;
+  }
+  sp.NX = NX;
+  sp.K = (int)K;
+  sp.NF = (int)NF;
+  // the unit-stride label of C decides which index the lanes run along
+  const int64_t xmin = xl.empty() ? INT64_MAX : xl.back().s2;
+  const int64_t fmin = fl.empty() ? INT64_MAX : fl.back().s2;
+  const bool ffast = fmin < xmin && NF >= 16;
+  const size_t lds = sizeof(double) * (size_t)(NF * K + K + NF);
+  const double beta = overwrite ? 0.0 : 1.0;
+#define NM_SMALLK(KERN, KM, GRID)                                                         \
+  hipLaunchKernelGGL((KERN<KM>), GRID, dim3(256), lds, s, C.p, X.p, F.p, sp, alpha, beta)
+#define NM_SMALLK_K(KERN, GRID)             \
+  if (K <= 16) NM_SMALLK(KERN, 16, GRID);   \
+  else if (K <= 32) NM_SMALLK(KERN, 32, GRID); \
+  else NM_SMALLK(KERN, 64, GRID)
+  if (ffast) {
+    const dim3 grid((unsigned)std::min<int64_t>((NX + 3) / 4, 4096), (unsigned)((NF + 63) / 64));
+    NM_SMALLK_K(smallk_ffast_kernel, grid);
+  } else {
+    const dim3 grid((unsigned)std::min<int64_t>((NX + 255) / 256, 8192));
+    NM_SMALLK_K(smallk_xfast_kernel, grid);
+  }
+#undef NM_SMALLK_K
+#undef NM_SMALLK
+  kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "short-K product");
+  return true;
+}
+
 // K split of a single large-tile GEMM.  A workgroup of 128 x 128 output
 // takes about `us_per_k` microseconds per unit of K when the device is full
 // and 512 workgroups (two per CU) run at once, so a grid of `tiles`
@@ -704,6 +897,12 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
         arena_.rewind(mk);
         return;
       }
+      // no GEMM-shaped layout without copies: the short-K kernels read the
+      // views as they are
+      if (smallk_contract(s_, alpha, X, F, C, overwrite)) {
+        arena_.rewind(mk);
+        return;
+      }
     }
   }
 
@@ -897,6 +1096,23 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
     } else if (!pa_lab.empty()) {
       sb = pa_lab;
       sm = strip(sm, pa_lab);
+    }
+  }
+  // contracted labels in the memory order of the larger operand when that
+  // lets it be read in place (the smaller one is packed instead)
+  if (sk.size() > 1) {
+    const bool bigB = prod_of(B, labels_of(B)) > prod_of(A, labels_of(A));
+    const DView& Big = bigB ? B : A;
+    std::string sko;
+    for (int d = 0; d < Big.nd; ++d)
+      if (sk.find(Big.lab[d]) != std::string::npos) sko += Big.lab[d];
+    if (sko != sk) {
+      int64_t l_, s_b;
+      const std::string bbig = bigB ? (!pa_lab.empty() ? "" : sb) : (!pb_lab.empty() ? "" : sb);
+      const std::string& free_ = bigB ? sn : sm;
+      const bool in_place_now = as_matrix(Big, bbig, sk, free_, l_, s_b) || as_matrix(Big, bbig, free_, sk, l_, s_b);
+      const bool in_place_new = as_matrix(Big, bbig, sko, free_, l_, s_b) || as_matrix(Big, bbig, free_, sko, l_, s_b);
+      if (!in_place_now && in_place_new) sk = sko;
     }
   }
   const bool bcastA = !pb_lab.empty(), bcastB = !pa_lab.empty();

@@ -38,6 +38,11 @@ CONTRACTIONS = [
     ("zik,zkj->zij", [(3, 130, 41), (3, 41, 140)], (3, 130, 140)),           # 128-tile, batch
     ("ijcd,cdab->ijab", [(4, 33, 13, 11), (13, 11, 12, 15)], (4, 33, 12, 15)),  # ladder, 128-tile
     ("ik,kj->ij", [(256, 64), (64, 1024)], (256, 1024)),                     # 8-divisible grid
+    # short contracted range, large operand with no GEMM-shaped layout (the
+    # short-K kernels): lanes along an x label, along an f label, two k labels
+    ("ikab,zkj->zijab", [(8, 33, 64, 64), (2, 33, 9)], (2, 8, 9, 64, 64)),
+    ("ijal,zlb->zijab", [(16, 16, 128, 33), (2, 33, 48)], (2, 16, 16, 128, 48)),
+    ("aikbc,kc->iab", [(48, 8, 4, 48, 15), (4, 15)], (8, 48, 48)),
 ]
 
 
