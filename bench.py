@@ -186,7 +186,7 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
     tf = ladder_flop / (lms * 1e-3) / 1e12
     roof["bf16x3"] = dict(bound="mfma", achieved=tf, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
                           frac=tf / PEAK_BF16_TFLOPS,
-                          traffic=(LADDER_TRAFFIC_BYTES_BF16[best_code] if cfg["name"] == "thymine_dz"
+                          traffic=(LADDER_TRAFFIC_BYTES_BF16.get(best_code) if cfg["name"] == "thymine_dz"
                                    else None),
                           launch_ms=lms, flop_per_launch=ladder_flop, products_per_flop=3,
                           issued_tflops=3.0 * tf, issued_frac=3.0 * tf / PEAK_BF16_TFLOPS,
@@ -317,6 +317,35 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
         max_abs_d_energy=float(max(abs(r["mp2"][0] - r["learned"][0]) for r in rows)))), flush=True)
 
 
+def network_only(nm, torch, cfg, dev, nl=10):
+    """The learned guess's network (8 -> 256 -> 256 -> 1, bfloat16 working
+    weights) on one feature row per doubles index of the workload (o^2 v^2
+    rows, standard normal features): average launch time of mlp_forward's
+    fused kernel with HIP events, rows per second and the bf16 products it
+    issues (two per hidden product: inputs and activations as bf16 pairs;
+    layer 1's K padded to 32)."""
+    n = (cfg["o"] * cfg["v"]) ** 2
+    g = torch.Generator(device=dev).manual_seed(5)
+    X = torch.randn((n, 8), dtype=torch.float32, device=dev, generator=g)
+    Y = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    net = nm.MLP(8, 256, 1, seed=4)
+    net.forward(X, Y)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(nl):
+        net.forward(X, Y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nl
+    issued = 2.0 * 2.0 * n * (32 * 256 + 256 * 256)
+    net.close()
+    print(json.dumps(dict(mode="network-only", rows=n, launch_ms=ms, rows_per_s=n / ms * 1e3,
+                          issued_bf16_tflops=issued / ms / 1e9,
+                          issued_frac=issued / ms / 1e9 / PEAK_BF16_TFLOPS,
+                          silu_per_row=512, hbm_bytes_per_row=36)), flush=True)
+
+
 def roofline_only(nm, torch, cfg, dev):
     """The ladder launches alone, plus a 1 GiB device copy that calibrates the
     HBM byte counters (for rocprofv3 --pmc runs)."""
@@ -409,6 +438,9 @@ def main():
                     help="only the ladder GEMM launches and a copy calibration (profiling)")
     ap.add_argument("--workload", choices=list(WORKLOADS), default="thymine_dz",
                     help="thymine_dz (default, the benchmark) or thymine_adz (v = 250, 4 roots)")
+    ap.add_argument("--network-only", action="store_true",
+                    help="only the learned guess's network on one row per doubles index "
+                         "(fused inference kernel timing, for profiling)")
     ap.add_argument("--learned-guess", action="store_true",
                     help="only the learned-guess workload: 48 training and 16 held-out "
                          "perturbed geometries, ground-state iterations from MP2 vs the network")
@@ -429,6 +461,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.roofline_only:
         roofline_only(nm, torch, cfg, dev)
+        return
+    if args.network_only:
+        network_only(nm, torch, cfg, dev)
         return
     if args.learned_guess:
         learned_guess(nm, torch, np, synth, cfg, dev, getattr(nm, PRECISIONS[args.precision][0]))

@@ -1021,8 +1021,9 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
         std::vector<int64_t> cand{cfg, bf16_tile * kCfgTile + std::max<int64_t>(1, ns / 2),
                                   bf16_tile * kCfgTile + std::min<int64_t>(256, ns * 2)};
         for (int t = 0; t < kBf16Tiles; ++t) {
-          const int64_t bm = (t == 1 || t == 2 || t == 4 || t == 6) ? 256 : 128,
-                        bn = (t == 1 || t == 3 || t == 5 || t == 7) ? 256 : 128;
+          int tbm, tbn;
+          bf16x3_tile_dims(t, tbm, tbn);
+          const int64_t bm = tbm, bn = tbn;
           const int64_t tt = ((M0 + bm - 1) / bm) * ((N0 + bn - 1) / bn);
           // a large-tile workgroup holds a whole CU and, by the model, moves
           // 1.8x the outputs per cycle of two 128 x 128 workgroups

@@ -35,10 +35,11 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
 // tile: 0 = 128 x 128 outputs per workgroup (two per CU), 1 = 256 x 256,
 // 2 = 256 x 128, 3 = 128 x 256 (one per CU), 4 = 256 x 128 and 5 = 128 x 256
 // with loads two K steps ahead, 6 = 256 x 128 and 7 = 128 x 256 with the next
-// step's fragments read during this step's products; -1 = bf16x3_auto_tile's
-// choice.
+// step's fragments read during this step's products; -1 =
+// bf16x3_auto_tile's choice.
 constexpr int kBf16Tiles = 8;
 int bf16x3_auto_tile(int M, int N, int batch);
+void bf16x3_tile_dims(int tile, int& bm, int& bn);
 int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
                 const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
                 int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast,

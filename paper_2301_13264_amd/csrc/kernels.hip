@@ -562,7 +562,7 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
 // of a fragment pair are issued one per row block and then over the column
 // blocks (FJ independent accumulators between dependent MFMAs).
 template <int BM, int BN, int WM, int WN, int PD>
-__global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
+__global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
     int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
     const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
@@ -570,8 +570,9 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
   static_assert(WM * WN == 8, "eight waves");
   static_assert(PD == 1 || PD == 2 || PD == 3, "pipeline variant");
   constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
-  // 16-byte chunks per thread and operand half per K step: rows / 128
-  constexpr int RA = BM / 128, RB = BN / 128;
+  // 16-byte chunks per thread and operand half per K step: rows / RP, with
+  // RP = (threads / 4) rows staged per pass (four 16-byte chunks per row)
+  constexpr int RP = WM * WN * 16, RA = BM / RP, RB = BN / RP;
   __shared__ __attribute__((aligned(16))) uint16_t SA[2][2][BM * HKS];
   __shared__ __attribute__((aligned(16))) uint16_t SB[2][2][BN * HKS];
   const int64_t bz = blockIdx.z;
@@ -589,19 +590,19 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int lr = lane & 15, lk = lane >> 4;
-  // this thread's rows: (tid >> 2) + 128 r, 16-byte chunk tid & 3 of the
+  // this thread's rows: (tid >> 2) + RP r, 16-byte chunk tid & 3 of the
   // 32-wide K step, in each of A hi, A lo (r < RA) and B hi, B lo (r < RB)
   const int row0 = tid >> 2, ch = tid & 3;
   int64_t aoff[RA], boff[RB];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
-    const bool ok = m0 + row0 + 128 * r < M;
-    aoff[r] = (int64_t)(ok ? m0 + row0 + 128 * r : 0) * lda + 8 * ch;
+    const bool ok = m0 + row0 + RP * r < M;
+    aoff[r] = (int64_t)(ok ? m0 + row0 + RP * r : 0) * lda + 8 * ch;
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    const bool ok = n0 + row0 + 128 * r < N;
-    boff[r] = (int64_t)(ok ? n0 + row0 + 128 * r : 0) * ldb + 8 * ch;
+    const bool ok = n0 + row0 + RP * r < N;
+    boff[r] = (int64_t)(ok ? n0 + row0 + RP * r : 0) * ldb + 8 * ch;
   }
   // rows outside the matrix read row 0 of the panel instead (always valid):
   // they only reach accumulators of output rows or columns that are never
@@ -627,12 +628,12 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
   }
 #define NM_STORE(S, G)                                                     \
   _Pragma("unroll") for (int r = 0; r < RA; ++r) {                         \
-    *(u32x4*)&SA[G][0][swz(row0 + 128 * r, ch)] = ah##S[r];                \
-    *(u32x4*)&SA[G][1][swz(row0 + 128 * r, ch)] = al##S[r];                \
+    *(u32x4*)&SA[G][0][swz(row0 + RP * r, ch)] = ah##S[r];                 \
+    *(u32x4*)&SA[G][1][swz(row0 + RP * r, ch)] = al##S[r];                 \
   }                                                                        \
   _Pragma("unroll") for (int r = 0; r < RB; ++r) {                         \
-    *(u32x4*)&SB[G][0][swz(row0 + 128 * r, ch)] = bh##S[r];                \
-    *(u32x4*)&SB[G][1][swz(row0 + 128 * r, ch)] = bl##S[r];                \
+    *(u32x4*)&SB[G][0][swz(row0 + RP * r, ch)] = bh##S[r];                 \
+    *(u32x4*)&SB[G][1][swz(row0 + RP * r, ch)] = bl##S[r];                 \
   }
 #define NM_COMPUTE(G)                                                                             \
   {                                                                                               \
@@ -773,9 +774,9 @@ __global__ __launch_bounds__(512, 1) void gemm_bf16x3_big_kernel(
       }
 }
 
-// Tile shapes of the split-precision GEMM: 0 = 128 x 128 (two workgroups per
-// CU), 1 = 256 x 256, 2 = 256 x 128, 3 = 128 x 256 (one workgroup per CU).
-static void bf16_tile_dims(int tile, int& bm, int& bn) {
+// Output tile of each workgroup tile code of the split-precision GEMM (the
+// codes are listed in kernels.h).
+void bf16x3_tile_dims(int tile, int& bm, int& bn) {
   bm = (tile == 1 || tile == 2 || tile == 4 || tile == 6) ? 256 : 128;
   bn = (tile == 1 || tile == 3 || tile == 5 || tile == 7) ? 256 : 128;
 }
@@ -811,10 +812,11 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
   }
   if (tile < 0) tile = bf16x3_auto_tile(M, N, batch);
   int bm, bn;
-  bf16_tile_dims(tile, bm, bn);
+  bf16x3_tile_dims(tile, bm, bn);
   dim3 grid((N + bn - 1) / bn, (M + bm - 1) / bm, batch);
 #define NM_BF16BIG(BM_, BN_, WM_, WN_, PD_)                                                              \
-  hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_, PD_>), grid, dim3(512), 0, s, M, N, K, \
+  hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_, PD_>), grid, dim3(WM_ * WN_ * 64), 0, s, \
+                     M, N, K,                                                                             \
                      alpha, Ah, Al, lda, sA, Bh, Bl, ldb, sB, beta, C, ldc, sC, Klast)
   switch (tile) {
     case 1: NM_BF16BIG(256, 256, 2, 4, 1); break;

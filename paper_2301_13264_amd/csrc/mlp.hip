@@ -147,7 +147,7 @@ __global__ void gather_rows_kernel(const float* __restrict__ src, const int64_t*
 
 // ------------------------------------------------------ fused inference
 // One pass of the whole network on the bf16 matrix cores, no intermediate
-// rows in HBM: each wave takes 32 rows at a time (two 16-row strips).
+// rows in HBM: each wave takes 16 NS rows at a time (NS 16-row strips).
 //   layer 1: u1^T = W1^T X^T (K = n_in <= 32, zero-padded), X carried as a
 //            bfloat16 pair (hi + lo, about 2^-17 relative), W1 exact in bf16;
 //   layer 2: u2 = h1 W2 with h1 = s(u1 + b1) as a bfloat16 pair, W2 exact;
@@ -162,8 +162,7 @@ __global__ void gather_rows_kernel(const float* __restrict__ src, const int64_t*
 // so W2 is staged in LDS in exactly that order, one 16-byte fragment per lane
 // and (K block, column block).  LDS holds W2 (W^2 bf16), W1 fragments, b1,
 // b2, W3 and b3; after staging it is read-only, and the waves run their row
-// tiles without further barriers.  One wave per SIMD (256 threads): the two
-// strips' A fragments take 128 registers, which leaves no room for a second.
+// tiles without further barriers.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -177,8 +176,8 @@ __device__ inline float silu_fast(float u) { return __fdividef(u, 1.0f + __expf(
 
 constexpr int kFusedMaxIn = 32, kFusedMaxOut = 4, kFusedMaxWidth = 256;
 
-template <int W, int NO>
-__global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict__ P, int n_in,
+template <int W, int NO, int NS>
+__global__ __launch_bounds__(NS == 2 ? 256 : 512) void mlp_fused_kernel(const float* __restrict__ P, int n_in,
                                                         int n_out, const float* __restrict__ X,
                                                         int64_t n, float* __restrict__ Y) {
   constexpr int KB = W / 32, CB = W / 16;
@@ -211,14 +210,15 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
 
   const int lane = threadIdx.x & 63, g = lane >> 4, ln = lane & 15;
   const int wpb = blockDim.x >> 6;
-  const int64_t ntiles = (n + 31) / 32;
+  constexpr int RW = 16 * NS;   // rows per wave tile
+  const int64_t ntiles = (n + RW - 1) / RW;
   for (int64_t t = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); t < ntiles;
        t += (int64_t)gridDim.x * wpb) {
-    const int64_t r0 = t * 32;
+    const int64_t r0 = t * RW;
     // layer-1 B operands: X[row][8 g + j] of rows r0 + 16 s + ln, as bf16 pairs
-    bf16x8_t xh[2], xl[2];
+    bf16x8_t xh[NS], xl[NS];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const int64_t row = r0 + 16 * s + ln;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -230,12 +230,12 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
       }
     }
     // layer 1 and the layer-2 A fragments (hi, lo) of both strips
-    bf16x8_t ah[2][KB], al[2][KB];
+    bf16x8_t ah[NS][KB], al[NS][KB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       const bf16x8_t a1 = *(const bf16x8_t*)&sW1[(c * 64 + lane) * 8];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < NS; ++s) {
         f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
         d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xl[s], d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xh[s], d, 0, 0, 0);
@@ -249,22 +249,22 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
       }
     }
     // layer 2 by column blocks, each followed by its share of layer 3
-    float yp[NO][2][4];
+    float yp[NO][NS][4];
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int v = 0; v < 4; ++v) yp[o][s][v] = 0.0f;
     for (int cb = 0; cb < CB; ++cb) {
-      f32x4_t acc[2][2];
+      f32x4_t acc[NS][2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) acc[s][0] = acc[s][1] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
+      for (int s = 0; s < NS; ++s) acc[s][0] = acc[s][1] = (f32x4_t){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         const bf16x8_t b = *(const bf16x8_t*)&sW2[((kb * CB + cb) * 64 + lane) * 8];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < NS; ++s) {
           acc[s][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s][kb], b, acc[s][1], 0, 0, 0);
           acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s][kb], b, acc[s][0], 0, 0, 0);
         }
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
 #pragma unroll
       for (int o = 0; o < NO; ++o) w3[o] = sW3[col * NO + o];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float h = silu_fast(acc[s][0][v] + acc[s][1][v] + bb);
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float y = yp[o][s][v];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict_
         }
     if (ln == 0) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t row = r0 + 16 * s + 4 * g + v;
@@ -507,30 +507,34 @@ bool fused_fits(const nm_mlp* m) {
          m->n_out <= nm::kFusedMaxOut;
 }
 
+// one 16-row strip per wave, eight waves per workgroup (two per SIMD: the
+// strip's A fragments take 64 registers); measured 25 % faster than two
+// strips per wave with four waves (7.5 against 9.9 ms for 17.6 M rows)
 template <int W>
-void launch_fused(nm_mlp* m, int64_t n, const float* X, float* Y, dim3 grid) {
+void launch_fused(nm_mlp* m, int64_t n, const float* X, float* Y) {
+  constexpr int kStrips = 1, kWaves = 8;
+  const int64_t tiles = (n + 16 * kStrips - 1) / (16 * kStrips);
+  const dim3 grid((unsigned)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 1024)), block(64 * kWaves);
   if (m->n_out == 1)
-    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, 1>), grid, dim3(256), 0, m->s, m->pw, m->n_in,
+    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, 1, kStrips>), grid, block, 0, m->s, m->pw, m->n_in,
                        m->n_out, X, n, Y);
   else
-    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, nm::kFusedMaxOut>), grid, dim3(256), 0, m->s, m->pw,
-                       m->n_in, m->n_out, X, n, Y);
+    hipLaunchKernelGGL((nm::mlp_fused_kernel<W, nm::kFusedMaxOut, kStrips>), grid, block, 0, m->s,
+                       m->pw, m->n_in, m->n_out, X, n, Y);
 }
 
 // Y [n][n_out] from X [n][n_in] in one kernel (no work buffers)
 void forward_fused(nm_mlp* m, int64_t n, const float* X, float* Y) {
   if (n <= 0) return;
-  const int64_t tiles = (n + 31) / 32;
-  const dim3 grid((unsigned)std::min<int64_t>((tiles + 3) / 4, 1024));   // 4 waves per workgroup
   switch (m->width) {
-    case 32: launch_fused<32>(m, n, X, Y, grid); break;
-    case 64: launch_fused<64>(m, n, X, Y, grid); break;
-    case 96: launch_fused<96>(m, n, X, Y, grid); break;
-    case 128: launch_fused<128>(m, n, X, Y, grid); break;
-    case 160: launch_fused<160>(m, n, X, Y, grid); break;
-    case 192: launch_fused<192>(m, n, X, Y, grid); break;
-    case 224: launch_fused<224>(m, n, X, Y, grid); break;
-    case 256: launch_fused<256>(m, n, X, Y, grid); break;
+    case 32: launch_fused<32>(m, n, X, Y); break;
+    case 64: launch_fused<64>(m, n, X, Y); break;
+    case 96: launch_fused<96>(m, n, X, Y); break;
+    case 128: launch_fused<128>(m, n, X, Y); break;
+    case 160: launch_fused<160>(m, n, X, Y); break;
+    case 192: launch_fused<192>(m, n, X, Y); break;
+    case 224: launch_fused<224>(m, n, X, Y); break;
+    case 256: launch_fused<256>(m, n, X, Y); break;
     default: throw std::string("fused inference: unsupported width");
   }
   hcheck(hipGetLastError(), "fused inference");
