@@ -299,6 +299,7 @@ enum Use { U_VOVO, U_OOOO, U_OOVV, U_VOOV, U_VVOV, U_VVOO, U_OOOV, U_FCORR, NUSE
 struct ResNodes {
   int t1, t2, f, bl, br, w, wov, gov;
   int om1, om2;
+  int ev = -1, eo = -1;   // dressed one-particle blocks Ev[b][c], Eo[k][j] of the doubles equations
   int first;  // first non-leaf node of the residual
   int use[NUSE];
 };
@@ -428,6 +429,8 @@ static ResNodes residual_graph(Graph& G, Ctx& c, const Tensor& T1, const Tensor&
                                  mul(-1, op(u, "klbd"), op(r.gov, "ldkc"), "bc")});
   const int Eo = G.node({o, o}, {lin(1, op(Fh, "kj", {O, O}), "kj"),
                                  mul(1, op(u, "ljcd"), op(r.gov, "kdlc"), "kj")});
+  r.ev = Ev;
+  r.eo = Eo;
   // Q_ijab = sum_kc t_kjbc Xc_kiac; the exchange partner sum_kc t_kibc Xc_kjac
   // is Q with i and j swapped, added as a permutation instead of a second GEMM
   const int Q = G.node({o, o, v, v}, {mul(1, op(t2, "kjbc"), op(Xc, "kiac"), "ijab")});
@@ -473,7 +476,26 @@ static Tensor T2of(Ctx& c, double* x) {
 }
 
 // Residual at amplitudes x -> out (amplitude-shaped).
-static void residual(Ctx& c, double* x, double* out) {
+// dressed orbital energies deps[n]: the diagonals of Eo (occupied) and Ev
+// (virtual), the one-particle blocks of the doubles equations
+static void dressed_diagonal(Ctx& c, Graph& G, const ResNodes& r, double* deps) {
+  ViewSpec vo;
+  vo.nd = 1;
+  vo.dims[0] = c.o;
+  vo.istr[0] = c.o + 1;
+  vo.ostr[0] = 1;
+  kc(view_gather(c.s, deps, G.val(r.eo).p, vo, 1.0, 0.0), "dressed diagonal");
+  ViewSpec vv;
+  vv.nd = 1;
+  vv.dims[0] = c.v;
+  vv.istr[0] = c.v + 1;
+  vv.ostr[0] = 1;
+  vv.obase = c.o;
+  kc(view_gather(c.s, deps, G.val(r.ev).p, vv, 1.0, 0.0), "dressed diagonal");
+}
+
+// out = Omega(x); deps (optional) <- the dressed orbital energies at x
+static void residual(Ctx& c, double* x, double* out, double* deps = nullptr) {
   ++c.n_residual;
   ArenaScope sc(c.eng->arena());
   Graph G(*c.eng);
@@ -481,6 +503,7 @@ static void residual(Ctx& c, double* x, double* out) {
   const int64_t nov = (int64_t)c.o * c.v;
   copy_d(c, out, G.val(r.om1).p, nov);
   copy_d(c, out + nov, G.val(r.om2).p, c.N - nov);
+  if (deps) dressed_diagonal(c, G, r, deps);
 }
 
 static double energy(Ctx& c, double* x) {
@@ -519,7 +542,11 @@ struct Tape {
     // the recorded values stay as they are while the tape lives: every
     // transform reuses their low-precision packings
     G.freeze(G.size());
+    // the solvers' preconditioner: dressed orbital energies at t
+    deps = cc.eng->arena().alloc(cc.n);
+    dressed_diagonal(cc, G, r, deps);
   }
+  double* deps = nullptr;   // [n] dressed orbital energies (Eo_ii, then Ev_aa)
   ~Tape() {
     c.eng->clear_frozen();
     c.eng->arena().rewind(base);
@@ -611,13 +638,16 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
   std::vector<std::vector<double>> B;   // error overlaps (host)
   int nh = 0, head = 0;
   std::vector<int> slot;                // history order -> slot
+  // quasi-Newton step -Omega / D with D from the dressed orbital energies of
+  // the current amplitudes (the bare ones at t = 0)
+  double* deps = c.eng->arena().alloc(c.n);
   int it = 0;
   double err = 0.0;
   int status = CC_NOT_CONVERGED;
   bool lowp = mixed(c);
   c.eng->set_lowp(lowp);
   for (it = 1; it <= c.opts.maxit; ++it) {
-    residual(c, c.t, r);
+    residual(c, c.t, r, deps);
     err = amax(c, r, N);
     if (!std::isfinite(err)) throw Error(-5, "non-finite CCSD residual");
     if (verbose()) std::fprintf(stderr, "[ground] it %d max|Omega| %.3e\n", it, err);
@@ -631,7 +661,7 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
       status = CC_OK;
       break;
     }
-    kc(apply_denominator(c.s, dt, r, c.eps.p, c.o, c.v, 0.0, 0), "denominator");  // -r/D
+    kc(apply_denominator(c.s, dt, r, deps, c.o, c.v, 0.0, 0), "denominator");  // -r/D
     axpby_(c, c.t, dt, 1.0, 1.0, N);
     // DIIS on (t, dt)
     int sidx;
@@ -685,10 +715,16 @@ struct Ritz {
 };
 
 // Lowest-nroots eigenpairs of a non-symmetric operator on amplitude-shaped
-// vectors (biorthonormal metric), preconditioned by orbital-energy differences.
+// vectors (biorthonormal metric), preconditioned by orbital-energy differences
+// (peps: the bare orbital energies by default; the EOM solvers pass the
+// dressed ones of the linearisation, the diagonals of the one-particle blocks
+// of the doubles equations at the converged amplitudes).
 // T(X, Y, k) applies the operator to k vectors stored [k][N] at once.
 static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*, double*, int)>& T,
-                     std::vector<double*>& out, const std::vector<double*>* guess = nullptr) {
+                     std::vector<double*>& out, const std::vector<double*>* guess = nullptr,
+                     const double* peps = nullptr) {
+  // orbital energies of the preconditioner's denominators
+  if (!peps) peps = c.eps.p;
   // Every subspace vector (basis, images, Ritz vectors, corrections) is kept
   // in the half layout (singles and the doubles (ia) <= (jb)), where the
   // biorthonormal product is the plain dot product: half the bytes of every
@@ -790,9 +826,13 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       orth(Rs, nullptr);
     }
   if (m < nb) {
+    // (the preconditioner's orbital energies decide which singles come first)
+    std::vector<double> eh(c.n);
+    hip_check(hipMemcpyAsync(eh.data(), peps, c.n * sizeof(double), hipMemcpyDeviceToHost, c.s), "D2H");
+    sync(c);
     std::vector<std::pair<double, int64_t>> d;
     for (int i = 0; i < c.o; ++i)
-      for (int a = 0; a < c.v; ++a) d.push_back({c.eps_h[c.o + a] - c.eps_h[i], (int64_t)i * c.v + a});
+      for (int a = 0; a < c.v; ++a) d.push_back({eh[c.o + a] - eh[i], (int64_t)i * c.v + a});
     std::sort(d.begin(), d.end());
     const double one = 1.0;
     for (int k = 0; k < (int)d.size() && m < nb; ++k) {
@@ -971,7 +1011,7 @@ static Ritz davidson(Ctx& c, int nroots, const std::function<void(const double*,
       double* x = Cblk + (int64_t)r * N;
       copy_d(c, x, AX + (int64_t)k * N, N);
       axpby_(c, x, X + (int64_t)k * N, -res.w[k], 1.0, N);
-      kc(half_denominator(c.s, x, x, c.eps.p, c.o, c.v, res.w[k]), "precondition");
+      kc(half_denominator(c.s, x, x, peps, c.o, c.v, res.w[k]), "precondition");
       n0.push_back(std::sqrt(std::max(0.0, dotb(x, x))));
       ++r;
     }
@@ -1181,7 +1221,7 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
   if (side & CC_RIGHT) {
     std::vector<double*> gr = guesses(c.guess_R);
     Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.right_block(x, y, k); }, c.R,
-                      gr.empty() ? nullptr : &gr);
+                      gr.empty() ? nullptr : &gr, tp.deps);
     c.guess_R.clear();
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_r = r.w;
@@ -1194,7 +1234,7 @@ static int eom(Ctx& c, int side, int nroots, double* omega, int* iters) {
     std::vector<double*> gl = guesses(c.guess_L);
     if (gl.empty() && c.have_right) gl = c.R;
     Ritz r = davidson(c, nroots, [&](const double* x, double* y, int k) { tp.left_block(x, y, k); },
-                      c.L, gl.empty() ? nullptr : &gl);
+                      c.L, gl.empty() ? nullptr : &gl, tp.deps);
     c.guess_L.clear();
     if (r.complex_root) return CC_ERR_COMPLEX_ROOT;
     c.omega_l = r.w;
@@ -1814,7 +1854,7 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       axpby_(c, b, b, -1.0, 0.0, N);
       auto T = [&](const double* x, double* y, int kk) { tp.left_block(x, y, kk); };
       auto pre = [&](double* y, const double* x) {
-        kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
+        kc(apply_denominator(c.s, y, x, tp.deps, c.o, c.v, 0.0, 0), "precondition");
       };
       int itl = 0;
       const int st = linsolve_block(c, N, true, 1, T, pre, b, c.Lam, c.opts.tol_mult, c.opts.maxit, &itl,
@@ -1929,7 +1969,7 @@ static int multipliers_impl(Ctx& c, const std::vector<std::pair<int, int>>& pl, 
       for (int q = 0; q < kb; ++q) axpby_(c, Bm + (int64_t)q * N, jobs[solve[b0 + q]].P->eta_t, -1.0, 0.0, N);
       auto T = [&](const double* x, double* y, int kk) { tp.left_block(x, y, kk); };
       auto pre = [&](double* y, const double* x) {
-        kc(apply_denominator(c.s, y, x, c.eps.p, c.o, c.v, 0.0, 0), "precondition");
+        kc(apply_denominator(c.s, y, x, tp.deps, c.o, c.v, 0.0, 0), "precondition");
       };
       std::vector<int> its(kb, 0);
       const int st = linsolve_block(c, N, true, kb, T, pre, Bm, Xm, c.opts.tol_mult, c.opts.maxit,
