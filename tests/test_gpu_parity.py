@@ -294,6 +294,8 @@ def test_energy_gradients_match_oracle(nm, o, v, naux, seed):
     ("kicd,adkc->ia", [(5, 33, 20, 31), (127, 31, 5, 20)], (33, 127)),       # split K, packed
     ("zik,zkj->zij", [(3, 130, 41), (3, 41, 140)], (3, 130, 140)),           # batched
     ("ik,kj->ij", [(257, 1000), (1000, 300)], (257, 300)),                   # several K tiles
+    ("iak,kjb->ijab", [(20, 30, 64), (64, 25, 35)], (20, 25, 30, 35)),       # rows and columns interleaved
+    ("iak,kjb->ijab", [(6, 10, 4100), (4100, 7, 9)], (6, 7, 10, 9)),         # the same, split K
 ])
 @pytest.mark.parametrize("prec", [1, 2])
 def test_contract_low_precision_operands(nm, spec, shapes, oshape, prec):
