@@ -171,7 +171,10 @@ struct ArenaScope {
 
 // Ground state in the mixed modes: fp32-operand residuals until max|Omega|
 // falls below kMixedSwitch, then fp64 residuals to the tolerance.
-constexpr double kMixedSwitch = 1e-5;
+constexpr double kMixedSwitch = 1e-6;
+// bf16 mode: bfloat16-pair operands while max|Omega| > kBf16GroundSwitch,
+// fp32 operands from there to kMixedSwitch
+constexpr double kBf16GroundSwitch = 1e-3;
 // Eigen- and linear solvers: fp32-operand images carry about 1e-7 relative
 // rounding (bf16 pairs about 1e-5), so the residual norms computed from them
 // level off there; at that point (or when they stall) the current solution
@@ -645,12 +648,18 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
   double err = 0.0;
   int status = CC_NOT_CONVERGED;
   bool lowp = mixed(c);
+  bool bf = lowp && solver_bf16(c);
   c.eng->set_lowp(lowp);
+  c.eng->set_bf16(bf);
   for (it = 1; it <= c.opts.maxit; ++it) {
     residual(c, c.t, r, deps);
     err = amax(c, r, N);
     if (!std::isfinite(err)) throw Error(-5, "non-finite CCSD residual");
     if (verbose()) std::fprintf(stderr, "[ground] it %d max|Omega| %.3e\n", it, err);
+    if (bf && err < kBf16GroundSwitch) {
+      bf = false;
+      c.eng->set_bf16(false);
+    }
     if (lowp && err < kMixedSwitch) {
       // iterative refinement: the remaining iterations use fp64 residuals
       lowp = false;
@@ -698,6 +707,7 @@ static int ground(Ctx& c, double* e_out, int* it_out) {
     }
   }
   c.eng->set_lowp(false);
+  c.eng->set_bf16(false);
   if (it > c.opts.maxit) it = c.opts.maxit;
   c.ecorr = energy(c, c.t);
   if (e_out) *e_out = c.ecorr;
