@@ -110,10 +110,10 @@ def run_step(nm, torch, inp, cfg, opts, start=None):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.944e+10, "fp32": 1.881e+10}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.951e+10, "fp32": 1.877e+10}
 # the same for each workgroup tile of the bfloat16-pair kernel
-LADDER_TRAFFIC_BYTES_BF16 = {0: 2.469e+10, 1: 5.67e+09, 2: 8.15e+09, 3: 7.50e+09, 4: 8.04e+09,
-                             5: 7.87e+09, 6: 8.51e+09, 7: 8.32e+09}
+LADDER_TRAFFIC_BYTES_BF16 = {0: 2.309e+10, 1: 5.75e+09, 2: 7.80e+09, 3: 7.49e+09, 4: 8.09e+09,
+                             5: 8.15e+09, 6: 8.52e+09, 7: 1.087e+10}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2

@@ -444,9 +444,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // copied by memcpy and can be left in private or shared memory)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int HBK = 32, HKS = 32;
-// 16-byte chunk c of tile row r sits at chunk c ^ ((r >> 2) & 3): the 16 rows
-// x one chunk of a quarter-wave's operand read cover all 64 banks
-__device__ inline int swz(int r, int c) { return r * HKS + 8 * (c ^ ((r >> 2) & 3)); }
+// 16-byte chunk c of tile row r sits at chunk c ^ ((r >> 1) & 3).  An operand
+// read has lane l take chunk l / 16 of row l % 16 (16 bytes a lane, ds_read_b128);
+// with this permutation it runs at the rate of a contiguous 1 KB read, where
+// c ^ ((r >> 2) & 3) or no swizzle take twice the LDS cycles (bank conflicts,
+// measured).  The staging stores write 16 whole rows a wave either way.
+__device__ inline int swz(int r, int c) { return r * HKS + 8 * (c ^ ((r >> 1) & 3)); }
 
 __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
     int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
