@@ -331,16 +331,28 @@ static DView packed_view(Arena& ar, const DView& src, const std::string& order, 
   return d;
 }
 
+// C = alpha sum_z part[z] + beta C, the partial products summed in split
+// order; the loads of four splits (and the old C) are issued together
 __global__ void splitk_fold_kernel(double* C, int64_t ldc, const double* part, int M, int N,
                                    int nsplit, double alpha, double beta) {
   const int64_t tot = (int64_t)M * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int z = 0; z < nsplit; ++z) acc += part[(int64_t)z * tot + e];
     const int64_t m = e / N, n = e - m * N;
     double* c = C + m * ldc + n;
-    *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * (*c));
+    const double old = beta == 0.0 ? 0.0 : *c;
+    double acc = 0.0;
+    int z = 0;
+    for (; z + 4 <= nsplit; z += 4) {
+      const double p0 = part[(int64_t)z * tot + e], p1 = part[(int64_t)(z + 1) * tot + e];
+      const double p2 = part[(int64_t)(z + 2) * tot + e], p3 = part[(int64_t)(z + 3) * tot + e];
+      acc += p0;
+      acc += p1;
+      acc += p2;
+      acc += p3;
+    }
+    for (; z < nsplit; ++z) acc += part[(int64_t)z * tot + e];
+    *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * old);
   }
 }
 
