@@ -110,10 +110,10 @@ def run_step(nm, torch, inp, cfg, opts, start=None):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.951e+10, "fp32": 1.877e+10}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.952e+10, "fp32": 1.899e+10}
 # the same for each workgroup tile of the bfloat16-pair kernel
-LADDER_TRAFFIC_BYTES_BF16 = {0: 2.309e+10, 1: 5.75e+09, 2: 7.80e+09, 3: 7.49e+09, 4: 8.09e+09,
-                             5: 8.15e+09, 6: 8.52e+09, 7: 1.087e+10}
+LADDER_TRAFFIC_BYTES_BF16 = {0: 2.047e+10, 1: 5.57e+09, 2: 7.50e+09, 3: 8.17e+09, 4: 1.339e+10,
+                             5: 7.62e+09, 6: 7.96e+09, 7: 7.87e+09}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2
@@ -163,8 +163,8 @@ def ladder_roofline(nm, torch, cfg, dev, st, nl=10):
     # bfloat16 pairs: three bf16 products per product, K padded to a multiple
     # of 32; achieved counts the bf16 matrix-core flops (3 x the ladder's)
     Kp = (v * v + 31) // 32 * 32
-    A = torch.randn(2, rows, Kp, device=dev).to(torch.bfloat16)
-    Bt = torch.randn(2, v * v, Kp, device=dev).to(torch.bfloat16)
+    A = torch.randn(rows, 2 * Kp, device=dev).to(torch.bfloat16)
+    Bt = torch.randn(v * v, 2 * Kp, device=dev).to(torch.bfloat16)
     C = torch.zeros(rows, v * v, dtype=torch.float64, device=dev)
     # every workgroup tile shape of the kernel; the fastest is the one the
     # contraction engine's autotuner keeps for this shape

@@ -220,10 +220,12 @@ int nm_contract(const char* spec, double alpha, const double* A, const int64_t* 
  * C[M][N] = alpha op(A) op(B) + beta C (row-major, leading dimensions lda,
  * ldb, ldc; ta / tb select A stored [K][M] / B stored [N][K]).  precision
  * CC_FP64: A, B double; CC_FP32_REFINE: A, B float (fp32 accumulation);
- * CC_BF16X3_REFINE: bfloat16 pairs (uint16 storage), A = hi [M][lda] followed
- * by lo [M][lda], B given transposed (tb = 1) as hi [N][ldb] then lo; K a
- * multiple of 32, lda / ldb multiples of 8, 16-byte aligned; each product
- * formed as three bf16 products with fp32 accumulation.
+ * CC_BF16X3_REFINE: bfloat16 pairs x = hi + lo (uint16 storage), A [M][lda]
+ * and B given transposed (tb = 1) as [N][ldb], hi and lo interleaved in
+ * 16-byte chunks: element k of a row has its hi at 2 (k - k % 8) + k % 8 and
+ * its lo 8 further; K a multiple of 32, lda / ldb (uint16 units) >= 2 K and
+ * multiples of 8, 16-byte aligned; each product formed as three bf16
+ * products with fp32 accumulation.
  * Asynchronous on `stream`.                                                 */
 int nm_gemm(int precision, int ta, int tb, int M, int N, int K, double alpha, const void* A,
             int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc,

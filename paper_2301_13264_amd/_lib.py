@@ -263,23 +263,33 @@ def contract(spec: str, alpha, A, B, beta, C, stream=None, precision=0):
     return C
 
 
+def pair_interleave(hi, lo):
+    """[R][K] hi and lo halves (K a multiple of 8) -> the library's pair
+    layout [R][2K]: each chunk of 8 hi values followed by its 8 lo values."""
+    import torch
+    R, K = hi.shape
+    return torch.stack([hi.reshape(R, K // 8, 8), lo.reshape(R, K // 8, 8)], dim=2).reshape(R, 2 * K)
+
+
 def gemm(precision, A, B, C, alpha=1.0, beta=0.0, stream=None, tile=-1):
     """One matrix-core GEMM launch C = alpha A B + beta C (2-D row-major
     device tensors; A, B float64 for precision 0, float32 for precision 1).
-    Precision 2: A [2][M][K] and Bt [2][N][K] bfloat16 pairs (hi, lo) with B
-    given transposed, K a multiple of 32; tile selects the kernel's workgroup
-    tile (nm_gemm_tiled, -1 = the library's choice)."""
+    Precision 2: A [M][2K] and Bt [N][2K] bfloat16 pairs with B given
+    transposed, hi and lo interleaved in chunks of 8 (pair_interleave), K a
+    multiple of 32; tile selects the kernel's workgroup tile (nm_gemm_tiled,
+    -1 = the library's choice)."""
     import torch
     if precision == 2:
         for t in (A, B):
-            if not t.is_cuda or t.dtype != torch.bfloat16 or not t.is_contiguous() or t.dim() != 3:
+            if not t.is_cuda or t.dtype != torch.bfloat16 or not t.is_contiguous() or t.dim() != 2:
                 raise ValueError("bad GEMM operand")
-        _, M, K = A.shape
-        _, N, K2 = B.shape
-        if K2 != K or tuple(C.shape) != (M, N):
+        M, K2a = A.shape
+        N, K2b = B.shape
+        if K2a != K2b or K2a % 2 or tuple(C.shape) != (M, N):
             raise ValueError("GEMM shape mismatch")
-        rc = lib().nm_gemm_tiled(2, tile, 0, 1, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), K,
-                                 ctypes.c_void_p(B.data_ptr()), K, beta, _ptr(C), N,
+        K = K2a // 2
+        rc = lib().nm_gemm_tiled(2, tile, 0, 1, M, N, K, alpha, ctypes.c_void_p(A.data_ptr()), 2 * K,
+                                 ctypes.c_void_p(B.data_ptr()), 2 * K, beta, _ptr(C), N,
                                  _stream_ptr(stream))
         if rc != CC_OK:
             raise CCError(rc, "nm_gemm")

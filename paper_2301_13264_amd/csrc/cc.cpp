@@ -2966,12 +2966,10 @@ int nm_gemm_tiled(int precision, int tile, int ta, int tb, int M, int N, int K, 
     rc = nm::gemm_f32acc(st, ta != 0, tb != 0, M, N, K, 1, alpha, (const float*)A, lda, 0,
                          (const float*)B, ldb, 0, beta, C, ldc, 0);
   else if (precision == CC_BF16X3_REFINE) {
-    // bfloat16 pairs: A = [hi | lo] each [M][lda], B = [hi | lo] each [N][ldb] (B^T)
-    if (ta || !tb || K % 32 || lda < K || ldb < K) return CC_ERR_ARG;
-    const uint16_t* a = (const uint16_t*)A;
-    const uint16_t* b = (const uint16_t*)B;
-    rc = nm::gemm_bf16x3(st, M, N, K, 1, alpha, a, a + (int64_t)M * lda, lda, 0, b, b + (int64_t)N * ldb,
-                         ldb, 0, beta, C, ldc, 0, 0, tile);
+    // interleaved bfloat16 pairs: A [M][lda], B^T [N][ldb], lda, ldb >= 2 K
+    if (ta || !tb || K % 32 || lda < 2 * (int64_t)K || ldb < 2 * (int64_t)K) return CC_ERR_ARG;
+    rc = nm::gemm_bf16x3(st, M, N, K, 1, alpha, (const uint16_t*)A, lda, 0, (const uint16_t*)B, ldb, 0, beta,
+                         C, ldc, 0, 0, tile);
     if (rc == -1) return CC_ERR_ARG;
   } else
     return CC_ERR_ARG;

@@ -760,7 +760,7 @@ const float* Engine::packed_f32(const DView& src, const std::string& order, bool
 }
 
 void Engine::packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K,
-                         int64_t Kp, const uint16_t** hi, const uint16_t** lo) {
+                         int64_t Kp, const uint16_t** pairs) {
   std::string key;
   if (src.constant || src.frozen) {
     int64_t cnt = 0;
@@ -773,14 +773,12 @@ void Engine::packed_bf16(const DView& src, const std::string& order, int64_t row
   if (src.constant) {
     auto it = bf16_cache_.find(key);
     if (it != bf16_cache_.end()) {
-      *hi = it->second;
-      *lo = it->second + n;
+      *pairs = it->second;
       return;
     }
   } else if (src.frozen) {
     if (void* hit = frozen_lookup("h" + key)) {
-      *hi = (const uint16_t*)hit;
-      *lo = (const uint16_t*)hit + n;
+      *pairs = (const uint16_t*)hit;
       return;
     }
   }
@@ -805,13 +803,12 @@ void Engine::packed_bf16(const DView& src, const std::string& order, int64_t row
   for (int64_t p = 1; nk < vs.nd && p < K; ++nk) p *= vs.dims[vs.nd - 1 - nk];
   if (nk == 0 && K == 1) nk = 1;
   for (int d = 0; d < vs.nd - nk; ++d) vs.ostr[d] = vs.ostr[d] / K * Kp;
-  kcheck(view_gather_bf16x2(s_, buf, (int64_t)n, src.p, vs, rows, (int)K, (int)Kp), "pack bf16 pairs");
+  kcheck(view_gather_bf16x2(s_, buf, src.p, vs, rows, (int)K, (int)Kp), "pack bf16 pairs");
   if (cached) {
     bf16_cache_[key] = buf;
     bf16_cache_bytes_ += 2 * n * sizeof(uint16_t);
   }
-  *hi = buf;
-  *lo = buf + n;
+  *pairs = buf;
 }
 
 void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const DView& C,
@@ -927,15 +924,16 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
       2.0 * (double)nb0 * (double)M0 * (double)N0 * (double)K >= lowp_min_flops_) {
     if (M0 > INT32_MAX || N0 > INT32_MAX || K > INT32_MAX || nb0 > INT32_MAX)
       throw Error(-1, "GEMM dimension overflow");
-    // bf16 pairs: A as [batch][rows][Kp], B transposed as [batch][cols][Kp]
+    // bf16 pairs: A as [batch][rows][2 Kp], B transposed as [batch][cols][2 Kp]
+    // (hi and lo interleaved in 16-byte chunks)
     const bool use_bf16 = bf16_ && K >= 32;
     const int64_t Kp = (K + 31) / 32 * 32;
     const float* a32 = nullptr;
     const float* b32 = nullptr;
-    const uint16_t *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr;
+    const uint16_t *ap = nullptr, *bp = nullptr;
     if (use_bf16) {
-      packed_bf16(A, sb + sm + sk, nb0 * M0, K, Kp, &ah, &al);
-      packed_bf16(B, sb + sn + sk, nb0 * N0, K, Kp, &bh, &bl);
+      packed_bf16(A, sb + sm + sk, nb0 * M0, K, Kp, &ap);
+      packed_bf16(B, sb + sn + sk, nb0 * N0, K, Kp, &bp);
     } else {
       a32 = packed_f32(A, sb + sm + sk);
       b32 = packed_f32(B, sb + sk + sn);
@@ -985,8 +983,8 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
           const int64_t klast = Kp - (nsr - 1) * kc;
           Arena::Mark pm = arena_.mark();
           double* part = arena_.alloc(nsr * M0 * N0);
-          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)kc, (int)nsr, 1.0, ah, al, Kp, kc, bh, bl, Kp, kc,
-                             0.0, part, N0, M0 * N0, (int)klast, tile),
+          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)kc, (int)nsr, 1.0, ap, 2 * Kp, 2 * kc, bp, 2 * Kp,
+                             2 * kc, 0.0, part, N0, M0 * N0, (int)klast, tile),
                  "gemm bf16x3 (split K)");
           const int64_t tot = M0 * N0;
           const int g = (int)std::min<int64_t>((tot + 255) / 256, 65536);
@@ -995,8 +993,8 @@ void Engine::contract(double alpha, const DView& A_in, const DView& B_in, const 
           kcheck(hipGetLastError() == hipSuccess ? 0 : -3, "splitk fold");
           arena_.rewind(pm);
         } else {
-          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)Kp, (int)nb0, aa, ah, al, Kp, M0 * Kp, bh, bl, Kp,
-                             N0 * Kp, bb, out, ldo, so, 0, tile),
+          kcheck(gemm_bf16x3(s_, (int)M0, (int)N0, (int)Kp, (int)nb0, aa, ap, 2 * Kp, 2 * M0 * Kp, bp,
+                             2 * Kp, 2 * N0 * Kp, bb, out, ldo, so, 0, tile),
                  "gemm bf16x3");
         }
         return;

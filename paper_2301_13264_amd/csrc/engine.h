@@ -167,7 +167,7 @@ class Engine {
   void* frozen_lookup(const std::string& key) const;
   void* frozen_store(const std::string& key, size_t bytes);
   void packed_bf16(const DView& src, const std::string& order, int64_t rows, int64_t K, int64_t Kp,
-                   const uint16_t** hi, const uint16_t** lo);
+                   const uint16_t** pairs);
 };
 
 class Graph {

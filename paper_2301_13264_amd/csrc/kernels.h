@@ -40,14 +40,17 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
 constexpr int kBf16Tiles = 8;
 int bf16x3_auto_tile(int M, int N, int batch);
 void bf16x3_tile_dims(int tile, int& bm, int& bn);
-int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
-                const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
-                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast,
-                int tile = -1);
-// bfloat16 pair (hi at out, lo at out + lo_off) of a strided double view
-// whose output strides address a [rows][Kp] layout; padding [K, Kp) zeroed
-int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const double* in,
-                       const ViewSpec& v, int64_t rows, int K, int Kp);
+// A, B: interleaved bfloat16 pair arrays (element k of a row: hi at
+// 2 (k - k % 8) + k % 8, lo 8 further); lda, ldb, sA, sB in uint16 units
+// (lda, ldb >= 2 K); a K offset k0 along a row is 2 k0 elements
+int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* A,
+                int64_t lda, int64_t sA, const uint16_t* B, int64_t ldb, int64_t sB, double beta,
+                double* C, int64_t ldc, int64_t sC, int Klast, int tile = -1);
+// bfloat16 pairs of a strided double view whose output strides address a
+// [rows][Kp] plane, written interleaved into out ([rows][2 Kp] uint16);
+// padding [K, Kp) zeroed
+int view_gather_bf16x2(hipStream_t s, uint16_t* out, const double* in, const ViewSpec& v, int64_t rows,
+                       int K, int Kp);
 int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch, double alpha,
                 const float* A, int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB,
                 double beta, double* C, int64_t ldc, int64_t sC, int Klast = 0);

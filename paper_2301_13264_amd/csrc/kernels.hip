@@ -430,10 +430,15 @@ int gemm_f32acc(hipStream_t s, bool ta, bool tb, int M, int N, int K, int batch,
 // so that x is held to about 2^-16 relative; every product is formed as
 // al*bh + ah*bl + ah*bh (the lo*lo term, ~2^-16 of the product, is dropped) on
 // the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with fp32 accumulation and
-// an fp64 epilogue.  Operands are K-contiguous: A [M][Kp] and B^T [N][Kp]
-// (uint16 storage of bf16, leading dimensions lda / ldb multiples of 8), K
-// zero-padded to a multiple of 32, so that every global load and LDS access is
-// a 16-byte vector and needs no K bound.  MFMA lane layout (checked on the
+// an fp64 epilogue.  Operands are K-contiguous pair arrays, A [M][2 Kp] and
+// B^T [N][2 Kp] (uint16 storage of bf16), hi and lo interleaved in 16-byte
+// chunks: element k of a row has its hi at 2 (k - k % 8) + k % 8 and its lo 8
+// further, so that a K step of 32 reads 128 contiguous bytes of a row (a whole
+// cache line; separate hi and lo rows would use half of two lines each, and
+// the launches ran 18 % longer).  Leading dimensions lda / ldb (uint16 units,
+// >= 2 K) multiples of 8, K zero-padded to a multiple of 32, so that every
+// global load and LDS access is a 16-byte vector and needs no K bound; K
+// offset k0 of a split sits 2 k0 along the row.  MFMA lane layout (checked on the
 // device): lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
 // for j < 8 and receives D rows 4 (l / 16) + v, column l % 16.
 // Tiles 128 x 128 x 32, 512 threads = 8 waves of 32 x 64 outputs, double-
@@ -452,16 +457,13 @@ constexpr int HBK = 32, HKS = 32;
 __device__ inline int swz(int r, int c) { return r * HKS + 8 * (c ^ ((r >> 1) & 3)); }
 
 __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
-    int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
-    const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
-    const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int M, int N, int K, double alpha, const uint16_t* __restrict__ A, int64_t lda, int64_t sA,
+    const uint16_t* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int Klast) {
   __shared__ __attribute__((aligned(16))) uint16_t S[2][4][128 * HKS];
   const int64_t bz = blockIdx.z;
-  Ah += bz * sA;
-  Al += bz * sA;
-  Bh += bz * sB;
-  Bl += bz * sB;
+  A += bz * sA;
+  B += bz * sB;
   C += bz * sC;
   if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
   const int gx = gridDim.x, gy = gridDim.y;
@@ -472,19 +474,20 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  // global loads: row tid / 4 of the tile, 8 consecutive k at 8 (tid % 4)
+  // global loads: row tid / 4 of the tile, the hi and lo chunks of the 8
+  // consecutive k at 8 (tid % 4)
   const int grow = tid >> 2, gch = (tid & 3) * 8;
   const bool aok = m0 + grow < M, bok = n0 + grow < N;
-  const int64_t aoff = (int64_t)(aok ? m0 + grow : 0) * lda + gch;
-  const int64_t boff = (int64_t)(bok ? n0 + grow : 0) * ldb + gch;
+  const int64_t aoff = (int64_t)(aok ? m0 + grow : 0) * lda + 2 * gch;
+  const int64_t boff = (int64_t)(bok ? n0 + grow : 0) * ldb + 2 * gch;
   const uint4 zero = {0u, 0u, 0u, 0u};
   uint4 r0, r1, r2, r3;
   auto gload = [&](int t) {
-    const int64_t k0 = (int64_t)t * HBK;
-    r0 = aok ? *(const uint4*)(Ah + aoff + k0) : zero;
-    r1 = aok ? *(const uint4*)(Al + aoff + k0) : zero;
-    r2 = bok ? *(const uint4*)(Bh + boff + k0) : zero;
-    r3 = bok ? *(const uint4*)(Bl + boff + k0) : zero;
+    const int64_t k0 = 2 * (int64_t)t * HBK;
+    r0 = aok ? *(const uint4*)(A + aoff + k0) : zero;
+    r1 = aok ? *(const uint4*)(A + aoff + k0 + 8) : zero;
+    r2 = bok ? *(const uint4*)(B + boff + k0) : zero;
+    r3 = bok ? *(const uint4*)(B + boff + k0 + 8) : zero;
   };
   auto sstore = [&](int buf) {
     const int o = swz(grow, gch >> 3);
@@ -566,9 +569,8 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
 // blocks (FJ independent accumulators between dependent MFMAs).
 template <int BM, int BN, int WM, int WN, int PD>
 __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
-    int M, int N, int K, double alpha, const uint16_t* __restrict__ Ah,
-    const uint16_t* __restrict__ Al, int64_t lda, int64_t sA, const uint16_t* __restrict__ Bh,
-    const uint16_t* __restrict__ Bl, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int M, int N, int K, double alpha, const uint16_t* __restrict__ A, int64_t lda, int64_t sA,
+    const uint16_t* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int Klast) {
   static_assert(WM * WN == 8, "eight waves");
   static_assert(PD == 1 || PD == 2 || PD == 3, "pipeline variant");
@@ -579,10 +581,8 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
   __shared__ __attribute__((aligned(16))) uint16_t SA[2][2][BM * HKS];
   __shared__ __attribute__((aligned(16))) uint16_t SB[2][2][BN * HKS];
   const int64_t bz = blockIdx.z;
-  Ah += bz * sA;
-  Al += bz * sA;
-  Bh += bz * sB;
-  Bl += bz * sB;
+  A += bz * sA;
+  B += bz * sB;
   C += bz * sC;
   if (Klast > 0 && blockIdx.z == gridDim.z - 1) K = Klast;
   const int gx = gridDim.x, gy = gridDim.y;
@@ -593,19 +593,19 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int lr = lane & 15, lk = lane >> 4;
-  // this thread's rows: (tid >> 2) + RP r, 16-byte chunk tid & 3 of the
-  // 32-wide K step, in each of A hi, A lo (r < RA) and B hi, B lo (r < RB)
+  // this thread's rows: (tid >> 2) + RP r, the hi and lo 16-byte chunks
+  // tid & 3 of the 32-wide K step, of A (r < RA) and B (r < RB)
   const int row0 = tid >> 2, ch = tid & 3;
   int64_t aoff[RA], boff[RB];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     const bool ok = m0 + row0 + RP * r < M;
-    aoff[r] = (int64_t)(ok ? m0 + row0 + RP * r : 0) * lda + 8 * ch;
+    aoff[r] = (int64_t)(ok ? m0 + row0 + RP * r : 0) * lda + 16 * ch;
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     const bool ok = n0 + row0 + RP * r < N;
-    boff[r] = (int64_t)(ok ? n0 + row0 + RP * r : 0) * ldb + 8 * ch;
+    boff[r] = (int64_t)(ok ? n0 + row0 + RP * r : 0) * ldb + 16 * ch;
   }
   // rows outside the matrix read row 0 of the panel instead (always valid):
   // they only reach accumulators of output rows or columns that are never
@@ -618,16 +618,16 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
 #pragma unroll
     for (int j = 0; j < FJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nk = K / HBK;
-  // K offset of step t (clamped to the last step)
-#define NM_KOFF(t) ((int64_t)((t) < nk ? (t) : nk - 1) * HBK)
+  // offset of K step t along a pair row (clamped to the last step)
+#define NM_KOFF(t) ((int64_t)((t) < nk ? (t) : nk - 1) * (2 * HBK))
 #define NM_LOAD(S, KO)                                     \
   _Pragma("unroll") for (int r = 0; r < RA; ++r) {         \
-    ah##S[r] = *(const u32x4*)(Ah + aoff[r] + (KO));       \
-    al##S[r] = *(const u32x4*)(Al + aoff[r] + (KO));       \
+    ah##S[r] = *(const u32x4*)(A + aoff[r] + (KO));        \
+    al##S[r] = *(const u32x4*)(A + aoff[r] + (KO) + 8);    \
   }                                                        \
   _Pragma("unroll") for (int r = 0; r < RB; ++r) {         \
-    bh##S[r] = *(const u32x4*)(Bh + boff[r] + (KO));       \
-    bl##S[r] = *(const u32x4*)(Bl + boff[r] + (KO));       \
+    bh##S[r] = *(const u32x4*)(B + boff[r] + (KO));        \
+    bl##S[r] = *(const u32x4*)(B + boff[r] + (KO) + 8);    \
   }
 #define NM_STORE(S, G)                                                     \
   _Pragma("unroll") for (int r = 0; r < RA; ++r) {                         \
@@ -795,20 +795,19 @@ int bf16x3_auto_tile(int M, int N, int batch) {
   return 0;
 }
 
-int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* Ah,
-                const uint16_t* Al, int64_t lda, int64_t sA, const uint16_t* Bh, const uint16_t* Bl,
-                int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC, int Klast,
-                int tile) {
+int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, const uint16_t* A,
+                int64_t lda, int64_t sA, const uint16_t* B, int64_t ldb, int64_t sB, double beta,
+                double* C, int64_t ldc, int64_t sC, int Klast, int tile) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (K <= 0 || K % HBK || (Klast > 0 && Klast % HBK) || lda % 8 || ldb % 8 || sA % 8 || sB % 8 ||
-      ((uintptr_t)Ah | (uintptr_t)Al | (uintptr_t)Bh | (uintptr_t)Bl) % 16 || tile >= kBf16Tiles)
+      lda < 2 * (int64_t)K || ldb < 2 * (int64_t)K || ((uintptr_t)A | (uintptr_t)B) % 16 ||
+      tile >= kBf16Tiles)
     return -1;
   if (batch > 32768) {
     for (int b0 = 0; b0 < batch; b0 += 32768) {
       const int nb = batch - b0 < 32768 ? batch - b0 : 32768;
-      int rc = gemm_bf16x3(s, M, N, K, nb, alpha, Ah + (int64_t)b0 * sA, Al + (int64_t)b0 * sA, lda, sA,
-                           Bh + (int64_t)b0 * sB, Bl + (int64_t)b0 * sB, ldb, sB, beta,
-                           C + (int64_t)b0 * sC, ldc, sC, b0 + nb == batch ? Klast : 0, tile);
+      int rc = gemm_bf16x3(s, M, N, K, nb, alpha, A + (int64_t)b0 * sA, lda, sA, B + (int64_t)b0 * sB, ldb,
+                           sB, beta, C + (int64_t)b0 * sC, ldc, sC, b0 + nb == batch ? Klast : 0, tile);
       if (rc) return rc;
     }
     return 0;
@@ -819,8 +818,7 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
   dim3 grid((N + bn - 1) / bn, (M + bm - 1) / bm, batch);
 #define NM_BF16BIG(BM_, BN_, WM_, WN_, PD_)                                                              \
   hipLaunchKernelGGL((gemm_bf16x3_big_kernel<BM_, BN_, WM_, WN_, PD_>), grid, dim3(WM_ * WN_ * 64), 0, s, \
-                     M, N, K,                                                                             \
-                     alpha, Ah, Al, lda, sA, Bh, Bl, ldb, sB, beta, C, ldc, sC, Klast)
+                     M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, Klast)
   switch (tile) {
     case 1: NM_BF16BIG(256, 256, 2, 4, 1); break;
     case 2: NM_BF16BIG(256, 128, 4, 2, 1); break;
@@ -830,8 +828,8 @@ int gemm_bf16x3(hipStream_t s, int M, int N, int K, int batch, double alpha, con
     case 6: NM_BF16BIG(256, 128, 4, 2, 3); break;
     case 7: NM_BF16BIG(128, 256, 2, 4, 3); break;
     default:
-      hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, Ah, Al, lda, sA, Bh,
-                         Bl, ldb, sB, beta, C, ldc, sC, Klast);
+      hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(512), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB,
+                         beta, C, ldc, sC, Klast);
   }
 #undef NM_BF16BIG
   return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -843,6 +841,11 @@ __device__ inline uint16_t bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
+
+// Position of the hi half of planar pair element p in an interleaved pair
+// array (rows of Kp elements, Kp a multiple of 8): the 8-element chunk of p
+// becomes 16 elements, hi first; its lo half sits 8 further.
+__device__ inline int64_t pair_index(int64_t p) { return 2 * p - (p & 7); }
 
 // ------------------------------------------------------ tiled strided copy
 // A strided copy without summed labels runs as 64 x 64 tiles of two of its
@@ -865,13 +868,15 @@ struct TileSpec {
 // before the LDS round trip, and 5-14 % for the direct one).
 constexpr int kTileThreads = 512;
 
-// PAIR: out is the hi array of a bfloat16 pair (uint16), lo at out + lo_off;
-// x = (float)(alpha in), hi = bf16(x), lo = bf16(x - hi)
+// PAIR: out is a bfloat16 pair array (uint16) whose planar position p (the
+// output strides address a [rows][Kp] plane, p counted from pbase) is stored
+// interleaved: hi at 2 p - p % 8, lo 8 further (pair_index); x = (float)(alpha
+// in), hi = bf16(x), lo = bf16(x - hi)
 template <typename TO, bool TRANS, bool PAIR = false>
 __global__ __launch_bounds__(kTileThreads) void tile_copy_kernel(TO* __restrict__ out,
                                                                 const double* __restrict__ in,
                                                                 TileSpec t, double alpha, double beta,
-                                                                int64_t lo_off = 0) {
+                                                                int64_t pbase = 0) {
   __shared__ double tile[TRANS ? 64 * 65 : 1];
   int64_t b = blockIdx.x;
   const int64_t txi = b % t.tx;
@@ -911,13 +916,14 @@ __global__ __launch_bounds__(kTileThreads) void tile_copy_kernel(TO* __restrict_
       const int64_t y = y0 + lane, x = x0 + row + RP * k;
       if (x < t.nx && y < t.ny) {
         const double val = alpha * tile[lane * 65 + row + RP * k];
-        TO* o = out + ob + x * t.osx + y * t.osy;
         if constexpr (PAIR) {
           const float xf = (float)val;
           const uint16_t h = bf16_rne(xf);
+          TO* o = out + pair_index(pbase + ob + x * t.osx + y * t.osy);
           o[0] = h;
-          o[lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+          o[8] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
         } else {
+          TO* o = out + ob + x * t.osx + y * t.osy;
           *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * prev[k]);
         }
       }
@@ -928,13 +934,14 @@ __global__ __launch_bounds__(kTileThreads) void tile_copy_kernel(TO* __restrict_
       const int64_t x = x0 + lane, y = y0 + r;
       if (x < t.nx && y < t.ny) {
         const double val = alpha * in[ib + x * t.isx + y * t.isy];
-        TO* o = out + ob + x * t.osx + y * t.osy;
         if constexpr (PAIR) {
           const float xf = (float)val;
           const uint16_t h = bf16_rne(xf);
+          TO* o = out + pair_index(pbase + ob + x * t.osx + y * t.osy);
           o[0] = h;
-          o[lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+          o[8] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
         } else {
+          TO* o = out + ob + x * t.osx + y * t.osy;
           *o = (beta == 0.0) ? (TO)val : (TO)(val + beta * (double)*o);
         }
       }
@@ -1062,10 +1069,10 @@ int view_gather_f32(hipStream_t s, float* out, const double* in, const ViewSpec&
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-// bfloat16 pair of in (double) through a strided view: hi at out, lo at
-// out + lo_off (generic path when the view does not tile)
-__global__ void view_gather_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off,
-                                          const double* __restrict__ in, ViewSpec v, int64_t total) {
+// bfloat16 pair of in (double) through a strided view into an interleaved
+// pair array (generic path when the view does not tile)
+__global__ void view_gather_bf16x2_kernel(uint16_t* __restrict__ out, const double* __restrict__ in,
+                                          ViewSpec v, int64_t total) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t rem = e, oo = v.obase, io = v.ibase;
@@ -1078,38 +1085,41 @@ __global__ void view_gather_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo
     }
     const float xf = (float)in[io];
     const uint16_t h = bf16_rne(xf);
-    out[oo] = h;
-    out[oo + lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+    uint16_t* o = out + pair_index(oo);
+    o[0] = h;
+    o[8] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
   }
 }
 
-__global__ void flat_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off,
+// planar positions pbase + e, e < total, from in[e]
+__global__ void flat_bf16x2_kernel(uint16_t* __restrict__ out, int64_t pbase,
                                    const double* __restrict__ in, int64_t total) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const float xf = (float)in[e];
     const uint16_t h = bf16_rne(xf);
-    out[e] = h;
-    out[e + lo_off] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
+    uint16_t* o = out + pair_index(pbase + e);
+    o[0] = h;
+    o[8] = bf16_rne(xf - __uint_as_float((uint32_t)h << 16));
   }
 }
 
-// zero the padding columns [K, Kp) of a [rows][Kp] pair
-__global__ void pad_bf16x2_kernel(uint16_t* __restrict__ out, int64_t lo_off, int64_t rows, int K,
-                                  int Kp) {
+// zero the padding columns [K, Kp) of a [rows][Kp] pair plane
+__global__ void pad_bf16x2_kernel(uint16_t* __restrict__ out, int64_t rows, int K, int Kp) {
   const int w = Kp - K;
   const int64_t total = rows * w;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / w;
-    const int64_t o = r * Kp + K + (e - r * w);
-    out[o] = 0;
-    out[o + lo_off] = 0;
+    uint16_t* o = out + pair_index(r * Kp + K + (e - r * w));
+    o[0] = 0;
+    o[8] = 0;
   }
 }
 
-int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const double* in,
-                       const ViewSpec& v, int64_t rows, int K, int Kp) {
+int view_gather_bf16x2(hipStream_t s, uint16_t* out, const double* in, const ViewSpec& v, int64_t rows,
+                       int K, int Kp) {
+  if (Kp % 8) return -1;
   int64_t total = 1;
   for (int d = 0; d < v.nd; ++d) total *= v.dims[d];
   // a contiguous view in its own order (no permutation, no padding): an
@@ -1123,8 +1133,8 @@ int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const doubl
   if (total > 0 && flat) {
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(flat_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out + v.obase, lo_off,
-                       in + v.ibase, total);
+    hipLaunchKernelGGL(flat_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, v.obase, in + v.ibase,
+                       total);
     if (hipGetLastError() != hipSuccess) return -3;
   } else if (total > 0) {
     TileSpec t;
@@ -1134,22 +1144,21 @@ int view_gather_bf16x2(hipStream_t s, uint16_t* out, int64_t lo_off, const doubl
       for (int d = 0; d < t.nb; ++d) blocks *= t.bdims[d];
       if (trans)
         hipLaunchKernelGGL((tile_copy_kernel<uint16_t, true, true>), dim3((unsigned)blocks),
-                           dim3(kTileThreads), 0, s, out + v.obase, in + v.ibase, t, 1.0, 0.0, lo_off);
+                           dim3(kTileThreads), 0, s, out, in + v.ibase, t, 1.0, 0.0, v.obase);
       else
         hipLaunchKernelGGL((tile_copy_kernel<uint16_t, false, true>), dim3((unsigned)blocks),
-                           dim3(kTileThreads), 0, s, out + v.obase, in + v.ibase, t, 1.0, 0.0, lo_off);
+                           dim3(kTileThreads), 0, s, out, in + v.ibase, t, 1.0, 0.0, v.obase);
     } else {
       int64_t g = (total + 255) / 256;
       if (g > 65536) g = 65536;
-      hipLaunchKernelGGL(view_gather_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, lo_off, in, v,
-                         total);
+      hipLaunchKernelGGL(view_gather_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, in, v, total);
     }
     if (hipGetLastError() != hipSuccess) return -3;
   }
   if (Kp > K && rows > 0) {
     int64_t g = (rows * (Kp - K) + 255) / 256;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(pad_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, lo_off, rows, K, Kp);
+    hipLaunchKernelGGL(pad_bf16x2_kernel, dim3((int)g), dim3(256), 0, s, out, rows, K, Kp);
     if (hipGetLastError() != hipSuccess) return -3;
   }
   return 0;

@@ -362,7 +362,7 @@ def test_gemm_bf16_pairs_kernel_surface(nm, M, N, K, tile):
     def pair(x):
         hi = x.to(torch.bfloat16)
         lo = (x - hi.float()).to(torch.bfloat16)
-        return torch.stack([hi, lo]).contiguous(), hi, lo
+        return nm.pair_interleave(hi, lo).contiguous(), hi, lo
     Ap, ah, al = pair(A)
     Bp, bh, bl = pair(Bt)
     C0 = torch.as_tensor(rng.normal(size=(M, N)), device="cuda")
