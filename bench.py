@@ -110,10 +110,10 @@ def run_step(nm, torch, inp, cfg, opts, start=None):
 # (profiles/ladder_gemm_thymine_dz_traffic.md), each counter scaled by the
 # ratio of a 1 GiB device copy's known bytes to what the counter reads for it.
 # Set to None whenever the GEMM kernels change, until the counters are re-taken.
-LADDER_TRAFFIC_BYTES = {"fp64": 3.952e+10, "fp32": 1.899e+10}
+LADDER_TRAFFIC_BYTES = {"fp64": 3.952e+10, "fp32": 1.89e+10}
 # the same for each workgroup tile of the bfloat16-pair kernel
-LADDER_TRAFFIC_BYTES_BF16 = {0: 2.047e+10, 1: 5.57e+09, 2: 7.50e+09, 3: 8.17e+09, 4: 1.339e+10,
-                             5: 7.62e+09, 6: 7.96e+09, 7: 7.87e+09}
+LADDER_TRAFFIC_BYTES_BF16 = {0: 2.008e+10, 1: 4.852e+09, 2: 7.274e+09, 3: 7.389e+09, 4: 7.262e+09,
+                             5: 7.351e+09, 6: 7.662e+09, 7: 7.432e+09}
 # trial vectors per ladder launch: the block the EOM solver pushes through each
 # Jacobian transform (the wanted roots)
 LADDER_VECTORS = 2

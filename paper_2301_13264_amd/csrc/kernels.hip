@@ -556,8 +556,11 @@ __global__ __launch_bounds__(512, 2) void gemm_bf16x3_kernel(
 // two stages of the four 32-wide bf16 row arrays (A hi, A lo, B hi, B lo),
 // 256 (BM + BN) bytes in all (128 KB at 256 x 256), with the same XOR-swizzled
 // 16-byte chunks as the 128 x 128 kernel.  Each thread moves
-// (BM + BN) / 64 16-byte chunks per K step through registers.  PD = 1: the
-// next K step is loaded while this one is multiplied; PD = 2 (two register
+// (BM + BN) / 64 16-byte chunks per K step through registers, eight lanes
+// to a row's 128-byte line (measured 3 % faster than four lanes to each of
+// its hi and lo halves: a load instruction then touches half as many
+// lines).  PD = 1: the next K step is loaded while this one is multiplied;
+// PD = 2 (two register
 // sets, the loop unrolled by two so that each set has fixed registers): the
 // K step after next, so a global load has two steps of products to arrive.
 // PD = 3: the fragments of the next K step are read from LDS into a second
@@ -575,9 +578,10 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
   static_assert(WM * WN == 8, "eight waves");
   static_assert(PD == 1 || PD == 2 || PD == 3, "pipeline variant");
   constexpr int TM = BM / WM, TN = BN / WN, FI = TM / 16, FJ = TN / 16;
-  // 16-byte chunks per thread and operand half per K step: rows / RP, with
-  // RP = (threads / 4) rows staged per pass (four 16-byte chunks per row)
-  constexpr int RP = WM * WN * 16, RA = BM / RP, RB = BN / RP;
+  // 16-byte chunks per thread and operand per K step: rows / RP, with
+  // RP = threads / 8 rows staged per pass (a row's K step is 8 chunks: hi and
+  // lo of four groups of 8 k, one whole 128-byte line)
+  constexpr int RP = WM * WN * 8, RA = BM / RP, RB = BN / RP;
   __shared__ __attribute__((aligned(16))) uint16_t SA[2][2][BM * HKS];
   __shared__ __attribute__((aligned(16))) uint16_t SB[2][2][BN * HKS];
   const int64_t bz = blockIdx.z;
@@ -593,25 +597,26 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
   const int lr = lane & 15, lk = lane >> 4;
-  // this thread's rows: (tid >> 2) + RP r, the hi and lo 16-byte chunks
-  // tid & 3 of the 32-wide K step, of A (r < RA) and B (r < RB)
-  const int row0 = tid >> 2, ch = tid & 3;
+  // this thread's rows: (tid >> 3) + RP r, chunk tid & 7 of the row's K
+  // step (the hi, for even chunks, or the lo half of k group (tid & 7) / 2),
+  // of A (r < RA) and B (r < RB): eight lanes read a row's whole line
+  const int row0 = tid >> 3, ch = tid & 7;
   int64_t aoff[RA], boff[RB];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     const bool ok = m0 + row0 + RP * r < M;
-    aoff[r] = (int64_t)(ok ? m0 + row0 + RP * r : 0) * lda + 16 * ch;
+    aoff[r] = (int64_t)(ok ? m0 + row0 + RP * r : 0) * lda + 8 * ch;
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     const bool ok = n0 + row0 + RP * r < N;
-    boff[r] = (int64_t)(ok ? n0 + row0 + RP * r : 0) * ldb + 16 * ch;
+    boff[r] = (int64_t)(ok ? n0 + row0 + RP * r : 0) * ldb + 8 * ch;
   }
   // rows outside the matrix read row 0 of the panel instead (always valid):
   // they only reach accumulators of output rows or columns that are never
   // stored, so they need no zeroing
-  u32x4 ah0[RA], al0[RA], bh0[RB], bl0[RB];
-  u32x4 ah1[RA], al1[RA], bh1[RB], bl1[RB];
+  u32x4 ra0[RA], rb0[RB];
+  u32x4 ra1[RA], rb1[RB];
   v4f acc[FI][FJ];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
@@ -620,24 +625,16 @@ __global__ __launch_bounds__(WM * WN * 64, 1) void gemm_bf16x3_big_kernel(
   const int nk = K / HBK;
   // offset of K step t along a pair row (clamped to the last step)
 #define NM_KOFF(t) ((int64_t)((t) < nk ? (t) : nk - 1) * (2 * HBK))
-#define NM_LOAD(S, KO)                                     \
-  _Pragma("unroll") for (int r = 0; r < RA; ++r) {         \
-    ah##S[r] = *(const u32x4*)(A + aoff[r] + (KO));        \
-    al##S[r] = *(const u32x4*)(A + aoff[r] + (KO) + 8);    \
-  }                                                        \
-  _Pragma("unroll") for (int r = 0; r < RB; ++r) {         \
-    bh##S[r] = *(const u32x4*)(B + boff[r] + (KO));        \
-    bl##S[r] = *(const u32x4*)(B + boff[r] + (KO) + 8);    \
-  }
-#define NM_STORE(S, G)                                                     \
-  _Pragma("unroll") for (int r = 0; r < RA; ++r) {                         \
-    *(u32x4*)&SA[G][0][swz(row0 + RP * r, ch)] = ah##S[r];                 \
-    *(u32x4*)&SA[G][1][swz(row0 + RP * r, ch)] = al##S[r];                 \
-  }                                                                        \
-  _Pragma("unroll") for (int r = 0; r < RB; ++r) {                         \
-    *(u32x4*)&SB[G][0][swz(row0 + RP * r, ch)] = bh##S[r];                 \
-    *(u32x4*)&SB[G][1][swz(row0 + RP * r, ch)] = bl##S[r];                 \
-  }
+#define NM_LOAD(S, KO)                                                       \
+  _Pragma("unroll") for (int r = 0; r < RA; ++r) ra##S[r] =                  \
+      *(const u32x4*)(A + aoff[r] + (KO));                                   \
+  _Pragma("unroll") for (int r = 0; r < RB; ++r) rb##S[r] =                  \
+      *(const u32x4*)(B + boff[r] + (KO));
+#define NM_STORE(S, G)                                                       \
+  _Pragma("unroll") for (int r = 0; r < RA; ++r)                             \
+      *(u32x4*)&SA[G][ch & 1][swz(row0 + RP * r, ch >> 1)] = ra##S[r];       \
+  _Pragma("unroll") for (int r = 0; r < RB; ++r)                             \
+      *(u32x4*)&SB[G][ch & 1][swz(row0 + RP * r, ch >> 1)] = rb##S[r];
 #define NM_COMPUTE(G)                                                                             \
   {                                                                                               \
     bf16x8 fbh[FJ], fbl[FJ];                                                                      \
