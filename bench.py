@@ -213,7 +213,8 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
     started from MP2 (the default) and from the network, at tolerance tol.
     Every answer is judged by the same residual tolerance.  On the first
     n_full held-out geometries the whole path to the couplings (pairs (1, 2)
-    and (2, 1), 45 directions) runs from each start as well."""
+    and (2, 1), 45 directions) runs from each start as well (twice each, the
+    faster run reported)."""
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
     base = synth.make_system(cfg["o"], cfg["v"], cfg["naux"], cfg["seed"], sigma_b=sigma_b(cfg))
     eps = T(base["eps"])
@@ -286,13 +287,19 @@ def learned_guess(nm, torch, np, synth, cfg, dev, prec, n_train=48, n_eval=16, s
             res = {}
             for mode in ("mp2", "learned"):
                 start = (lambda c: c.guess_t2(net, mu_h, sd_h, zs)) if mode == "learned" else None
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ctx, out = run_step(nm, torch, inp, cfg, popts, start=start)
-                res[mode] = dict(time_to_nacme_s=time.perf_counter() - t0, stage_s=out["stage_s"],
-                                 ground_iters=out["ground_iters"], eom_iters=out["eom_iters"],
-                                 F=out["F"])
-                ctx.close()
+                # each start timed twice, the faster run kept: a GEMM shape
+                # the solvers meet for the first time in this process (say a
+                # block of one vector once a root has converged) puts the
+                # autotuner's first-use timings into one run only
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ctx, out = run_step(nm, torch, inp, cfg, popts, start=start)
+                    rec = dict(time_to_nacme_s=time.perf_counter() - t0, stage_s=out["stage_s"],
+                               ground_iters=out["ground_iters"], eom_iters=out["eom_iters"], F=out["F"])
+                    ctx.close()
+                    if mode not in res or rec["time_to_nacme_s"] < res[mode]["time_to_nacme_s"]:
+                        res[mode] = rec
             dF = max(float(np.abs(np.asarray(res["mp2"]["F"][p]) - np.asarray(res["learned"]["F"][p])).max())
                      for p in PAIRS)
             for r in res.values():
