@@ -1,5 +1,6 @@
 """CPU-side checks of the built library: it loads, exports every symbol of
-include/nacme.h, and its host-only subspace eigensolver is correct."""
+include/nacme.h, and its host-only subspace eigensolver is correct; and the
+binding's bf16-pair layout helper."""
 import ctypes
 import os
 import re
@@ -46,3 +47,21 @@ def test_host_eigensolver():
 def test_version():
     _lib = _lib_or_skip()
     assert b"gfx950" in _lib.lib().nm_version()
+
+
+def test_pair_interleave_layout():
+    """The bf16-pair operand layout of the GEMM surface: each group of 8 hi
+    values of a row is followed by the group's 8 lo values, so element k sits
+    at 2 (k - k % 8) + k % 8 (hi) and 8 further (lo)."""
+    import torch
+
+    from paper_2301_13264_amd import pair_interleave
+    R, K = 3, 32
+    hi = torch.arange(R * K, dtype=torch.float32).reshape(R, K)
+    lo = -hi - 1
+    P = pair_interleave(hi, lo)
+    assert tuple(P.shape) == (R, 2 * K)
+    for r in range(R):
+        for k in range(K):
+            assert P[r, 2 * (k - k % 8) + k % 8] == hi[r, k]
+            assert P[r, 2 * (k - k % 8) + k % 8 + 8] == lo[r, k]
