@@ -23,7 +23,7 @@ static void kcheck(int rc, const char* what) {
 
 // ------------------------------------------------------------------- Arena
 Arena::~Arena() {
-  for (auto& c : chunks_) hipFree(c.base);
+  for (auto& c : chunks_) (void)hipFree(c.base);
 }
 
 double* Arena::alloc(int64_t ndouble) {
@@ -132,12 +132,6 @@ static int find_lab(const DView& v, char c) {
   for (int k = 0; k < v.nd; ++k)
     if (v.lab[k] == c) return k;
   return -1;
-}
-
-static int64_t vsize(const DView& v) {
-  int64_t s = 1;
-  for (int k = 0; k < v.nd; ++k) s *= v.dims[k];
-  return s;
 }
 
 // Is `v` a contiguous row-major tensor when its dims are taken in label
