@@ -325,7 +325,8 @@ def test_contract_low_precision_operands(nm, spec, shapes, oshape, prec):
 
 
 @pytest.mark.parametrize("spec,ashape", [("ik,kj->ij", (300, 64)), ("ki,kj->ij", (64, 300)),
-                                         ("ik,kj->ij", (257, 100))])
+                                         ("ik,kj->ij", (257, 100)), ("ik,kj->ij", (33, 45)),
+                                         ("ki,kj->ij", (77, 129))])
 def test_bf16_pair_packing_is_exact(nm, spec, ashape):
     """Through the bf16-pair path with B = identity every output is hi + lo
     of its input (B's pair is (1, 0)): the packing (fp64 -> fp32 -> hi =
@@ -334,7 +335,7 @@ def test_bf16_pair_packing_is_exact(nm, spec, ashape):
     say(f"[bf16 packing] {spec} {ashape}")
     rng = np.random.default_rng(17)
     A = T(rng.normal(size=ashape) * np.exp(rng.normal(size=ashape)))
-    K = 64 if spec.startswith("ki") else ashape[1]
+    K = ashape[0] if spec.startswith("ki") else ashape[1]
     M = ashape[1] if spec.startswith("ki") else ashape[0]
     I = torch.eye(K, dtype=torch.float64, device="cuda")
     C = torch.zeros((M, K), dtype=torch.float64, device="cuda")
