@@ -422,7 +422,24 @@ __global__ __launch_bounds__(256) void smallk_xfast_kernel(double* __restrict__ 
     double xv[KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) xv[k] = k < sp.K ? X[ox + sxk[k]] : 0.0;
-    for (int f = 0; f < sp.NF; ++f) {
+    // four outputs at a time, their old values loaded together
+    int f = 0;
+    for (; f + 4 <= sp.NF; f += 4) {
+      double old[4], acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) old[u] = beta == 0.0 ? 0.0 : C[oc + scf[f + u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* fr = sF + (f + u) * sp.K;
+        acc[u] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+          if (k < sp.K) acc[u] = fma(xv[k], fr[k], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) C[oc + scf[f + u]] = alpha * acc[u] + (beta == 0.0 ? 0.0 : beta * old[u]);
+    }
+    for (; f < sp.NF; ++f) {
       const double* fr = sF + f * sp.K;
       double acc = 0.0;
 #pragma unroll
